@@ -1,0 +1,16 @@
+"""FP64 CPU oracle for the room-simulator hot path (test infrastructure only).
+
+Only the tests, the smoke check and the CPU-baseline leg of the benchmark may
+import this package.  It shares no code with the GPU path.
+"""
+from .rsim_oracle import (  # noqa: F401
+    cut_scale,
+    cut_rir,
+    dry_power,
+    snr_gains,
+    convolve,
+    mix,
+    mix_at,
+    mix_backward,
+    simulate,
+)
