@@ -105,11 +105,13 @@ def snr_gains(p_dry: Sequence[float], snr_db: Sequence[float], n_mic: int) -> np
 def convolve(x: np.ndarray, h: np.ndarray) -> np.ndarray:
     """Linear convolution (h * x)[n] = sum_k h[k] x[n-k], length Nx + L - 1.
 
-    numpy.convolve evaluates the sum directly in the time domain (no FFT)."""
+    numpy.convolve evaluates the sum directly in the time domain (no FFT).
+    An empty signal or an empty RIR (a RIR of length 0 has no taps) gives an
+    empty result: it contributes nothing to eq. (2)."""
     x64 = np.asarray(x, dtype=np.float64)
     h64 = np.asarray(h, dtype=np.float64)
     if x64.size == 0 or h64.size == 0:
-        return np.zeros(max(0, x64.size + h64.size - 1), np.float64)
+        return np.zeros(0, np.float64)
     return np.convolve(x64, h64)
 
 

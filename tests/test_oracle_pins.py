@@ -307,3 +307,12 @@ def test_simulate_cuts_then_mixes():
     assert L[0][0] == 4 and y20.shape == (1, 53)
     y30, nc, L, _ = O.simulate(x, [[h]], [0.0], 30.0)
     assert L[0][0] == 22 and y30.shape == (1, 71)
+
+
+def test_empty_rir_contributes_nothing():
+    x = np.arange(5, dtype=np.float32)
+    assert oracle.convolve(x, np.zeros(0, np.float32)).size == 0
+    y = O.mix([x], [[np.zeros(0, np.float32), np.array([2.0], np.float32)]], np.ones((1, 2)))
+    assert y.shape == (2, 5)
+    assert not np.any(y[0]) and np.allclose(y[1], 2 * x)
+    assert O.mix([x], [[np.zeros(0, np.float32)]], np.ones((1, 1))).shape == (1, 0)
