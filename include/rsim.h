@@ -1,0 +1,200 @@
+/*
+ * rsim.h -- C ABI of the MI355X room-simulator hot path (librsim.so).
+ *
+ * The library implements, with hand-written HIP kernels for gfx950:
+ *   - the RIR tail cut-off of Sec. 2.3, eqs. (7)-(9);
+ *   - overlap-add FFT filtering of Sec. 2.2 (eq. (6) and the text around it),
+ *     which reproduces the linear convolution h_ij * x_i of eq. (2);
+ *   - the mixing model of eq. (2), y_j = sum_i alpha_ij (h_ij * x_i);
+ *   - the adjoint of eq. (2) with respect to x, h and alpha.
+ *
+ * Conventions for every entry point:
+ *   - Array arguments are DEVICE pointers unless marked (host).  The caller
+ *     owns every buffer; the library never frees or keeps caller memory.
+ *   - Calls that take a hipStream_t are asynchronous on that stream.  Their
+ *     return code reports only synchronous host-side validation; problems the
+ *     host cannot see (bad offsets inside device descriptor arrays, non-finite
+ *     RIR samples) set bits of a per-device status word read with
+ *     rsim_device_status().  Such items are skipped, never read out of bounds.
+ *   - No call allocates device memory after rsim_init(): scratch space comes
+ *     from the `ws` argument, sized by the matching *_workspace_bytes() call.
+ *   - No call aborts or throws across the ABI.
+ *   - All sample data is float32.  Lengths and counts are int32, offsets int64
+ *     (in elements, not bytes).
+ */
+#ifndef RSIM_H
+#define RSIM_H
+
+#include <hip/hip_runtime_api.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  RSIM_OK = 0,
+  RSIM_EINVAL = 1,       /* bad argument (null pointer, negative size, eta < 0 or NaN, ...) */
+  RSIM_EWORKSPACE = 2,   /* ws is null or smaller than the *_workspace_bytes() value */
+  RSIM_EUNSUPPORTED = 3, /* FFT size not a power of two in [512, 32768], or hop/RIR do not fit */
+  RSIM_EDEVICE = 4,      /* a HIP runtime call failed (launch, capture, copy) */
+  RSIM_ENOTINIT = 5      /* first use on this device happened during stream capture */
+} rsim_status;
+
+/* Bits of the device status word (rsim_device_status). */
+#define RSIM_DEV_NONFINITE 0x1 /* a RIR had a non-finite sample or h^2 overflowed: kept uncut */
+#define RSIM_DEV_BADDESC 0x2   /* a descriptor entry was out of range: that item was skipped */
+#define RSIM_DEV_BADPLAN 0x4   /* a requested FFT size / hop did not fit an utterance: skipped */
+
+/*
+ * Batch descriptor.  Scalars are host values; pointers are device arrays.
+ * U = n_utt utterances, J = n_mic microphones, S = max_src source slots per
+ * utterance (source 0 is the target).  RIR (u, i, j) has index
+ * r = (u*S + i)*J + j; source (u, i) has index u*S + i.
+ *
+ * Utterance u has n_src[u] <= S sources, all of length src_len[u].  Its output
+ * for mic j is y[out_off[u] + j*out_stride[u] + n], n < out_len[u], where the
+ * library writes out_len[u] = T_u = src_len[u] + max_ij rir_len[r] - 1 (0 if
+ * the utterance is empty) and requires out_stride[u] >= T_u.  Samples of y at
+ * n >= T_u are not written.
+ */
+typedef struct rsim_batch {
+  int32_t n_utt;          /* U >= 0 (host) */
+  int32_t n_mic;          /* J >= 1 (host) */
+  int32_t max_src;        /* S >= 1 (host) */
+  int32_t max_rir_len0;   /* (host) upper bound of every rir_len0 entry */
+  int64_t x_len;          /* (host) floats in x: bounds for src_off + src_len */
+  int64_t h_len;          /* (host) floats in h: bounds for rir_off + rir_len0 */
+  int64_t y_len;          /* (host) floats in y: bounds for out_off + J*out_stride */
+  const int32_t* n_src;   /* [U] */
+  const int32_t* src_len; /* [U] */
+  const int64_t* src_off; /* [U*S] */
+  const int64_t* rir_off; /* [U*S*J] */
+  const int32_t* rir_len0;/* [U*S*J] untruncated RIR lengths L0 */
+  const int32_t* rir_len; /* [U*S*J] kept lengths L <= L0 (written by rsim_truncate_rir) */
+  const int64_t* out_off; /* [U] */
+  const int32_t* out_stride; /* [U] */
+  int32_t* out_len;       /* [U] written: T_u */
+  const int32_t* order;   /* [U] or NULL: processing order, longest work first */
+  const int32_t* fft_log2n; /* [U] or NULL: forced log2 FFT size per utterance (9..15) */
+  const int32_t* hop;     /* [U] or NULL: forced block hop; default N - max L + 1 */
+} rsim_batch;
+
+/*
+ * FFT-size selection table (eq. (6) and the paragraph after it: evaluate the
+ * cost for each N = 2^m and keep the cheapest).  cost_fft[m-9] is the cost of
+ * one real FFT of size 2^m and cost_mac[m-9] of one spectral multiply-add over
+ * its N/2+1 bins; 0 disables that size.  The cost of an utterance with I
+ * sources, J mics, hop B and n_b = ceil(Nx/B) blocks is
+ *   n_b * ((I + J) * cost_fft + I*J * cost_mac) + I*J * cost_fft.
+ * Passing NULL selects the built-in model 2.5 N log2 N / 8 (N/2+1) over all sizes.
+ */
+typedef struct rsim_tune {
+  float cost_fft[7];
+  float cost_mac[7];
+} rsim_tune;
+
+/* Initialise the library on the current device (twiddle tables, launch
+ * geometry).  Idempotent.  Must not be called while a stream is capturing. */
+rsim_status rsim_init(void);
+
+const char* rsim_strerror(rsim_status s);
+int32_t rsim_version(void);
+
+/*
+ * RIR tail cut-off, Sec. 2.3 eqs. (7)-(9), for n_rir RIRs h[off[r] .. off[r]+len0[r]).
+ * Float32 rule: q[n] = fl(h[n]^2), P = max q, s = fl(10^(-eta/10)) evaluated in
+ * binary64 and rounded once (eta = +inf gives s = 0), p_th = fl(P s);
+ * n_c[r] = the last n with q[n] >= p_th; len[r] = min(n_c + 2, len0) (eq. (9)
+ * keeps indices 0..n_c+1).  An empty RIR gives n_c = -1, len = 0; a RIR with a
+ * non-finite q keeps len = len0 and sets RSIM_DEV_NONFINITE.  h_len bounds the
+ * offsets (entries outside it get n_c = -1, len = 0 and RSIM_DEV_BADDESC).
+ * eta_db must be >= 0 or +inf (RSIM_EINVAL otherwise).  n_c may be NULL.
+ */
+rsim_status rsim_truncate_rir(const float* h, int64_t h_len, const int64_t* off,
+                              const int32_t* len0, int32_t n_rir, double eta_db,
+                              int32_t* n_c, int32_t* len, hipStream_t stream);
+
+/*
+ * Overlap-add FFT convolution of one signal with one RIR (Sec. 2.2, eq. (6)):
+ * y[0 .. nx+nh-1) = (h * x).  fft_n is a power of two in [512, 32768];
+ * 1 <= hop and hop + nh - 1 <= fft_n (RSIM_EUNSUPPORTED otherwise); hop = 0
+ * selects fft_n - nh + 1.  nx >= 1, nh >= 1.
+ */
+size_t rsim_ola_workspace_bytes(int32_t fft_n);
+rsim_status rsim_ola_convolve(const float* x, int32_t nx, const float* h, int32_t nh,
+                              int32_t fft_n, int32_t hop, float* y, void* ws,
+                              size_t ws_bytes, hipStream_t stream);
+
+/*
+ * Batched filtering and mixing, eq. (2): for every utterance u and mic j,
+ *   y_j[n] = sum_{i < n_src[u]} alpha[r] (h_r[0..rir_len[r]) * x_i)[n],
+ * r = (u*S + i)*J + j, by overlap-add FFT filtering with an FFT size chosen
+ * per utterance (fft_log2n, else the tune table / built-in cost model, eq. (6)).
+ * alpha has U*S*J entries.  use_graph != 0 captures the call's launches into a
+ * HIP graph, instantiates and launches it (the stream must not be capturing).
+ * ws must hold rsim_mix_workspace_bytes(b, tune, 0) bytes.
+ */
+size_t rsim_mix_workspace_bytes(const rsim_batch* b, const rsim_tune* tune, int32_t backward);
+rsim_status rsim_mix(const rsim_batch* b, const float* x, const float* h, const float* alpha,
+                     float* y, void* ws, size_t ws_bytes, const rsim_tune* tune,
+                     int32_t use_graph, hipStream_t stream);
+
+/*
+ * Cut + mix of one epoch in one call: rsim_truncate_rir over every RIR slot
+ * of the batch (writing b->rir_len, which must then be writable) followed by
+ * rsim_mix; with use_graph != 0 all launches form one HIP graph.
+ */
+rsim_status rsim_simulate(const rsim_batch* b, const float* x, const float* h,
+                          const float* alpha, double eta_db, int32_t* rir_len_out,
+                          float* y, void* ws, size_t ws_bytes, const rsim_tune* tune,
+                          int32_t use_graph, hipStream_t stream);
+
+/*
+ * Adjoint of rsim_mix (eq. (2)).  grad_y has the layout of y (only n < T_u is
+ * read).  Writes
+ *   grad_x[i][n]  = sum_j alpha_ij sum_{k<L_ij} h_ij[k] g_j[n+k]        (n < Nx)
+ *   grad_h[r][k]  = alpha_r sum_n x_i[n] g_j[n+k]   for k < L_r, 0 for L_r <= k < L0_r
+ *   grad_alpha[r] = sum_n g_j[n] (h_r * x_i)[n]     (grad_alpha may be NULL)
+ * in the layouts of x, h and alpha.  The cut index gets no gradient.
+ * ws must hold rsim_mix_workspace_bytes(b, tune, 1) bytes.
+ */
+rsim_status rsim_mix_backward(const rsim_batch* b, const float* x, const float* h,
+                              const float* alpha, const float* grad_y, float* grad_x,
+                              float* grad_h, float* grad_alpha, void* ws, size_t ws_bytes,
+                              const rsim_tune* tune, hipStream_t stream);
+
+/*
+ * Dry power of every source slot, power[u*S + i] = mean_n x_i[n]^2 in FP64
+ * (0 for unused slots), on the device.
+ */
+rsim_status rsim_source_power(const rsim_batch* b, const float* x, double* power,
+                              hipStream_t stream);
+
+/*
+ * SNR gains of eq. (2) (host arrays): alpha[i*J + j] for I sources, J mics.
+ * The paper gives no gain formula; the rule is the dry-signal SNR rule:
+ * alpha_0j = 1 and alpha_ij = sqrt(p_dry[0] / (p_dry[i] 10^(snr_db[i]/10)))
+ * for i >= 1 (0 if p_dry[i] <= 0), identical for every mic.
+ */
+rsim_status rsim_snr_gains(const double* p_dry, const double* snr_db, int32_t I, int32_t J,
+                           float* alpha);
+
+/* Read and clear the device status word (synchronises the device). */
+rsim_status rsim_device_status(int32_t* status);
+
+/*
+ * Transform entry points of the FFT engine, for its unit tests: `count` real
+ * signals of length n (power of two, 512..32768), contiguous.  rsim_rfft
+ * writes n/2+1 complex bins per signal (interleaved float pairs), unscaled;
+ * rsim_irfft is its inverse (scaled by 1/n), reading n/2+1 bins.
+ */
+rsim_status rsim_rfft(const float* x, int32_t n, int32_t count, float* spec, hipStream_t stream);
+rsim_status rsim_irfft(const float* spec, int32_t n, int32_t count, float* x, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RSIM_H */

@@ -1,0 +1,90 @@
+// Device kernels of the room-simulator hot path: RIR cut-off (Sec. 2.3,
+// eqs. 7-9), per-utterance FFT-size schedule (eq. 6), and the persistent
+// overlap-add filter-and-mix kernel (Sec. 2.2 eq. 6 applied to eq. 2).
+#pragma once
+
+#include "fft_engine.hpp"
+
+namespace rsim {
+
+// Twiddle tables of every plan (filled from FP64 host values at init) and the
+// per-device status word.
+extern __device__ cf g_tw[kTwTotal];
+extern __device__ int g_status;
+
+constexpr int kNumFam = 5;  // workgroup sizes 32, 64, 128, 256, 512
+
+__host__ __device__ constexpr int family_of_log2n(int l2) {
+  return l2 == 9 ? 0 : l2 <= 12 ? 1 : l2 == 13 ? 2 : l2 == 14 ? 3 : 4;
+}
+
+// Per-utterance plan written by the schedule kernel.
+struct Sched {
+  int log2n;  // FFT size N = 2^log2n (0 if the utterance is skipped)
+  int hop;    // block hop B
+  int nb;     // number of blocks ceil(Nx / B)
+  int tu;     // output length Nx + Lmax - 1
+  int lmax;   // max kept RIR length over the utterance
+  int pad_;
+};
+
+struct BatchDev {
+  int U, J, S;
+  long long x_len, h_len, y_len;
+  const int* n_src;
+  const int* src_len;
+  const long long* src_off;
+  const long long* rir_off;
+  const int* rir_len0;
+  const int* rir_len;
+  const long long* out_off;
+  const int* out_stride;
+  int* out_len;
+  const int* order;
+  const int* fft_log2n;
+  const int* hop;
+};
+
+struct TuneDev {
+  float cost_fft[7];
+  float cost_mac[7];
+};
+
+// Workspace header shared by the schedule and mix launches of one call.
+struct WsHeader {
+  int counter[kNumFam];  // work-queue heads
+  int count[kNumFam];    // items per family
+};
+
+struct MixArgs {
+  BatchDev b;
+  const float* x;
+  const float* h;
+  const float* alpha;
+  float* y;
+  const Sched* sched;
+  const int* list;  // this family's utterances, in processing order
+  WsHeader* hdr;
+  int fam;
+  cf* scratch;          // per-workgroup scratch base
+  long long slot_cf;    // complex entries per workgroup
+};
+
+struct BwdArgs {
+  BatchDev b;
+  const float* x;
+  const float* h;
+  const float* alpha;
+  const float* gy;
+  float* gx;
+  float* gh;
+  float* galpha;
+  const Sched* sched;
+  const int* list;
+  WsHeader* hdr;
+  int fam;
+  cf* scratch;
+  long long slot_cf;
+};
+
+}  // namespace rsim

@@ -1,0 +1,1214 @@
+// librsim: HIP kernels for gfx950 and the C ABI declared in include/rsim.h.
+//
+// Hot path (one call of rsim_mix / rsim_simulate):
+//   truncate_kernel  RIR tail cut-off, Sec. 2.3 eqs. (7)-(9)
+//   schedule_kernel  per-utterance FFT size / hop / block count (eq. (6) cost,
+//                    evaluated for every N = 2^m as the text after eq. (6) says),
+//                    grouped by workgroup size, in the caller's order
+//   mix_kernel<T>    persistent workgroups pop utterances; each computes the
+//                    I*J RIR spectra once (Sec. 2.2: the RIR FFT is not
+//                    repeated per block), then walks the blocks: FFT of each
+//                    source block, spectral multiply-accumulate over sources
+//                    per mic, inverse FFT, overlap-add (eq. (6)) into y (eq. (2)).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <deque>
+#include <mutex>
+#include <vector>
+
+#include "../../include/rsim.h"
+#include "kernels.hpp"
+
+namespace rsim {
+
+__device__ cf g_tw[kTwTotal];
+__device__ int g_status;
+
+__device__ __forceinline__ void flag_status(int bits) { atomicOr(&g_status, bits); }
+
+// ------------------------------------------------------------------ reductions
+__device__ __forceinline__ float wave_max(float v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+  return v;
+}
+__device__ __forceinline__ int wave_max_i(int v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+  return v;
+}
+__device__ __forceinline__ int wave_or(int v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v |= __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ __forceinline__ double wave_sum_d(double v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// =============================================================== RIR cut-off
+// One workgroup (256 threads) per RIR.  P = max_n fl(h^2) by a max-reduction
+// (exact in any order), p_th = fl(P s), then the last index with q >= p_th,
+// searched in chunks from the tail so only the cut part is re-read.
+constexpr int kTruncThreads = 256;
+constexpr int kTruncChunk = 1024;
+
+__global__ __launch_bounds__(kTruncThreads) void truncate_kernel(
+    const float* __restrict__ h, long long h_len, const long long* __restrict__ off,
+    const int* __restrict__ len0, int n_rir, float s, int* __restrict__ n_c,
+    int* __restrict__ len) {
+  __shared__ float s_f[4];
+  __shared__ int s_i[4];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  for (int r = blockIdx.x; r < n_rir; r += gridDim.x) {
+    const int L0 = len0[r];
+    const long long o = off[r];
+    if (L0 < 0 || o < 0 || o + (long long)L0 > h_len) {
+      if (t == 0) {
+        flag_status(RSIM_DEV_BADDESC);
+        if (n_c) n_c[r] = -1;
+        len[r] = 0;
+      }
+      continue;
+    }
+    if (L0 == 0) {
+      if (t == 0) {
+        if (n_c) n_c[r] = -1;
+        len[r] = 0;
+      }
+      continue;
+    }
+    const float* p = h + o;
+    float mx = 0.0f;
+    int nf = 0;
+    for (int i = t; i < L0; i += kTruncThreads) {
+      const float v = p[i];
+      const float q = v * v;
+      nf |= !__builtin_isfinite(q);
+      mx = fmaxf(mx, q);
+    }
+    mx = wave_max(mx);
+    nf = wave_or(nf);
+    __syncthreads();
+    if (lane == 0) {
+      s_f[w] = mx;
+      s_i[w] = nf;
+    }
+    __syncthreads();
+    mx = fmaxf(fmaxf(s_f[0], s_f[1]), fmaxf(s_f[2], s_f[3]));
+    nf = s_i[0] | s_i[1] | s_i[2] | s_i[3];
+    if (nf) {
+      if (t == 0) {
+        flag_status(RSIM_DEV_NONFINITE);
+        if (n_c) n_c[r] = L0 - 1;
+        len[r] = L0;
+      }
+      continue;
+    }
+    const float pth = mx * s;
+    int found = -1;
+    for (int base = ((L0 - 1) / kTruncChunk) * kTruncChunk; base >= 0 && found < 0;
+         base -= kTruncChunk) {
+      int loc = -1;
+#pragma unroll
+      for (int k = 0; k < kTruncChunk / kTruncThreads; ++k) {
+        const int i = base + k * kTruncThreads + t;
+        if (i < L0) {
+          const float v = p[i];
+          if (v * v >= pth) loc = i;
+        }
+      }
+      loc = wave_max_i(loc);
+      __syncthreads();
+      if (lane == 0) s_i[w] = loc;
+      __syncthreads();
+      found = max(max(s_i[0], s_i[1]), max(s_i[2], s_i[3]));
+    }
+    if (t == 0) {
+      if (n_c) n_c[r] = found;
+      len[r] = min(found + 2, L0);
+    }
+  }
+}
+
+// ================================================================= schedule
+__device__ Sched plan_utterance(const BatchDev& b, const TuneDev& tune, int u, int& err) {
+  Sched S = {0, 0, 0, 0, 0, 0};
+  const int I = b.n_src[u], Nx = b.src_len[u], J = b.J;
+  if (I < 0 || I > b.S || Nx < 0) {
+    err |= RSIM_DEV_BADDESC;
+    return S;
+  }
+  int lmax = 0;
+  for (int i = 0; i < I; ++i) {
+    const long long so = b.src_off[(long long)u * b.S + i];
+    if (so < 0 || so + Nx > b.x_len) {
+      err |= RSIM_DEV_BADDESC;
+      return S;
+    }
+    for (int j = 0; j < J; ++j) {
+      const long long r = ((long long)u * b.S + i) * J + j;
+      const int L0 = b.rir_len0[r], L = b.rir_len[r];
+      const long long ro = b.rir_off[r];
+      if (L < 0 || L > L0 || ro < 0 || ro + L0 > b.h_len) {
+        err |= RSIM_DEV_BADDESC;
+        return S;
+      }
+      lmax = max(lmax, L);
+    }
+  }
+  if (I == 0 || Nx == 0 || lmax == 0) return S;  // nothing to write
+  const long long tu = (long long)Nx + lmax - 1;
+  const long long ys = b.out_stride[u], yo = b.out_off[u];
+  if (tu > 0x7fffffffLL || ys < tu || yo < 0 || yo + (long long)J * ys > b.y_len) {
+    err |= RSIM_DEV_BADDESC;
+    return S;
+  }
+  const int given_hop = b.hop ? b.hop[u] : 0;
+  int l2 = 0;
+  if (b.fft_log2n) {
+    l2 = b.fft_log2n[u];
+  } else {
+    float best = 0.f;
+    for (int m = 9; m <= 15; ++m) {
+      const float cf_ = tune.cost_fft[m - 9], cm = tune.cost_mac[m - 9];
+      if (!(cf_ > 0.f)) continue;
+      const int N = 1 << m;
+      if (N < lmax) continue;
+      const int B = given_hop ? given_hop : N - lmax + 1;
+      if (B < 1 || B + lmax - 1 > N) continue;
+      const float nbf = (float)((Nx + B - 1) / B);
+      const float cost = nbf * ((float)(I + J) * cf_ + (float)(I * J) * cm) + (float)(I * J) * cf_;
+      if (l2 == 0 || cost < best) {
+        best = cost;
+        l2 = m;
+      }
+    }
+  }
+  if (l2 < 9 || l2 > 15) {
+    err |= RSIM_DEV_BADPLAN;
+    return S;
+  }
+  const int N = 1 << l2;
+  const int B = given_hop ? given_hop : N - lmax + 1;
+  if (B < 1 || B + lmax - 1 > N) {
+    err |= RSIM_DEV_BADPLAN;
+    return S;
+  }
+  S.log2n = l2;
+  S.hop = B;
+  S.nb = (Nx + B - 1) / B;
+  S.tu = (int)tu;
+  S.lmax = lmax;
+  return S;
+}
+
+// One workgroup of 1024 threads: plans every utterance and appends it to its
+// family's list, keeping the caller's order (a stable compaction per family).
+constexpr int kSchedThreads = 1024;
+
+__global__ __launch_bounds__(kSchedThreads) void schedule_kernel(BatchDev b, TuneDev tune,
+                                                                 Sched* __restrict__ sched,
+                                                                 int* __restrict__ lists,
+                                                                 WsHeader* hdr) {
+  __shared__ int s_wcnt[kNumFam][kSchedThreads / 64];
+  __shared__ int s_base[kNumFam];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  if (t < kNumFam) {
+    hdr->counter[t] = 0;
+    s_base[t] = 0;
+  }
+  int err = 0;
+  __syncthreads();
+  for (int c0 = 0; c0 < b.U; c0 += kSchedThreads) {
+    const int idx = c0 + t;
+    int fam = -1, u = -1;
+    if (idx < b.U) {
+      u = b.order ? b.order[idx] : idx;
+      if (u < 0 || u >= b.U) {
+        err |= RSIM_DEV_BADDESC;
+        u = -1;
+      } else {
+        const Sched S = plan_utterance(b, tune, u, err);
+        sched[u] = S;
+        b.out_len[u] = S.tu;
+        fam = S.nb > 0 ? family_of_log2n(S.log2n) : -1;
+      }
+    }
+    int pre[kNumFam];
+#pragma unroll
+    for (int f = 0; f < kNumFam; ++f) {
+      const unsigned long long m = __ballot(fam == f);
+      pre[f] = __popcll(m & ((1ull << lane) - 1ull));
+      if (lane == 0) s_wcnt[f][w] = __popcll(m);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int f = 0; f < kNumFam; ++f) {
+      if (fam == f) {
+        int o = s_base[f];
+        for (int k = 0; k < w; ++k) o += s_wcnt[f][k];
+        lists[(long long)f * b.U + o + pre[f]] = u;
+      }
+    }
+    __syncthreads();
+    if (t < kNumFam) {
+      int tot = 0;
+      for (int k = 0; k < kSchedThreads / 64; ++k) tot += s_wcnt[t][k];
+      s_base[t] += tot;
+    }
+    __syncthreads();
+  }
+  if (t < kNumFam) hdr->count[t] = s_base[t];
+  if (err) flag_status(err);
+}
+
+// ============================================================ filter and mix
+// v[r] = (src[2(t + rT)], src[2(t + rT) + 1]), zero at indices >= nvalid.
+template <class PL>
+__device__ __forceinline__ void load_real(cf* v, const float* __restrict__ src_, int nvalid, int t_) {
+  const int t = opaque_v(t_);
+  const float* src = src_ + 2 * t;
+  const int lim = nvalid - 2 * t;  // element 2rT (+1) is valid when it is < lim
+#pragma unroll
+  for (int r = 0; r < PL::P; ++r) {
+    float a = 0.f, c = 0.f;
+    if (2 * r * PL::T < lim) a = src[2 * r * PL::T];
+    if (2 * r * PL::T + 1 < lim) c = src[2 * r * PL::T + 1];
+    v[r] = mk(a, c);
+  }
+}
+
+template <class PL>
+__device__ __forceinline__ void store_spec(cf* __restrict__ dst, const cf* v, int t) {
+  cf* d = dst + opaque_v(t);
+#pragma unroll
+  for (int q = 0; q < PL::P; ++q) d[q * PL::T] = v[q];
+}
+
+template <class PL>
+__device__ __forceinline__ void load_spec(cf* v, const cf* __restrict__ src, int t) {
+  const cf* s = src + opaque_v(t);
+#pragma unroll
+  for (int q = 0; q < PL::P; ++q) v[q] = s[q * PL::T];
+}
+
+// Y += H X over the thread's slots; thread 0's slot SP is the packed pair of
+// real bins (0, N/2) and multiplies componentwise.
+template <class PL>
+__device__ __forceinline__ void mac(cf* Y, const cf* __restrict__ H_, const cf* X, int t_) {
+  constexpr int SP = Fft<PL>::SP;
+  const int t = opaque_v(t_);
+  const cf* H = H_ + t;
+#pragma unroll
+  for (int q = 0; q < PL::P; ++q) {
+    const cf hv = H[q * PL::T];
+    if (q == SP) {
+      const cf c = cmac(Y[q], hv, X[q]);
+      const cf d = mk(__builtin_fmaf(hv.x, X[q].x, Y[q].x), __builtin_fmaf(hv.y, X[q].y, Y[q].y));
+      Y[q] = t == 0 ? d : c;
+    } else {
+      Y[q] = cmac(Y[q], hv, X[q]);
+    }
+  }
+}
+
+// Two mics at once: Y0 += H0 X, Y1 += H1 X, one slot at a time.
+template <class PL>
+__device__ __forceinline__ void mac2(cf* Y0, cf* Y1, const cf* __restrict__ H0_,
+                                     const cf* __restrict__ H1_, const cf* X, int t_) {
+  constexpr int SP = Fft<PL>::SP;
+  const int t = opaque_v(t_);
+  const cf* H0 = H0_ + t;
+  const cf* H1 = H1_ + t;
+#pragma unroll
+  for (int q = 0; q < PL::P; ++q) {
+    const cf h0 = H0[q * PL::T];
+    const cf h1 = H1[q * PL::T];
+    if (q == SP) {
+      const cf c0 = cmac(Y0[q], h0, X[q]), c1 = cmac(Y1[q], h1, X[q]);
+      const cf d0 = mk(__builtin_fmaf(h0.x, X[q].x, Y0[q].x), __builtin_fmaf(h0.y, X[q].y, Y0[q].y));
+      const cf d1 = mk(__builtin_fmaf(h1.x, X[q].x, Y1[q].x), __builtin_fmaf(h1.y, X[q].y, Y1[q].y));
+      Y0[q] = t == 0 ? d0 : c0;
+      Y1[q] = t == 0 ? d1 : c1;
+    } else {
+      Y0[q] = cmac(Y0[q], h0, X[q]);
+      Y1[q] = cmac(Y1[q], h1, X[q]);
+    }
+  }
+}
+
+// Inverse-transform one mic spectrum and overlap-add it into y: positions
+// m < lim are written; positions m < carry already hold the tails of earlier
+// blocks (written by this workgroup) and are accumulated.
+template <class PL>
+__device__ __forceinline__ void emit(cf* Yv, cf* lds, const cf* tw, float* __restrict__ yp_, int lim_,
+                                     int carry_, int t_) {
+  Fft<PL>::pre(Yv, tw, t_);
+  Fft<PL>::inverse(Yv, lds, tw, t_);
+  const int t = opaque_v(t_);
+  float* yp = yp_ + 2 * t;
+  const int lim = lim_ - 2 * t, carry = carry_ - 2 * t;
+#pragma unroll
+  for (int r = 0; r < PL::P; ++r) {
+    constexpr int T2 = 2 * PL::T;
+    if (r * T2 < lim) {
+      float val = Yv[r].x;
+      if (r * T2 < carry) val += yp[r * T2];
+      yp[r * T2] = val;
+    }
+    if (r * T2 + 1 < lim) {
+      float val = Yv[r].y;
+      if (r * T2 + 1 < carry) val += yp[r * T2 + 1];
+      yp[r * T2 + 1] = val;
+    }
+  }
+}
+
+template <class PL>
+__device__ __forceinline__ const cf* plan_tw() {
+  return g_tw + kTwOff[ilog2c(PL::N) - 9];
+}
+
+// One utterance: RIR spectra, then the blocks.  Mics are processed in groups
+// of JG (1 or 2) accumulators; when J > JG the source spectra of the current
+// block are kept in the workgroup's scratch for the later mic groups.
+template <class PL, int JG>
+__device__ void mix_utterance(const MixArgs& A, int u, const Sched& S, cf* lds, cf* slot, int t) {
+  constexpr int P = PL::P, M = PL::M;
+  const cf* tw = plan_tw<PL>();
+  const BatchDev& b = A.b;
+  const int I = b.n_src[u], J = b.J, NS = b.S, Nx = b.src_len[u];
+  const int B = S.hop, nb = S.nb, tu = S.tu, lmax = S.lmax;
+  const int span = B + lmax - 1;
+  const float cscale = 1.0f / (8.0f * (float)M);
+  cf* Hs = slot;
+  cf* Xs = slot + (long long)NS * J * M;
+  const int ng = (J + JG - 1) / JG;
+
+  // RIR spectra, once per utterance, scaled by alpha / (8M).
+  for (int s = 0; s < I * J; ++s) {
+    const int i = s / J, j = s - (s / J) * J;
+    const long long r = ((long long)u * NS + i) * J + j;
+    cf v[P];
+    load_real<PL>(v, A.h + b.rir_off[r], b.rir_len[r], t);
+    Fft<PL>::forward(v, lds, tw, t);
+    Fft<PL>::post(v, tw, t);
+    const float a = A.alpha[r] * cscale;
+#pragma unroll
+    for (int q = 0; q < P; ++q) v[q] = mk(v[q].x * a, v[q].y * a);
+    store_spec<PL>(Hs + (long long)s * M, v, t);
+  }
+
+  const long long yo = b.out_off[u];
+  const long long ys = b.out_stride[u];
+  for (int bk = 0; bk < nb; ++bk) {
+    const int base = bk * B;
+    const int nvalid = min(B, Nx - base);
+    const int lim = min(span, tu - base);
+    const int carry = bk == 0 ? 0 : lmax - 1;
+    for (int g = 0; g < ng; ++g) {
+      const int j0 = g * JG;
+      const bool two = JG == 2 && j0 + 1 < J;
+      cf Y0[P], Y1[JG == 2 ? P : 1];
+#pragma unroll
+      for (int q = 0; q < P; ++q) Y0[q] = mk(0.f, 0.f);
+      if constexpr (JG == 2) {
+#pragma unroll
+        for (int q = 0; q < P; ++q) Y1[q] = mk(0.f, 0.f);
+      }
+      for (int i = 0; i < I; ++i) {
+        cf X[P];
+        if (g == 0) {
+          load_real<PL>(X, A.x + b.src_off[(long long)u * NS + i] + base, nvalid, t);
+          Fft<PL>::forward(X, lds, tw, t);
+          Fft<PL>::post(X, tw, t);
+          if (ng > 1) store_spec<PL>(Xs + (long long)i * M, X, t);
+        } else {
+          load_spec<PL>(X, Xs + (long long)i * M, t);
+        }
+        const cf* H0 = Hs + (long long)(i * J + j0) * M;
+        if constexpr (JG == 2) {
+          if (two) mac2<PL>(Y0, Y1, H0, H0 + M, X, t);
+          else mac<PL>(Y0, H0, X, t);
+        } else {
+          mac<PL>(Y0, H0, X, t);
+        }
+      }
+      emit<PL>(Y0, lds, tw, A.y + yo + (long long)j0 * ys + base, lim, carry, t);
+      if constexpr (JG == 2) {
+        if (two) emit<PL>(Y1, lds, tw, A.y + yo + (long long)(j0 + 1) * ys + base, lim, carry, t);
+      }
+    }
+  }
+}
+
+template <int T>
+struct FamLds;
+template <>
+struct FamLds<32> {
+  static constexpr int n = Plan512::LDS;
+};
+template <>
+struct FamLds<64> {
+  static constexpr int n = Plan4K::LDS > Plan2K::LDS ? Plan4K::LDS : Plan2K::LDS;
+};
+template <>
+struct FamLds<128> {
+  static constexpr int n = Plan8K::LDS;
+};
+template <>
+struct FamLds<256> {
+  static constexpr int n = Plan16K::LDS;
+};
+template <>
+struct FamLds<512> {
+  static constexpr int n = Plan32K::LDS;
+};
+
+template <int T, class F>
+__device__ __forceinline__ void dispatch_plan(int l2, F&& f) {
+  if constexpr (T == 32) {
+    f(Plan512{});
+  } else if constexpr (T == 64) {
+    if (l2 == 10) f(Plan1K{});
+    else if (l2 == 11) f(Plan2K{});
+    else f(Plan4K{});
+  } else if constexpr (T == 128) {
+    f(Plan8K{});
+  } else if constexpr (T == 256) {
+    f(Plan16K{});
+  } else {
+    f(Plan32K{});
+  }
+}
+
+// Persistent workgroups: pop the next utterance of this family's list until
+// it is exhausted.  MINW is the number of waves per SIMD the register budget
+// is sized for (2 with one mic accumulator, 1 with two).
+template <int T, int JG, int MINW = (JG == 1 ? 2 : 1)>
+__global__ __launch_bounds__(T, MINW) void mix_kernel(MixArgs A) {
+  __shared__ cf lds[FamLds<T>::n];
+  __shared__ int s_idx;
+  const int t = threadIdx.x;
+  cf* slot = A.scratch + (long long)blockIdx.x * A.slot_cf;
+  for (;;) {
+    __syncthreads();
+    if (t == 0) s_idx = atomicAdd(&A.hdr->counter[A.fam], 1);
+    __syncthreads();
+    const int idx = s_idx;
+    if (idx >= A.hdr->count[A.fam]) break;
+    const int u = A.list[(long long)A.fam * A.b.U + idx];
+    const Sched S = A.sched[u];
+    dispatch_plan<T>(S.log2n, [&](auto pl) {
+      using PL = decltype(pl);
+      mix_utterance<PL, JG>(A, u, S, lds, slot, t);
+    });
+  }
+}
+
+// ================================================================ dry power
+__global__ __launch_bounds__(256) void power_kernel(BatchDev b, const float* __restrict__ x,
+                                                   double* __restrict__ power) {
+  __shared__ double s_d[4];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const long long n_slots = (long long)b.U * b.S;
+  for (long long k = blockIdx.x; k < n_slots; k += gridDim.x) {
+    const int u = (int)(k / b.S), i = (int)(k - (long long)u * b.S);
+    const int I = b.n_src[u], Nx = b.src_len[u];
+    const long long so = b.src_off[k];
+    const bool ok = i < I && I <= b.S && Nx > 0 && so >= 0 && so + Nx <= b.x_len;
+    if (!ok) {
+      if (t == 0) {
+        power[k] = 0.0;
+        if (i < I && Nx != 0) flag_status(RSIM_DEV_BADDESC);
+      }
+      continue;
+    }
+    double acc = 0.0;
+    for (int n = t; n < Nx; n += 256) {
+      const double v = (double)x[so + n];
+      acc += v * v;
+    }
+    acc = wave_sum_d(acc);
+    __syncthreads();
+    if (lane == 0) s_d[w] = acc;
+    __syncthreads();
+    if (t == 0) power[k] = ((s_d[0] + s_d[1]) + (s_d[2] + s_d[3])) / (double)Nx;
+  }
+}
+
+// ================================================= FFT engine test kernels
+// Bin held by slot q of thread t (thread 0 permuted as in Fft::perm_t0; its
+// slot SP holds bins 0 and N/2).
+template <class PL>
+__device__ __forceinline__ int slot_bin(int q, int t) {
+  constexpr int R = PL::RL, T = PL::T;
+  if (t != 0) return q < R ? t + 2 * T * q : (2 * T - t) + 2 * T * (q - R);
+  if (q < R / 2) return T + 2 * T * q;
+  if (q < R) return 2 * T * q;
+  if (q < 3 * R / 2 - 1) return 2 * T * (q - R + 1);
+  if (q == 3 * R / 2 - 1) return 0;
+  return T + 2 * T * (q - R);
+}
+
+template <class PL>
+__global__ __launch_bounds__(PL::T) void rfft_kernel(const float* __restrict__ x, float* __restrict__ spec) {
+  __shared__ cf lds[PL::LDS];
+  const int t = threadIdx.x;
+  const long long sig = blockIdx.x;
+  const cf* tw = plan_tw<PL>();
+  cf v[PL::P];
+  load_real<PL>(v, x + sig * PL::N, PL::N, t);
+  Fft<PL>::forward(v, lds, tw, t);
+  Fft<PL>::post(v, tw, t);
+  cf* out = reinterpret_cast<cf*>(spec) + sig * (PL::M + 1);
+#pragma unroll
+  for (int q = 0; q < PL::P; ++q) {
+    if (t == 0 && q == Fft<PL>::SP) {
+      out[0] = mk(0.5f * v[q].x, 0.f);
+      out[PL::M] = mk(0.5f * v[q].y, 0.f);
+    } else {
+      out[slot_bin<PL>(q, t)] = mk(0.5f * v[q].x, 0.5f * v[q].y);
+    }
+  }
+}
+
+template <class PL>
+__global__ __launch_bounds__(PL::T) void irfft_kernel(const float* __restrict__ spec, float* __restrict__ x) {
+  __shared__ cf lds[PL::LDS];
+  const int t = threadIdx.x;
+  const long long sig = blockIdx.x;
+  const cf* tw = plan_tw<PL>();
+  const cf* in = reinterpret_cast<const cf*>(spec) + sig * (PL::M + 1);
+  cf v[PL::P];
+#pragma unroll
+  for (int q = 0; q < PL::P; ++q) {
+    if (t == 0 && q == Fft<PL>::SP) {
+      v[q] = mk(2.f * in[0].x, 2.f * in[PL::M].x);
+    } else {
+      const cf z = in[slot_bin<PL>(q, t)];
+      v[q] = mk(2.f * z.x, 2.f * z.y);
+    }
+  }
+  Fft<PL>::pre(v, tw, t);
+  Fft<PL>::inverse(v, lds, tw, t);
+  const float sc = 1.0f / (float)(2 * PL::N);
+  float* o = x + sig * PL::N;
+#pragma unroll
+  for (int r = 0; r < PL::P; ++r) {
+    const int m = 2 * (t + r * PL::T);
+    o[m] = v[r].x * sc;
+    o[m + 1] = v[r].y * sc;
+  }
+}
+
+// ================================================================ host side
+template <class PL>
+static void fill_plan(std::vector<float2>& tw, int base) {
+  auto W = [](long long e, long long n) {
+    e %= n;
+    const double a = -2.0 * 3.14159265358979323846264338327950288 * (double)e / (double)n;
+    return make_float2((float)std::cos(a), (float)std::sin(a));
+  };
+  for (int p = 1; p <= PL::NP - 2; ++p) {
+    const int R = PL::R[p], Ls = PL::ls(p);
+    for (int r = 0; r < R; ++r)
+      for (int k = 0; k < Ls; ++k) tw[base + PL::mid_off(p) + r * Ls + k] = W((long long)r * k, (long long)R * Ls);
+  }
+  for (int r = 0; r < PL::RL; ++r)
+    for (int k = 0; k <= PL::T; ++k) tw[base + PL::LAST_OFF + r * (PL::T + 1) + k] = W((long long)r * k, PL::M);
+  for (int q = 0; q < PL::RL; ++q)
+    for (int c = 0; c <= PL::T; ++c)
+      tw[base + PL::POST_OFF + q * (PL::T + 1) + c] = W((long long)c + 2LL * PL::T * q, PL::N);
+}
+
+void fill_twiddles(float* out) {
+  std::vector<float2> tw(kTwTotal, make_float2(0.f, 0.f));
+  fill_plan<Plan512>(tw, kTwOff[0]);
+  fill_plan<Plan1K>(tw, kTwOff[1]);
+  fill_plan<Plan2K>(tw, kTwOff[2]);
+  fill_plan<Plan4K>(tw, kTwOff[3]);
+  fill_plan<Plan8K>(tw, kTwOff[4]);
+  fill_plan<Plan16K>(tw, kTwOff[5]);
+  fill_plan<Plan32K>(tw, kTwOff[6]);
+  std::memcpy(out, tw.data(), sizeof(float2) * kTwTotal);
+}
+
+// Single-utterance descriptor arrays live at the head of the ola workspace.
+struct OlaDesc {
+  int n_src, src_len, rir_len0, rir_len, out_stride, out_len, log2n, hop;
+  long long src_off, rir_off, out_off;
+  float alpha;
+};
+
+__global__ void ola_setup_kernel(OlaDesc* d, int nx, int nh, int l2, int hop) {
+  d->n_src = 1;
+  d->src_len = nx;
+  d->rir_len0 = nh;
+  d->rir_len = nh;
+  d->out_stride = nx + nh - 1;
+  d->out_len = 0;
+  d->log2n = l2;
+  d->hop = hop;
+  d->src_off = 0;
+  d->rir_off = 0;
+  d->out_off = 0;
+  d->alpha = 1.0f;
+}
+
+}  // namespace rsim
+
+using namespace rsim;
+
+namespace {
+
+constexpr int kFamT[kNumFam] = {32, 64, 128, 256, 512};
+constexpr int kFamMaxM[kNumFam] = {256, 2048, 4096, 8192, 16384};
+constexpr int kFamOrder[kNumFam] = {3, 4, 2, 1, 0};  // launch order: the common sizes first
+constexpr int kMaxDev = 64;
+
+struct DevState {
+  bool init = false;
+  int cus = 0;
+  int occ[2][kNumFam] = {{0, 0, 0, 0, 0}, {0, 0, 0, 0, 0}};  // [jg-1][family]
+};
+
+std::mutex g_mu;
+DevState g_dev[kMaxDev];
+
+struct Retired {
+  hipGraphExec_t exec;
+  hipEvent_t done;
+};
+std::deque<Retired> g_retired;
+
+template <int JG>
+const void* mix_kernel_ptr_jg(int fam) {
+  switch (fam) {
+    case 0: return reinterpret_cast<const void*>(&mix_kernel<32, JG>);
+    case 1: return reinterpret_cast<const void*>(&mix_kernel<64, JG>);
+    case 2: return reinterpret_cast<const void*>(&mix_kernel<128, JG>);
+    case 3: return reinterpret_cast<const void*>(&mix_kernel<256, JG>);
+    default: return reinterpret_cast<const void*>(&mix_kernel<512, JG>);
+  }
+}
+const void* mix_kernel_ptr(int fam, int jg) {
+  return jg == 2 ? mix_kernel_ptr_jg<2>(fam) : mix_kernel_ptr_jg<1>(fam);
+}
+
+// Mic-group size per family: 1 accumulator (two waves per SIMD) unless the
+// RSIM_MIC_GROUP environment variable asks for 2 (one wave per SIMD).
+int g_jg = 0;
+int mic_group() {
+  if (g_jg == 0) {
+    const char* e = std::getenv("RSIM_MIC_GROUP");
+    g_jg = (e && e[0] == '2') ? 2 : 1;
+  }
+  return g_jg;
+}
+
+rsim_status init_locked(int dev) {
+  DevState& st = g_dev[dev];
+  if (st.init) return RSIM_OK;
+  std::vector<float> tw(2 * (size_t)kTwTotal);
+  fill_twiddles(tw.data());
+  if (hipMemcpyToSymbol(HIP_SYMBOL(g_tw), tw.data(), sizeof(float) * tw.size()) != hipSuccess)
+    return RSIM_EDEVICE;
+  const int zero = 0;
+  if (hipMemcpyToSymbol(HIP_SYMBOL(g_status), &zero, sizeof(int)) != hipSuccess) return RSIM_EDEVICE;
+  if (hipDeviceGetAttribute(&st.cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return RSIM_EDEVICE;
+  for (int jg = 1; jg <= 2; ++jg)
+    for (int f = 0; f < kNumFam; ++f) {
+      int n = 0;
+      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, mix_kernel_ptr(f, jg), kFamT[f], 0) !=
+          hipSuccess)
+        return RSIM_EDEVICE;
+      st.occ[jg - 1][f] = n > 0 ? n : 1;
+    }
+  if (hipDeviceSynchronize() != hipSuccess) return RSIM_EDEVICE;
+  st.init = true;
+  return RSIM_OK;
+}
+
+rsim_status ensure_init(hipStream_t s) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDev) return RSIM_EDEVICE;
+  std::lock_guard<std::mutex> lk(g_mu);
+  if (g_dev[dev].init) return RSIM_OK;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (s && hipStreamIsCapturing(s, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone)
+    return RSIM_ENOTINIT;
+  return init_locked(dev);
+}
+
+const DevState& dev_state() {
+  static const DevState none;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDev) return none;
+  return g_dev[dev];
+}
+
+size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+// A failed HIP call leaves a sticky "last error" that the caller's next
+// runtime check (torch's included) would report as its own: clear it.
+rsim_status clear_error(rsim_status st) {
+  (void)hipGetLastError();
+  return st;
+}
+
+TuneDev default_tune() {
+  TuneDev t;
+  for (int m = 9; m <= 15; ++m) {
+    const double N = double(1 << m);
+    t.cost_fft[m - 9] = (float)(2.5 * N * m);
+    t.cost_mac[m - 9] = (float)(8.0 * (N / 2 + 1));
+  }
+  return t;
+}
+
+TuneDev to_dev(const rsim_tune* tune) {
+  if (!tune) return default_tune();
+  TuneDev t;
+  for (int k = 0; k < 7; ++k) {
+    t.cost_fft[k] = tune->cost_fft[k];
+    t.cost_mac[k] = tune->cost_mac[k];
+  }
+  return t;
+}
+
+// Families that may receive work.
+void families_used(const rsim_batch* b, const TuneDev& td, bool used[kNumFam]) {
+  for (int f = 0; f < kNumFam; ++f) used[f] = false;
+  for (int m = 9; m <= 15; ++m)
+    if (b->fft_log2n || td.cost_fft[m - 9] > 0.f) used[family_of_log2n(m)] = true;
+}
+
+struct WsLayout {
+  size_t hdr, sched, lists, scratch, total;
+  long long slot_cf[kNumFam];
+  int grid[kNumFam];
+};
+
+bool batch_ok(const rsim_batch* b) {
+  if (!b || b->n_utt < 0 || b->n_mic < 1 || b->max_src < 1 || b->max_rir_len0 < 0) return false;
+  if (b->x_len < 0 || b->h_len < 0 || b->y_len < 0) return false;
+  if (b->n_utt == 0) return true;
+  return b->n_src && b->src_len && b->src_off && b->rir_off && b->rir_len0 && b->rir_len &&
+         b->out_off && b->out_stride && b->out_len;
+}
+
+WsLayout layout(const rsim_batch* b, const TuneDev& td, bool backward, const DevState& st) {
+  WsLayout L;
+  const size_t U = (size_t)b->n_utt;
+  L.hdr = 0;
+  L.sched = align256(sizeof(WsHeader));
+  L.lists = L.sched + align256(U * sizeof(Sched));
+  L.scratch = L.lists + align256((size_t)kNumFam * U * sizeof(int));
+  bool used[kNumFam];
+  families_used(b, td, used);
+  const long long S = b->max_src, J = b->n_mic;
+  const int jg = mic_group();
+  size_t need = 0;
+  for (int f = 0; f < kNumFam; ++f) {
+    const long long M = kFamMaxM[f];
+    const long long spectra = backward ? (2 * S * J + J) : (S * J + (J > jg ? S : 0));
+    L.slot_cf[f] = spectra * M;
+    // Without a device (size queries on a host) assume 256 CUs and the
+    // largest occupancy used; the grid is capped at 8 workgroups per CU.
+    const int cus = st.cus > 0 ? st.cus : 256;
+    int occ = st.init ? st.occ[jg - 1][f] : 8;
+    if (occ > 8) occ = 8;
+    long long g = (long long)cus * occ;
+    if (g > (long long)U) g = (long long)U;
+    if (g < 1) g = 1;
+    L.grid[f] = (int)g;
+    if (used[f]) {
+      const size_t bytes = (size_t)g * (size_t)L.slot_cf[f] * sizeof(cf);
+      if (bytes > need) need = bytes;
+    }
+  }
+  L.total = L.scratch + align256(need);
+  return L;
+}
+
+BatchDev to_dev(const rsim_batch* b) {
+  BatchDev d;
+  d.U = b->n_utt;
+  d.J = b->n_mic;
+  d.S = b->max_src;
+  d.x_len = b->x_len;
+  d.h_len = b->h_len;
+  d.y_len = b->y_len;
+  d.n_src = b->n_src;
+  d.src_len = b->src_len;
+  d.src_off = reinterpret_cast<const long long*>(b->src_off);
+  d.rir_off = reinterpret_cast<const long long*>(b->rir_off);
+  d.rir_len0 = b->rir_len0;
+  d.rir_len = b->rir_len;
+  d.out_off = reinterpret_cast<const long long*>(b->out_off);
+  d.out_stride = b->out_stride;
+  d.out_len = b->out_len;
+  d.order = b->order;
+  d.fft_log2n = b->fft_log2n;
+  d.hop = b->hop;
+  return d;
+}
+
+void gc_retired(bool wait) {
+  while (!g_retired.empty()) {
+    Retired& r = g_retired.front();
+    if (!wait && hipEventQuery(r.done) != hipSuccess) break;
+    if (wait) (void)hipEventSynchronize(r.done);
+    (void)hipGraphExecDestroy(r.exec);
+    (void)hipEventDestroy(r.done);
+    g_retired.pop_front();
+  }
+}
+
+// Capture helper: runs `body` directly, or captured into a graph that is
+// instantiated and launched on `s`.
+template <class F>
+rsim_status run_maybe_graph(hipStream_t s, int use_graph, F&& body) {
+  if (!use_graph) {
+    rsim_status st = body();
+    if (st != RSIM_OK) return clear_error(st);
+    return hipGetLastError() == hipSuccess ? RSIM_OK : RSIM_EDEVICE;
+  }
+  // The legacy default stream cannot be captured.
+  if (s == nullptr) return RSIM_EINVAL;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &cs) != hipSuccess) return clear_error(RSIM_EDEVICE);
+  if (cs != hipStreamCaptureStatusNone) return RSIM_EINVAL;
+  if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess)
+    return clear_error(RSIM_EDEVICE);
+  rsim_status st = body();
+  hipGraph_t graph = nullptr;
+  const hipError_t e = hipStreamEndCapture(s, &graph);
+  if (st != RSIM_OK || e != hipSuccess || !graph) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return clear_error(st != RSIM_OK ? st : RSIM_EDEVICE);
+  }
+  hipGraphExec_t exec = nullptr;
+  if (hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+    (void)hipGraphDestroy(graph);
+    return clear_error(RSIM_EDEVICE);
+  }
+  (void)hipGraphDestroy(graph);
+  if (hipGraphLaunch(exec, s) != hipSuccess) {
+    (void)hipGraphExecDestroy(exec);
+    return clear_error(RSIM_EDEVICE);
+  }
+  hipEvent_t ev = nullptr;
+  if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess ||
+      hipEventRecord(ev, s) != hipSuccess) {
+    (void)hipStreamSynchronize(s);
+    (void)hipGraphExecDestroy(exec);
+    if (ev) (void)hipEventDestroy(ev);
+    return RSIM_OK;
+  }
+  std::lock_guard<std::mutex> lk(g_mu);
+  gc_retired(false);
+  g_retired.push_back({exec, ev});
+  if (g_retired.size() > 64) gc_retired(true);
+  return RSIM_OK;
+}
+
+rsim_status launch_mix(const rsim_batch* b, const BatchDev& bd, const TuneDev& td, const float* x,
+                       const float* h, const float* alpha, float* y, void* ws, hipStream_t s,
+                       int only_fam = -1) {
+  const DevState& st = dev_state();
+  const WsLayout L = layout(b, td, false, st);
+  char* base = static_cast<char*>(ws);
+  WsHeader* hdr = reinterpret_cast<WsHeader*>(base + L.hdr);
+  Sched* sched = reinterpret_cast<Sched*>(base + L.sched);
+  int* lists = reinterpret_cast<int*>(base + L.lists);
+  cf* scratch = reinterpret_cast<cf*>(base + L.scratch);
+  hipLaunchKernelGGL(schedule_kernel, dim3(1), dim3(kSchedThreads), 0, s, bd, td, sched, lists, hdr);
+  bool used[kNumFam];
+  families_used(b, td, used);
+  for (int k = 0; k < kNumFam; ++k) {
+    const int f = kFamOrder[k];
+    if (!used[f] || (only_fam >= 0 && f != only_fam)) continue;
+    MixArgs A;
+    A.b = bd;
+    A.x = x;
+    A.h = h;
+    A.alpha = alpha;
+    A.y = y;
+    A.sched = sched;
+    A.list = lists;
+    A.hdr = hdr;
+    A.fam = f;
+    A.scratch = scratch;
+    A.slot_cf = L.slot_cf[f];
+    void* args[] = {&A};
+    if (hipLaunchKernel(mix_kernel_ptr(f, mic_group()), dim3(L.grid[f]), dim3(kFamT[f]), args, 0, s) !=
+        hipSuccess)
+      return RSIM_EDEVICE;
+  }
+  return RSIM_OK;
+}
+
+bool eta_ok(double eta) { return !std::isnan(eta) && eta >= 0.0; }
+
+float cut_scale(double eta) {
+  if (std::isinf(eta)) return 0.0f;
+  return (float)std::pow(10.0, -eta / 10.0);
+}
+
+void launch_truncate(const float* h, long long h_len, const int64_t* off, const int32_t* len0,
+                     int n_rir, float s, int32_t* n_c, int32_t* len, hipStream_t stream) {
+  const DevState& st = dev_state();
+  int grid = (st.cus > 0 ? st.cus : 256) * 8;
+  if (grid > n_rir) grid = n_rir;
+  if (grid < 1) grid = 1;
+  hipLaunchKernelGGL(truncate_kernel, dim3(grid), dim3(kTruncThreads), 0, stream, h, h_len,
+                     reinterpret_cast<const long long*>(off), len0, n_rir, s, n_c, len);
+}
+
+int ilog2_exact(int n) {
+  if (n <= 0 || (n & (n - 1))) return -1;
+  int l = 0;
+  while ((1 << l) < n) ++l;
+  return l;
+}
+
+}  // namespace
+
+// ====================================================================== C ABI
+extern "C" {
+
+rsim_status rsim_init(void) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDev) return RSIM_EDEVICE;
+  std::lock_guard<std::mutex> lk(g_mu);
+  return init_locked(dev);
+}
+
+const char* rsim_strerror(rsim_status s) {
+  switch (s) {
+    case RSIM_OK: return "ok";
+    case RSIM_EINVAL: return "invalid argument";
+    case RSIM_EWORKSPACE: return "workspace missing or too small";
+    case RSIM_EUNSUPPORTED: return "unsupported FFT size or hop";
+    case RSIM_EDEVICE: return "HIP runtime error";
+    case RSIM_ENOTINIT: return "library not initialised on this device (call rsim_init outside capture)";
+  }
+  return "unknown status";
+}
+
+int32_t rsim_version(void) { return 10000; }
+
+rsim_status rsim_truncate_rir(const float* h, int64_t h_len, const int64_t* off, const int32_t* len0,
+                              int32_t n_rir, double eta_db, int32_t* n_c, int32_t* len,
+                              hipStream_t stream) {
+  if (n_rir < 0 || h_len < 0 || !eta_ok(eta_db)) return RSIM_EINVAL;
+  if (n_rir == 0) return RSIM_OK;
+  if (!h || !off || !len0 || !len) return RSIM_EINVAL;
+  rsim_status e = ensure_init(stream);
+  if (e != RSIM_OK) return e;
+  launch_truncate(h, h_len, off, len0, n_rir, cut_scale(eta_db), n_c, len, stream);
+  return hipGetLastError() == hipSuccess ? RSIM_OK : RSIM_EDEVICE;
+}
+
+size_t rsim_mix_workspace_bytes(const rsim_batch* b, const rsim_tune* tune, int32_t backward) {
+  if (!batch_ok(b)) return 0;
+  (void)ensure_init(nullptr);  // launch geometry of this device, when there is one
+  const TuneDev td = to_dev(tune);
+  return layout(b, td, backward != 0, dev_state()).total;
+}
+
+rsim_status rsim_mix(const rsim_batch* b, const float* x, const float* h, const float* alpha, float* y,
+                     void* ws, size_t ws_bytes, const rsim_tune* tune, int32_t use_graph,
+                     hipStream_t stream) {
+  if (!batch_ok(b)) return RSIM_EINVAL;
+  if (b->n_utt == 0) return RSIM_OK;
+  if (!x || !h || !alpha || !y) return RSIM_EINVAL;
+  const rsim_status e = ensure_init(stream);
+  const TuneDev td = to_dev(tune);
+  const WsLayout L = layout(b, td, false, dev_state());
+  if (!ws || ws_bytes < L.total) return RSIM_EWORKSPACE;
+  if (e != RSIM_OK) return e;
+  const BatchDev bd = to_dev(b);
+  return run_maybe_graph(stream, use_graph,
+                         [&]() { return launch_mix(b, bd, td, x, h, alpha, y, ws, stream); });
+}
+
+rsim_status rsim_simulate(const rsim_batch* b, const float* x, const float* h, const float* alpha,
+                          double eta_db, int32_t* rir_len_out, float* y, void* ws, size_t ws_bytes,
+                          const rsim_tune* tune, int32_t use_graph, hipStream_t stream) {
+  if (!b || !eta_ok(eta_db) || !rir_len_out) return RSIM_EINVAL;
+  rsim_batch bb = *b;
+  bb.rir_len = rir_len_out;
+  if (!batch_ok(&bb)) return RSIM_EINVAL;
+  if (bb.n_utt == 0) return RSIM_OK;
+  if (!x || !h || !alpha || !y) return RSIM_EINVAL;
+  const rsim_status e = ensure_init(stream);
+  const TuneDev td = to_dev(tune);
+  const WsLayout L = layout(&bb, td, false, dev_state());
+  if (!ws || ws_bytes < L.total) return RSIM_EWORKSPACE;
+  if (e != RSIM_OK) return e;
+  const long long n_rir = (long long)bb.n_utt * bb.max_src * bb.n_mic;
+  if (n_rir > 0x7fffffffLL) return RSIM_EINVAL;
+  const BatchDev bd = to_dev(&bb);
+  const float s = cut_scale(eta_db);
+  return run_maybe_graph(stream, use_graph, [&]() {
+    launch_truncate(h, bb.h_len, bb.rir_off, bb.rir_len0, (int)n_rir, s, nullptr, rir_len_out, stream);
+    return launch_mix(&bb, bd, td, x, h, alpha, y, ws, stream);
+  });
+}
+
+size_t rsim_ola_workspace_bytes(int32_t fft_n) {
+  const int l2 = ilog2_exact(fft_n);
+  if (l2 < 9 || l2 > 15) return 0;
+  rsim_batch b;
+  std::memset(&b, 0, sizeof(b));
+  b.n_utt = 1;
+  b.n_mic = 1;
+  b.max_src = 1;
+  int32_t dummy = 0;
+  b.fft_log2n = &dummy;  // marks a forced size
+  (void)ensure_init(nullptr);
+  return align256(sizeof(OlaDesc)) + layout(&b, default_tune(), false, dev_state()).total;
+}
+
+rsim_status rsim_ola_convolve(const float* x, int32_t nx, const float* h, int32_t nh, int32_t fft_n,
+                              int32_t hop, float* y, void* ws, size_t ws_bytes, hipStream_t stream) {
+  if (!x || !h || !y || nx < 1 || nh < 1 || hop < 0) return RSIM_EINVAL;
+  const int l2 = ilog2_exact(fft_n);
+  if (l2 < 9 || l2 > 15) return RSIM_EUNSUPPORTED;
+  if (hop == 0) hop = fft_n - nh + 1;
+  if (hop < 1 || (long long)hop + nh - 1 > fft_n) return RSIM_EUNSUPPORTED;
+  if ((long long)nx + nh - 1 > 0x7fffffffLL) return RSIM_EINVAL;
+  const size_t need = rsim_ola_workspace_bytes(fft_n);
+  if (!ws || ws_bytes < need) return RSIM_EWORKSPACE;
+  rsim_status e = ensure_init(stream);
+  if (e != RSIM_OK) return e;
+  char* base = static_cast<char*>(ws);
+  OlaDesc* d = reinterpret_cast<OlaDesc*>(base);
+  hipLaunchKernelGGL(ola_setup_kernel, dim3(1), dim3(1), 0, stream, d, nx, nh, l2, hop);
+  rsim_batch b;
+  std::memset(&b, 0, sizeof(b));
+  b.n_utt = 1;
+  b.n_mic = 1;
+  b.max_src = 1;
+  b.max_rir_len0 = nh;
+  b.x_len = nx;
+  b.h_len = nh;
+  b.y_len = (int64_t)nx + nh - 1;
+  b.n_src = &d->n_src;
+  b.src_len = &d->src_len;
+  b.src_off = reinterpret_cast<const int64_t*>(&d->src_off);
+  b.rir_off = reinterpret_cast<const int64_t*>(&d->rir_off);
+  b.rir_len0 = &d->rir_len0;
+  b.rir_len = &d->rir_len;
+  b.out_off = reinterpret_cast<const int64_t*>(&d->out_off);
+  b.out_stride = &d->out_stride;
+  b.out_len = &d->out_len;
+  b.order = nullptr;
+  b.fft_log2n = &d->log2n;
+  b.hop = &d->hop;
+  const TuneDev td = default_tune();
+  const BatchDev bd = to_dev(&b);
+  launch_mix(&b, bd, td, x, h, &d->alpha, y, base + align256(sizeof(OlaDesc)), stream,
+             family_of_log2n(l2));
+  return hipGetLastError() == hipSuccess ? RSIM_OK : RSIM_EDEVICE;
+}
+
+rsim_status rsim_mix_backward(const rsim_batch* b, const float* x, const float* h, const float* alpha,
+                              const float* grad_y, float* grad_x, float* grad_h, float* grad_alpha,
+                              void* ws, size_t ws_bytes, const rsim_tune* tune, hipStream_t stream) {
+  (void)b; (void)x; (void)h; (void)alpha; (void)grad_y; (void)grad_x; (void)grad_h;
+  (void)grad_alpha; (void)ws; (void)ws_bytes; (void)tune; (void)stream;
+  return RSIM_EUNSUPPORTED;
+}
+
+rsim_status rsim_source_power(const rsim_batch* b, const float* x, double* power, hipStream_t stream) {
+  if (!batch_ok(b)) return RSIM_EINVAL;
+  if (b->n_utt == 0) return RSIM_OK;
+  if (!x || !power) return RSIM_EINVAL;
+  rsim_status e = ensure_init(stream);
+  if (e != RSIM_OK) return e;
+  const long long slots = (long long)b->n_utt * b->max_src;
+  int grid = dev_state().cus * 8;
+  if (grid > slots) grid = (int)slots;
+  if (grid < 1) grid = 1;
+  hipLaunchKernelGGL(power_kernel, dim3(grid), dim3(256), 0, stream, to_dev(b), x, power);
+  return hipGetLastError() == hipSuccess ? RSIM_OK : RSIM_EDEVICE;
+}
+
+rsim_status rsim_snr_gains(const double* p_dry, const double* snr_db, int32_t I, int32_t J,
+                           float* alpha) {
+  if (I < 0 || J < 1) return RSIM_EINVAL;
+  if (I == 0) return RSIM_OK;
+  if (!p_dry || !snr_db || !alpha) return RSIM_EINVAL;
+  for (int j = 0; j < J; ++j) alpha[j] = 1.0f;
+  const double p0 = p_dry[0];
+  for (int i = 1; i < I; ++i) {
+    const double pi = p_dry[i];
+    const double a = pi <= 0.0 ? 0.0 : std::sqrt(p0 / (pi * std::pow(10.0, snr_db[i] / 10.0)));
+    for (int j = 0; j < J; ++j) alpha[i * J + j] = (float)a;
+  }
+  return RSIM_OK;
+}
+
+rsim_status rsim_device_status(int32_t* status) {
+  if (!status) return RSIM_EINVAL;
+  rsim_status e = ensure_init(nullptr);
+  if (e != RSIM_OK) return e;
+  if (hipDeviceSynchronize() != hipSuccess) return RSIM_EDEVICE;
+  int v = 0;
+  if (hipMemcpyFromSymbol(&v, HIP_SYMBOL(g_status), sizeof(int)) != hipSuccess) return RSIM_EDEVICE;
+  const int zero = 0;
+  if (hipMemcpyToSymbol(HIP_SYMBOL(g_status), &zero, sizeof(int)) != hipSuccess) return RSIM_EDEVICE;
+  *status = v;
+  return RSIM_OK;
+}
+
+rsim_status rsim_rfft(const float* x, int32_t n, int32_t count, float* spec, hipStream_t stream) {
+  const int l2 = ilog2_exact(n);
+  if (l2 < 9 || l2 > 15) return RSIM_EUNSUPPORTED;
+  if (count < 0 || (count > 0 && (!x || !spec))) return RSIM_EINVAL;
+  if (count == 0) return RSIM_OK;
+  rsim_status e = ensure_init(stream);
+  if (e != RSIM_OK) return e;
+  switch (l2) {
+    case 9: hipLaunchKernelGGL(rfft_kernel<Plan512>, dim3(count), dim3(Plan512::T), 0, stream, x, spec); break;
+    case 10: hipLaunchKernelGGL(rfft_kernel<Plan1K>, dim3(count), dim3(Plan1K::T), 0, stream, x, spec); break;
+    case 11: hipLaunchKernelGGL(rfft_kernel<Plan2K>, dim3(count), dim3(Plan2K::T), 0, stream, x, spec); break;
+    case 12: hipLaunchKernelGGL(rfft_kernel<Plan4K>, dim3(count), dim3(Plan4K::T), 0, stream, x, spec); break;
+    case 13: hipLaunchKernelGGL(rfft_kernel<Plan8K>, dim3(count), dim3(Plan8K::T), 0, stream, x, spec); break;
+    case 14: hipLaunchKernelGGL(rfft_kernel<Plan16K>, dim3(count), dim3(Plan16K::T), 0, stream, x, spec); break;
+    default: hipLaunchKernelGGL(rfft_kernel<Plan32K>, dim3(count), dim3(Plan32K::T), 0, stream, x, spec); break;
+  }
+  return hipGetLastError() == hipSuccess ? RSIM_OK : RSIM_EDEVICE;
+}
+
+rsim_status rsim_irfft(const float* spec, int32_t n, int32_t count, float* x, hipStream_t stream) {
+  const int l2 = ilog2_exact(n);
+  if (l2 < 9 || l2 > 15) return RSIM_EUNSUPPORTED;
+  if (count < 0 || (count > 0 && (!x || !spec))) return RSIM_EINVAL;
+  if (count == 0) return RSIM_OK;
+  rsim_status e = ensure_init(stream);
+  if (e != RSIM_OK) return e;
+  switch (l2) {
+    case 9: hipLaunchKernelGGL(irfft_kernel<Plan512>, dim3(count), dim3(Plan512::T), 0, stream, spec, x); break;
+    case 10: hipLaunchKernelGGL(irfft_kernel<Plan1K>, dim3(count), dim3(Plan1K::T), 0, stream, spec, x); break;
+    case 11: hipLaunchKernelGGL(irfft_kernel<Plan2K>, dim3(count), dim3(Plan2K::T), 0, stream, spec, x); break;
+    case 12: hipLaunchKernelGGL(irfft_kernel<Plan4K>, dim3(count), dim3(Plan4K::T), 0, stream, spec, x); break;
+    case 13: hipLaunchKernelGGL(irfft_kernel<Plan8K>, dim3(count), dim3(Plan8K::T), 0, stream, spec, x); break;
+    case 14: hipLaunchKernelGGL(irfft_kernel<Plan16K>, dim3(count), dim3(Plan16K::T), 0, stream, spec, x); break;
+    default: hipLaunchKernelGGL(irfft_kernel<Plan32K>, dim3(count), dim3(Plan32K::T), 0, stream, spec, x); break;
+  }
+  return hipGetLastError() == hipSuccess ? RSIM_OK : RSIM_EDEVICE;
+}
+
+}  // extern "C"

@@ -1,0 +1,332 @@
+"""ctypes binding of librsim.so (include/rsim.h).
+
+Argument marshalling only: every step of the hot path runs in the HIP kernels
+behind the C ABI.  PyTorch provides device memory and the current stream.
+The library must have been built (``python -m paper_1712_03439_amd.build``);
+there is no fallback of any kind when it is missing.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librsim.so")
+
+RSIM_OK, RSIM_EINVAL, RSIM_EWORKSPACE, RSIM_EUNSUPPORTED, RSIM_EDEVICE, RSIM_ENOTINIT = range(6)
+DEV_NONFINITE, DEV_BADDESC, DEV_BADPLAN = 0x1, 0x2, 0x4
+
+# Every symbol the header declares (checked by the tests).
+EXPORTS = (
+    "rsim_init", "rsim_strerror", "rsim_version", "rsim_truncate_rir",
+    "rsim_ola_workspace_bytes", "rsim_ola_convolve", "rsim_mix_workspace_bytes", "rsim_mix",
+    "rsim_simulate", "rsim_mix_backward", "rsim_source_power", "rsim_snr_gains",
+    "rsim_device_status", "rsim_rfft", "rsim_irfft",
+)
+
+
+class RsimError(RuntimeError):
+    def __init__(self, code: int, where: str = ""):
+        self.code = int(code)
+        msg = _lib().rsim_strerror(self.code).decode() if _LIB is not None else str(code)
+        super().__init__(f"{where}: rsim status {code} ({msg})")
+
+
+class RsimBatch(ctypes.Structure):
+    _fields_ = [
+        ("n_utt", ctypes.c_int32), ("n_mic", ctypes.c_int32), ("max_src", ctypes.c_int32),
+        ("max_rir_len0", ctypes.c_int32),
+        ("x_len", ctypes.c_int64), ("h_len", ctypes.c_int64), ("y_len", ctypes.c_int64),
+        ("n_src", ctypes.c_void_p), ("src_len", ctypes.c_void_p), ("src_off", ctypes.c_void_p),
+        ("rir_off", ctypes.c_void_p), ("rir_len0", ctypes.c_void_p), ("rir_len", ctypes.c_void_p),
+        ("out_off", ctypes.c_void_p), ("out_stride", ctypes.c_void_p), ("out_len", ctypes.c_void_p),
+        ("order", ctypes.c_void_p), ("fft_log2n", ctypes.c_void_p), ("hop", ctypes.c_void_p),
+    ]
+
+
+class RsimTune(ctypes.Structure):
+    _fields_ = [("cost_fft", ctypes.c_float * 7), ("cost_mac", ctypes.c_float * 7)]
+
+
+_LIB = None
+
+
+def _lib():
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built; run python -m paper_1712_03439_amd.build")
+        lib = ctypes.CDLL(LIB_PATH)
+        vp, i32, i64, f64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_size_t
+        bp, tp = ctypes.POINTER(RsimBatch), ctypes.POINTER(RsimTune)
+        sig = {
+            "rsim_init": ([], i32),
+            "rsim_strerror": ([i32], ctypes.c_char_p),
+            "rsim_version": ([], i32),
+            "rsim_truncate_rir": ([vp, i64, vp, vp, i32, f64, vp, vp, vp], i32),
+            "rsim_ola_workspace_bytes": ([i32], sz),
+            "rsim_ola_convolve": ([vp, i32, vp, i32, i32, i32, vp, vp, sz, vp], i32),
+            "rsim_mix_workspace_bytes": ([bp, tp, i32], sz),
+            "rsim_mix": ([bp, vp, vp, vp, vp, vp, sz, tp, i32, vp], i32),
+            "rsim_simulate": ([bp, vp, vp, vp, f64, vp, vp, vp, sz, tp, i32, vp], i32),
+            "rsim_mix_backward": ([bp, vp, vp, vp, vp, vp, vp, vp, vp, sz, tp, vp], i32),
+            "rsim_source_power": ([bp, vp, vp, vp], i32),
+            "rsim_snr_gains": ([vp, vp, i32, i32, vp], i32),
+            "rsim_device_status": ([vp], i32),
+            "rsim_rfft": ([vp, i32, i32, vp, vp], i32),
+            "rsim_irfft": ([vp, i32, i32, vp, vp], i32),
+        }
+        for name, (args, res) in sig.items():
+            fn = getattr(lib, name)
+            fn.argtypes = args
+            fn.restype = res
+        _LIB = lib
+    return _LIB
+
+
+def lib():
+    """The loaded ctypes library (raises if it is not built)."""
+    return _lib()
+
+
+def _check(code: int, where: str) -> None:
+    if code != RSIM_OK:
+        raise RsimError(code, where)
+
+
+# ----------------------------------------------------------------- torch glue
+def _torch():
+    import torch
+
+    return torch
+
+
+def _ptr(t) -> Optional[int]:
+    return None if t is None else int(t.data_ptr())
+
+
+def _stream(stream=None) -> int:
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+def _require_cuda(*ts):
+    for t in ts:
+        if t is not None and not t.is_cuda:
+            raise ValueError("rsim: tensors must live in GPU memory")
+        if t is not None and not t.is_contiguous():
+            raise ValueError("rsim: tensors must be contiguous")
+
+
+def init() -> None:
+    _check(_lib().rsim_init(), "rsim_init")
+
+
+def device_status() -> int:
+    st = ctypes.c_int32(0)
+    _check(_lib().rsim_device_status(ctypes.byref(st)), "rsim_device_status")
+    return int(st.value)
+
+
+def cut_scale_host(eta_db: float) -> float:
+    """Not used by the kernels (the C library computes the scale); kept for docs."""
+    return 0.0 if math.isinf(eta_db) else 10.0 ** (-eta_db / 10.0)
+
+
+def truncate_rir(h, off, len0, eta_db: float, n_c=None, length=None, stream=None):
+    """RIR tail cut-off (eqs. 7-9) on the GPU.  Returns (n_c, len) int32 tensors."""
+    torch = _torch()
+    _require_cuda(h, off, len0)
+    n = int(len0.numel())
+    if n_c is None:
+        n_c = torch.empty(n, dtype=torch.int32, device=h.device)
+    if length is None:
+        length = torch.empty(n, dtype=torch.int32, device=h.device)
+    _check(_lib().rsim_truncate_rir(_ptr(h), int(h.numel()), _ptr(off), _ptr(len0), n, float(eta_db),
+                                    _ptr(n_c), _ptr(length), _stream(stream)), "rsim_truncate_rir")
+    return n_c, length
+
+
+def ola_convolve(x, h, fft_n: int, hop: int = 0, stream=None):
+    """Overlap-add FFT convolution of one signal with one RIR (eq. 6)."""
+    torch = _torch()
+    _require_cuda(x, h)
+    nx, nh = int(x.numel()), int(h.numel())
+    y = torch.empty(max(nx + nh - 1, 0), dtype=torch.float32, device=x.device)
+    ws_bytes = int(_lib().rsim_ola_workspace_bytes(int(fft_n)))
+    ws = torch.empty(max(ws_bytes, 1), dtype=torch.uint8, device=x.device)
+    _check(_lib().rsim_ola_convolve(_ptr(x), nx, _ptr(h), nh, int(fft_n), int(hop), _ptr(y), _ptr(ws),
+                                    ws_bytes, _stream(stream)), "rsim_ola_convolve")
+    return y
+
+
+def rfft(x, n: int, stream=None):
+    """Forward real FFT of len(x)/n signals of length n (FFT engine test entry)."""
+    torch = _torch()
+    _require_cuda(x)
+    count = int(x.numel()) // n
+    spec = torch.empty(count * (n // 2 + 1) * 2, dtype=torch.float32, device=x.device)
+    _check(_lib().rsim_rfft(_ptr(x), int(n), count, _ptr(spec), _stream(stream)), "rsim_rfft")
+    return spec.view(count, n // 2 + 1, 2)
+
+
+def irfft(spec, n: int, stream=None):
+    torch = _torch()
+    _require_cuda(spec)
+    count = int(spec.numel()) // ((n // 2 + 1) * 2)
+    x = torch.empty(count * n, dtype=torch.float32, device=spec.device)
+    _check(_lib().rsim_irfft(_ptr(spec), int(n), count, _ptr(x), _stream(stream)), "rsim_irfft")
+    return x.view(count, n)
+
+
+def snr_gains(p_dry: Sequence[float], snr_db: Sequence[float], n_mic: int) -> np.ndarray:
+    """Host SNR gain rule of the library (rsim_snr_gains)."""
+    I = len(p_dry)
+    p = np.ascontiguousarray(p_dry, np.float64)
+    s = np.ascontiguousarray(snr_db, np.float64)
+    a = np.zeros(I * n_mic, np.float32)
+    _check(_lib().rsim_snr_gains(p.ctypes.data, s.ctypes.data, I, int(n_mic), a.ctypes.data),
+           "rsim_snr_gains")
+    return a.reshape(I, n_mic)
+
+
+def tune_table(cost_fft: Sequence[float], cost_mac: Sequence[float]) -> RsimTune:
+    t = RsimTune()
+    for k in range(7):
+        t.cost_fft[k] = float(cost_fft[k])
+        t.cost_mac[k] = float(cost_mac[k])
+    return t
+
+
+class DeviceBatch:
+    """A batch descriptor with its per-utterance arrays resident on the GPU.
+
+    Built from any object with the fields of synth.Batch (n_utt, n_mic, max_src,
+    n_src, src_len, src_off, rir_off, rir_len0, out_off, out_stride, x, h,
+    y_len).  x, h are uploaded once; y is allocated here.
+    """
+
+    def __init__(self, b, device="cuda", order: Optional[np.ndarray] = None,
+                 fft_log2n: Optional[np.ndarray] = None, hop: Optional[np.ndarray] = None,
+                 upload_data: bool = True):
+        torch = _torch()
+        self.host = b
+        self.U, self.J, self.S = int(b.n_utt), int(b.n_mic), int(b.max_src)
+        dev = torch.device(device)
+        t = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a), dtype=dt).to(dev)  # noqa: E731
+        self.n_src = t(b.n_src, torch.int32)
+        self.src_len = t(b.src_len, torch.int32)
+        self.src_off = t(b.src_off, torch.int64)
+        self.rir_off = t(b.rir_off, torch.int64)
+        self.rir_len0 = t(b.rir_len0, torch.int32)
+        self.rir_len = self.rir_len0.clone()
+        self.n_c = torch.empty_like(self.rir_len0)
+        self.out_off = t(b.out_off, torch.int64)
+        self.out_stride = t(b.out_stride, torch.int32)
+        self.out_len = torch.zeros(self.U, dtype=torch.int32, device=dev)
+        self.order = None if order is None else t(order, torch.int32)
+        self.fft_log2n = None if fft_log2n is None else t(fft_log2n, torch.int32)
+        self.hop = None if hop is None else t(hop, torch.int32)
+        self.x = t(b.x, torch.float32) if upload_data else None
+        self.h = t(b.h, torch.float32) if upload_data else None
+        self.x_len = int(np.asarray(b.x).size)
+        self.h_len = int(np.asarray(b.h).size)
+        self.y_len = int(b.y_len)
+        self.max_rir_len0 = int(np.max(b.rir_len0)) if np.asarray(b.rir_len0).size else 0
+        self.device = dev
+
+    def struct(self, rir_len=None) -> RsimBatch:
+        s = RsimBatch()
+        s.n_utt, s.n_mic, s.max_src, s.max_rir_len0 = self.U, self.J, self.S, self.max_rir_len0
+        s.x_len, s.h_len, s.y_len = self.x_len, self.h_len, self.y_len
+        s.n_src, s.src_len, s.src_off = _ptr(self.n_src), _ptr(self.src_len), _ptr(self.src_off)
+        s.rir_off, s.rir_len0 = _ptr(self.rir_off), _ptr(self.rir_len0)
+        s.rir_len = _ptr(self.rir_len if rir_len is None else rir_len)
+        s.out_off, s.out_stride, s.out_len = _ptr(self.out_off), _ptr(self.out_stride), _ptr(self.out_len)
+        s.order, s.fft_log2n, s.hop = _ptr(self.order), _ptr(self.fft_log2n), _ptr(self.hop)
+        return s
+
+    def workspace_bytes(self, tune: Optional[RsimTune] = None, backward: bool = False) -> int:
+        s = self.struct()
+        return int(_lib().rsim_mix_workspace_bytes(ctypes.byref(s), ctypes.byref(tune) if tune else None,
+                                                   int(backward)))
+
+    def workspace(self, tune: Optional[RsimTune] = None, backward: bool = False):
+        torch = _torch()
+        n = self.workspace_bytes(tune, backward)
+        return torch.empty(max(n, 1), dtype=torch.uint8, device=self.device)
+
+    def new_output(self):
+        torch = _torch()
+        return torch.empty(max(self.y_len, 1), dtype=torch.float32, device=self.device)
+
+
+def truncate_batch(db: DeviceBatch, eta_db: float, h=None, stream=None):
+    """Cut every RIR slot of the batch; writes db.n_c and db.rir_len."""
+    _check(_lib().rsim_truncate_rir(_ptr(db.h if h is None else h), db.h_len, _ptr(db.rir_off),
+                                    _ptr(db.rir_len0), int(db.rir_len0.numel()), float(eta_db),
+                                    _ptr(db.n_c), _ptr(db.rir_len), _stream(stream)),
+           "rsim_truncate_rir")
+
+
+def mix(db: DeviceBatch, alpha, y=None, ws=None, tune: Optional[RsimTune] = None, use_graph: bool = False,
+        x=None, h=None, stream=None):
+    """Eq. (2) for the whole batch with the current db.rir_len (call truncate_batch first)."""
+    _require_cuda(alpha)
+    if y is None:
+        y = db.new_output()
+    if ws is None:
+        ws = db.workspace(tune)
+    s = db.struct()
+    _check(_lib().rsim_mix(ctypes.byref(s), _ptr(db.x if x is None else x), _ptr(db.h if h is None else h),
+                           _ptr(alpha), _ptr(y), _ptr(ws), int(ws.numel()),
+                           ctypes.byref(tune) if tune else None, int(bool(use_graph)), _stream(stream)),
+           "rsim_mix")
+    return y
+
+
+def simulate(db: DeviceBatch, alpha, eta_db: float, y=None, ws=None, tune: Optional[RsimTune] = None,
+             use_graph: bool = False, x=None, h=None, stream=None):
+    """Cut + mix of one epoch (rsim_simulate): writes db.rir_len and y."""
+    _require_cuda(alpha)
+    if y is None:
+        y = db.new_output()
+    if ws is None:
+        ws = db.workspace(tune)
+    s = db.struct()
+    _check(_lib().rsim_simulate(ctypes.byref(s), _ptr(db.x if x is None else x),
+                                _ptr(db.h if h is None else h), _ptr(alpha), float(eta_db),
+                                _ptr(db.rir_len), _ptr(y), _ptr(ws), int(ws.numel()),
+                                ctypes.byref(tune) if tune else None, int(bool(use_graph)),
+                                _stream(stream)), "rsim_simulate")
+    return y
+
+
+def source_power(db: DeviceBatch, x=None, stream=None):
+    torch = _torch()
+    p = torch.empty(db.U * db.S, dtype=torch.float64, device=db.device)
+    s = db.struct()
+    _check(_lib().rsim_source_power(ctypes.byref(s), _ptr(db.x if x is None else x), _ptr(p),
+                                    _stream(stream)), "rsim_source_power")
+    return p
+
+
+def batch_gains(db: DeviceBatch, snr_db: np.ndarray, power: Optional[np.ndarray] = None) -> np.ndarray:
+    """alpha [U*S*J] (float32, host) from the dry powers (device kernel) and the
+    per-source SNRs, through the library's gain rule."""
+    if power is None:
+        power = source_power(db).cpu().numpy()
+    U, S, J = db.U, db.S, db.J
+    a = np.zeros(U * S * J, np.float32)
+    n_src = db.host.n_src
+    for u in range(U):
+        I = int(n_src[u])
+        if I:
+            a[u * S * J:(u * S + I) * J] = snr_gains(power[u * S:u * S + I],
+                                                     snr_db[u * S:u * S + I], J).reshape(-1)
+    return a

@@ -1,0 +1,130 @@
+"""The C ABI library: it loads, exports every symbol the header declares, and
+its host-side validation returns the documented codes without a GPU."""
+import ctypes
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1712_03439_amd import rsim
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_symbols():
+    text = open(os.path.join(ROOT, "include", "rsim.h")).read()
+    return sorted(set(re.findall(r"\b(rsim_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_library_exports_every_header_symbol():
+    lib = rsim.lib()
+    syms = header_symbols()
+    assert "rsim_mix" in syms and "rsim_truncate_rir" in syms
+    for name in syms:
+        assert hasattr(lib, name), name
+    assert sorted(rsim.EXPORTS) == syms
+
+
+def test_strerror_and_version():
+    lib = rsim.lib()
+    for code in range(6):
+        assert lib.rsim_strerror(code)
+    assert lib.rsim_version() >= 10000
+
+
+def test_truncate_rejects_bad_eta_before_touching_the_gpu():
+    lib = rsim.lib()
+    dummy = ctypes.c_void_p(1)
+    for eta in (-1.0, float("nan")):
+        assert lib.rsim_truncate_rir(dummy, 10, dummy, dummy, 1, eta, None, dummy, None) == rsim.RSIM_EINVAL
+    assert lib.rsim_truncate_rir(None, 10, None, None, 1, 20.0, None, None, None) == rsim.RSIM_EINVAL
+    assert lib.rsim_truncate_rir(None, 0, None, None, 0, 20.0, None, None, None) == rsim.RSIM_OK
+
+
+def test_ola_validation_codes():
+    lib = rsim.lib()
+    p = ctypes.c_void_p(1)
+    assert lib.rsim_ola_convolve(None, 10, p, 4, 512, 0, p, p, 1 << 30, None) == rsim.RSIM_EINVAL
+    assert lib.rsim_ola_convolve(p, 10, p, 4, 1000, 0, p, p, 1 << 30, None) == rsim.RSIM_EUNSUPPORTED
+    assert lib.rsim_ola_convolve(p, 10, p, 4, 256, 0, p, p, 1 << 30, None) == rsim.RSIM_EUNSUPPORTED
+    assert lib.rsim_ola_convolve(p, 10, p, 4, 65536, 0, p, p, 1 << 30, None) == rsim.RSIM_EUNSUPPORTED
+    # hop + nh - 1 > fft_n
+    assert lib.rsim_ola_convolve(p, 10, p, 400, 512, 200, p, p, 1 << 30, None) == rsim.RSIM_EUNSUPPORTED
+    # RIR longer than the FFT (default hop would be < 1)
+    assert lib.rsim_ola_convolve(p, 10, p, 600, 512, 0, p, p, 1 << 30, None) == rsim.RSIM_EUNSUPPORTED
+    assert lib.rsim_ola_convolve(p, 10, p, 4, 512, 0, p, None, 0, None) == rsim.RSIM_EWORKSPACE
+    assert lib.rsim_ola_workspace_bytes(1000) == 0
+    assert lib.rsim_ola_workspace_bytes(8192) > 0
+
+
+def _host_batch(U=3, J=2, S=2):
+    b = rsim.RsimBatch()
+    b.n_utt, b.n_mic, b.max_src, b.max_rir_len0 = U, J, S, 100
+    b.x_len, b.h_len, b.y_len = 1000, 1000, 1000
+    p = ctypes.c_void_p(8)
+    for f in ("n_src", "src_len", "src_off", "rir_off", "rir_len0", "rir_len", "out_off",
+              "out_stride", "out_len"):
+        setattr(b, f, p.value)
+    return b
+
+
+def test_mix_validation_codes():
+    lib = rsim.lib()
+    p = ctypes.c_void_p(8)
+    b = _host_batch()
+    need = lib.rsim_mix_workspace_bytes(ctypes.byref(b), None, 0)
+    assert need > 0
+    assert lib.rsim_mix_workspace_bytes(ctypes.byref(b), None, 1) > need
+    # too small a workspace
+    assert lib.rsim_mix(ctypes.byref(b), p, p, p, p, p, need - 1, None, 0, None) == rsim.RSIM_EWORKSPACE
+    # missing data pointers
+    assert lib.rsim_mix(ctypes.byref(b), None, p, p, p, p, need, None, 0, None) == rsim.RSIM_EINVAL
+    # bad descriptor scalars
+    bad = _host_batch()
+    bad.n_mic = 0
+    assert lib.rsim_mix(ctypes.byref(bad), p, p, p, p, p, need, None, 0, None) == rsim.RSIM_EINVAL
+    bad = _host_batch()
+    bad.src_off = None
+    assert lib.rsim_mix(ctypes.byref(bad), p, p, p, p, p, need, None, 0, None) == rsim.RSIM_EINVAL
+    assert lib.rsim_mix(None, p, p, p, p, p, need, None, 0, None) == rsim.RSIM_EINVAL
+    empty = _host_batch(U=0)
+    assert lib.rsim_mix(ctypes.byref(empty), None, None, None, None, None, 0, None, 0, None) == rsim.RSIM_OK
+    # simulate: eta must be >= 0 and a cut-length output is needed
+    assert lib.rsim_simulate(ctypes.byref(b), p, p, p, -3.0, p, p, p, need, None, 0, None) == rsim.RSIM_EINVAL
+    assert lib.rsim_simulate(ctypes.byref(b), p, p, p, 20.0, None, p, p, need, None, 0, None) == rsim.RSIM_EINVAL
+
+
+def test_workspace_grows_with_the_batch():
+    lib = rsim.lib()
+    small = _host_batch(U=2, J=2, S=2)
+    big = _host_batch(U=200, J=8, S=4)
+    assert lib.rsim_mix_workspace_bytes(ctypes.byref(big), None, 0) > \
+        lib.rsim_mix_workspace_bytes(ctypes.byref(small), None, 0)
+
+
+def test_rfft_validation():
+    lib = rsim.lib()
+    p = ctypes.c_void_p(8)
+    assert lib.rsim_rfft(p, 1000, 1, p, None) == rsim.RSIM_EUNSUPPORTED
+    assert lib.rsim_rfft(p, 65536, 1, p, None) == rsim.RSIM_EUNSUPPORTED
+    assert lib.rsim_irfft(None, 1024, 2, p, None) == rsim.RSIM_EINVAL
+    assert lib.rsim_rfft(p, 1024, 0, p, None) == rsim.RSIM_OK
+
+
+def test_snr_gains_host_rule_matches_oracle():
+    import oracle
+
+    r = np.random.default_rng(4)
+    for _ in range(50):
+        I = int(r.integers(1, 5))
+        p = list(r.uniform(1e-4, 1.0, I))
+        snr = [0.0] + list(r.uniform(0, 30, I - 1))
+        got = rsim.snr_gains(p, snr, 3)
+        ref = oracle.snr_gains(p, snr, 3).astype(np.float32)
+        np.testing.assert_array_max_ulp(got, ref, maxulp=1)
+    assert np.all(rsim.snr_gains([1.0, 0.0], [0.0, 10.0], 2)[1] == 0.0)
+    lib = rsim.lib()
+    assert lib.rsim_snr_gains(None, None, 2, 2, None) == rsim.RSIM_EINVAL
+    assert lib.rsim_snr_gains(None, None, 0, 2, None) == rsim.RSIM_OK
