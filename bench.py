@@ -1,0 +1,276 @@
+#!/usr/bin/env python3
+"""Benchmark of the room-simulator hot path on one MI355X.
+
+One step = one epoch of the batched workload: 2048 utterances of 1-15 s at
+16 kHz, each with a target and 0-3 noise sources, 2 microphones, RIRs of
+ceil(T60 fs) taps with T60 ~ U(0.1, 0.9) s drawn fresh for every epoch, cut at
+eta = 20 dB below the peak power, SNRs ~ U(0, 30) dB.  A step runs the RIR
+cut-off and the batched overlap-add filter-and-mix (one HIP graph, captured
+anew for the epoch).  Inputs (sources, that epoch's RIRs and gains) are resident
+in HBM before the timed region starts.
+
+Prints one JSON line with the throughput in simulated audio-seconds per second,
+the roofline of the dominant kernel (the filter-and-mix kernel, HBM-bound by
+the published peaks), the plain per-utterance GPU path and the FP64 oracle on
+the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+FP32_PEAK_TFLOPS = 157.3
+
+
+def log(msg: str) -> None:
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def lpt_order(b) -> np.ndarray:
+    """Longest work first: utterance length times (sources + mics)."""
+    cost = b.src_len.astype(np.int64) * (b.n_src.astype(np.int64) + b.n_mic)
+    return np.argsort(-cost, kind="stable").astype(np.int32)
+
+
+def host_plan(nx, I, J, lmax, tune_fft, tune_mac):
+    """The FFT size the schedule kernel picks (same cost rule), for FLOP accounting."""
+    best, l2b = None, 0
+    for m in range(9, 16):
+        c = tune_fft[m - 9]
+        if not c > 0:
+            continue
+        N = 1 << m
+        if N < lmax:
+            continue
+        B = N - lmax + 1
+        nb = (nx + B - 1) // B
+        cost = nb * ((I + J) * c + I * J * tune_mac[m - 9]) + I * J * c
+        if best is None or cost < best:
+            best, l2b = cost, m
+    N = 1 << l2b
+    B = N - lmax + 1
+    return N, B, (nx + B - 1) // B
+
+
+def oracle_utterance(args):
+    import oracle
+
+    sources, rirs, snrs, eta = args
+    oracle.simulate(sources, rirs, snrs, eta)
+    return 0
+
+
+def cpu_baseline(base, eta, n_utt, max_workers=16):
+    """The FP64 oracle (cut + gains + direct convolution + mix) on a seeded
+    sample of utterances, one process per host core (at most 16)."""
+    import multiprocessing as mp
+
+    rng = np.random.default_rng(1234)
+    idx = rng.choice(base.n_utt, size=min(n_utt, base.n_utt), replace=False)
+    tasks = [(base.sources(int(u)), base.rirs(int(u)), list(base.snrs(int(u))), eta) for u in idx]
+    audio = float(np.sum(base.src_len[idx].astype(np.float64))) / 16000.0
+    cores = max(1, min(max_workers, os.cpu_count() or 1))
+    ctx = mp.get_context("spawn")
+    with ctx.Pool(cores) as pool:
+        pool.map(oracle_utterance, tasks[:cores])          # warm the workers
+        t0 = time.perf_counter()
+        pool.map(oracle_utterance, tasks, chunksize=1)
+        dt = time.perf_counter() - t0
+    return {"value": audio / dt, "unit": "audio-s/s", "cores": cores, "kind": "oracle",
+            "sample": f"{len(idx)} seeded utterances of the batched workload ({audio:.0f} audio-s), "
+                      f"FP64 direct convolution, {dt:.1f} s wall"}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--eta", type=float, default=20.0)
+    ap.add_argument("--n-utt", type=int, default=2048)
+    ap.add_argument("--distinct-rooms", type=int, default=0,
+                    help="distinct epochs of RIRs to draw (default: warmup + steps)")
+    ap.add_argument("--plain-utts", type=int, default=256)
+    ap.add_argument("--cpu-utts", type=int, default=96)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--tune", default="auto", help="autotune table JSON, 'auto' or 'model'")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py: this build runs the hot path on one GPU; --gpus {args.gpus} is not "
+              f"supported (each GPU would take its own share of utterances, see DESIGN.md).",
+              file=sys.stderr)
+        return 2
+
+    import torch
+
+    import synth
+    from paper_1712_03439_amd import autotune, rsim
+
+    torch.cuda.set_device(0)
+    rsim.init()
+    dev = torch.device("cuda:0")
+    W, K = args.warmup, args.steps
+    E = args.distinct_rooms or (W + K)
+
+    t0 = time.perf_counter()
+    base = synth.make_config2(epoch=0, n_utt=args.n_utt)
+    log(f"dataset: {base.n_utt} utterances, {base.audio_seconds:.0f} audio-s, "
+        f"{base.x.nbytes / 1e9:.2f} GB of sources ({time.perf_counter() - t0:.1f} s)")
+    order = lpt_order(base)
+    tune = autotune.load(args.tune)
+    tf, tm = autotune.costs(tune)
+
+    x_dev = torch.from_numpy(base.x).to(dev)
+    epochs = []
+    power = None
+    for e in range(E):
+        b = base if e == 0 else synth.reroom(base, 2, e, (0.1, 0.9))
+        db = rsim.DeviceBatch(b, device=dev, order=order, upload_data=False)
+        db.x = x_dev
+        db.h = torch.from_numpy(b.h).to(dev)
+        if power is None:
+            power = rsim.source_power(db).cpu().numpy()
+        alpha = torch.from_numpy(rsim.batch_gains(db, b.snr_db, power)).to(dev)
+        epochs.append((b, db, alpha))
+        if e % 5 == 0:
+            log(f"rooms for epoch {e} ready ({time.perf_counter() - t0:.1f} s)")
+    y = torch.empty(max(b.y_len for b, _, _ in epochs), dtype=torch.float32, device=dev)
+    ws = torch.empty(max(db.workspace_bytes(tune) for _, db, _ in epochs), dtype=torch.uint8, device=dev)
+    stream = torch.cuda.Stream()
+    stream.wait_stream(torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    use_graph = not args.no_graph
+
+    def run_epoch(k, ev=None):
+        b, db, alpha = epochs[k % E]
+        if ev:
+            ev[0].record(stream)
+        rsim.truncate_batch(db, args.eta, stream=stream)
+        if ev:
+            ev[1].record(stream)
+        rsim.mix(db, alpha, y=y, ws=ws, tune=tune, use_graph=use_graph, stream=stream)
+        if ev:
+            ev[2].record(stream)
+
+    with torch.cuda.stream(stream):
+        for k in range(W):
+            run_epoch(k)
+        torch.cuda.synchronize()
+        log("warmup done")
+        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(K)]
+        torch.cuda.synchronize()
+        t_start = time.perf_counter()
+        for k in range(K):
+            run_epoch(W + k, evs[k])
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t_start
+    st = rsim.device_status()
+    if st:
+        log(f"device status word {st:#x}")
+    trunc_ms = [e[0].elapsed_time(e[1]) for e in evs]
+    mix_ms = [e[1].elapsed_time(e[2]) for e in evs]
+    audio = base.audio_seconds
+    value = K * audio / elapsed
+    log(f"timed {K} epochs: {elapsed * 1e3 / K:.3f} ms/epoch, cut {np.mean(trunc_ms):.3f} ms, "
+        f"mix {np.mean(mix_ms):.3f} ms, {value:.4g} audio-s/s")
+
+    # Algorithmic bytes and FLOPs of the mix launches of the timed epochs.
+    byt, flops, byt_cut = [], [], []
+    for k in range(K):
+        b, db, _ = epochs[(W + k) % E]
+        L = db.rir_len.cpu().numpy().astype(np.int64)
+        T = db.out_len.cpu().numpy().astype(np.int64)
+        I = b.n_src.astype(np.int64)
+        J = b.n_mic
+        byt.append(4 * (np.sum(I * b.src_len) + np.sum(L) + J * np.sum(T)))
+        byt_cut.append(4 * np.sum(b.rir_len0.astype(np.int64)))
+        f = 0.0
+        Lr = L.reshape(b.n_utt, b.max_src * J)
+        for u in range(b.n_utt):
+            lmax = int(Lr[u].max())
+            if lmax == 0 or b.src_len[u] == 0:
+                continue
+            N, B, nb = host_plan(int(b.src_len[u]), int(I[u]), J, lmax, tf, tm)
+            c = 2.5 * N * math.log2(N)
+            f += nb * ((I[u] + J) * c + I[u] * J * 8 * (N / 2 + 1)) + I[u] * J * c
+        flops.append(f)
+    t_mix = float(np.mean(mix_ms)) * 1e-3
+    achieved = float(np.mean(byt)) / t_mix / 1e9
+    alu = float(np.mean(flops)) / t_mix / 1e12
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None}
+    result = {
+        "metric": "simulated audio-sec/sec (FP32, 1 MI355X) batched vs plain; HBM GB/s fraction",
+        "value": round(value, 1),
+        "unit": "audio-s/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": W,
+        "ms_per_step": round(elapsed * 1e3 / K, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"batched: {base.n_utt} utterances of 1-15 s at 16 kHz, 1 target + "
+                               f"U{{0..3}} noises, 2 mics, T60 U(0.1,0.9) s, L0 = ceil(T60 fs), cut "
+                               f"{args.eta:g} dB, SNR U(0,30) dB, fresh RIRs every epoch",
+                   "global_batch": base.n_utt, "audio_s_per_step": round(audio, 1),
+                   "eta_db": args.eta, "hip_graph": use_graph,
+                   "tune": "autotuned" if args.tune != "model" and tune is not None else "cost model"},
+        "roofline": roof,
+        "kernel_ms": {"cut": round(float(np.mean(trunc_ms)), 4), "mix": round(float(np.mean(mix_ms)), 4)},
+        "alu": {"achieved_tflops": round(alu, 2), "peak_tflops": FP32_PEAK_TFLOPS,
+                "frac": round(alu / FP32_PEAK_TFLOPS, 4),
+                "flop_model": "2.5 N log2 N per real FFT + 8 (N/2+1) per spectral MAC"},
+        "bytes_per_step": {"mix": int(np.mean(byt)), "cut": int(np.mean(byt_cut))},
+    }
+
+    if not args.no_plain:
+        # Plain per-utterance path: the same kernels, one utterance per call, no
+        # graph, synchronised after every utterance.
+        b, db, alpha = epochs[0]
+        rng = np.random.default_rng(7)
+        sub = np.sort(rng.choice(b.n_utt, size=min(args.plain_utts, b.n_utt), replace=False))
+        ws1 = torch.empty(rsim.single_workspace_bytes(db), dtype=torch.uint8, device=dev)
+        t_sum, audio_sub = 0.0, 0.0
+        with torch.cuda.stream(stream):
+            for u in sub:
+                torch.cuda.synchronize()
+                t0u = time.perf_counter()
+                rsim.simulate_one(db, int(u), alpha, args.eta, y, ws1, stream=stream)
+                torch.cuda.synchronize()
+                t_sum += time.perf_counter() - t0u
+                audio_sub += float(b.src_len[u]) / 16000.0
+        plain = audio_sub / t_sum
+        result["plain_gpu"] = {"value": round(plain, 1), "unit": "audio-s/s",
+                               "sample": f"{len(sub)} utterances, one call each, no graph, "
+                                         f"synchronised per utterance"}
+        result["speedup_vs_plain"] = round(value / plain, 2)
+        log(f"plain per-utterance path: {plain:.4g} audio-s/s ({value / plain:.1f}x)")
+
+    if not args.no_cpu:
+        log("timing the FP64 oracle on the host cores ...")
+        result["cpu_baseline"] = cpu_baseline(base, args.eta, args.cpu_utts)
+        log(f"oracle: {result['cpu_baseline']['value']:.4g} audio-s/s on "
+            f"{result['cpu_baseline']['cores']} cores")
+    print(json.dumps(result), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -54,12 +54,47 @@ __device__ __forceinline__ const T* opaque(const T* p) {
   asm volatile("" : "+s"(p));
   return p;
 }
+// ------------------------------------------------------------ buffer access
+// Raw buffer resources: the base lives in scalar registers and each access
+// needs one 32-bit lane offset.  The `vo` operand (and any immediate the
+// compiler folds out of it) is range-checked against the resource size:
+// loads past it return 0 and stores past it are dropped, which gives the
+// zero padding of a signal block and the clipping of an output block without
+// branches.  The `so` operand is not range-checked (constant strides only).
+typedef __amdgpu_buffer_rsrc_t rsrc_t;
+constexpr int kRsrcWord3 = 0x00020000;  // raw buffer, 32-bit data format (gfx9 family)
+
+__device__ __forceinline__ rsrc_t make_rsrc(const void* p, int bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, bytes, kRsrcWord3);
+}
+__device__ __forceinline__ float ld1(rsrc_t r, int vo, int so = 0) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, vo, so, 0));
+}
+__device__ __forceinline__ void st1(rsrc_t r, int vo, float v, int so = 0) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, vo, so, 0);
+}
+__device__ __forceinline__ cf ld2(rsrc_t r, int vo, int so = 0) {
+  return __builtin_bit_cast(cf, __builtin_amdgcn_raw_buffer_load_b64(r, vo, so, 0));
+}
+__device__ __forceinline__ void st2(rsrc_t r, int vo, cf v, int so = 0) {
+  typedef unsigned u2 __attribute__((ext_vector_type(2)));
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), r, vo, so, 0);
+}
+
 // Same for the thread index: values derived from it inside a helper (LDS and
 // global offsets) are recomputed per call instead of being hoisted out of the
 // caller's loops and kept live (or spilled) for the whole kernel.
 __device__ __forceinline__ int opaque_v(int x) {
   asm volatile("" : "+v"(x));
   return x;
+}
+__device__ __forceinline__ cf opaque_c(cf z) {
+  asm volatile("" : "+v"(z.x), "+v"(z.y));
+  return z;
+}
+// a * a
+__device__ __forceinline__ cf csq(cf a) {
+  return mk(__builtin_fmaf(a.x, a.x, -(a.y * a.y)), 2.f * (a.x * a.y));
 }
 // acc + a * b
 __device__ __forceinline__ cf cmac(cf acc, cf a, cf b) {
@@ -133,6 +168,44 @@ template <int R, int K, bool INV>
 __device__ __forceinline__ cf twc(cf a) {
   static_assert(32 % R == 0, "radix must divide 32");
   return rot32<(INV ? -K : K) * (32 / R)>(a);
+}
+
+// wp[r] = w1^r for r = 1..R-1, by squaring (even r) or one product (odd r):
+// at most 2 log2 R roundings per power.
+template <int R>
+__device__ __forceinline__ void powers(cf* wp, cf w1) {
+  wp[1] = w1;
+  sfor<R - 2>([&](auto rc) {
+    constexpr int r = decltype(rc)::value + 2;
+    if constexpr (r % 2 == 0) {
+      wp[r] = csq(wp[r / 2]);
+    } else {
+      wp[r] = cmul(wp[r - 1], w1);
+    }
+  });
+}
+
+// Calls f(r, w^r) for r = 1..R-1 (r as a compile-time constant), forming the
+// powers on the fly from w, w^2, w^3, w^4 and the anchors w^{4m}: at most
+// about R/4 + 2 roundings per power and a handful of live registers.
+template <int R, class F>
+__device__ __forceinline__ void for_powers(cf w1, F&& f) {
+  const cf w2 = csq(w1);
+  const cf w3 = cmul(w2, w1);
+  const cf w4 = csq(w2);
+  cf g = w4;
+  sfor<R - 1>([&](auto rc) {
+    constexpr int r = decltype(rc)::value + 1;
+    constexpr int e = r % 4;
+    if constexpr (r < 4) {
+      f(std::integral_constant<int, r>{}, e == 1 ? w1 : e == 2 ? w2 : w3);
+    } else if constexpr (e == 0) {
+      if constexpr (r > 4) g = cmul(g, w4);
+      f(std::integral_constant<int, r>{}, g);
+    } else {
+      f(std::integral_constant<int, r>{}, cmul(g, e == 1 ? w1 : e == 2 ? w2 : w3));
+    }
+  });
 }
 
 // --------------------------------------------------------------- DFT codelets
@@ -243,6 +316,7 @@ using Plan2K = Plan<1024, 64, 16, 8, 8>;
 using Plan4K = Plan<2048, 64, 32, 4, 16>;
 using Plan8K = Plan<4096, 128, 32, 8, 16>;
 using Plan16K = Plan<8192, 256, 32, 16, 16>;
+using Plan16KW = Plan<8192, 512, 16, 8, 8, 8>;  // 16 points per thread: room to prefetch
 using Plan32K = Plan<16384, 512, 32, 32, 16>;
 
 // Offsets of each plan's table inside the one twiddle array (log2 N = 9..15).
@@ -257,7 +331,8 @@ constexpr int kTwOff[8] = {
         Plan16K::TW_SIZE,
     Plan512::TW_SIZE + Plan1K::TW_SIZE + Plan2K::TW_SIZE + Plan4K::TW_SIZE + Plan8K::TW_SIZE +
         Plan16K::TW_SIZE + Plan32K::TW_SIZE};
-constexpr int kTwTotal = kTwOff[7];
+constexpr int kTwOff16W = kTwOff[7];
+constexpr int kTwTotal = kTwOff16W + Plan16KW::TW_SIZE;
 
 template <class PL>
 __device__ __forceinline__ int pad(int i) {
@@ -265,19 +340,46 @@ __device__ __forceinline__ int pad(int i) {
 }
 
 // ------------------------------------------------------------ the transforms
+// Per-thread twiddle bases of a plan.  Every twiddle a thread applies is a
+// power of one base per pass (the middle-pass butterflies of a thread share
+// k = t mod Ls because T is a multiple of Ls), or, for the real
+// post-processing, one base times a compile-time root of unity.  The bases are
+// loaded once per utterance and the powers are formed in registers, so the
+// transforms read no twiddle memory.
+struct TwBase {
+  cf mid[2];  // W_{R_p Ls_p}^{k}, k = t mod Ls_p, for middle passes p = 1, 2
+  cf last;    // W_M^{kb}, kb = t (thread 0: T)
+  cf post;    // W_N^{c}, c = t (thread 0: T)
+};
+
 template <class PL>
 struct Fft {
   static constexpr int M = PL::M, T = PL::T, P = PL::P, NP = PL::NP, RL = PL::RL;
+  static_assert(NP - 2 <= 2, "at most two middle passes");
 
   // LDS index strides after padding: every stride used below is a multiple
   // of 2^PSH, so pad(i + r s) = pad(i) + r ps(s).
   static constexpr int ps(int s) { return s + (s >> PL::PSH); }
 
+  __device__ static __forceinline__ TwBase bases(const cf* __restrict__ tw_, int t) {
+    const rsrc_t tw = make_rsrc(tw_, PL::TW_SIZE * 8);
+    TwBase B;
+    B.mid[0] = B.mid[1] = mk(1.f, 0.f);
+    sfor<NP - 2>([&](auto pc) {
+      constexpr int p = decltype(pc)::value + 1;
+      constexpr int Ls = PL::ls(p);
+      B.mid[p - 1] = ld2(tw, 8 * (t & (Ls - 1)), 8 * (PL::mid_off(p) + Ls));
+    });
+    const int kb = t ? t : T;
+    B.last = ld2(tw, 8 * kb, 8 * (PL::LAST_OFF + (T + 1)));
+    B.post = ld2(tw, 8 * kb, 8 * PL::POST_OFF);
+    return B;
+  }
+
   // Forward complex FFT.  In: v[r] = z[t + rT].  Out: slot layout (before the
-  // real post-processing).  `lds` holds PL::LDS entries; `tw` is the plan's
-  // table.  Contains barriers: every thread of the workgroup must call it.
-  __device__ static void forward(cf* v, cf* lds, const cf* __restrict__ tw_, int t_) {
-    const cf* tw = opaque(tw_);
+  // real post-processing).  `lds` holds PL::LDS entries.  Contains barriers:
+  // every thread of the workgroup must call it.
+  __device__ static __forceinline__ void forward(cf* v, cf* lds, const TwBase& B, int t_) {
     const int t = opaque_v(t_);
     // pass 0 (Ls = 1): no twiddles; outputs of butterfly t go to t*R0 + r
     dft<PL::R[0], false>(v);
@@ -291,7 +393,6 @@ struct Fft {
     sfor<NP - 2>([&](auto pc) {
       constexpr int p = decltype(pc)::value + 1;
       constexpr int R = PL::R[p], Ls = PL::ls(p), NB = P / R;
-      const cf* twp = tw + PL::mid_off(p);
 #pragma unroll
       for (int b = 0; b < NB; ++b) {
         const cf* src = lds + pad<PL>(t + T * b);
@@ -299,14 +400,16 @@ struct Fft {
         for (int r = 0; r < R; ++r) v[b * R + r] = src[r * ps(M / R)];
       }
       __syncthreads();
+      for_powers<R>(opaque_c(B.mid[p - 1]), [&](auto rc, cf w) {
+        constexpr int r = decltype(rc)::value;
+#pragma unroll
+        for (int b = 0; b < NB; ++b) v[b * R + r] = cmul(v[b * R + r], w);
+      });
 #pragma unroll
       for (int b = 0; b < NB; ++b) {
         const int j = t + T * b;
         const int k = j & (Ls - 1);
         cf* u = v + b * R;
-        const cf* twk = twp + k;
-#pragma unroll
-        for (int r = 1; r < R; ++r) u[r] = cmul(u[r], twk[r * Ls]);
         dft<R, false>(u);
         cf* dst = lds + pad<PL>((j - k) * R + k);
 #pragma unroll
@@ -318,9 +421,8 @@ struct Fft {
     // twiddles W_M^{r kb}: butterfly jb = 2T - t needs conj(W_M^{r t}) times
     // W_R^r, and the W_R^r factor is a rotation of its outputs by one bin.
     // Thread 0 (ja = 0, jb = T) uses W_M^{r T} for jb and 1 for ja.
-    const int ja = t, jb = t ? 2 * T - t : T, kb = t ? t : T;
+    const int ja = t, jb = t ? 2 * T - t : T;
     const bool t0 = t == 0;
-    const cf* twl = tw + PL::LAST_OFF + kb;
     cf a[RL], b[RL];
     {
       const cf* sa = lds + pad<PL>(ja);
@@ -331,13 +433,12 @@ struct Fft {
         b[r] = sb[r * ps(2 * T)];
       }
     }
-#pragma unroll
-    for (int r = 1; r < RL; ++r) {
-      const cf w = twl[r * (T + 1)];
+    for_powers<RL>(opaque_c(B.last), [&](auto rc, cf w) {
+      constexpr int r = decltype(rc)::value;
       const cf aw = cmul(a[r], w);
       a[r] = t0 ? a[r] : aw;
       b[r] = cmulc(b[r], w);
-    }
+    });
     dft<RL, false>(a);
     dft<RL, false>(b);
 #pragma unroll
@@ -348,12 +449,10 @@ struct Fft {
   }
 
   // Adjoint of forward(): slot layout in, v[r] = M * z[t + rT] out.
-  __device__ static void inverse(cf* v, cf* lds, const cf* __restrict__ tw_, int t_) {
-    const cf* tw = opaque(tw_);
+  __device__ static __forceinline__ void inverse(cf* v, cf* lds, const TwBase& B, int t_) {
     const int t = opaque_v(t_);
-    const int ja = t, jb = t ? 2 * T - t : T, kb = t ? t : T;
+    const int ja = t, jb = t ? 2 * T - t : T;
     const bool t0 = t == 0;
-    const cf* twl = tw + PL::LAST_OFF + kb;
     cf a[RL], b[RL];
 #pragma unroll
     for (int q = 0; q < RL; ++q) {
@@ -362,13 +461,12 @@ struct Fft {
     }
     dft<RL, true>(a);
     dft<RL, true>(b);
-#pragma unroll
-    for (int r = 1; r < RL; ++r) {
-      const cf w = twl[r * (T + 1)];
+    for_powers<RL>(opaque_c(B.last), [&](auto rc, cf w) {
+      constexpr int r = decltype(rc)::value;
       const cf aw = cmulc(a[r], w);
       a[r] = t0 ? a[r] : aw;
       b[r] = cmul(b[r], w);
-    }
+    });
     __syncthreads();  // previous users of lds are done
     {
       cf* da = lds + pad<PL>(ja);
@@ -383,7 +481,6 @@ struct Fft {
     sfor<NP - 2>([&](auto pc) {
       constexpr int p = NP - 2 - decltype(pc)::value;
       constexpr int R = PL::R[p], Ls = PL::ls(p), NB = P / R;
-      const cf* twp = tw + PL::mid_off(p);
 #pragma unroll
       for (int bb = 0; bb < NB; ++bb) {
         const int j = t + T * bb;
@@ -394,14 +491,16 @@ struct Fft {
       }
       __syncthreads();
 #pragma unroll
+      for (int bb = 0; bb < NB; ++bb) dft<R, true>(v + bb * R);
+      for_powers<R>(opaque_c(B.mid[p - 1]), [&](auto rc, cf w) {
+        constexpr int r = decltype(rc)::value;
+#pragma unroll
+        for (int bb = 0; bb < NB; ++bb) v[bb * R + r] = cmulc(v[bb * R + r], w);
+      });
+#pragma unroll
       for (int bb = 0; bb < NB; ++bb) {
         const int j = t + T * bb;
-        const int k = j & (Ls - 1);
         cf* u = v + bb * R;
-        dft<R, true>(u);
-        const cf* twk = twp + k;
-#pragma unroll
-        for (int r = 1; r < R; ++r) u[r] = cmulc(u[r], twk[r * Ls]);
         cf* dst = lds + pad<PL>(j);
 #pragma unroll
         for (int r = 0; r < R; ++r) dst[r * ps(M / R)] = u[r];
@@ -474,22 +573,24 @@ struct Fft {
     }
   }
   // Post-processing twiddles W_N^k of the first bin of each generic pair:
-  // column t, except thread 0 uses column T for its b-pairs (q < R/2).
-  __device__ static __forceinline__ void post_twiddles(cf* w, const cf* twp, int t) {
-    const cf* lo = twp + (t ? t : T);
-    const cf* hi = twp + t;
-#pragma unroll
-    for (int q = 0; q < RL; ++q) w[q] = (q < RL / 2 ? lo : hi)[q * (T + 1)];
+  // k = c + 2Tq with column c = t, except that thread 0 uses c = T for its
+  // b-pairs (q < R/2) and c = 0 otherwise.  W_N^{c + 2Tq} = W_N^c W_{2R}^q.
+  __device__ static __forceinline__ void post_twiddles(cf* w, const TwBase& B, bool t0) {
+    const cf lo = opaque_c(B.post);
+    const cf hi = t0 ? mk(1.f, 0.f) : lo;
+    sfor<RL>([&](auto qc) {
+      constexpr int q = decltype(qc)::value;
+      w[q] = rot32<q * (32 / (2 * RL))>(q < RL / 2 ? lo : hi);
+    });
   }
 
   // Real post-processing: Z (transform of x[2n] + i x[2n+1]) -> 2 X[k] in the
   // slot layout (thread 0 permuted as above).
-  __device__ static void post(cf* v, const cf* __restrict__ tw, int t_) {
-    const cf* twp = opaque(tw + PL::POST_OFF);
+  __device__ static __forceinline__ void post(cf* v, const TwBase& B, int t_) {
     const int t = opaque_v(t_);
     const bool t0 = t == 0;
     cf w[RL];
-    post_twiddles(w, twp, t);
+    post_twiddles(w, B, t0);
     const cf s0 = v[0], sh = v[RL / 2];
     perm_t0(v, t0);
 #pragma unroll
@@ -508,12 +609,11 @@ struct Fft {
 
   // Inverse of post() up to a factor 2: 2 Y[k] (slot layout) -> Z' such that
   // inverse() returns 4 M y.
-  __device__ static void pre(cf* v, const cf* __restrict__ tw, int t_) {
-    const cf* twp = opaque(tw + PL::POST_OFF);
+  __device__ static __forceinline__ void pre(cf* v, const TwBase& B, int t_) {
     const int t = opaque_v(t_);
     const bool t0 = t == 0;
     cf w[RL];
-    post_twiddles(w, twp, t);
+    post_twiddles(w, B, t0);
     const cf d = v[SP], sh = v[RL / 2];
 #pragma unroll
     for (int q = 0; q < RL; ++q) {

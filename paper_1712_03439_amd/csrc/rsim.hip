@@ -29,6 +29,16 @@ __device__ int g_status;
 
 __device__ __forceinline__ void flag_status(int bits) { atomicOr(&g_status, bits); }
 
+// Values that are the same in every lane (descriptor entries of the current
+// utterance): keeping them in scalar registers keeps the buffer resources
+// built from them scalar.
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ long long uni64(long long v) {
+  const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(v & 0xffffffffLL));
+  const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)((unsigned long long)v >> 32));
+  return (long long)(((unsigned long long)hi << 32) | lo);
+}
+
 // ------------------------------------------------------------------ reductions
 __device__ __forceinline__ float wave_max(float v) {
 #pragma unroll
@@ -269,45 +279,63 @@ __global__ __launch_bounds__(kSchedThreads) void schedule_kernel(BatchDev b, Tun
 }
 
 // ============================================================ filter and mix
-// v[r] = (src[2(t + rT)], src[2(t + rT) + 1]), zero at indices >= nvalid.
+// v[r] = (src[2(t + rT)], src[2(t + rT) + 1]), zero at indices >= nvalid
+// (the buffer range check supplies the zero padding of the block).
 template <class PL>
-__device__ __forceinline__ void load_real(cf* v, const float* __restrict__ src_, int nvalid, int t_) {
+__device__ __forceinline__ void load_real(cf* v, const float* __restrict__ src, int nvalid, int t_) {
   const int t = opaque_v(t_);
-  const float* src = src_ + 2 * t;
-  const int lim = nvalid - 2 * t;  // element 2rT (+1) is valid when it is < lim
+  const rsrc_t rs = make_rsrc(src, nvalid * 4);
+  const int vo = 8 * t;
 #pragma unroll
-  for (int r = 0; r < PL::P; ++r) {
-    float a = 0.f, c = 0.f;
-    if (2 * r * PL::T < lim) a = src[2 * r * PL::T];
-    if (2 * r * PL::T + 1 < lim) c = src[2 * r * PL::T + 1];
-    v[r] = mk(a, c);
-  }
+  for (int r = 0; r < PL::P; ++r) v[r] = mk(ld1(rs, vo + 8 * r * PL::T), ld1(rs, vo + 8 * r * PL::T + 4));
 }
 
+// Spectra in memory: slot q of thread t at index q * T + t.
 template <class PL>
 __device__ __forceinline__ void store_spec(cf* __restrict__ dst, const cf* v, int t) {
-  cf* d = dst + opaque_v(t);
+  const rsrc_t rs = make_rsrc(dst, PL::P * PL::T * 8);
+  const int vo = 8 * opaque_v(t);
 #pragma unroll
-  for (int q = 0; q < PL::P; ++q) d[q * PL::T] = v[q];
+  for (int q = 0; q < PL::P; ++q) st2(rs, vo, v[q], 8 * q * PL::T);
 }
 
 template <class PL>
 __device__ __forceinline__ void load_spec(cf* v, const cf* __restrict__ src, int t) {
-  const cf* s = src + opaque_v(t);
+  const rsrc_t rs = make_rsrc(src, PL::P * PL::T * 8);
+  const int vo = 8 * opaque_v(t);
 #pragma unroll
-  for (int q = 0; q < PL::P; ++q) v[q] = s[q * PL::T];
+  for (int q = 0; q < PL::P; ++q) v[q] = ld2(rs, vo, 8 * q * PL::T);
 }
 
 // Y += H X over the thread's slots; thread 0's slot SP is the packed pair of
 // real bins (0, N/2) and multiplies componentwise.
 template <class PL>
-__device__ __forceinline__ void mac(cf* Y, const cf* __restrict__ H_, const cf* X, int t_) {
+__device__ __forceinline__ void mac(cf* Y, const cf* __restrict__ H, const cf* X, int t_) {
   constexpr int SP = Fft<PL>::SP;
   const int t = opaque_v(t_);
-  const cf* H = H_ + t;
+  const rsrc_t rs = make_rsrc(H, PL::P * PL::T * 8);
+  const int vo = 8 * t;
 #pragma unroll
   for (int q = 0; q < PL::P; ++q) {
-    const cf hv = H[q * PL::T];
+    const cf hv = ld2(rs, vo, 8 * q * PL::T);
+    if (q == SP) {
+      const cf c = cmac(Y[q], hv, X[q]);
+      const cf d = mk(__builtin_fmaf(hv.x, X[q].x, Y[q].x), __builtin_fmaf(hv.y, X[q].y, Y[q].y));
+      Y[q] = t == 0 ? d : c;
+    } else {
+      Y[q] = cmac(Y[q], hv, X[q]);
+    }
+  }
+}
+
+// Y += H X with H already in registers.
+template <class PL>
+__device__ __forceinline__ void mac_regs(cf* Y, const cf* Hr, const cf* X, int t_) {
+  constexpr int SP = Fft<PL>::SP;
+  const int t = opaque_v(t_);
+#pragma unroll
+  for (int q = 0; q < PL::P; ++q) {
+    const cf hv = Hr[q];
     if (q == SP) {
       const cf c = cmac(Y[q], hv, X[q]);
       const cf d = mk(__builtin_fmaf(hv.x, X[q].x, Y[q].x), __builtin_fmaf(hv.y, X[q].y, Y[q].y));
@@ -320,16 +348,17 @@ __device__ __forceinline__ void mac(cf* Y, const cf* __restrict__ H_, const cf* 
 
 // Two mics at once: Y0 += H0 X, Y1 += H1 X, one slot at a time.
 template <class PL>
-__device__ __forceinline__ void mac2(cf* Y0, cf* Y1, const cf* __restrict__ H0_,
-                                     const cf* __restrict__ H1_, const cf* X, int t_) {
+__device__ __forceinline__ void mac2(cf* Y0, cf* Y1, const cf* __restrict__ H0,
+                                     const cf* __restrict__ H1, const cf* X, int t_) {
   constexpr int SP = Fft<PL>::SP;
   const int t = opaque_v(t_);
-  const cf* H0 = H0_ + t;
-  const cf* H1 = H1_ + t;
+  const rsrc_t r0 = make_rsrc(H0, PL::P * PL::T * 8);
+  const rsrc_t r1 = make_rsrc(H1, PL::P * PL::T * 8);
+  const int vo = 8 * t;
 #pragma unroll
   for (int q = 0; q < PL::P; ++q) {
-    const cf h0 = H0[q * PL::T];
-    const cf h1 = H1[q * PL::T];
+    const cf h0 = ld2(r0, vo, 8 * q * PL::T);
+    const cf h1 = ld2(r1, vo, 8 * q * PL::T);
     if (q == SP) {
       const cf c0 = cmac(Y0[q], h0, X[q]), c1 = cmac(Y1[q], h1, X[q]);
       const cf d0 = mk(__builtin_fmaf(h0.x, X[q].x, Y0[q].x), __builtin_fmaf(h0.y, X[q].y, Y0[q].y));
@@ -346,32 +375,32 @@ __device__ __forceinline__ void mac2(cf* Y0, cf* Y1, const cf* __restrict__ H0_,
 // Inverse-transform one mic spectrum and overlap-add it into y: positions
 // m < lim are written; positions m < carry already hold the tails of earlier
 // blocks (written by this workgroup) and are accumulated.
+// Inverse-transform one mic spectrum and overlap-add it into y: positions
+// m < lim are written; positions m < carry already hold the tails of earlier
+// blocks (written by this workgroup) and are accumulated.  Both limits are
+// buffer range checks, so no element needs a branch.
 template <class PL>
-__device__ __forceinline__ void emit(cf* Yv, cf* lds, const cf* tw, float* __restrict__ yp_, int lim_,
-                                     int carry_, int t_) {
+__device__ __forceinline__ void emit(cf* Yv, cf* lds, const TwBase& tw, float* __restrict__ yp, int lim,
+                                     int carry, int t_) {
   Fft<PL>::pre(Yv, tw, t_);
   Fft<PL>::inverse(Yv, lds, tw, t_);
   const int t = opaque_v(t_);
-  float* yp = yp_ + 2 * t;
-  const int lim = lim_ - 2 * t, carry = carry_ - 2 * t;
+  const rsrc_t wr = make_rsrc(yp, lim * 4);
+  const rsrc_t rd = make_rsrc(yp, min(carry, lim) * 4);
+  const int vo = 8 * t;
 #pragma unroll
   for (int r = 0; r < PL::P; ++r) {
-    constexpr int T2 = 2 * PL::T;
-    if (r * T2 < lim) {
-      float val = Yv[r].x;
-      if (r * T2 < carry) val += yp[r * T2];
-      yp[r * T2] = val;
-    }
-    if (r * T2 + 1 < lim) {
-      float val = Yv[r].y;
-      if (r * T2 + 1 < carry) val += yp[r * T2 + 1];
-      yp[r * T2 + 1] = val;
-    }
+    const int o = vo + 8 * r * PL::T;
+    const float a = Yv[r].x + ld1(rd, o);
+    const float b = Yv[r].y + ld1(rd, o + 4);
+    st1(wr, o, a);
+    st1(wr, o + 4, b);
   }
 }
 
 template <class PL>
 __device__ __forceinline__ const cf* plan_tw() {
+  if constexpr (std::is_same<PL, Plan16KW>::value) return g_tw + kTwOff16W;
   return g_tw + kTwOff[ilog2c(PL::N) - 9];
 }
 
@@ -379,11 +408,11 @@ __device__ __forceinline__ const cf* plan_tw() {
 // of JG (1 or 2) accumulators; when J > JG the source spectra of the current
 // block are kept in the workgroup's scratch for the later mic groups.
 template <class PL, int JG>
-__device__ void mix_utterance(const MixArgs& A, int u, const Sched& S, cf* lds, cf* slot, int t) {
+__device__ __forceinline__ void mix_utterance(const MixArgs& A, int u, const Sched& S, cf* lds, cf* slot, int t) {
   constexpr int P = PL::P, M = PL::M;
-  const cf* tw = plan_tw<PL>();
+  const TwBase tw = Fft<PL>::bases(plan_tw<PL>(), t);
   const BatchDev& b = A.b;
-  const int I = b.n_src[u], J = b.J, NS = b.S, Nx = b.src_len[u];
+  const int I = uni(b.n_src[u]), J = b.J, NS = b.S, Nx = uni(b.src_len[u]);
   const int B = S.hop, nb = S.nb, tu = S.tu, lmax = S.lmax;
   const int span = B + lmax - 1;
   const float cscale = 1.0f / (8.0f * (float)M);
@@ -392,21 +421,26 @@ __device__ void mix_utterance(const MixArgs& A, int u, const Sched& S, cf* lds, 
   const int ng = (J + JG - 1) / JG;
 
   // RIR spectra, once per utterance, scaled by alpha / (8M).
-  for (int s = 0; s < I * J; ++s) {
-    const int i = s / J, j = s - (s / J) * J;
-    const long long r = ((long long)u * NS + i) * J + j;
-    cf v[P];
-    load_real<PL>(v, A.h + b.rir_off[r], b.rir_len[r], t);
-    Fft<PL>::forward(v, lds, tw, t);
-    Fft<PL>::post(v, tw, t);
-    const float a = A.alpha[r] * cscale;
+  for (int i = 0; i < I; ++i) {
+    for (int j = 0; j < J; ++j) {
+      const long long r = ((long long)u * NS + i) * J + j;
+      cf v[P];
+      load_real<PL>(v, A.h + uni64(b.rir_off[r]), uni(b.rir_len[r]), t);
+      Fft<PL>::forward(v, lds, tw, t);
+      Fft<PL>::post(v, tw, t);
+      const float a = A.alpha[r] * cscale;
 #pragma unroll
-    for (int q = 0; q < P; ++q) v[q] = mk(v[q].x * a, v[q].y * a);
-    store_spec<PL>(Hs + (long long)s * M, v, t);
+      for (int q = 0; q < P; ++q) v[q] = mk(v[q].x * a, v[q].y * a);
+      store_spec<PL>(Hs + (long long)(i * J + j) * M, v, t);
+    }
   }
 
-  const long long yo = b.out_off[u];
-  const long long ys = b.out_stride[u];
+  const long long yo = uni64(b.out_off[u]);
+  const long long ys = uni(b.out_stride[u]);
+  // With 16 points per thread there is room to prefetch: the RIR spectra of
+  // a source are requested when its iteration starts and the next source's
+  // block while the current one is transformed, so the loads overlap the FFT.
+  constexpr bool kPrefetch = P <= 16;
   for (int bk = 0; bk < nb; ++bk) {
     const int base = bk * B;
     const int nvalid = min(B, Nx - base);
@@ -422,22 +456,48 @@ __device__ void mix_utterance(const MixArgs& A, int u, const Sched& S, cf* lds, 
 #pragma unroll
         for (int q = 0; q < P; ++q) Y1[q] = mk(0.f, 0.f);
       }
+      auto fetch_x = [&](cf* dst, int i) __attribute__((always_inline)) {
+        if (g == 0) load_real<PL>(dst, A.x + uni64(b.src_off[(long long)u * NS + i]) + base, nvalid, t);
+        else load_spec<PL>(dst, Xs + (long long)i * M, t);
+      };
+      cf Xn[kPrefetch ? P : 1];
+      if constexpr (kPrefetch) fetch_x(Xn, 0);
       for (int i = 0; i < I; ++i) {
         cf X[P];
-        if (g == 0) {
-          load_real<PL>(X, A.x + b.src_off[(long long)u * NS + i] + base, nvalid, t);
-          Fft<PL>::forward(X, lds, tw, t);
-          Fft<PL>::post(X, tw, t);
-          if (ng > 1) store_spec<PL>(Xs + (long long)i * M, X, t);
-        } else {
-          load_spec<PL>(X, Xs + (long long)i * M, t);
-        }
         const cf* H0 = Hs + (long long)(i * J + j0) * M;
-        if constexpr (JG == 2) {
-          if (two) mac2<PL>(Y0, Y1, H0, H0 + M, X, t);
-          else mac<PL>(Y0, H0, X, t);
+        if constexpr (kPrefetch) {
+          cf Hp0[P], Hp1[JG == 2 ? P : 1];
+          load_spec<PL>(Hp0, H0, t);
+          if constexpr (JG == 2) {
+            if (two) load_spec<PL>(Hp1, H0 + M, t);
+          }
+#pragma unroll
+          for (int q = 0; q < P; ++q) X[q] = Xn[q];
+          if (i + 1 < I) fetch_x(Xn, i + 1);
+          if (g == 0) {
+            Fft<PL>::forward(X, lds, tw, t);
+            Fft<PL>::post(X, tw, t);
+            if (ng > 1) store_spec<PL>(Xs + (long long)i * M, X, t);
+          }
+          mac_regs<PL>(Y0, Hp0, X, t);
+          if constexpr (JG == 2) {
+            if (two) mac_regs<PL>(Y1, Hp1, X, t);
+          }
         } else {
-          mac<PL>(Y0, H0, X, t);
+          if (g == 0) {
+            load_real<PL>(X, A.x + uni64(b.src_off[(long long)u * NS + i]) + base, nvalid, t);
+            Fft<PL>::forward(X, lds, tw, t);
+            Fft<PL>::post(X, tw, t);
+            if (ng > 1) store_spec<PL>(Xs + (long long)i * M, X, t);
+          } else {
+            load_spec<PL>(X, Xs + (long long)i * M, t);
+          }
+          if constexpr (JG == 2) {
+            if (two) mac2<PL>(Y0, Y1, H0, H0 + M, X, t);
+            else mac<PL>(Y0, H0, X, t);
+          } else {
+            mac<PL>(Y0, H0, X, t);
+          }
         }
       }
       emit<PL>(Y0, lds, tw, A.y + yo + (long long)j0 * ys + base, lim, carry, t);
@@ -484,14 +544,19 @@ __device__ __forceinline__ void dispatch_plan(int l2, F&& f) {
   } else if constexpr (T == 256) {
     f(Plan16K{});
   } else {
-    f(Plan32K{});
+    if constexpr (kWide16K) {
+      if (l2 == 14) f(Plan16KW{});
+      else f(Plan32K{});
+    } else {
+      f(Plan32K{});
+    }
   }
 }
 
 // Persistent workgroups: pop the next utterance of this family's list until
 // it is exhausted.  MINW is the number of waves per SIMD the register budget
 // is sized for (2 with one mic accumulator, 1 with two).
-template <int T, int JG, int MINW = (JG == 1 ? 2 : 1)>
+template <int T, int JG, int MINW>
 __global__ __launch_bounds__(T, MINW) void mix_kernel(MixArgs A) {
   __shared__ cf lds[FamLds<T>::n];
   __shared__ int s_idx;
@@ -501,11 +566,18 @@ __global__ __launch_bounds__(T, MINW) void mix_kernel(MixArgs A) {
     __syncthreads();
     if (t == 0) s_idx = atomicAdd(&A.hdr->counter[A.fam], 1);
     __syncthreads();
-    const int idx = s_idx;
+    // Work-item values are uniform across the workgroup; saying so keeps the
+    // descriptor loads scalar and the buffer resources in scalar registers.
+    const int idx = __builtin_amdgcn_readfirstlane(s_idx);
     if (idx >= A.hdr->count[A.fam]) break;
-    const int u = A.list[(long long)A.fam * A.b.U + idx];
-    const Sched S = A.sched[u];
-    dispatch_plan<T>(S.log2n, [&](auto pl) {
+    const int u = __builtin_amdgcn_readfirstlane(A.list[(long long)A.fam * A.b.U + idx]);
+    Sched S = A.sched[u];
+    S.log2n = __builtin_amdgcn_readfirstlane(S.log2n);
+    S.hop = __builtin_amdgcn_readfirstlane(S.hop);
+    S.nb = __builtin_amdgcn_readfirstlane(S.nb);
+    S.tu = __builtin_amdgcn_readfirstlane(S.tu);
+    S.lmax = __builtin_amdgcn_readfirstlane(S.lmax);
+    dispatch_plan<T>(S.log2n, [&](auto pl) __attribute__((always_inline)) {
       using PL = decltype(pl);
       mix_utterance<PL, JG>(A, u, S, lds, slot, t);
     });
@@ -562,7 +634,7 @@ __global__ __launch_bounds__(PL::T) void rfft_kernel(const float* __restrict__ x
   __shared__ cf lds[PL::LDS];
   const int t = threadIdx.x;
   const long long sig = blockIdx.x;
-  const cf* tw = plan_tw<PL>();
+  const TwBase tw = Fft<PL>::bases(plan_tw<PL>(), t);
   cf v[PL::P];
   load_real<PL>(v, x + sig * PL::N, PL::N, t);
   Fft<PL>::forward(v, lds, tw, t);
@@ -584,7 +656,7 @@ __global__ __launch_bounds__(PL::T) void irfft_kernel(const float* __restrict__ 
   __shared__ cf lds[PL::LDS];
   const int t = threadIdx.x;
   const long long sig = blockIdx.x;
-  const cf* tw = plan_tw<PL>();
+  const TwBase tw = Fft<PL>::bases(plan_tw<PL>(), t);
   const cf* in = reinterpret_cast<const cf*>(spec) + sig * (PL::M + 1);
   cf v[PL::P];
 #pragma unroll
@@ -637,6 +709,7 @@ void fill_twiddles(float* out) {
   fill_plan<Plan8K>(tw, kTwOff[4]);
   fill_plan<Plan16K>(tw, kTwOff[5]);
   fill_plan<Plan32K>(tw, kTwOff[6]);
+  fill_plan<Plan16KW>(tw, kTwOff16W);
   std::memcpy(out, tw.data(), sizeof(float2) * kTwTotal);
 }
 
@@ -669,6 +742,10 @@ using namespace rsim;
 namespace {
 
 constexpr int kFamT[kNumFam] = {32, 64, 128, 256, 512};
+// Kernel variants: (mic accumulators JG, waves per SIMD the registers are
+// sized for).  0: JG 1 / 2 waves, 1: JG 2 / 1 wave, 2: JG 2 / 2 waves.
+constexpr int kNumVar = 3;
+constexpr int kVarJG[kNumVar] = {1, 2, 2};
 constexpr int kFamMaxM[kNumFam] = {256, 2048, 4096, 8192, 16384};
 constexpr int kFamOrder[kNumFam] = {3, 4, 2, 1, 0};  // launch order: the common sizes first
 constexpr int kMaxDev = 64;
@@ -676,7 +753,7 @@ constexpr int kMaxDev = 64;
 struct DevState {
   bool init = false;
   int cus = 0;
-  int occ[2][kNumFam] = {{0, 0, 0, 0, 0}, {0, 0, 0, 0, 0}};  // [jg-1][family]
+  int occ[kNumVar][kNumFam] = {};  // [variant][family]
 };
 
 std::mutex g_mu;
@@ -688,30 +765,35 @@ struct Retired {
 };
 std::deque<Retired> g_retired;
 
-template <int JG>
-const void* mix_kernel_ptr_jg(int fam) {
+
+template <int JG, int MINW>
+const void* mix_kernel_ptr_v(int fam) {
   switch (fam) {
-    case 0: return reinterpret_cast<const void*>(&mix_kernel<32, JG>);
-    case 1: return reinterpret_cast<const void*>(&mix_kernel<64, JG>);
-    case 2: return reinterpret_cast<const void*>(&mix_kernel<128, JG>);
-    case 3: return reinterpret_cast<const void*>(&mix_kernel<256, JG>);
-    default: return reinterpret_cast<const void*>(&mix_kernel<512, JG>);
+    case 0: return reinterpret_cast<const void*>(&mix_kernel<32, JG, MINW>);
+    case 1: return reinterpret_cast<const void*>(&mix_kernel<64, JG, MINW>);
+    case 2: return reinterpret_cast<const void*>(&mix_kernel<128, JG, MINW>);
+    case 3: return reinterpret_cast<const void*>(&mix_kernel<256, JG, MINW>);
+    default: return reinterpret_cast<const void*>(&mix_kernel<512, JG, MINW>);
   }
 }
-const void* mix_kernel_ptr(int fam, int jg) {
-  return jg == 2 ? mix_kernel_ptr_jg<2>(fam) : mix_kernel_ptr_jg<1>(fam);
+const void* mix_kernel_ptr(int fam, int var) {
+  switch (var) {
+    case 0: return mix_kernel_ptr_v<1, 2>(fam);
+    case 1: return mix_kernel_ptr_v<2, 1>(fam);
+    default: return mix_kernel_ptr_v<2, 2>(fam);
+  }
 }
 
-// Mic-group size per family: 1 accumulator (two waves per SIMD) unless the
-// RSIM_MIC_GROUP environment variable asks for 2 (one wave per SIMD).
-int g_jg = 0;
-int mic_group() {
-  if (g_jg == 0) {
-    const char* e = std::getenv("RSIM_MIC_GROUP");
-    g_jg = (e && e[0] == '2') ? 2 : 1;
+// Variant used by every launch; RSIM_VARIANT (0, 1, 2) overrides it.
+int g_var = -1;
+int kernel_variant() {
+  if (g_var < 0) {
+    const char* e = std::getenv("RSIM_VARIANT");
+    g_var = (e && e[0] >= '0' && e[0] <= '2') ? e[0] - '0' : 1;
   }
-  return g_jg;
+  return g_var;
 }
+int mic_group() { return kVarJG[kernel_variant()]; }
 
 rsim_status init_locked(int dev) {
   DevState& st = g_dev[dev];
@@ -724,13 +806,13 @@ rsim_status init_locked(int dev) {
   if (hipMemcpyToSymbol(HIP_SYMBOL(g_status), &zero, sizeof(int)) != hipSuccess) return RSIM_EDEVICE;
   if (hipDeviceGetAttribute(&st.cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
     return RSIM_EDEVICE;
-  for (int jg = 1; jg <= 2; ++jg)
+  for (int v = 0; v < kNumVar; ++v)
     for (int f = 0; f < kNumFam; ++f) {
       int n = 0;
-      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, mix_kernel_ptr(f, jg), kFamT[f], 0) !=
+      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, mix_kernel_ptr(f, v), kFamT[f], 0) !=
           hipSuccess)
         return RSIM_EDEVICE;
-      st.occ[jg - 1][f] = n > 0 ? n : 1;
+      st.occ[v][f] = n > 0 ? n : 1;
     }
   if (hipDeviceSynchronize() != hipSuccess) return RSIM_EDEVICE;
   st.init = true;
@@ -824,7 +906,7 @@ WsLayout layout(const rsim_batch* b, const TuneDev& td, bool backward, const Dev
     // Without a device (size queries on a host) assume 256 CUs and the
     // largest occupancy used; the grid is capped at 8 workgroups per CU.
     const int cus = st.cus > 0 ? st.cus : 256;
-    int occ = st.init ? st.occ[jg - 1][f] : 8;
+    int occ = st.init ? st.occ[kernel_variant()][f] : 8;
     if (occ > 8) occ = 8;
     long long g = (long long)cus * occ;
     if (g > (long long)U) g = (long long)U;
@@ -950,7 +1032,7 @@ rsim_status launch_mix(const rsim_batch* b, const BatchDev& bd, const TuneDev& t
     A.scratch = scratch;
     A.slot_cf = L.slot_cf[f];
     void* args[] = {&A};
-    if (hipLaunchKernel(mix_kernel_ptr(f, mic_group()), dim3(L.grid[f]), dim3(kFamT[f]), args, 0, s) !=
+    if (hipLaunchKernel(mix_kernel_ptr(f, kernel_variant()), dim3(L.grid[f]), dim3(kFamT[f]), args, 0, s) !=
         hipSuccess)
       return RSIM_EDEVICE;
   }

@@ -266,6 +266,43 @@ class DeviceBatch:
         return torch.empty(max(self.y_len, 1), dtype=torch.float32, device=self.device)
 
 
+def _one(db: DeviceBatch, u: int) -> RsimBatch:
+    """Descriptor of utterance u alone (views into db's device arrays)."""
+    S, J = db.S, db.J
+    s = db.struct()
+    s.n_utt = 1
+    s.n_src += 4 * u
+    s.src_len += 4 * u
+    s.src_off += 8 * u * S
+    s.rir_off += 8 * u * S * J
+    s.rir_len0 += 4 * u * S * J
+    s.rir_len += 4 * u * S * J
+    s.out_off += 8 * u
+    s.out_stride += 4 * u
+    s.out_len += 4 * u
+    s.order = None
+    if db.fft_log2n is not None:
+        s.fft_log2n += 4 * u
+    if db.hop is not None:
+        s.hop += 4 * u
+    return s
+
+
+def single_workspace_bytes(db: DeviceBatch, tune: Optional[RsimTune] = None) -> int:
+    s = _one(db, 0)
+    return max(1, int(_lib().rsim_mix_workspace_bytes(ctypes.byref(s), ctypes.byref(tune) if tune else None, 0)))
+
+
+def simulate_one(db: DeviceBatch, u: int, alpha, eta_db: float, y, ws, tune: Optional[RsimTune] = None,
+                 stream=None):
+    """Cut + mix of utterance u alone (the plain per-utterance path)."""
+    s = _one(db, u)
+    a = _ptr(alpha) + 4 * u * db.S * db.J
+    _check(_lib().rsim_simulate(ctypes.byref(s), _ptr(db.x), _ptr(db.h), a, float(eta_db), s.rir_len,
+                                _ptr(y), _ptr(ws), int(ws.numel()), ctypes.byref(tune) if tune else None,
+                                0, _stream(stream)), "rsim_simulate")
+
+
 def truncate_batch(db: DeviceBatch, eta_db: float, h=None, stream=None):
     """Cut every RIR slot of the batch; writes db.n_c and db.rir_len."""
     _check(_lib().rsim_truncate_rir(_ptr(db.h if h is None else h), db.h_len, _ptr(db.rir_off),

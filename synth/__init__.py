@@ -242,7 +242,7 @@ def make_utterances(cid: int, epoch: int, n_utt: int, len_s: tuple, max_noise: i
                     sources_seed_epoch: int = 0) -> Batch:
     """Random utterances.  Utterance lengths, source counts and source signals
     come from the epoch-0 stream (the dataset), while RIRs, T60s and SNRs come
-    from the `epoch` stream (a fresh room every epoch)."""
+    from the `epoch` stream (a fresh room every epoch, see `reroom`)."""
     drng = rng_for(cid, sources_seed_epoch)
     if lengths is None:
         lengths = np.round(drng.uniform(len_s[0], len_s[1], n_utt) * FS).astype(np.int64)
@@ -253,38 +253,76 @@ def make_utterances(cid: int, epoch: int, n_utt: int, len_s: tuple, max_noise: i
     # random offsets: the same statistics as drawing each one afresh, at a
     # fraction of the cost for thousands of utterances.
     pool_len = max(POOL_LEN, int(np.max(lengths)) + 1)
-    pools = {"speech": speech_like(drng, pool_len), "white": white_noise(drng, pool_len),
-             "pink": pink_noise(drng, pool_len)}
-    sources = []
+    pools = [speech_like(drng, pool_len), white_noise(drng, pool_len), pink_noise(drng, pool_len)]
+    S = int(max(1, np.max(n_src)))
+    total = int(np.sum(lengths * n_src))
+    x = np.empty(total, np.float32)
+    src_off = np.zeros(n_utt * S, np.int64)
+    o = 0
     for u in range(n_utt):
         n = int(lengths[u])
-        off = drng.integers(0, pool_len - n + 1, int(n_src[u]))
-        s = [pools["speech"][off[0]:off[0] + n]]
-        for i in range(1, int(n_src[u])):
-            kind = "white" if kinds[u, i] == 0 else "pink"
-            s.append(pools[kind][off[i]:off[i] + n])
-        sources.append(s)
-    return attach_rooms(cid, epoch, sources, n_mic, t60_range, max_taps)
+        offs = drng.integers(0, pool_len - n + 1, int(n_src[u]))
+        for i in range(int(n_src[u])):
+            pool = pools[0] if i == 0 else pools[1 + int(kinds[u, i])]
+            x[o:o + n] = pool[offs[i]:offs[i] + n]
+            src_off[u * S + i] = o
+            o += n
+    base = Batch(n_utt, n_mic, S, np.asarray(n_src, np.int32), np.asarray(lengths, np.int32), src_off,
+                 np.zeros(0, np.int64), np.zeros(0, np.int32), np.zeros(n_utt, np.int64),
+                 np.zeros(n_utt, np.int32), x, np.zeros(0, np.float32), np.zeros(n_utt * S),
+                 np.zeros(0), 0)
+    return reroom(base, cid, epoch, t60_range, max_taps)
 
 
-def attach_rooms(cid: int, epoch: int, sources, n_mic: int, t60_range: tuple,
-                 max_taps: Optional[int] = None) -> Batch:
-    """Draw a fresh room (RIRs, T60s, SNRs) for each utterance of `sources`."""
+def reroom(base: Batch, cid: int, epoch: int, t60_range: tuple,
+           max_taps: Optional[int] = None) -> Batch:
+    """The utterances of `base` in a fresh room for `epoch`: one T60 per
+    utterance (every RIR of it has L0 = ceil(T60 fs) taps, capped at
+    max_taps), a direct-path delay U{20..400} per RIR, Gaussian noise decaying
+    by 60 dB over T60 (the `rir` recipe, drawn for all RIRs at once) and an SNR
+    U(0, 30) dB per noise source.  Sources are shared with `base`."""
     rrng = rng_for(cid, 10_000 + epoch)
-    rirs, snrs, t60s = [], [], []
-    for s in sources:
-        I = len(s)
-        t60 = rrng.uniform(t60_range[0], t60_range[1])
-        L0 = int(math.ceil(t60 * FS))
-        if max_taps is not None:
-            L0 = min(L0, max_taps)
-        rows = []
-        for i in range(I):
-            rows.append([rir(rrng, L0, t60, int(rrng.integers(20, 401))) for _ in range(n_mic)])
-        rirs.append(rows)
-        snrs.append([0.0] + list(rrng.uniform(0.0, 30.0, I - 1)))
-        t60s.append([[t60] * n_mic for _ in range(I)])
-    return pack(sources, rirs, snrs, n_mic, t60s)
+    U, S, J = base.n_utt, base.max_src, base.n_mic
+    n_src = base.n_src.astype(np.int64)
+    t60 = rrng.uniform(t60_range[0], t60_range[1], U)
+    L0 = np.ceil(t60 * FS).astype(np.int64)
+    if max_taps is not None:
+        L0 = np.minimum(L0, max_taps)
+    slot_u = np.repeat(np.arange(U), S * J)
+    slot_i = np.tile(np.repeat(np.arange(S), J), U)
+    used = slot_i < n_src[slot_u]
+    slot_len = np.where(used, L0[slot_u], 0).astype(np.int64)
+    rir_off = np.concatenate([[0], np.cumsum(slot_len)[:-1]]).astype(np.int64)
+    ur = np.nonzero(used)[0]
+    lens = slot_len[ur]
+    delay = np.minimum(rrng.integers(20, 401, ur.size), lens - 1)
+    k = np.arange(U * S)
+    noise = (k % S >= 1) & (k % S < np.repeat(n_src, S))
+    snr = np.zeros(U * S)
+    snr[noise] = rrng.uniform(0.0, 30.0, int(np.sum(noise)))
+    total = int(np.sum(lens))
+    h = rrng.standard_normal(total, dtype=np.float32)
+    starts = np.concatenate([[0], np.cumsum(lens)[:-1]]).astype(np.int64)
+    # Every RIR of an utterance shares its T60: one decay curve per utterance,
+    # shifted to each RIR's direct-path delay.
+    env_u = {}
+    for k_, r in enumerate(ur):
+        u = int(slot_u[r])
+        L = int(lens[k_])
+        if u not in env_u:
+            rate = 3.0 * math.log(10.0) / (t60[u] * FS)
+            env_u[u] = (0.25 * np.exp(-rate * np.arange(L, dtype=np.float64))).astype(np.float32)
+        s0, d = int(starts[k_]), int(delay[k_])
+        seg = h[s0:s0 + L]
+        seg[:d] = 0.0
+        seg[d] = 1.0
+        seg[d + 1:] *= env_u[u][1:L - d]
+    nx = base.src_len.astype(np.int64)
+    stride = np.where((nx > 0) & (n_src > 0), nx + L0 - 1, 0)
+    out_off = np.concatenate([[0], np.cumsum(J * stride)[:-1]]).astype(np.int64)
+    return Batch(U, J, S, base.n_src, base.src_len, base.src_off, rir_off, slot_len.astype(np.int32),
+                 out_off, stride.astype(np.int32), base.x, h, snr, np.where(used, t60[slot_u], 0.0),
+                 int(np.sum(J * stride)))
 
 
 def make_config2(epoch: int = 0, n_utt: int = 2048) -> Batch:
