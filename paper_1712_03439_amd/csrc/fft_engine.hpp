@@ -109,11 +109,11 @@ __device__ __forceinline__ cf cmacc(cf acc, cf a, cf b) {
 
 // ------------------------------------------------------------ compile-time loops
 template <class F, int... Is>
-__device__ __forceinline__ void sfor_impl(F&& f, std::integer_sequence<int, Is...>) {
+__host__ __device__ __forceinline__ void sfor_impl(F&& f, std::integer_sequence<int, Is...>) {
   (f(std::integral_constant<int, Is>{}), ...);
 }
 template <int N, class F>
-__device__ __forceinline__ void sfor(F&& f) {
+__host__ __device__ __forceinline__ void sfor(F&& f) {
   sfor_impl(f, std::make_integer_sequence<int, N>{});
 }
 
@@ -310,29 +310,100 @@ struct Plan {
   static constexpr int TW_SIZE = POST_OFF + RL * (T + 1);
 };
 
-using Plan512 = Plan<256, 32, 8, 8, 4>;
-using Plan1K = Plan<512, 64, 8, 4, 4, 4>;
-using Plan2K = Plan<1024, 64, 16, 8, 8>;
-using Plan4K = Plan<2048, 64, 32, 4, 16>;
-using Plan8K = Plan<4096, 128, 32, 8, 16>;
-using Plan16K = Plan<8192, 256, 32, 16, 16>;
-using Plan16KW = Plan<8192, 512, 16, 8, 8, 8>;  // 16 points per thread: room to prefetch
-using Plan32K = Plan<16384, 512, 32, 32, 16>;
+// The plan of each FFT size N = 2^L2, L2 = 9..15.  From N = 2048 on every
+// plan holds 16 points per thread (T = N/32 threads), which leaves registers
+// for prefetching the next operands while a transform runs.
+constexpr int kMinL2 = 9, kMaxL2 = 15, kNumSizes = kMaxL2 - kMinL2 + 1;
+template <int L2>
+struct PlanFor;
+template <>
+struct PlanFor<9> {
+  using type = Plan<256, 32, 8, 8, 4>;
+};
+template <>
+struct PlanFor<10> {
+  using type = Plan<512, 64, 8, 4, 4, 4>;
+};
+template <>
+struct PlanFor<11> {
+  using type = Plan<1024, 64, 16, 8, 8>;
+};
+template <>
+struct PlanFor<12> {
+  using type = Plan<2048, 128, 16, 16, 8>;
+};
+template <>
+struct PlanFor<13> {
+  using type = Plan<4096, 256, 16, 8, 4, 8>;
+};
+template <>
+struct PlanFor<14> {
+  using type = Plan<8192, 512, 16, 8, 8, 8>;
+};
+template <>
+struct PlanFor<15> {
+  using type = Plan<16384, 1024, 16, 16, 8, 8>;
+};
+template <int L2>
+using PlanOf = typename PlanFor<L2>::type;
 
-// Offsets of each plan's table inside the one twiddle array (log2 N = 9..15).
-constexpr int kTwOff[8] = {
-    0,
-    Plan512::TW_SIZE,
-    Plan512::TW_SIZE + Plan1K::TW_SIZE,
-    Plan512::TW_SIZE + Plan1K::TW_SIZE + Plan2K::TW_SIZE,
-    Plan512::TW_SIZE + Plan1K::TW_SIZE + Plan2K::TW_SIZE + Plan4K::TW_SIZE,
-    Plan512::TW_SIZE + Plan1K::TW_SIZE + Plan2K::TW_SIZE + Plan4K::TW_SIZE + Plan8K::TW_SIZE,
-    Plan512::TW_SIZE + Plan1K::TW_SIZE + Plan2K::TW_SIZE + Plan4K::TW_SIZE + Plan8K::TW_SIZE +
-        Plan16K::TW_SIZE,
-    Plan512::TW_SIZE + Plan1K::TW_SIZE + Plan2K::TW_SIZE + Plan4K::TW_SIZE + Plan8K::TW_SIZE +
-        Plan16K::TW_SIZE + Plan32K::TW_SIZE};
-constexpr int kTwOff16W = kTwOff[7];
-constexpr int kTwTotal = kTwOff16W + Plan16KW::TW_SIZE;
+// Offset of each plan's table inside the one twiddle array.
+template <int L2>
+constexpr int tw_off() {
+  if constexpr (L2 == kMinL2) return 0;
+  else return tw_off<L2 - 1>() + PlanOf<L2 - 1>::TW_SIZE;
+}
+constexpr int kTwTotal = tw_off<kMaxL2 + 1>();
+
+// Threads of the plan of size 2^l2 (0 outside 9..15).
+__host__ __device__ constexpr int plan_threads(int l2) {
+  return l2 == 9    ? PlanOf<9>::T
+         : l2 == 10 ? PlanOf<10>::T
+         : l2 == 11 ? PlanOf<11>::T
+         : l2 == 12 ? PlanOf<12>::T
+         : l2 == 13 ? PlanOf<13>::T
+         : l2 == 14 ? PlanOf<14>::T
+         : l2 == 15 ? PlanOf<15>::T
+                    : 0;
+}
+
+// Calls f(PlanOf<L2>{}) for the runtime size l2 among the plans with T
+// threads; with a single such plan the size is not tested.
+template <int T, int L2 = kMinL2>
+constexpr int plans_with_threads() {
+  if constexpr (L2 > kMaxL2) return 0;
+  else return (PlanOf<L2>::T == T ? 1 : 0) + plans_with_threads<T, L2 + 1>();
+}
+template <int T, int L2 = kMinL2, class F>
+__device__ __forceinline__ void dispatch_plan(int l2, F&& f) {
+  if constexpr (L2 <= kMaxL2) {
+    if constexpr (PlanOf<L2>::T == T) {
+      if (plans_with_threads<T>() == 1 || l2 == L2) {
+        f(PlanOf<L2>{});
+        return;
+      }
+    }
+    dispatch_plan<T, L2 + 1>(l2, f);
+  }
+}
+
+// Largest M and LDS footprint over the plans with T threads.
+template <int T, int L2 = kMinL2>
+constexpr int max_m_with_threads() {
+  if constexpr (L2 > kMaxL2) return 0;
+  else {
+    constexpr int rest = max_m_with_threads<T, L2 + 1>();
+    return PlanOf<L2>::T == T && PlanOf<L2>::M > rest ? PlanOf<L2>::M : rest;
+  }
+}
+template <int T, int L2 = kMinL2>
+constexpr int max_lds_with_threads() {
+  if constexpr (L2 > kMaxL2) return 0;
+  else {
+    constexpr int rest = max_lds_with_threads<T, L2 + 1>();
+    return PlanOf<L2>::T == T && PlanOf<L2>::LDS > rest ? PlanOf<L2>::LDS : rest;
+  }
+}
 
 template <class PL>
 __device__ __forceinline__ int pad(int i) {

@@ -12,17 +12,12 @@ namespace rsim {
 extern __device__ cf g_tw[kTwTotal];
 extern __device__ int g_status;
 
-constexpr int kNumFam = 5;  // workgroup sizes 32, 64, 128, 256, 512
-
-// N = 16384 runs either with 256 threads x 32 points or with 512 threads x
-// 16 points (fewer registers per thread, which leaves room for prefetching).
-#ifndef RSIM_WIDE16K
-#define RSIM_WIDE16K 0
-#endif
-constexpr bool kWide16K = RSIM_WIDE16K != 0;
+// Kernel families, one per workgroup size T = 32 << f (f = 0..5): every
+// FFT size runs in the family of its plan's thread count.
+constexpr int kNumFam = 6;
 
 __host__ __device__ constexpr int family_of_log2n(int l2) {
-  return l2 == 9 ? 0 : l2 <= 12 ? 1 : l2 == 13 ? 2 : l2 == 14 ? (kWide16K ? 4 : 3) : 4;
+  return ilog2c(plan_threads(l2)) - 5;
 }
 
 // Per-utterance plan written by the schedule kernel.

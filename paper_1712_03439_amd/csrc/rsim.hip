@@ -68,10 +68,26 @@ __device__ __forceinline__ double wave_sum_d(double v) {
 constexpr int kTruncThreads = 256;
 constexpr int kTruncChunk = 1024;
 
-__global__ __launch_bounds__(kTruncThreads) void truncate_kernel(
-    const float* __restrict__ h, long long h_len, const long long* __restrict__ off,
-    const int* __restrict__ len0, int n_rir, float s, int* __restrict__ n_c,
-    int* __restrict__ len) {
+struct TruncArgs {
+  const float* h;
+  long long h_len;
+  const long long* off;
+  const int* len0;
+  int n_rir;
+  float s;     // fl32(10^(-eta/10)), 0 for eta = inf
+  int* n_c;    // may be null
+  int* len;
+};
+
+__global__ __launch_bounds__(kTruncThreads) void truncate_kernel(TruncArgs A) {
+  const float* __restrict__ h = A.h;
+  const long long h_len = A.h_len;
+  const long long* __restrict__ off = A.off;
+  const int* __restrict__ len0 = A.len0;
+  const int n_rir = A.n_rir;
+  const float s = A.s;
+  int* __restrict__ n_c = A.n_c;
+  int* __restrict__ len = A.len;
   __shared__ float s_f[4];
   __shared__ int s_i[4];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
@@ -222,10 +238,20 @@ __device__ Sched plan_utterance(const BatchDev& b, const TuneDev& tune, int u, i
 // family's list, keeping the caller's order (a stable compaction per family).
 constexpr int kSchedThreads = 1024;
 
-__global__ __launch_bounds__(kSchedThreads) void schedule_kernel(BatchDev b, TuneDev tune,
-                                                                 Sched* __restrict__ sched,
-                                                                 int* __restrict__ lists,
-                                                                 WsHeader* hdr) {
+struct SchedArgs {
+  BatchDev b;
+  TuneDev tune;
+  Sched* sched;
+  int* lists;
+  WsHeader* hdr;
+};
+
+__global__ __launch_bounds__(kSchedThreads) void schedule_kernel(SchedArgs A) {
+  const BatchDev& b = A.b;
+  const TuneDev& tune = A.tune;
+  Sched* __restrict__ sched = A.sched;
+  int* __restrict__ lists = A.lists;
+  WsHeader* hdr = A.hdr;
   __shared__ int s_wcnt[kNumFam][kSchedThreads / 64];
   __shared__ int s_base[kNumFam];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
@@ -400,14 +426,13 @@ __device__ __forceinline__ void emit(cf* Yv, cf* lds, const TwBase& tw, float* _
 
 template <class PL>
 __device__ __forceinline__ const cf* plan_tw() {
-  if constexpr (std::is_same<PL, Plan16KW>::value) return g_tw + kTwOff16W;
-  return g_tw + kTwOff[ilog2c(PL::N) - 9];
+  return g_tw + tw_off<ilog2c(PL::N)>();
 }
 
 // One utterance: RIR spectra, then the blocks.  Mics are processed in groups
 // of JG (1 or 2) accumulators; when J > JG the source spectra of the current
 // block are kept in the workgroup's scratch for the later mic groups.
-template <class PL, int JG>
+template <class PL, int JG, int MINW>
 __device__ __forceinline__ void mix_utterance(const MixArgs& A, int u, const Sched& S, cf* lds, cf* slot, int t) {
   constexpr int P = PL::P, M = PL::M;
   const TwBase tw = Fft<PL>::bases(plan_tw<PL>(), t);
@@ -437,10 +462,13 @@ __device__ __forceinline__ void mix_utterance(const MixArgs& A, int u, const Sch
 
   const long long yo = uni64(b.out_off[u]);
   const long long ys = uni(b.out_stride[u]);
-  // With 16 points per thread there is room to prefetch: the RIR spectra of
-  // a source are requested when its iteration starts and the next source's
-  // block while the current one is transformed, so the loads overlap the FFT.
-  constexpr bool kPrefetch = P <= 16;
+  // When the register budget allows (16 points per thread and few enough
+  // waves per SIMD), the RIR spectra of a source are requested when its
+  // iteration starts and the next source's block while the current one is
+  // transformed, so the loads overlap the FFT.  The live set is then about
+  // (3 + 2 JG) arrays of P complex values.
+  constexpr int kWavesPerSimd = MINW > PL::T / 256 ? MINW : PL::T / 256;
+  constexpr bool kPrefetch = P <= 16 && (3 + 2 * JG) * 2 * P <= 512 / kWavesPerSimd;
   for (int bk = 0; bk < nb; ++bk) {
     const int base = bk * B;
     const int nvalid = min(B, Nx - base);
@@ -508,57 +536,12 @@ __device__ __forceinline__ void mix_utterance(const MixArgs& A, int u, const Sch
   }
 }
 
-template <int T>
-struct FamLds;
-template <>
-struct FamLds<32> {
-  static constexpr int n = Plan512::LDS;
-};
-template <>
-struct FamLds<64> {
-  static constexpr int n = Plan4K::LDS > Plan2K::LDS ? Plan4K::LDS : Plan2K::LDS;
-};
-template <>
-struct FamLds<128> {
-  static constexpr int n = Plan8K::LDS;
-};
-template <>
-struct FamLds<256> {
-  static constexpr int n = Plan16K::LDS;
-};
-template <>
-struct FamLds<512> {
-  static constexpr int n = Plan32K::LDS;
-};
-
-template <int T, class F>
-__device__ __forceinline__ void dispatch_plan(int l2, F&& f) {
-  if constexpr (T == 32) {
-    f(Plan512{});
-  } else if constexpr (T == 64) {
-    if (l2 == 10) f(Plan1K{});
-    else if (l2 == 11) f(Plan2K{});
-    else f(Plan4K{});
-  } else if constexpr (T == 128) {
-    f(Plan8K{});
-  } else if constexpr (T == 256) {
-    f(Plan16K{});
-  } else {
-    if constexpr (kWide16K) {
-      if (l2 == 14) f(Plan16KW{});
-      else f(Plan32K{});
-    } else {
-      f(Plan32K{});
-    }
-  }
-}
-
 // Persistent workgroups: pop the next utterance of this family's list until
 // it is exhausted.  MINW is the number of waves per SIMD the register budget
 // is sized for (2 with one mic accumulator, 1 with two).
 template <int T, int JG, int MINW>
 __global__ __launch_bounds__(T, MINW) void mix_kernel(MixArgs A) {
-  __shared__ cf lds[FamLds<T>::n];
+  __shared__ cf lds[max_lds_with_threads<T>()];
   __shared__ int s_idx;
   const int t = threadIdx.x;
   cf* slot = A.scratch + (long long)blockIdx.x * A.slot_cf;
@@ -579,7 +562,7 @@ __global__ __launch_bounds__(T, MINW) void mix_kernel(MixArgs A) {
     S.lmax = __builtin_amdgcn_readfirstlane(S.lmax);
     dispatch_plan<T>(S.log2n, [&](auto pl) __attribute__((always_inline)) {
       using PL = decltype(pl);
-      mix_utterance<PL, JG>(A, u, S, lds, slot, t);
+      mix_utterance<PL, JG, MINW>(A, u, S, lds, slot, t);
     });
   }
 }
@@ -702,14 +685,10 @@ static void fill_plan(std::vector<float2>& tw, int base) {
 
 void fill_twiddles(float* out) {
   std::vector<float2> tw(kTwTotal, make_float2(0.f, 0.f));
-  fill_plan<Plan512>(tw, kTwOff[0]);
-  fill_plan<Plan1K>(tw, kTwOff[1]);
-  fill_plan<Plan2K>(tw, kTwOff[2]);
-  fill_plan<Plan4K>(tw, kTwOff[3]);
-  fill_plan<Plan8K>(tw, kTwOff[4]);
-  fill_plan<Plan16K>(tw, kTwOff[5]);
-  fill_plan<Plan32K>(tw, kTwOff[6]);
-  fill_plan<Plan16KW>(tw, kTwOff16W);
+  sfor<kNumSizes>([&](auto c) {
+    constexpr int l2 = kMinL2 + decltype(c)::value;
+    fill_plan<PlanOf<l2>>(tw, tw_off<l2>());
+  });
   std::memcpy(out, tw.data(), sizeof(float2) * kTwTotal);
 }
 
@@ -741,19 +720,27 @@ using namespace rsim;
 
 namespace {
 
-constexpr int kFamT[kNumFam] = {32, 64, 128, 256, 512};
+constexpr int kFamT[kNumFam] = {32, 64, 128, 256, 512, 1024};
 // Kernel variants: (mic accumulators JG, waves per SIMD the registers are
-// sized for).  0: JG 1 / 2 waves, 1: JG 2 / 1 wave, 2: JG 2 / 2 waves.
-constexpr int kNumVar = 3;
-constexpr int kVarJG[kNumVar] = {1, 2, 2};
-constexpr int kFamMaxM[kNumFam] = {256, 2048, 4096, 8192, 16384};
-constexpr int kFamOrder[kNumFam] = {3, 4, 2, 1, 0};  // launch order: the common sizes first
+// sized for).  0: JG 1 / 2 waves, 1: JG 2 / 1 wave, 2: JG 2 / 2 waves,
+// 3: JG 1 / 4 waves.
+constexpr int kNumVar = 4;
+constexpr int kVarJG[kNumVar] = {1, 2, 2, 1};
+constexpr int kFamMaxM[kNumFam] = {max_m_with_threads<32>(),  max_m_with_threads<64>(),
+                                   max_m_with_threads<128>(), max_m_with_threads<256>(),
+                                   max_m_with_threads<512>(), max_m_with_threads<1024>()};
+constexpr int kFamOrder[kNumFam] = {4, 5, 3, 2, 1, 0};  // launch order: the common sizes first
 constexpr int kMaxDev = 64;
 
 struct DevState {
   bool init = false;
   int cus = 0;
   int occ[kNumVar][kNumFam] = {};  // [variant][family]
+  // Side streams (default priority) and events that let the family kernels
+  // of one call run concurrently: the tail of one family overlaps the next.
+  hipStream_t side[kNumFam - 1] = {};
+  hipEvent_t fork = nullptr;
+  hipEvent_t join[kNumFam - 1] = {};
 };
 
 std::mutex g_mu;
@@ -773,23 +760,25 @@ const void* mix_kernel_ptr_v(int fam) {
     case 1: return reinterpret_cast<const void*>(&mix_kernel<64, JG, MINW>);
     case 2: return reinterpret_cast<const void*>(&mix_kernel<128, JG, MINW>);
     case 3: return reinterpret_cast<const void*>(&mix_kernel<256, JG, MINW>);
-    default: return reinterpret_cast<const void*>(&mix_kernel<512, JG, MINW>);
+    case 4: return reinterpret_cast<const void*>(&mix_kernel<512, JG, MINW>);
+    default: return reinterpret_cast<const void*>(&mix_kernel<1024, JG, MINW>);
   }
 }
 const void* mix_kernel_ptr(int fam, int var) {
   switch (var) {
     case 0: return mix_kernel_ptr_v<1, 2>(fam);
     case 1: return mix_kernel_ptr_v<2, 1>(fam);
-    default: return mix_kernel_ptr_v<2, 2>(fam);
+    case 2: return mix_kernel_ptr_v<2, 2>(fam);
+    default: return mix_kernel_ptr_v<1, 4>(fam);
   }
 }
 
-// Variant used by every launch; RSIM_VARIANT (0, 1, 2) overrides it.
+// Variant used by every launch; RSIM_VARIANT (0..3) overrides it.
 int g_var = -1;
 int kernel_variant() {
   if (g_var < 0) {
     const char* e = std::getenv("RSIM_VARIANT");
-    g_var = (e && e[0] >= '0' && e[0] <= '2') ? e[0] - '0' : 1;
+    g_var = (e && e[0] >= '0' && e[0] < '0' + kNumVar) ? e[0] - '0' : 1;
   }
   return g_var;
 }
@@ -814,6 +803,14 @@ rsim_status init_locked(int dev) {
         return RSIM_EDEVICE;
       st.occ[v][f] = n > 0 ? n : 1;
     }
+  if (!st.fork) {
+    if (hipEventCreateWithFlags(&st.fork, hipEventDisableTiming) != hipSuccess) return RSIM_EDEVICE;
+    for (int k = 0; k < kNumFam - 1; ++k) {
+      if (hipStreamCreateWithFlags(&st.side[k], hipStreamNonBlocking) != hipSuccess ||
+          hipEventCreateWithFlags(&st.join[k], hipEventDisableTiming) != hipSuccess)
+        return RSIM_EDEVICE;
+    }
+  }
   if (hipDeviceSynchronize() != hipSuccess) return RSIM_EDEVICE;
   st.init = true;
   return RSIM_OK;
@@ -875,6 +872,7 @@ void families_used(const rsim_batch* b, const TuneDev& td, bool used[kNumFam]) {
 
 struct WsLayout {
   size_t hdr, sched, lists, scratch, total;
+  size_t fam_scratch[kNumFam];  // byte offset of each family's slots (families run concurrently)
   long long slot_cf[kNumFam];
   int grid[kNumFam];
 };
@@ -898,7 +896,7 @@ WsLayout layout(const rsim_batch* b, const TuneDev& td, bool backward, const Dev
   families_used(b, td, used);
   const long long S = b->max_src, J = b->n_mic;
   const int jg = mic_group();
-  size_t need = 0;
+  size_t off = L.scratch;
   for (int f = 0; f < kNumFam; ++f) {
     const long long M = kFamMaxM[f];
     const long long spectra = backward ? (2 * S * J + J) : (S * J + (J > jg ? S : 0));
@@ -912,12 +910,10 @@ WsLayout layout(const rsim_batch* b, const TuneDev& td, bool backward, const Dev
     if (g > (long long)U) g = (long long)U;
     if (g < 1) g = 1;
     L.grid[f] = (int)g;
-    if (used[f]) {
-      const size_t bytes = (size_t)g * (size_t)L.slot_cf[f] * sizeof(cf);
-      if (bytes > need) need = bytes;
-    }
+    L.fam_scratch[f] = off;
+    if (used[f]) off += align256((size_t)g * (size_t)L.slot_cf[f] * sizeof(cf));
   }
-  L.total = L.scratch + align256(need);
+  L.total = off;
   return L;
 }
 
@@ -944,53 +940,128 @@ BatchDev to_dev(const rsim_batch* b) {
   return d;
 }
 
+// The kernels of one call, recorded as data so that they can be issued on
+// streams or built into a graph: an optional cut, the schedule, then one
+// persistent kernel per FFT-size family (independent of each other).
+struct Node {
+  const void* fn = nullptr;
+  dim3 grid, block;
+  alignas(16) unsigned char arg[512];
+  void* params[1];
+  template <class A>
+  void set(const void* f, dim3 g, dim3 bl, const A& a) {
+    static_assert(sizeof(A) <= sizeof(arg), "kernel argument block too large");
+    fn = f;
+    grid = g;
+    block = bl;
+    std::memcpy(arg, &a, sizeof(A));
+  }
+  void** p() {
+    params[0] = arg;
+    return params;
+  }
+};
+
+struct CallPlan {
+  bool has_cut = false;
+  Node cut, sched;
+  Node fam[kNumFam];
+  int nf = 0;
+};
+
+bool capturing(hipStream_t s) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (!s) return false;
+  return hipStreamIsCapturing(s, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone;
+}
+
+// Issues the plan on s.  Several families run concurrently on the library's
+// side streams (forked from s after the schedule and joined back into s);
+// when s is being captured by the caller they run one after the other on s.
+rsim_status issue_eager(CallPlan& P, hipStream_t s) {
+  const DevState& st = dev_state();
+  if (P.has_cut && hipLaunchKernel(P.cut.fn, P.cut.grid, P.cut.block, P.cut.p(), 0, s) != hipSuccess)
+    return RSIM_EDEVICE;
+  if (hipLaunchKernel(P.sched.fn, P.sched.grid, P.sched.block, P.sched.p(), 0, s) != hipSuccess)
+    return RSIM_EDEVICE;
+  const bool fork = P.nf > 1 && st.fork && !capturing(s);
+  // The fork/join events are shared device state: serialise their use.
+  std::unique_lock<std::mutex> lk(g_mu, std::defer_lock);
+  if (fork) {
+    lk.lock();
+    if (hipEventRecord(st.fork, s) != hipSuccess) return RSIM_EDEVICE;
+  }
+  for (int k = 0; k < P.nf; ++k) {
+    hipStream_t fs = s;
+    if (fork && k > 0) {
+      fs = st.side[k - 1];
+      if (hipStreamWaitEvent(fs, st.fork, 0) != hipSuccess) return RSIM_EDEVICE;
+    }
+    Node& n = P.fam[k];
+    if (hipLaunchKernel(n.fn, n.grid, n.block, n.p(), 0, fs) != hipSuccess) return RSIM_EDEVICE;
+    if (fork && k > 0) {
+      if (hipEventRecord(st.join[k - 1], fs) != hipSuccess ||
+          hipStreamWaitEvent(s, st.join[k - 1], 0) != hipSuccess)
+        return RSIM_EDEVICE;
+    }
+  }
+  return RSIM_OK;
+}
+
 void gc_retired(bool wait) {
   while (!g_retired.empty()) {
     Retired& r = g_retired.front();
-    if (!wait && hipEventQuery(r.done) != hipSuccess) break;
-    if (wait) (void)hipEventSynchronize(r.done);
+    if (!wait) {
+      const hipError_t q = hipEventQuery(r.done);
+      if (q == hipErrorNotReady) (void)hipGetLastError();  // not an error: leave none behind
+      if (q != hipSuccess) break;
+    } else {
+      (void)hipEventSynchronize(r.done);
+    }
     (void)hipGraphExecDestroy(r.exec);
     (void)hipEventDestroy(r.done);
     g_retired.pop_front();
   }
 }
 
-// Capture helper: runs `body` directly, or captured into a graph that is
-// instantiated and launched on `s`.
-template <class F>
-rsim_status run_maybe_graph(hipStream_t s, int use_graph, F&& body) {
-  if (!use_graph) {
-    rsim_status st = body();
-    if (st != RSIM_OK) return clear_error(st);
-    return hipGetLastError() == hipSuccess ? RSIM_OK : RSIM_EDEVICE;
-  }
-  // The legacy default stream cannot be captured.
-  if (s == nullptr) return RSIM_EINVAL;
-  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-  if (hipStreamIsCapturing(s, &cs) != hipSuccess) return clear_error(RSIM_EDEVICE);
-  if (cs != hipStreamCaptureStatusNone) return RSIM_EINVAL;
-  if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess)
-    return clear_error(RSIM_EDEVICE);
-  rsim_status st = body();
-  hipGraph_t graph = nullptr;
-  const hipError_t e = hipStreamEndCapture(s, &graph);
-  if (st != RSIM_OK || e != hipSuccess || !graph) {
-    if (graph) (void)hipGraphDestroy(graph);
-    return clear_error(st != RSIM_OK ? st : RSIM_EDEVICE);
-  }
+// Builds the plan into a graph (cut -> schedule -> the family kernels as
+// parallel branches), instantiates it and launches it on s.  The graph is
+// built node by node, not captured, so no stream other than s is involved.
+// The executable graph is destroyed once an event recorded after its launch
+// has completed.
+rsim_status issue_graph(CallPlan& P, hipStream_t s) {
+  if (capturing(s)) return RSIM_EINVAL;
+  hipGraph_t g = nullptr;
+  if (hipGraphCreate(&g, 0) != hipSuccess) return RSIM_EDEVICE;
+  auto add = [&](Node& n, const hipGraphNode_t* deps, size_t nd, hipGraphNode_t* out) {
+    hipKernelNodeParams kp;
+    std::memset(&kp, 0, sizeof(kp));
+    kp.func = const_cast<void*>(n.fn);
+    kp.gridDim = n.grid;
+    kp.blockDim = n.block;
+    kp.sharedMemBytes = 0;
+    kp.kernelParams = n.p();
+    kp.extra = nullptr;
+    return hipGraphAddKernelNode(out, g, deps, nd, &kp) == hipSuccess;
+  };
+  hipGraphNode_t cut = nullptr, sch = nullptr, fam = nullptr;
+  bool ok = true;
+  if (P.has_cut) ok = add(P.cut, nullptr, 0, &cut);
+  ok = ok && add(P.sched, P.has_cut ? &cut : nullptr, P.has_cut ? 1 : 0, &sch);
+  for (int k = 0; ok && k < P.nf; ++k) ok = add(P.fam[k], &sch, 1, &fam);
   hipGraphExec_t exec = nullptr;
-  if (hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
-    (void)hipGraphDestroy(graph);
-    return clear_error(RSIM_EDEVICE);
+  ok = ok && hipGraphInstantiate(&exec, g, nullptr, nullptr, 0) == hipSuccess;
+  (void)hipGraphDestroy(g);
+  if (!ok) {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    return RSIM_EDEVICE;
   }
-  (void)hipGraphDestroy(graph);
   if (hipGraphLaunch(exec, s) != hipSuccess) {
     (void)hipGraphExecDestroy(exec);
-    return clear_error(RSIM_EDEVICE);
+    return RSIM_EDEVICE;
   }
   hipEvent_t ev = nullptr;
-  if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess ||
-      hipEventRecord(ev, s) != hipSuccess) {
+  if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess || hipEventRecord(ev, s) != hipSuccess) {
     (void)hipStreamSynchronize(s);
     (void)hipGraphExecDestroy(exec);
     if (ev) (void)hipEventDestroy(ev);
@@ -1003,19 +1074,28 @@ rsim_status run_maybe_graph(hipStream_t s, int use_graph, F&& body) {
   return RSIM_OK;
 }
 
-rsim_status launch_mix(const rsim_batch* b, const BatchDev& bd, const TuneDev& td, const float* x,
-                       const float* h, const float* alpha, float* y, void* ws, hipStream_t s,
-                       int only_fam = -1) {
+rsim_status issue(CallPlan& P, hipStream_t s, int use_graph) {
+  const rsim_status st = use_graph ? issue_graph(P, s) : issue_eager(P, s);
+  if (st != RSIM_OK) return clear_error(st);
+  return hipGetLastError() == hipSuccess ? RSIM_OK : RSIM_EDEVICE;
+}
+
+// Records the schedule and family kernels of a mix into P.
+void plan_mix(CallPlan& P, const rsim_batch* b, const BatchDev& bd, const TuneDev& td, const float* x,
+              const float* h, const float* alpha, float* y, void* ws, int only_fam = -1) {
   const DevState& st = dev_state();
   const WsLayout L = layout(b, td, false, st);
   char* base = static_cast<char*>(ws);
-  WsHeader* hdr = reinterpret_cast<WsHeader*>(base + L.hdr);
-  Sched* sched = reinterpret_cast<Sched*>(base + L.sched);
-  int* lists = reinterpret_cast<int*>(base + L.lists);
-  cf* scratch = reinterpret_cast<cf*>(base + L.scratch);
-  hipLaunchKernelGGL(schedule_kernel, dim3(1), dim3(kSchedThreads), 0, s, bd, td, sched, lists, hdr);
+  SchedArgs SA;
+  SA.b = bd;
+  SA.tune = td;
+  SA.hdr = reinterpret_cast<WsHeader*>(base + L.hdr);
+  SA.sched = reinterpret_cast<Sched*>(base + L.sched);
+  SA.lists = reinterpret_cast<int*>(base + L.lists);
+  P.sched.set(reinterpret_cast<const void*>(&schedule_kernel), dim3(1), dim3(kSchedThreads), SA);
   bool used[kNumFam];
   families_used(b, td, used);
+  P.nf = 0;
   for (int k = 0; k < kNumFam; ++k) {
     const int f = kFamOrder[k];
     if (!used[f] || (only_fam >= 0 && f != only_fam)) continue;
@@ -1025,18 +1105,14 @@ rsim_status launch_mix(const rsim_batch* b, const BatchDev& bd, const TuneDev& t
     A.h = h;
     A.alpha = alpha;
     A.y = y;
-    A.sched = sched;
-    A.list = lists;
-    A.hdr = hdr;
+    A.sched = SA.sched;
+    A.list = SA.lists;
+    A.hdr = SA.hdr;
     A.fam = f;
-    A.scratch = scratch;
+    A.scratch = reinterpret_cast<cf*>(base + L.fam_scratch[f]);
     A.slot_cf = L.slot_cf[f];
-    void* args[] = {&A};
-    if (hipLaunchKernel(mix_kernel_ptr(f, kernel_variant()), dim3(L.grid[f]), dim3(kFamT[f]), args, 0, s) !=
-        hipSuccess)
-      return RSIM_EDEVICE;
+    P.fam[P.nf++].set(mix_kernel_ptr(f, kernel_variant()), dim3(L.grid[f]), dim3(kFamT[f]), A);
   }
-  return RSIM_OK;
 }
 
 bool eta_ok(double eta) { return !std::isnan(eta) && eta >= 0.0; }
@@ -1046,14 +1122,22 @@ float cut_scale(double eta) {
   return (float)std::pow(10.0, -eta / 10.0);
 }
 
-void launch_truncate(const float* h, long long h_len, const int64_t* off, const int32_t* len0,
-                     int n_rir, float s, int32_t* n_c, int32_t* len, hipStream_t stream) {
+void plan_truncate(Node& n, const float* h, long long h_len, const int64_t* off, const int32_t* len0,
+                   int n_rir, float s, int32_t* n_c, int32_t* len) {
   const DevState& st = dev_state();
   int grid = (st.cus > 0 ? st.cus : 256) * 8;
   if (grid > n_rir) grid = n_rir;
   if (grid < 1) grid = 1;
-  hipLaunchKernelGGL(truncate_kernel, dim3(grid), dim3(kTruncThreads), 0, stream, h, h_len,
-                     reinterpret_cast<const long long*>(off), len0, n_rir, s, n_c, len);
+  TruncArgs A;
+  A.h = h;
+  A.h_len = h_len;
+  A.off = reinterpret_cast<const long long*>(off);
+  A.len0 = len0;
+  A.n_rir = n_rir;
+  A.s = s;
+  A.n_c = n_c;
+  A.len = len;
+  n.set(reinterpret_cast<const void*>(&truncate_kernel), dim3(grid), dim3(kTruncThreads), A);
 }
 
 int ilog2_exact(int n) {
@@ -1097,8 +1181,10 @@ rsim_status rsim_truncate_rir(const float* h, int64_t h_len, const int64_t* off,
   if (!h || !off || !len0 || !len) return RSIM_EINVAL;
   rsim_status e = ensure_init(stream);
   if (e != RSIM_OK) return e;
-  launch_truncate(h, h_len, off, len0, n_rir, cut_scale(eta_db), n_c, len, stream);
-  return hipGetLastError() == hipSuccess ? RSIM_OK : RSIM_EDEVICE;
+  Node n;
+  plan_truncate(n, h, h_len, off, len0, n_rir, cut_scale(eta_db), n_c, len);
+  if (hipLaunchKernel(n.fn, n.grid, n.block, n.p(), 0, stream) != hipSuccess) return clear_error(RSIM_EDEVICE);
+  return RSIM_OK;
 }
 
 size_t rsim_mix_workspace_bytes(const rsim_batch* b, const rsim_tune* tune, int32_t backward) {
@@ -1120,8 +1206,9 @@ rsim_status rsim_mix(const rsim_batch* b, const float* x, const float* h, const 
   if (!ws || ws_bytes < L.total) return RSIM_EWORKSPACE;
   if (e != RSIM_OK) return e;
   const BatchDev bd = to_dev(b);
-  return run_maybe_graph(stream, use_graph,
-                         [&]() { return launch_mix(b, bd, td, x, h, alpha, y, ws, stream); });
+  CallPlan P;
+  plan_mix(P, b, bd, td, x, h, alpha, y, ws);
+  return issue(P, stream, use_graph);
 }
 
 rsim_status rsim_simulate(const rsim_batch* b, const float* x, const float* h, const float* alpha,
@@ -1142,10 +1229,11 @@ rsim_status rsim_simulate(const rsim_batch* b, const float* x, const float* h, c
   if (n_rir > 0x7fffffffLL) return RSIM_EINVAL;
   const BatchDev bd = to_dev(&bb);
   const float s = cut_scale(eta_db);
-  return run_maybe_graph(stream, use_graph, [&]() {
-    launch_truncate(h, bb.h_len, bb.rir_off, bb.rir_len0, (int)n_rir, s, nullptr, rir_len_out, stream);
-    return launch_mix(&bb, bd, td, x, h, alpha, y, ws, stream);
-  });
+  CallPlan P;
+  P.has_cut = true;
+  plan_truncate(P.cut, h, bb.h_len, bb.rir_off, bb.rir_len0, (int)n_rir, s, nullptr, rir_len_out);
+  plan_mix(P, &bb, bd, td, x, h, alpha, y, ws);
+  return issue(P, stream, use_graph);
 }
 
 size_t rsim_ola_workspace_bytes(int32_t fft_n) {
@@ -1200,9 +1288,9 @@ rsim_status rsim_ola_convolve(const float* x, int32_t nx, const float* h, int32_
   b.hop = &d->hop;
   const TuneDev td = default_tune();
   const BatchDev bd = to_dev(&b);
-  launch_mix(&b, bd, td, x, h, &d->alpha, y, base + align256(sizeof(OlaDesc)), stream,
-             family_of_log2n(l2));
-  return hipGetLastError() == hipSuccess ? RSIM_OK : RSIM_EDEVICE;
+  CallPlan P;
+  plan_mix(P, &b, bd, td, x, h, &d->alpha, y, base + align256(sizeof(OlaDesc)), family_of_log2n(l2));
+  return issue(P, stream, 0);
 }
 
 rsim_status rsim_mix_backward(const rsim_batch* b, const float* x, const float* h, const float* alpha,
@@ -1262,15 +1350,11 @@ rsim_status rsim_rfft(const float* x, int32_t n, int32_t count, float* spec, hip
   if (count == 0) return RSIM_OK;
   rsim_status e = ensure_init(stream);
   if (e != RSIM_OK) return e;
-  switch (l2) {
-    case 9: hipLaunchKernelGGL(rfft_kernel<Plan512>, dim3(count), dim3(Plan512::T), 0, stream, x, spec); break;
-    case 10: hipLaunchKernelGGL(rfft_kernel<Plan1K>, dim3(count), dim3(Plan1K::T), 0, stream, x, spec); break;
-    case 11: hipLaunchKernelGGL(rfft_kernel<Plan2K>, dim3(count), dim3(Plan2K::T), 0, stream, x, spec); break;
-    case 12: hipLaunchKernelGGL(rfft_kernel<Plan4K>, dim3(count), dim3(Plan4K::T), 0, stream, x, spec); break;
-    case 13: hipLaunchKernelGGL(rfft_kernel<Plan8K>, dim3(count), dim3(Plan8K::T), 0, stream, x, spec); break;
-    case 14: hipLaunchKernelGGL(rfft_kernel<Plan16K>, dim3(count), dim3(Plan16K::T), 0, stream, x, spec); break;
-    default: hipLaunchKernelGGL(rfft_kernel<Plan32K>, dim3(count), dim3(Plan32K::T), 0, stream, x, spec); break;
-  }
+  sfor<kNumSizes>([&](auto c) {
+    constexpr int L2 = kMinL2 + decltype(c)::value;
+    using PL = PlanOf<L2>;
+    if (l2 == L2) hipLaunchKernelGGL(rfft_kernel<PL>, dim3(count), dim3(PL::T), 0, stream, x, spec);
+  });
   return hipGetLastError() == hipSuccess ? RSIM_OK : RSIM_EDEVICE;
 }
 
@@ -1281,15 +1365,11 @@ rsim_status rsim_irfft(const float* spec, int32_t n, int32_t count, float* x, hi
   if (count == 0) return RSIM_OK;
   rsim_status e = ensure_init(stream);
   if (e != RSIM_OK) return e;
-  switch (l2) {
-    case 9: hipLaunchKernelGGL(irfft_kernel<Plan512>, dim3(count), dim3(Plan512::T), 0, stream, spec, x); break;
-    case 10: hipLaunchKernelGGL(irfft_kernel<Plan1K>, dim3(count), dim3(Plan1K::T), 0, stream, spec, x); break;
-    case 11: hipLaunchKernelGGL(irfft_kernel<Plan2K>, dim3(count), dim3(Plan2K::T), 0, stream, spec, x); break;
-    case 12: hipLaunchKernelGGL(irfft_kernel<Plan4K>, dim3(count), dim3(Plan4K::T), 0, stream, spec, x); break;
-    case 13: hipLaunchKernelGGL(irfft_kernel<Plan8K>, dim3(count), dim3(Plan8K::T), 0, stream, spec, x); break;
-    case 14: hipLaunchKernelGGL(irfft_kernel<Plan16K>, dim3(count), dim3(Plan16K::T), 0, stream, spec, x); break;
-    default: hipLaunchKernelGGL(irfft_kernel<Plan32K>, dim3(count), dim3(Plan32K::T), 0, stream, spec, x); break;
-  }
+  sfor<kNumSizes>([&](auto c) {
+    constexpr int L2 = kMinL2 + decltype(c)::value;
+    using PL = PlanOf<L2>;
+    if (l2 == L2) hipLaunchKernelGGL(irfft_kernel<PL>, dim3(count), dim3(PL::T), 0, stream, spec, x);
+  });
   return hipGetLastError() == hipSuccess ? RSIM_OK : RSIM_EDEVICE;
 }
 

@@ -66,7 +66,7 @@ def _simulate(b, eta, fft_log2n=None, hop=None, order=None, tune=None, use_graph
 
     db = rsim.DeviceBatch(b, order=order, fft_log2n=fft_log2n, hop=hop)
     alpha = torch.from_numpy(rsim.batch_gains(db, b.snr_db)).cuda()
-    stream = torch.cuda.Stream() if use_graph else None   # the null stream cannot be captured
+    stream = torch.cuda.Stream() if use_graph else None
     if stream is not None:
         stream.wait_stream(torch.cuda.current_stream())
         with torch.cuda.stream(stream):
@@ -181,3 +181,48 @@ def test_bad_descriptor_is_skipped_and_flagged():
     assert int(ol[1]) == 0
     for u in (0, 2, 3):
         _check_utterance(b, u, 20.0, y, rl, ol)
+
+
+@pytest.mark.gpu
+def test_graph_and_eager_calls_agree_across_families():
+    # One utterance per FFT-size family, so every call runs several family
+    # kernels side by side; eager and graph calls on the null stream and on a
+    # side stream, interleaved, must all give the same bits.
+    torch = cuda()
+    from paper_1712_03439_amd import rsim
+
+    rng = synth.rng_for(13, 0)
+    sizes = [9, 11, 12, 13, 14, 15, 14, 13]
+    srcs, rirs = [], []
+    for l2 in sizes:
+        n = int(rng.integers(2000, 40000))
+        srcs.append([synth.speech_like(rng, n), synth.white_noise(rng, n)])
+        L0 = int(rng.integers(20, min(2 ** l2 // 2, 5000)))
+        rirs.append([[synth.rir(rng, L0, 0.3, 10) for _ in range(2)] for _ in range(2)])
+    b = synth.pack(srcs, rirs, [[0.0, 6.0]] * len(sizes), 2)
+    db = rsim.DeviceBatch(b, fft_log2n=np.asarray(sizes, np.int32))
+    alpha = torch.from_numpy(rsim.batch_gains(db, b.snr_db)).cuda()
+    rsim.truncate_batch(db, 20.0)
+    side = torch.cuda.Stream()
+    outs = []
+    for k, (graph, on_side) in enumerate([(False, False), (True, False), (True, True), (False, True),
+                                           (True, False), (False, False)]):
+        y = torch.full((max(db.y_len, 1),), float("nan"), device="cuda")
+        if on_side:
+            side.wait_stream(torch.cuda.current_stream())
+            with torch.cuda.stream(side):
+                rsim.mix(db, alpha, y=y, use_graph=graph)
+            torch.cuda.current_stream().wait_stream(side)
+        else:
+            rsim.mix(db, alpha, y=y, use_graph=graph)
+        torch.cuda.synchronize()
+        outs.append(y.cpu().numpy())
+    rl, ol = db.rir_len.cpu().numpy(), db.out_len.cpu().numpy()
+    for u in range(b.n_utt):
+        _check_utterance(b, u, 20.0, outs[0], rl, ol)
+    for u in range(b.n_utt):
+        off, st, T = int(b.out_off[u]), int(b.out_stride[u]), int(ol[u])
+        for j in range(b.n_mic):
+            ref = outs[0][off + j * st: off + j * st + T]
+            for k in range(1, len(outs)):
+                assert np.array_equal(outs[k][off + j * st: off + j * st + T], ref), (k, u, j)
