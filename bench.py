@@ -5,7 +5,7 @@ One step = one epoch of the batched workload: 2048 utterances of 1-15 s at
 16 kHz, each with a target and 0-3 noise sources, 2 microphones, RIRs of
 ceil(T60 fs) taps with T60 ~ U(0.1, 0.9) s drawn fresh for every epoch, cut at
 eta = 20 dB below the peak power, SNRs ~ U(0, 30) dB.  A step runs the RIR
-cut-off and the batched overlap-add filter-and-mix (one HIP graph, captured
+cut-off and the batched overlap-add filter-and-mix (one HIP graph, built
 anew for the epoch).  Inputs (sources, that epoch's RIRs and gains) are resident
 in HBM before the timed region starts.
 
@@ -102,11 +102,14 @@ def main() -> int:
     ap.add_argument("--distinct-rooms", type=int, default=0,
                     help="distinct epochs of RIRs to draw (default: warmup + steps)")
     ap.add_argument("--plain-utts", type=int, default=256)
-    ap.add_argument("--cpu-utts", type=int, default=96)
+    ap.add_argument("--cpu-utts", type=int, default=1024)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--tune", default="auto", help="autotune table JSON, 'auto' or 'model'")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="before the warmup, fill and copy a buffer of this size (a reference "
+                         "for the HBM byte counters)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -165,6 +168,16 @@ def main() -> int:
         rsim.mix(db, alpha, y=y, ws=ws, tune=tune, use_graph=use_graph, stream=stream)
         if ev:
             ev[2].record(stream)
+
+    if args.copy_probe_mib:
+        n = args.copy_probe_mib * (1 << 20) // 4
+        a = torch.empty(n, dtype=torch.float32, device=dev)
+        c = torch.empty_like(a)
+        a.fill_(1.0)       # writes n * 4 bytes
+        c.copy_(a)         # reads and writes n * 4 bytes
+        torch.cuda.synchronize()
+        del a, c
+        log(f"copy probe: fill + copy of {args.copy_probe_mib} MiB")
 
     with torch.cuda.stream(stream):
         for k in range(W):
