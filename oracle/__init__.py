@@ -12,5 +12,7 @@ from .rsim_oracle import (  # noqa: F401
     mix,
     mix_at,
     mix_backward,
+    mix_backward_at,
+    out_length,
     simulate,
 )

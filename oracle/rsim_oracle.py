@@ -194,6 +194,32 @@ def mix_backward(sources: Sequence[np.ndarray], rirs: Sequence[Sequence[np.ndarr
     return dx, dh, da
 
 
+def mix_backward_at(sources: Sequence[np.ndarray], rirs: Sequence[Sequence[np.ndarray]],
+                    alpha: np.ndarray, grad_y: np.ndarray, i: int, j: int,
+                    x_idx: Sequence[int], h_idx: Sequence[int]):
+    """Samples of the adjoint of eq. (2), each as its own direct sum:
+    dx_i[n] for n in x_idx (summed over every mic) and dh_ij[k] for k in h_idx,
+    plus dalpha_ij in full."""
+    g = np.asarray(grad_y, np.float64)
+    J = len(rirs[0])
+    x = np.asarray(sources[i], np.float64)
+    nx = x.size
+    dx = np.zeros(len(x_idx), np.float64)
+    for t, n in enumerate(x_idx):
+        acc = 0.0
+        for jj in range(J):
+            h = np.asarray(rirs[i][jj], np.float64)
+            L = h.size
+            acc += float(alpha[i][jj]) * float(np.dot(h, g[jj, n: n + L])) if L else 0.0
+        dx[t] = acc
+    h = np.asarray(rirs[i][j], np.float64)
+    L = h.size
+    a = float(alpha[i][j])
+    dh = np.array([a * float(np.dot(x, g[j, k: k + nx])) if k < L else 0.0 for k in h_idx])
+    da = float(np.dot(g[j, : nx + L - 1], convolve(x, h))) if L and nx else 0.0
+    return dx, dh, da
+
+
 def simulate(sources: Sequence[np.ndarray], rirs: Sequence[Sequence[np.ndarray]],
              snr_db: Sequence[float], eta_db: float, alpha: np.ndarray = None):
     """One utterance end to end: cut every RIR (eqs. 7-9), compute the gains,

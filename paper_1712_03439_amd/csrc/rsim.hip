@@ -567,6 +567,233 @@ __global__ __launch_bounds__(T, MINW) void mix_kernel(MixArgs A) {
   }
 }
 
+// ============================================================== the adjoint
+// Y += conj(A) B over the thread's slots, A and B from memory (slot SP of
+// thread 0 holds two real bins, for which conj is the identity).
+template <class PL>
+__device__ __forceinline__ void macc_mem(cf* Y, const cf* __restrict__ Am, const cf* __restrict__ Bm, int t_) {
+  constexpr int SP = Fft<PL>::SP;
+  const int t = opaque_v(t_);
+  const rsrc_t ra = make_rsrc(Am, PL::P * PL::T * 8);
+  const rsrc_t rb = make_rsrc(Bm, PL::P * PL::T * 8);
+  const int vo = 8 * t;
+#pragma unroll
+  for (int q = 0; q < PL::P; ++q) {
+    const cf a = ld2(ra, vo, 8 * q * PL::T);
+    const cf bv = ld2(rb, vo, 8 * q * PL::T);
+    if (q == SP) {
+      const cf c = cmacc(Y[q], a, bv);
+      const cf d = mk(__builtin_fmaf(a.x, bv.x, Y[q].x), __builtin_fmaf(a.y, bv.y, Y[q].y));
+      Y[q] = t == 0 ? d : c;
+    } else {
+      Y[q] = cmacc(Y[q], a, bv);
+    }
+  }
+}
+
+// R (memory) = (first ? 0 : R) + conj(X) B, X in registers, B from memory.
+template <class PL>
+__device__ __forceinline__ void acc_corr(cf* __restrict__ Rm, const cf* X, const cf* __restrict__ Bm, bool first,
+                                         int t_) {
+  constexpr int SP = Fft<PL>::SP;
+  const int t = opaque_v(t_);
+  const rsrc_t rr = make_rsrc(Rm, first ? 0 : PL::P * PL::T * 8);  // a zero range reads zeros
+  const rsrc_t rw = make_rsrc(Rm, PL::P * PL::T * 8);
+  const rsrc_t rb = make_rsrc(Bm, PL::P * PL::T * 8);
+  const int vo = 8 * t;
+#pragma unroll
+  for (int q = 0; q < PL::P; ++q) {
+    const cf acc = ld2(rr, vo, 8 * q * PL::T);
+    const cf bv = ld2(rb, vo, 8 * q * PL::T);
+    cf o;
+    if (q == SP) {
+      const cf c = cmacc(acc, X[q], bv);
+      const cf d = mk(__builtin_fmaf(X[q].x, bv.x, acc.x), __builtin_fmaf(X[q].y, bv.y, acc.y));
+      o = t == 0 ? d : c;
+    } else {
+      o = cmacc(acc, X[q], bv);
+    }
+    st2(rw, vo, o, 8 * q * PL::T);
+  }
+}
+
+// Inverse-transform a spectrum and store the first `lim` samples at yp.
+template <class PL>
+__device__ __forceinline__ void emit_store(cf* Yv, cf* lds, const TwBase& tw, float* __restrict__ yp, int lim,
+                                           int t_) {
+  Fft<PL>::pre(Yv, tw, t_);
+  Fft<PL>::inverse(Yv, lds, tw, t_);
+  const int t = opaque_v(t_);
+  const rsrc_t wr = make_rsrc(yp, lim * 4);
+  const int vo = 8 * t;
+#pragma unroll
+  for (int r = 0; r < PL::P; ++r) {
+    const int o = vo + 8 * r * PL::T;
+    st1(wr, o, Yv[r].x);
+    st1(wr, o + 4, Yv[r].y);
+  }
+}
+
+// Sum over the workgroup's T threads (T a power of two, any T <= 1024): a
+// tree in LDS, so partial waves (T = 32) need no cross-lane operation.
+template <int T>
+__device__ __forceinline__ double block_sum_d(double v, double* s_red, int t) {
+  __syncthreads();  // earlier readers of s_red are done
+  s_red[t] = v;
+  __syncthreads();
+#pragma unroll
+  for (int h = T / 2; h > 0; h >>= 1) {
+    if (t < h) s_red[t] += s_red[t + h];
+    __syncthreads();
+  }
+  return s_red[0];
+}
+
+// One utterance of the adjoint.  With g_j the output gradient of mic j:
+//   dx_i[n]   = sum_j alpha_ij (h_ij corr g_j)[n]        per block, overlap-save
+//   r_ij[k]   = sum_n x_i[n] g_j[n + k]                  spectra summed over blocks
+//   dh_ij[k]  = alpha_ij r_ij[k],   dalpha_ij = sum_k h_ij[k] r_ij[k]
+// Block b of the output gradient, g_j[bB .. bB + N), holds every sample the
+// block's dx and the block's share of r need (B + L_max - 1 <= N, no wrap).
+// Scratch: alpha-scaled RIR spectra (I J), this block's gradient spectra (J)
+// and the correlation accumulators (I J).
+template <class PL>
+__device__ __forceinline__ void bwd_utterance(const BwdArgs& A, int u, const Sched& S, cf* lds, double* s_red,
+                                              cf* slot, int t) {
+  constexpr int P = PL::P, M = PL::M, N = PL::N;
+  const TwBase tw = Fft<PL>::bases(plan_tw<PL>(), t);
+  const BatchDev& b = A.b;
+  const int I = uni(b.n_src[u]), J = b.J, NS = b.S, Nx = uni(b.src_len[u]);
+  const int B = S.hop, nb = S.nb, tu = S.tu;
+  const float gscale = 1.0f / (8.0f * (float)M);
+  cf* Hs = slot;
+  cf* Gs = slot + (long long)NS * J * M;
+  cf* Rs = Gs + (long long)J * M;
+  const long long yo = uni64(b.out_off[u]);
+  const long long ys = uni(b.out_stride[u]);
+
+  for (int i = 0; i < I; ++i) {
+    for (int j = 0; j < J; ++j) {
+      const long long r = ((long long)u * NS + i) * J + j;
+      cf v[P];
+      load_real<PL>(v, A.h + uni64(b.rir_off[r]), uni(b.rir_len[r]), t);
+      Fft<PL>::forward(v, lds, tw, t);
+      Fft<PL>::post(v, tw, t);
+      const float a = A.alpha[r];
+#pragma unroll
+      for (int q = 0; q < P; ++q) v[q] = mk(v[q].x * a, v[q].y * a);
+      store_spec<PL>(Hs + (long long)(i * J + j) * M, v, t);
+    }
+  }
+
+  for (int bk = 0; bk < nb; ++bk) {
+    const int base = bk * B;
+    const int nvalid = min(B, Nx - base);
+    for (int j = 0; j < J; ++j) {
+      cf v[P];
+      load_real<PL>(v, A.gy + yo + (long long)j * ys + base, min(N, tu - base), t);
+      Fft<PL>::forward(v, lds, tw, t);
+      Fft<PL>::post(v, tw, t);
+#pragma unroll
+      for (int q = 0; q < P; ++q) v[q] = mk(v[q].x * gscale, v[q].y * gscale);
+      store_spec<PL>(Gs + (long long)j * M, v, t);
+    }
+    for (int i = 0; i < I; ++i) {
+      const long long so = uni64(b.src_off[(long long)u * NS + i]);
+      cf D[P];
+#pragma unroll
+      for (int q = 0; q < P; ++q) D[q] = mk(0.f, 0.f);
+      for (int j = 0; j < J; ++j) macc_mem<PL>(D, Hs + (long long)(i * J + j) * M, Gs + (long long)j * M, t);
+      emit_store<PL>(D, lds, tw, A.gx + so + base, nvalid, t);
+      cf X[P];
+      load_real<PL>(X, A.x + so + base, nvalid, t);
+      Fft<PL>::forward(X, lds, tw, t);
+      Fft<PL>::post(X, tw, t);
+      for (int j = 0; j < J; ++j)
+        acc_corr<PL>(Rs + (long long)(i * J + j) * M, X, Gs + (long long)j * M, bk == 0, t);
+    }
+  }
+
+  for (int i = 0; i < I; ++i) {
+    for (int j = 0; j < J; ++j) {
+      const long long r = ((long long)u * NS + i) * J + j;
+      const int L = uni(b.rir_len[r]), L0 = uni(b.rir_len0[r]);
+      const long long ro = uni64(b.rir_off[r]);
+      const float a = A.alpha[r];
+      cf v[P];
+      load_spec<PL>(v, Rs + (long long)(i * J + j) * M, t);
+      Fft<PL>::pre(v, tw, t);
+      Fft<PL>::inverse(v, lds, tw, t);
+      // v[q] holds r at samples 2(t + qT), 2(t + qT) + 1.
+      const rsrc_t hr = make_rsrc(A.h + ro, L * 4);
+      const rsrc_t gw = make_rsrc(A.gh + ro, L * 4);
+      double part = 0.0;
+#pragma unroll
+      for (int q = 0; q < P; ++q) {
+        const int o = 8 * (t + q * PL::T);
+        part += (double)ld1(hr, o) * (double)v[q].x + (double)ld1(hr, o + 4) * (double)v[q].y;
+        st1(gw, o, a * v[q].x);
+        st1(gw, o + 4, a * v[q].y);
+      }
+      const double da = block_sum_d<PL::T>(part, s_red, t);
+      if (t == 0 && A.galpha) A.galpha[r] = (float)da;
+      for (int k = L + t; k < L0; k += PL::T) A.gh[ro + k] = 0.0f;
+    }
+  }
+}
+
+template <int T>
+__global__ __launch_bounds__(T, 2) void bwd_kernel(BwdArgs A) {
+  __shared__ cf lds[max_lds_with_threads<T>()];
+  __shared__ double s_red[T];
+  __shared__ int s_idx;
+  const int t = threadIdx.x;
+  cf* slot = A.scratch + (long long)blockIdx.x * A.slot_cf;
+  for (;;) {
+    __syncthreads();
+    if (t == 0) s_idx = atomicAdd(&A.hdr->counter[A.fam], 1);
+    __syncthreads();
+    const int idx = __builtin_amdgcn_readfirstlane(s_idx);
+    if (idx >= A.hdr->count[A.fam]) break;
+    const int u = __builtin_amdgcn_readfirstlane(A.list[(long long)A.fam * A.b.U + idx]);
+    Sched S = A.sched[u];
+    S.log2n = __builtin_amdgcn_readfirstlane(S.log2n);
+    S.hop = __builtin_amdgcn_readfirstlane(S.hop);
+    S.nb = __builtin_amdgcn_readfirstlane(S.nb);
+    S.tu = __builtin_amdgcn_readfirstlane(S.tu);
+    S.lmax = __builtin_amdgcn_readfirstlane(S.lmax);
+    dispatch_plan<T>(S.log2n, [&](auto pl) __attribute__((always_inline)) {
+      using PL = decltype(pl);
+      bwd_utterance<PL>(A, u, S, lds, s_red, slot, t);
+    });
+  }
+}
+
+// Utterances without work (no source, no samples or no RIR tap) still get
+// their gradients: zeros.  One workgroup per utterance, grid-stride.
+__global__ __launch_bounds__(256) void bwd_zero_kernel(BwdArgs A) {
+  const BatchDev& b = A.b;
+  for (int u = blockIdx.x; u < b.U; u += gridDim.x) {
+    const Sched S = A.sched[u];
+    if (S.nb > 0) continue;
+    const int I = b.n_src[u], J = b.J, NS = b.S, Nx = b.src_len[u];
+    if (I < 0 || I > NS || Nx < 0) continue;  // flagged by the schedule
+    for (int i = 0; i < I; ++i) {
+      const long long so = b.src_off[(long long)u * NS + i];
+      if (so < 0 || so + Nx > b.x_len) continue;
+      for (int n = threadIdx.x; n < Nx; n += 256) A.gx[so + n] = 0.0f;
+      for (int j = 0; j < J; ++j) {
+        const long long r = ((long long)u * NS + i) * J + j;
+        const long long ro = b.rir_off[r];
+        const int L0 = b.rir_len0[r];
+        if (L0 < 0 || ro < 0 || ro + L0 > b.h_len) continue;
+        for (int k = threadIdx.x; k < L0; k += 256) A.gh[ro + k] = 0.0f;
+        if (threadIdx.x == 0 && A.galpha) A.galpha[r] = 0.0f;
+      }
+    }
+  }
+}
+
 // ================================================================ dry power
 __global__ __launch_bounds__(256) void power_kernel(BatchDev b, const float* __restrict__ x,
                                                    double* __restrict__ power) {
@@ -736,11 +963,13 @@ struct DevState {
   bool init = false;
   int cus = 0;
   int occ[kNumVar][kNumFam] = {};  // [variant][family]
+  int occ_bwd[kNumFam] = {};
   // Side streams (default priority) and events that let the family kernels
   // of one call run concurrently: the tail of one family overlaps the next.
-  hipStream_t side[kNumFam - 1] = {};
+  static constexpr int kSide = kNumFam;  // a call issues at most kNumFam + 1 parallel kernels
+  hipStream_t side[kSide] = {};
   hipEvent_t fork = nullptr;
-  hipEvent_t join[kNumFam - 1] = {};
+  hipEvent_t join[kSide] = {};
 };
 
 std::mutex g_mu;
@@ -762,6 +991,16 @@ const void* mix_kernel_ptr_v(int fam) {
     case 3: return reinterpret_cast<const void*>(&mix_kernel<256, JG, MINW>);
     case 4: return reinterpret_cast<const void*>(&mix_kernel<512, JG, MINW>);
     default: return reinterpret_cast<const void*>(&mix_kernel<1024, JG, MINW>);
+  }
+}
+const void* bwd_kernel_ptr(int fam) {
+  switch (fam) {
+    case 0: return reinterpret_cast<const void*>(&bwd_kernel<32>);
+    case 1: return reinterpret_cast<const void*>(&bwd_kernel<64>);
+    case 2: return reinterpret_cast<const void*>(&bwd_kernel<128>);
+    case 3: return reinterpret_cast<const void*>(&bwd_kernel<256>);
+    case 4: return reinterpret_cast<const void*>(&bwd_kernel<512>);
+    default: return reinterpret_cast<const void*>(&bwd_kernel<1024>);
   }
 }
 const void* mix_kernel_ptr(int fam, int var) {
@@ -803,9 +1042,15 @@ rsim_status init_locked(int dev) {
         return RSIM_EDEVICE;
       st.occ[v][f] = n > 0 ? n : 1;
     }
+  for (int f = 0; f < kNumFam; ++f) {
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, bwd_kernel_ptr(f), kFamT[f], 0) != hipSuccess)
+      return RSIM_EDEVICE;
+    st.occ_bwd[f] = n > 0 ? n : 1;
+  }
   if (!st.fork) {
     if (hipEventCreateWithFlags(&st.fork, hipEventDisableTiming) != hipSuccess) return RSIM_EDEVICE;
-    for (int k = 0; k < kNumFam - 1; ++k) {
+    for (int k = 0; k < DevState::kSide; ++k) {
       if (hipStreamCreateWithFlags(&st.side[k], hipStreamNonBlocking) != hipSuccess ||
           hipEventCreateWithFlags(&st.join[k], hipEventDisableTiming) != hipSuccess)
         return RSIM_EDEVICE;
@@ -904,7 +1149,7 @@ WsLayout layout(const rsim_batch* b, const TuneDev& td, bool backward, const Dev
     // Without a device (size queries on a host) assume 256 CUs and the
     // largest occupancy used; the grid is capped at 8 workgroups per CU.
     const int cus = st.cus > 0 ? st.cus : 256;
-    int occ = st.init ? st.occ[kernel_variant()][f] : 8;
+    int occ = st.init ? (backward ? st.occ_bwd[f] : st.occ[kernel_variant()][f]) : 8;
     if (occ > 8) occ = 8;
     long long g = (long long)cus * occ;
     if (g > (long long)U) g = (long long)U;
@@ -965,7 +1210,7 @@ struct Node {
 struct CallPlan {
   bool has_cut = false;
   Node cut, sched;
-  Node fam[kNumFam];
+  Node fam[kNumFam + 1];  // the family kernels (and, for the adjoint, the zero fill)
   int nf = 0;
 };
 
@@ -984,6 +1229,7 @@ rsim_status issue_eager(CallPlan& P, hipStream_t s) {
     return RSIM_EDEVICE;
   if (hipLaunchKernel(P.sched.fn, P.sched.grid, P.sched.block, P.sched.p(), 0, s) != hipSuccess)
     return RSIM_EDEVICE;
+  static_assert(sizeof(P.fam) / sizeof(P.fam[0]) <= DevState::kSide + 1, "one side stream per extra kernel");
   const bool fork = P.nf > 1 && st.fork && !capturing(s);
   // The fork/join events are shared device state: serialise their use.
   std::unique_lock<std::mutex> lk(g_mu, std::defer_lock);
@@ -1112,6 +1358,52 @@ void plan_mix(CallPlan& P, const rsim_batch* b, const BatchDev& bd, const TuneDe
     A.scratch = reinterpret_cast<cf*>(base + L.fam_scratch[f]);
     A.slot_cf = L.slot_cf[f];
     P.fam[P.nf++].set(mix_kernel_ptr(f, kernel_variant()), dim3(L.grid[f]), dim3(kFamT[f]), A);
+  }
+}
+
+// Records the schedule, the zero fill of idle utterances and the adjoint
+// family kernels into P.
+void plan_bwd(CallPlan& P, const rsim_batch* b, const BatchDev& bd, const TuneDev& td, const float* x,
+              const float* h, const float* alpha, const float* gy, float* gx, float* gh, float* galpha,
+              void* ws) {
+  const DevState& st = dev_state();
+  const WsLayout L = layout(b, td, true, st);
+  char* base = static_cast<char*>(ws);
+  SchedArgs SA;
+  SA.b = bd;
+  SA.tune = td;
+  SA.hdr = reinterpret_cast<WsHeader*>(base + L.hdr);
+  SA.sched = reinterpret_cast<Sched*>(base + L.sched);
+  SA.lists = reinterpret_cast<int*>(base + L.lists);
+  P.sched.set(reinterpret_cast<const void*>(&schedule_kernel), dim3(1), dim3(kSchedThreads), SA);
+  BwdArgs A;
+  A.b = bd;
+  A.x = x;
+  A.h = h;
+  A.alpha = alpha;
+  A.gy = gy;
+  A.gx = gx;
+  A.gh = gh;
+  A.galpha = galpha;
+  A.sched = SA.sched;
+  A.list = SA.lists;
+  A.hdr = SA.hdr;
+  A.fam = -1;
+  A.scratch = nullptr;
+  A.slot_cf = 0;
+  P.nf = 0;
+  const int cus = st.cus > 0 ? st.cus : 256;
+  P.fam[P.nf++].set(reinterpret_cast<const void*>(&bwd_zero_kernel), dim3(std::min(b->n_utt, cus * 4)),
+                    dim3(256), A);
+  bool used[kNumFam];
+  families_used(b, td, used);
+  for (int k = 0; k < kNumFam; ++k) {
+    const int f = kFamOrder[k];
+    if (!used[f]) continue;
+    A.fam = f;
+    A.scratch = reinterpret_cast<cf*>(base + L.fam_scratch[f]);
+    A.slot_cf = L.slot_cf[f];
+    P.fam[P.nf++].set(bwd_kernel_ptr(f), dim3(L.grid[f]), dim3(kFamT[f]), A);
   }
 }
 
@@ -1296,9 +1588,18 @@ rsim_status rsim_ola_convolve(const float* x, int32_t nx, const float* h, int32_
 rsim_status rsim_mix_backward(const rsim_batch* b, const float* x, const float* h, const float* alpha,
                               const float* grad_y, float* grad_x, float* grad_h, float* grad_alpha,
                               void* ws, size_t ws_bytes, const rsim_tune* tune, hipStream_t stream) {
-  (void)b; (void)x; (void)h; (void)alpha; (void)grad_y; (void)grad_x; (void)grad_h;
-  (void)grad_alpha; (void)ws; (void)ws_bytes; (void)tune; (void)stream;
-  return RSIM_EUNSUPPORTED;
+  if (!batch_ok(b)) return RSIM_EINVAL;
+  if (b->n_utt == 0) return RSIM_OK;
+  if (!x || !h || !alpha || !grad_y || !grad_x || !grad_h) return RSIM_EINVAL;
+  const rsim_status e = ensure_init(stream);
+  const TuneDev td = to_dev(tune);
+  const WsLayout L = layout(b, td, true, dev_state());
+  if (!ws || ws_bytes < L.total) return RSIM_EWORKSPACE;
+  if (e != RSIM_OK) return e;
+  const BatchDev bd = to_dev(b);
+  CallPlan P;
+  plan_bwd(P, b, bd, td, x, h, alpha, grad_y, grad_x, grad_h, grad_alpha, ws);
+  return issue(P, stream, 0);
 }
 
 rsim_status rsim_source_power(const rsim_batch* b, const float* x, double* power, hipStream_t stream) {

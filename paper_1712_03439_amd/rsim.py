@@ -344,6 +344,75 @@ def simulate(db: DeviceBatch, alpha, eta_db: float, y=None, ws=None, tune: Optio
     return y
 
 
+def mix_backward(db: DeviceBatch, alpha, grad_y, x=None, h=None, ws=None, tune: Optional[RsimTune] = None,
+                 need_alpha: bool = True, stream=None):
+    """Adjoint of `mix` (rsim_mix_backward): (grad_x, grad_h, grad_alpha) in the
+    layouts of x, h and alpha, for the current db.rir_len.  grad_h is zero
+    beyond each cut length; grad_alpha is None unless need_alpha."""
+    torch = _torch()
+    x = db.x if x is None else x
+    h = db.h if h is None else h
+    _require_cuda(alpha, grad_y, x, h)
+    if ws is None:
+        ws = db.workspace(tune, backward=True)
+    # zeros: parts of the packed arrays that belong to no utterance keep a zero gradient
+    gx = torch.zeros(max(db.x_len, 1), dtype=torch.float32, device=db.device)
+    gh = torch.zeros(max(db.h_len, 1), dtype=torch.float32, device=db.device)
+    ga = torch.zeros(max(db.U * db.S * db.J, 1), dtype=torch.float32, device=db.device) if need_alpha else None
+    s = db.struct()
+    _check(_lib().rsim_mix_backward(ctypes.byref(s), _ptr(x), _ptr(h), _ptr(alpha), _ptr(grad_y), _ptr(gx),
+                                    _ptr(gh), _ptr(ga), _ptr(ws), int(ws.numel()),
+                                    ctypes.byref(tune) if tune else None, _stream(stream)),
+           "rsim_mix_backward")
+    return gx[: db.x_len], gh[: db.h_len], (ga[: db.U * db.S * db.J] if need_alpha else None)
+
+
+class _MixFunction:
+    """Built lazily so that importing this module does not import torch."""
+
+    fn = None
+
+    @classmethod
+    def get(cls):
+        if cls.fn is None:
+            torch = _torch()
+
+            class MixFunction(torch.autograd.Function):
+                """y = mix(x, h, alpha) of eq. (2) with the hand-written adjoint.
+
+                x, h: packed float32 sources and RIRs (db's layouts); alpha:
+                [U*S*J] gains.  The cut lengths db.rir_len are constants (no
+                gradient flows through the cut index)."""
+
+                @staticmethod
+                def forward(ctx, x, h, alpha, db, tune):
+                    # zeros: the padding of each mic beyond T_u is part of y too
+                    y = torch.zeros(max(db.y_len, 1), dtype=torch.float32, device=db.device)
+                    mix(db, alpha, y=y, tune=tune, x=x, h=h)
+                    ctx.save_for_backward(x, h, alpha)
+                    ctx.db, ctx.tune = db, tune
+                    return y[: db.y_len]
+
+                @staticmethod
+                def backward(ctx, gy):
+                    x, h, alpha = ctx.saved_tensors
+                    gy = gy.contiguous()
+                    gx, gh, ga = mix_backward(ctx.db, alpha, gy, x=x, h=h, tune=ctx.tune,
+                                              need_alpha=ctx.needs_input_grad[2])
+                    return (gx if ctx.needs_input_grad[0] else None,
+                            gh if ctx.needs_input_grad[1] else None,
+                            ga, None, None)
+
+            cls.fn = MixFunction
+        return cls.fn
+
+
+def mix_autograd(db: DeviceBatch, x, h, alpha, tune: Optional[RsimTune] = None):
+    """Differentiable eq. (2): returns y (layout of db's outputs, length
+    db.y_len); backward runs rsim_mix_backward."""
+    return _MixFunction.get().apply(x, h, alpha, db, tune)
+
+
 def source_power(db: DeviceBatch, x=None, stream=None):
     torch = _torch()
     p = torch.empty(db.U * db.S, dtype=torch.float64, device=db.device)

@@ -316,3 +316,42 @@ def test_empty_rir_contributes_nothing():
     assert y.shape == (2, 5)
     assert not np.any(y[0]) and np.allclose(y[1], 2 * x)
     assert O.mix([x], [[np.zeros(0, np.float32)]], np.ones((1, 1))).shape == (1, 0)
+
+
+def test_sampled_adjoint_agrees_with_central_differences():
+    # mix_backward_at evaluates each gradient entry as its own direct sum; pin it
+    # by central differences of the quadratic loss, like the full adjoint.
+    r, xs, hs, a = _random_problem(4, I=2, J=3, nx=90, L=20)
+    T = O.mix(xs, hs, a).shape[1]
+    w = r.uniform(0, 1, (3, T))
+    y = O.mix(xs, hs, a)
+    g = 2.0 * w * y
+
+    def loss(xs_, hs_, a_):
+        yy = O.mix(xs_, hs_, a_)
+        return float(np.sum(w * yy * yy))
+
+    eps = 1e-3
+    x_idx, h_idx = [0, 45, 89], [0, 7, len(hs[1][2]) - 1]
+    dx, dh, da = O.mix_backward_at(xs, hs, a, g, 1, 2, x_idx, h_idx)
+    for t, n in enumerate(x_idx):
+        xp = [v.copy() for v in xs]
+        xm = [v.copy() for v in xs]
+        xp[1][n] += eps
+        xm[1][n] -= eps
+        fd = (loss(xp, hs, a) - loss(xm, hs, a)) / (2 * eps)
+        assert abs(fd - dx[t]) <= 1e-6 * max(1.0, abs(fd))
+    for t, k in enumerate(h_idx):
+        hp = [[v.copy() for v in row] for row in hs]
+        hm = [[v.copy() for v in row] for row in hs]
+        hp[1][2][k] += eps
+        hm[1][2][k] -= eps
+        fd = (loss(xs, hp, a) - loss(xs, hm, a)) / (2 * eps)
+        assert abs(fd - dh[t]) <= 1e-6 * max(1.0, abs(fd))
+    ap, am = a.copy(), a.copy()
+    ap[1, 2] += eps
+    am[1, 2] -= eps
+    fd = (loss(xs, hs, ap) - loss(xs, hs, am)) / (2 * eps)
+    assert abs(fd - da) <= 1e-6 * max(1.0, abs(fd))
+    # a tap index beyond the RIR has no gradient
+    assert O.mix_backward_at(xs, hs, a, g, 1, 2, [], [len(hs[1][2]) + 3])[1][0] == 0.0
