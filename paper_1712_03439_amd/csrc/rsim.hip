@@ -400,9 +400,6 @@ __device__ __forceinline__ void mac2(cf* Y0, cf* Y1, const cf* __restrict__ H0,
 
 // Inverse-transform one mic spectrum and overlap-add it into y: positions
 // m < lim are written; positions m < carry already hold the tails of earlier
-// blocks (written by this workgroup) and are accumulated.
-// Inverse-transform one mic spectrum and overlap-add it into y: positions
-// m < lim are written; positions m < carry already hold the tails of earlier
 // blocks (written by this workgroup) and are accumulated.  Both limits are
 // buffer range checks, so no element needs a branch.
 template <class PL>
@@ -421,6 +418,40 @@ __device__ __forceinline__ void emit(cf* Yv, cf* lds, const TwBase& tw, float* _
     const float b = Yv[r].y + ld1(rd, o + 4);
     st1(wr, o, a);
     st1(wr, o + 4, b);
+  }
+}
+
+// The overlap-add carry of one mic block, for carries that fit the first CR
+// slots (carry <= 2 T CR): c[r] = y at the thread's samples 2(t + rT),
+// 2(t + rT) + 1 below min(carry, lim), zero elsewhere.
+template <class PL, int CR>
+__device__ __forceinline__ void load_carry(cf* c, const float* __restrict__ yp, int lim, int carry, int t_) {
+  const int t = opaque_v(t_);
+  const rsrc_t rd = make_rsrc(yp, min(carry, lim) * 4);
+  const int vo = 8 * t;
+#pragma unroll
+  for (int r = 0; r < CR; ++r) {
+    const int o = vo + 8 * r * PL::T;
+    c[r] = mk(ld1(rd, o), ld1(rd, o + 4));
+  }
+}
+
+// Inverse-transform one mic spectrum, add the preloaded carry (first CR
+// slots) and store the samples below lim.
+template <class PL, int CR>
+__device__ __forceinline__ void emit_carried(cf* Yv, const cf* c, cf* lds, const TwBase& tw, float* __restrict__ yp,
+                                             int lim, int t_) {
+  Fft<PL>::pre(Yv, tw, t_);
+  Fft<PL>::inverse(Yv, lds, tw, t_);
+  const int t = opaque_v(t_);
+  const rsrc_t wr = make_rsrc(yp, lim * 4);
+  const int vo = 8 * t;
+#pragma unroll
+  for (int r = 0; r < PL::P; ++r) {
+    const int o = vo + 8 * r * PL::T;
+    const cf cr = r < CR ? c[r] : mk(0.f, 0.f);
+    st1(wr, o, Yv[r].x + cr.x);
+    st1(wr, o + 4, Yv[r].y + cr.y);
   }
 }
 
@@ -445,18 +476,24 @@ __device__ __forceinline__ void mix_utterance(const MixArgs& A, int u, const Sch
   cf* Xs = slot + (long long)NS * J * M;
   const int ng = (J + JG - 1) / JG;
 
-  // RIR spectra, once per utterance, scaled by alpha / (8M).
-  for (int i = 0; i < I; ++i) {
-    for (int j = 0; j < J; ++j) {
-      const long long r = ((long long)u * NS + i) * J + j;
+  // RIR spectra, once per utterance, scaled by alpha / (8M); the next RIR
+  // is requested while the current one is transformed.
+  {
+    const int n_rir = I * J;
+    const long long r0 = (long long)u * NS * J;  // slot of (i, j) is r0 + i J + j
+    cf vn[P];
+    if (n_rir > 0) load_real<PL>(vn, A.h + uni64(b.rir_off[r0]), uni(b.rir_len[r0]), t);
+    for (int k = 0; k < n_rir; ++k) {
       cf v[P];
-      load_real<PL>(v, A.h + uni64(b.rir_off[r]), uni(b.rir_len[r]), t);
+#pragma unroll
+      for (int q = 0; q < P; ++q) v[q] = vn[q];
+      if (k + 1 < n_rir) load_real<PL>(vn, A.h + uni64(b.rir_off[r0 + k + 1]), uni(b.rir_len[r0 + k + 1]), t);
       Fft<PL>::forward(v, lds, tw, t);
       Fft<PL>::post(v, tw, t);
-      const float a = A.alpha[r] * cscale;
+      const float a = A.alpha[r0 + k] * cscale;
 #pragma unroll
       for (int q = 0; q < P; ++q) v[q] = mk(v[q].x * a, v[q].y * a);
-      store_spec<PL>(Hs + (long long)(i * J + j) * M, v, t);
+      store_spec<PL>(Hs + (long long)k * M, v, t);
     }
   }
 
@@ -469,39 +506,49 @@ __device__ __forceinline__ void mix_utterance(const MixArgs& A, int u, const Sch
   // (3 + 2 JG) arrays of P complex values.
   constexpr int kWavesPerSimd = MINW > PL::T / 256 ? MINW : PL::T / 256;
   constexpr bool kPrefetch = P <= 16 && (3 + 2 * JG) * 2 * P <= 512 / kWavesPerSimd;
-  for (int bk = 0; bk < nb; ++bk) {
-    const int base = bk * B;
-    const int nvalid = min(B, Nx - base);
-    const int lim = min(span, tu - base);
-    const int carry = bk == 0 ? 0 : lmax - 1;
-    for (int g = 0; g < ng; ++g) {
-      const int j0 = g * JG;
-      const bool two = JG == 2 && j0 + 1 < J;
-      cf Y0[P], Y1[JG == 2 ? P : 1];
-#pragma unroll
-      for (int q = 0; q < P; ++q) Y0[q] = mk(0.f, 0.f);
-      if constexpr (JG == 2) {
-#pragma unroll
-        for (int q = 0; q < P; ++q) Y1[q] = mk(0.f, 0.f);
+  if constexpr (kPrefetch) {
+    // Work items in order (block, mic group, source).  Xn always holds the
+    // input of the next item: the next source of this group, else the first
+    // source of the next group (cached spectra), else the first source of
+    // the next block, so loads are in flight across group and block ends.
+    // The RIR spectra of a source are requested when its item starts.  The
+    // live set is about (3 + 2 JG) arrays of P complex values.
+    cf Xn[P];
+    auto fetch = [&](int bk, int g, int i) __attribute__((always_inline)) {
+      if (g == 0) {
+        const int base = bk * B;
+        load_real<PL>(Xn, A.x + uni64(b.src_off[(long long)u * NS + i]) + base, min(B, Nx - base), t);
+      } else {
+        load_spec<PL>(Xn, Xs + (long long)i * M, t);
       }
-      auto fetch_x = [&](cf* dst, int i) __attribute__((always_inline)) {
-        if (g == 0) load_real<PL>(dst, A.x + uni64(b.src_off[(long long)u * NS + i]) + base, nvalid, t);
-        else load_spec<PL>(dst, Xs + (long long)i * M, t);
-      };
-      cf Xn[kPrefetch ? P : 1];
-      if constexpr (kPrefetch) fetch_x(Xn, 0);
-      for (int i = 0; i < I; ++i) {
-        cf X[P];
-        const cf* H0 = Hs + (long long)(i * J + j0) * M;
-        if constexpr (kPrefetch) {
-          cf Hp0[P], Hp1[JG == 2 ? P : 1];
+    };
+    fetch(0, 0, 0);
+    for (int bk = 0; bk < nb; ++bk) {
+      const int base = bk * B;
+      const int lim = min(span, tu - base);
+      const int carry = bk == 0 ? 0 : lmax - 1;
+      for (int g = 0; g < ng; ++g) {
+        const int j0 = g * JG;
+        const bool two = JG == 2 && j0 + 1 < J;
+        cf Y0[P], Y1[JG == 2 ? P : 1];
+#pragma unroll
+        for (int q = 0; q < P; ++q) Y0[q] = mk(0.f, 0.f);
+        if constexpr (JG == 2) {
+#pragma unroll
+          for (int q = 0; q < P; ++q) Y1[q] = mk(0.f, 0.f);
+        }
+        for (int i = 0; i < I; ++i) {
+          const cf* H0 = Hs + (long long)(i * J + j0) * M;
+          cf X[P], Hp0[P], Hp1[JG == 2 ? P : 1];
           load_spec<PL>(Hp0, H0, t);
           if constexpr (JG == 2) {
             if (two) load_spec<PL>(Hp1, H0 + M, t);
           }
 #pragma unroll
           for (int q = 0; q < P; ++q) X[q] = Xn[q];
-          if (i + 1 < I) fetch_x(Xn, i + 1);
+          if (i + 1 < I) fetch(bk, g, i + 1);
+          else if (g + 1 < ng) fetch(bk, g + 1, 0);
+          else if (bk + 1 < nb) fetch(bk + 1, 0, 0);
           if (g == 0) {
             Fft<PL>::forward(X, lds, tw, t);
             Fft<PL>::post(X, tw, t);
@@ -511,7 +558,49 @@ __device__ __forceinline__ void mix_utterance(const MixArgs& A, int u, const Sch
           if constexpr (JG == 2) {
             if (two) mac_regs<PL>(Y1, Hp1, X, t);
           }
+        }
+        // Carries that fit the first P/4 slots of each thread (all but very
+        // long RIRs) are requested for both mics before either inverse
+        // transform, so their latency is hidden; longer ones are read after.
+        float* y0 = A.y + yo + (long long)j0 * ys + base;
+        constexpr int CR = P / 4;
+        if (carry <= 2 * PL::T * CR) {
+          cf C0[CR], C1[CR];
+          load_carry<PL, CR>(C0, y0, lim, carry, t);
+          if constexpr (JG == 2) {
+            if (two) load_carry<PL, CR>(C1, y0 + ys, lim, carry, t);
+          }
+          emit_carried<PL, CR>(Y0, C0, lds, tw, y0, lim, t);
+          if constexpr (JG == 2) {
+            if (two) emit_carried<PL, CR>(Y1, C1, lds, tw, y0 + ys, lim, t);
+          }
         } else {
+          emit<PL>(Y0, lds, tw, y0, lim, carry, t);
+          if constexpr (JG == 2) {
+            if (two) emit<PL>(Y1, lds, tw, y0 + ys, lim, carry, t);
+          }
+        }
+      }
+    }
+  } else {
+    for (int bk = 0; bk < nb; ++bk) {
+      const int base = bk * B;
+      const int nvalid = min(B, Nx - base);
+      const int lim = min(span, tu - base);
+      const int carry = bk == 0 ? 0 : lmax - 1;
+      for (int g = 0; g < ng; ++g) {
+        const int j0 = g * JG;
+        const bool two = JG == 2 && j0 + 1 < J;
+        cf Y0[P], Y1[JG == 2 ? P : 1];
+#pragma unroll
+        for (int q = 0; q < P; ++q) Y0[q] = mk(0.f, 0.f);
+        if constexpr (JG == 2) {
+#pragma unroll
+          for (int q = 0; q < P; ++q) Y1[q] = mk(0.f, 0.f);
+        }
+        for (int i = 0; i < I; ++i) {
+          cf X[P];
+          const cf* H0 = Hs + (long long)(i * J + j0) * M;
           if (g == 0) {
             load_real<PL>(X, A.x + uni64(b.src_off[(long long)u * NS + i]) + base, nvalid, t);
             Fft<PL>::forward(X, lds, tw, t);
@@ -527,10 +616,10 @@ __device__ __forceinline__ void mix_utterance(const MixArgs& A, int u, const Sch
             mac<PL>(Y0, H0, X, t);
           }
         }
-      }
-      emit<PL>(Y0, lds, tw, A.y + yo + (long long)j0 * ys + base, lim, carry, t);
-      if constexpr (JG == 2) {
-        if (two) emit<PL>(Y1, lds, tw, A.y + yo + (long long)(j0 + 1) * ys + base, lim, carry, t);
+        emit<PL>(Y0, lds, tw, A.y + yo + (long long)j0 * ys + base, lim, carry, t);
+        if constexpr (JG == 2) {
+          if (two) emit<PL>(Y1, lds, tw, A.y + yo + (long long)(j0 + 1) * ys + base, lim, carry, t);
+        }
       }
     }
   }
