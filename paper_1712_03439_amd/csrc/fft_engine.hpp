@@ -61,6 +61,8 @@ __device__ __forceinline__ const T* opaque(const T* p) {
 // loads past it return 0 and stores past it are dropped, which gives the
 // zero padding of a signal block and the clipping of an output block without
 // branches.  The `so` operand is not range-checked (constant strides only).
+// The check is per 32-bit word: a 64-bit access that straddles the end keeps
+// its first word and drops (reads 0 for) the second.
 typedef __amdgpu_buffer_rsrc_t rsrc_t;
 constexpr int kRsrcWord3 = 0x00020000;  // raw buffer, 32-bit data format (gfx9 family)
 

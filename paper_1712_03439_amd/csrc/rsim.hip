@@ -313,7 +313,7 @@ __device__ __forceinline__ void load_real(cf* v, const float* __restrict__ src, 
   const rsrc_t rs = make_rsrc(src, nvalid * 4);
   const int vo = 8 * t;
 #pragma unroll
-  for (int r = 0; r < PL::P; ++r) v[r] = mk(ld1(rs, vo + 8 * r * PL::T), ld1(rs, vo + 8 * r * PL::T + 4));
+  for (int r = 0; r < PL::P; ++r) v[r] = ld2(rs, vo + 8 * r * PL::T);
 }
 
 // Spectra in memory: slot q of thread t at index q * T + t.
@@ -414,10 +414,8 @@ __device__ __forceinline__ void emit(cf* Yv, cf* lds, const TwBase& tw, float* _
 #pragma unroll
   for (int r = 0; r < PL::P; ++r) {
     const int o = vo + 8 * r * PL::T;
-    const float a = Yv[r].x + ld1(rd, o);
-    const float b = Yv[r].y + ld1(rd, o + 4);
-    st1(wr, o, a);
-    st1(wr, o + 4, b);
+    const cf c = ld2(rd, o);
+    st2(wr, o, mk(Yv[r].x + c.x, Yv[r].y + c.y));
   }
 }
 
@@ -432,7 +430,7 @@ __device__ __forceinline__ void load_carry(cf* c, const float* __restrict__ yp, 
 #pragma unroll
   for (int r = 0; r < CR; ++r) {
     const int o = vo + 8 * r * PL::T;
-    c[r] = mk(ld1(rd, o), ld1(rd, o + 4));
+    c[r] = ld2(rd, o);
   }
 }
 
@@ -450,8 +448,7 @@ __device__ __forceinline__ void emit_carried(cf* Yv, const cf* c, cf* lds, const
   for (int r = 0; r < PL::P; ++r) {
     const int o = vo + 8 * r * PL::T;
     const cf cr = r < CR ? c[r] : mk(0.f, 0.f);
-    st1(wr, o, Yv[r].x + cr.x);
-    st1(wr, o + 4, Yv[r].y + cr.y);
+    st2(wr, o, mk(Yv[r].x + cr.x, Yv[r].y + cr.y));
   }
 }
 
@@ -718,8 +715,7 @@ __device__ __forceinline__ void emit_store(cf* Yv, cf* lds, const TwBase& tw, fl
 #pragma unroll
   for (int r = 0; r < PL::P; ++r) {
     const int o = vo + 8 * r * PL::T;
-    st1(wr, o, Yv[r].x);
-    st1(wr, o + 4, Yv[r].y);
+    st2(wr, o, Yv[r]);
   }
 }
 
@@ -820,9 +816,9 @@ __device__ __forceinline__ void bwd_utterance(const BwdArgs& A, int u, const Sch
 #pragma unroll
       for (int q = 0; q < P; ++q) {
         const int o = 8 * (t + q * PL::T);
-        part += (double)ld1(hr, o) * (double)v[q].x + (double)ld1(hr, o + 4) * (double)v[q].y;
-        st1(gw, o, a * v[q].x);
-        st1(gw, o + 4, a * v[q].y);
+        const cf hv = ld2(hr, o);
+        part += (double)hv.x * (double)v[q].x + (double)hv.y * (double)v[q].y;
+        st2(gw, o, mk(a * v[q].x, a * v[q].y));
       }
       const double da = block_sum_d<PL::T>(part, s_red, t);
       if (t == 0 && A.galpha) A.galpha[r] = (float)da;
