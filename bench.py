@@ -30,7 +30,35 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-FP32_PEAK_TFLOPS = 157.3
+# FP32 vector peak without packed FP32 instructions (which this build does not
+# emit): 256 CUs x 64 lanes x 2 FLOP per FMA x 2.4 GHz.
+FP32_PEAK_TFLOPS = 78.6
+COUNTERS = os.path.join(ROOT, "profiles", "mix_kernel_batched2048_hbm_counters.json")
+
+
+def source_digest() -> str:
+    """Digest of the kernel sources; counters taken on other sources are stale."""
+    import hashlib
+
+    h = hashlib.sha256()
+    for rel in ("paper_1712_03439_amd/csrc/rsim.hip", "paper_1712_03439_amd/csrc/fft_engine.hpp",
+                "paper_1712_03439_amd/csrc/kernels.hpp", "include/rsim.h"):
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def counter_traffic():
+    """HBM bytes per mix launch from the committed rocprofv3 counter summary,
+    or None when the kernels have changed since it was taken."""
+    try:
+        with open(COUNTERS) as f:
+            c = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if c.get("source_sha256") != source_digest():
+        return None
+    return int(c["fetch_bytes_per_launch"] + c["write_bytes_per_launch"])
 
 
 def log(msg: str) -> None:
@@ -43,22 +71,37 @@ def lpt_order(b) -> np.ndarray:
     return np.argsort(-cost, kind="stable").astype(np.int32)
 
 
-def host_plan(nx, I, J, lmax, tune_fft, tune_mac):
-    """The FFT size the schedule kernel picks (same cost rule), for FLOP accounting."""
-    best, l2b = None, 0
+def utt_cost(nx, I, J, lmax, m, tune_fft, tune_mac):
+    """The schedule's cost of one utterance at N = 2^m (None if N cannot serve it)."""
+    c = tune_fft[m - 9]
+    N = 1 << m
+    if not c > 0 or N < lmax:
+        return None
+    B = N - lmax + 1
+    nb = (nx + B - 1) // B
+    return nb * ((I + J) * c + I * J * tune_mac[m - 9]) + I * J * c
+
+
+def batch_log2n(shapes, tune_fft, tune_mac):
+    """The one size the schedule picks for a batch (smallest summed cost among
+    the sizes every utterance can use), or 0."""
+    tot = {}
     for m in range(9, 16):
-        c = tune_fft[m - 9]
-        if not c > 0:
-            continue
-        N = 1 << m
-        if N < lmax:
-            continue
-        B = N - lmax + 1
-        nb = (nx + B - 1) // B
-        cost = nb * ((I + J) * c + I * J * tune_mac[m - 9]) + I * J * c
-        if best is None or cost < best:
-            best, l2b = cost, m
-    N = 1 << l2b
+        cs = [utt_cost(nx, I, J, lmax, m, tune_fft, tune_mac) for nx, I, J, lmax in shapes]
+        if all(c is not None for c in cs):
+            tot[m] = sum(cs)
+    return min(tot, key=tot.get) if tot else 0
+
+
+def host_plan(nx, I, J, lmax, tune_fft, tune_mac, l2=0):
+    """The FFT size the schedule kernel picks (same cost rule), for FLOP accounting."""
+    if not l2:
+        best = None
+        for m in range(9, 16):
+            cost = utt_cost(nx, I, J, lmax, m, tune_fft, tune_mac)
+            if cost is not None and (best is None or cost < best):
+                best, l2 = cost, m
+    N = 1 << l2
     B = N - lmax + 1
     return N, B, (nx + B - 1) // B
 
@@ -203,6 +246,8 @@ def main() -> int:
 
     # Algorithmic bytes and FLOPs of the mix launches of the timed epochs.
     byt, flops, byt_cut = [], [], []
+    sizes = {}
+    one_size = True if tune is None else bool(tune.one_size)
     for k in range(K):
         b, db, _ = epochs[(W + k) % E]
         L = db.rir_len.cpu().numpy().astype(np.int64)
@@ -213,19 +258,28 @@ def main() -> int:
         byt_cut.append(4 * np.sum(b.rir_len0.astype(np.int64)))
         f = 0.0
         Lr = L.reshape(b.n_utt, b.max_src * J)
-        for u in range(b.n_utt):
-            lmax = int(Lr[u].max())
-            if lmax == 0 or b.src_len[u] == 0:
-                continue
-            N, B, nb = host_plan(int(b.src_len[u]), int(I[u]), J, lmax, tf, tm)
+        shapes = [(int(b.src_len[u]), int(I[u]), J, int(Lr[u].max())) for u in range(b.n_utt)
+                  if int(Lr[u].max()) > 0 and b.src_len[u] > 0]
+        l2b = batch_log2n(shapes, tf, tm) if one_size else 0
+        for nx, Iu, _, lmax in shapes:
+            N, B, nb = host_plan(nx, Iu, J, lmax, tf, tm, l2b)
             c = 2.5 * N * math.log2(N)
-            f += nb * ((I[u] + J) * c + I[u] * J * 8 * (N / 2 + 1)) + I[u] * J * c
+            f += nb * ((Iu + J) * c + Iu * J * 8 * (N / 2 + 1)) + Iu * J * c
+            sizes[N] = sizes.get(N, 0) + 1
         flops.append(f)
     t_mix = float(np.mean(mix_ms)) * 1e-3
     achieved = float(np.mean(byt)) / t_mix / 1e9
     alu = float(np.mean(flops)) / t_mix / 1e12
-    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None}
+    # The binding bound of the mix is the one with the longer time at peak:
+    # FP32 vector arithmetic (no packed FP32 in this build) or HBM.
+    t_alu, t_hbm = float(np.mean(flops)) / (FP32_PEAK_TFLOPS * 1e12), float(np.mean(byt)) / (HBM_PEAK_GBS * 1e9)
+    traffic = counter_traffic()
+    if t_alu >= t_hbm:
+        roof = {"bound": "alu", "achieved": round(alu, 2), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(alu / FP32_PEAK_TFLOPS, 4), "traffic": traffic}
+    else:
+        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic}
     result = {
         "metric": "simulated audio-sec/sec (FP32, 1 MI355X) batched vs plain; HBM GB/s fraction",
         "value": round(value, 1),
@@ -244,12 +298,15 @@ def main() -> int:
                                f"{args.eta:g} dB, SNR U(0,30) dB, fresh RIRs every epoch",
                    "global_batch": base.n_utt, "audio_s_per_step": round(audio, 1),
                    "eta_db": args.eta, "hip_graph": use_graph,
-                   "tune": "autotuned" if args.tune != "model" and tune is not None else "cost model"},
+                   "fft_sizes": {str(k): v // K for k, v in sorted(sizes.items())},
+                   "tune": ("measured table" if args.tune != "model" and tune is not None else "cost model")
+                           + (", one size per batch" if one_size else ", size per utterance")},
         "roofline": roof,
+        "hbm": {"achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4)},
         "kernel_ms": {"cut": round(float(np.mean(trunc_ms)), 4), "mix": round(float(np.mean(mix_ms)), 4)},
-        "alu": {"achieved_tflops": round(alu, 2), "peak_tflops": FP32_PEAK_TFLOPS,
-                "frac": round(alu / FP32_PEAK_TFLOPS, 4),
-                "flop_model": "2.5 N log2 N per real FFT + 8 (N/2+1) per spectral MAC"},
+        "alu_model": "2.5 N log2 N per real FFT + 8 (N/2+1) per spectral MAC; peak = 256 CUs x 64 lanes x "
+                     "2 FLOP (FMA) x 2.4 GHz",
         "bytes_per_step": {"mix": int(np.mean(byt)), "cut": int(np.mean(byt_cut))},
     }
 

@@ -38,7 +38,7 @@ typedef enum {
   RSIM_EINVAL = 1,       /* bad argument (null pointer, negative size, eta < 0 or NaN, ...) */
   RSIM_EWORKSPACE = 2,   /* ws is null or smaller than the *_workspace_bytes() value */
   RSIM_EUNSUPPORTED = 3, /* FFT size not a power of two in [512, 32768], or hop/RIR do not fit */
-  RSIM_EDEVICE = 4,      /* a HIP runtime call failed (launch, capture, copy) */
+  RSIM_EDEVICE = 4,      /* a HIP runtime call failed (launch, graph, copy) */
   RSIM_ENOTINIT = 5      /* first use on this device happened during stream capture */
 } rsim_status;
 
@@ -88,11 +88,17 @@ typedef struct rsim_batch {
  * its N/2+1 bins; 0 disables that size.  The cost of an utterance with I
  * sources, J mics, hop B and n_b = ceil(Nx/B) blocks is
  *   n_b * ((I + J) * cost_fft + I*J * cost_mac) + I*J * cost_fft.
- * Passing NULL selects the built-in model 2.5 N log2 N / 8 (N/2+1) over all sizes.
+ * Passing NULL selects the built-in model 2.5 N log2 N / 8 (N/2+1) over all
+ * sizes with one_size = 1.
+ * one_size != 0 picks one N for the whole batch instead: the size with the
+ * smallest cost summed over the utterances among the sizes that every
+ * utterance can use (each utterance keeps its own choice if there is none).
+ * Sizes forced through rsim_batch.fft_log2n take precedence over both rules.
  */
 typedef struct rsim_tune {
   float cost_fft[7];
   float cost_mac[7];
+  int32_t one_size;
 } rsim_tune;
 
 /* Initialise the library on the current device (twiddle tables, launch
@@ -132,8 +138,13 @@ rsim_status rsim_ola_convolve(const float* x, int32_t nx, const float* h, int32_
  *   y_j[n] = sum_{i < n_src[u]} alpha[r] (h_r[0..rir_len[r]) * x_i)[n],
  * r = (u*S + i)*J + j, by overlap-add FFT filtering with an FFT size chosen
  * per utterance (fft_log2n, else the tune table / built-in cost model, eq. (6)).
- * alpha has U*S*J entries.  use_graph != 0 captures the call's launches into a
- * HIP graph, instantiates and launches it (the stream must not be capturing).
+ * alpha has U*S*J entries.  The call's kernels are a schedule kernel and one
+ * persistent kernel per FFT-size family; eagerly (use_graph == 0) the family
+ * kernels run concurrently on the library's side streams, forked from and
+ * joined back into `stream` (one after the other when `stream` is being
+ * captured).  use_graph != 0 builds them into one HIP graph, a chain (the
+ * family kernels one after the other), instantiates it and launches it on
+ * `stream` (which must not be capturing; the null stream is allowed).
  * ws must hold rsim_mix_workspace_bytes(b, tune, 0) bytes.
  */
 size_t rsim_mix_workspace_bytes(const rsim_batch* b, const rsim_tune* tune, int32_t backward);

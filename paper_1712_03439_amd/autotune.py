@@ -2,7 +2,8 @@
 
 For every utterance the schedule kernel evaluates, for each N = 2^m,
     n_b (I + J) c_fft(N) + n_b I J c_mac(N) + I J c_fft(N),   n_b = ceil(Nx / (N - L + 1)),
-and keeps the cheapest N.  The paper's cost model counts multiplications
+and keeps the cheapest N, or (one_size, the default) the one N with the
+smallest cost summed over the batch.  The paper's cost model counts multiplications
 (eq. (6)); the kernels do I + J transforms per block (source spectra are shared
 across mics and the sum over sources is taken in the spectral domain), so the
 built-in model uses that count with 2.5 N log2 N per real FFT.  `tune()`
@@ -168,7 +169,7 @@ def load(which: str = "auto"):
     entry = data if "cost_fft" in data else data.get(device_name())
     if not entry:
         return None
-    return rsim.tune_table(entry["cost_fft"], entry["cost_mac"])
+    return rsim.tune_table(entry["cost_fft"], entry["cost_mac"], entry.get("one_size", True))
 
 
 if __name__ == "__main__":

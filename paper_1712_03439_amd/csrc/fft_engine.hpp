@@ -78,6 +78,10 @@ __device__ __forceinline__ void st1(rsrc_t r, int vo, float v, int so = 0) {
 __device__ __forceinline__ cf ld2(rsrc_t r, int vo, int so = 0) {
   return __builtin_bit_cast(cf, __builtin_amdgcn_raw_buffer_load_b64(r, vo, so, 0));
 }
+typedef float f4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ f4 ld4(rsrc_t r, int vo, int so = 0) {
+  return __builtin_bit_cast(f4, __builtin_amdgcn_raw_buffer_load_b128(r, vo, so, 0));
+}
 __device__ __forceinline__ void st2(rsrc_t r, int vo, cf v, int so = 0) {
   typedef unsigned u2 __attribute__((ext_vector_type(2)));
   __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), r, vo, so, 0);

@@ -50,6 +50,7 @@ struct BatchDev {
 struct TuneDev {
   float cost_fft[7];
   float cost_mac[7];
+  int one_size;
 };
 
 // Workspace header shared by the schedule and mix launches of one call.

@@ -62,11 +62,14 @@ __device__ __forceinline__ double wave_sum_d(double v) {
 }
 
 // =============================================================== RIR cut-off
-// One workgroup (256 threads) per RIR.  P = max_n fl(h^2) by a max-reduction
-// (exact in any order), p_th = fl(P s), then the last index with q >= p_th,
-// searched in chunks from the tail so only the cut part is re-read.
+// One wave per RIR (four per workgroup), no workgroup barrier: each lane
+// reads four consecutive taps per step (one 128-bit access; the range check
+// zero-fills past L0).  P = max_n fl(h^2) by a max-reduction (exact in any
+// order), p_th = fl(P s), then the last index with q >= p_th, searched 256
+// taps at a time from the tail, so only the part behind the cut is read
+// twice (the second time from cache).
 constexpr int kTruncThreads = 256;
-constexpr int kTruncChunk = 1024;
+constexpr int kTruncWaves = kTruncThreads / 64;
 
 struct TruncArgs {
   const float* h;
@@ -80,102 +83,88 @@ struct TruncArgs {
 };
 
 __global__ __launch_bounds__(kTruncThreads) void truncate_kernel(TruncArgs A) {
-  const float* __restrict__ h = A.h;
-  const long long h_len = A.h_len;
-  const long long* __restrict__ off = A.off;
-  const int* __restrict__ len0 = A.len0;
-  const int n_rir = A.n_rir;
-  const float s = A.s;
-  int* __restrict__ n_c = A.n_c;
-  int* __restrict__ len = A.len;
-  __shared__ float s_f[4];
-  __shared__ int s_i[4];
-  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  for (int r = blockIdx.x; r < n_rir; r += gridDim.x) {
-    const int L0 = len0[r];
-    const long long o = off[r];
-    if (L0 < 0 || o < 0 || o + (long long)L0 > h_len) {
-      if (t == 0) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int r0 = blockIdx.x * kTruncWaves; r0 < A.n_rir; r0 += gridDim.x * kTruncWaves) {
+    const int r = r0 + w;
+    if (r >= A.n_rir) continue;
+    const int L0 = uni(A.len0[r]);
+    const long long o = uni64(A.off[r]);
+    if (L0 < 0 || o < 0 || o + (long long)L0 > A.h_len) {
+      if (lane == 0) {
         flag_status(RSIM_DEV_BADDESC);
-        if (n_c) n_c[r] = -1;
-        len[r] = 0;
+        if (A.n_c) A.n_c[r] = -1;
+        A.len[r] = 0;
       }
       continue;
     }
     if (L0 == 0) {
-      if (t == 0) {
-        if (n_c) n_c[r] = -1;
-        len[r] = 0;
+      if (lane == 0) {
+        if (A.n_c) A.n_c[r] = -1;
+        A.len[r] = 0;
       }
       continue;
     }
-    const float* p = h + o;
+    const rsrc_t rs = make_rsrc(A.h + o, L0 * 4);
+    const int vo = 16 * lane;
     float mx = 0.0f;
     int nf = 0;
-    for (int i = t; i < L0; i += kTruncThreads) {
-      const float v = p[i];
-      const float q = v * v;
-      nf |= !__builtin_isfinite(q);
-      mx = fmaxf(mx, q);
+    for (int base = 0; base < L0; base += 256) {
+      const f4 v = ld4(rs, vo + 4 * base);  // whole offset range-checked
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const float q = v[k] * v[k];
+        nf |= !__builtin_isfinite(q);
+        mx = fmaxf(mx, q);
+      }
     }
     mx = wave_max(mx);
     nf = wave_or(nf);
-    __syncthreads();
-    if (lane == 0) {
-      s_f[w] = mx;
-      s_i[w] = nf;
-    }
-    __syncthreads();
-    mx = fmaxf(fmaxf(s_f[0], s_f[1]), fmaxf(s_f[2], s_f[3]));
-    nf = s_i[0] | s_i[1] | s_i[2] | s_i[3];
     if (nf) {
-      if (t == 0) {
+      if (lane == 0) {
         flag_status(RSIM_DEV_NONFINITE);
-        if (n_c) n_c[r] = L0 - 1;
-        len[r] = L0;
+        if (A.n_c) A.n_c[r] = L0 - 1;
+        A.len[r] = L0;
       }
       continue;
     }
-    const float pth = mx * s;
+    const float pth = mx * A.s;
     int found = -1;
-    for (int base = ((L0 - 1) / kTruncChunk) * kTruncChunk; base >= 0 && found < 0;
-         base -= kTruncChunk) {
+    for (int base = ((L0 - 1) / 256) * 256; base >= 0; base -= 256) {
+      const f4 v = ld4(rs, vo + 4 * base);  // whole offset range-checked
       int loc = -1;
 #pragma unroll
-      for (int k = 0; k < kTruncChunk / kTruncThreads; ++k) {
-        const int i = base + k * kTruncThreads + t;
-        if (i < L0) {
-          const float v = p[i];
-          if (v * v >= pth) loc = i;
-        }
+      for (int k = 0; k < 4; ++k) {
+        const int idx = base + 4 * lane + k;
+        if (idx < L0 && v[k] * v[k] >= pth) loc = idx;
       }
       loc = wave_max_i(loc);
-      __syncthreads();
-      if (lane == 0) s_i[w] = loc;
-      __syncthreads();
-      found = max(max(s_i[0], s_i[1]), max(s_i[2], s_i[3]));
+      if (loc >= 0) {
+        found = loc;
+        break;
+      }
     }
-    if (t == 0) {
-      if (n_c) n_c[r] = found;
-      len[r] = min(found + 2, L0);
+    if (lane == 0) {
+      if (A.n_c) A.n_c[r] = found;
+      A.len[r] = min(found + 2, L0);
     }
   }
 }
 
 // ================================================================= schedule
-__device__ Sched plan_utterance(const BatchDev& b, const TuneDev& tune, int u, int& err) {
-  Sched S = {0, 0, 0, 0, 0, 0};
+// Validates utterance u's descriptor and returns its longest kept RIR
+// (0: nothing to write); -1 (with err set) for a bad descriptor.
+__device__ int utterance_lmax(const BatchDev& b, int u, int& err) {
   const int I = b.n_src[u], Nx = b.src_len[u], J = b.J;
   if (I < 0 || I > b.S || Nx < 0) {
     err |= RSIM_DEV_BADDESC;
-    return S;
+    return -1;
   }
   int lmax = 0;
   for (int i = 0; i < I; ++i) {
     const long long so = b.src_off[(long long)u * b.S + i];
     if (so < 0 || so + Nx > b.x_len) {
       err |= RSIM_DEV_BADDESC;
-      return S;
+      return -1;
     }
     for (int j = 0; j < J; ++j) {
       const long long r = ((long long)u * b.S + i) * J + j;
@@ -183,33 +172,55 @@ __device__ Sched plan_utterance(const BatchDev& b, const TuneDev& tune, int u, i
       const long long ro = b.rir_off[r];
       if (L < 0 || L > L0 || ro < 0 || ro + L0 > b.h_len) {
         err |= RSIM_DEV_BADDESC;
-        return S;
+        return -1;
       }
       lmax = max(lmax, L);
     }
   }
-  if (I == 0 || Nx == 0 || lmax == 0) return S;  // nothing to write
+  if (I == 0 || Nx == 0 || lmax == 0) return 0;  // nothing to write
   const long long tu = (long long)Nx + lmax - 1;
   const long long ys = b.out_stride[u], yo = b.out_off[u];
   if (tu > 0x7fffffffLL || ys < tu || yo < 0 || yo + (long long)J * ys > b.y_len) {
     err |= RSIM_DEV_BADDESC;
-    return S;
+    return -1;
   }
+  return lmax;
+}
+
+// Cost of utterance u at N = 2^m under the tune table (eq. 6's rule with the
+// kernel's transform count); negative when N cannot serve it.
+__device__ float utterance_cost(const BatchDev& b, const TuneDev& tune, int u, int lmax, int m) {
+  const float cf_ = tune.cost_fft[m - 9], cm = tune.cost_mac[m - 9];
+  if (!(cf_ > 0.f)) return -1.f;
+  const int N = 1 << m;
+  if (N < lmax) return -1.f;
+  const int given_hop = b.hop ? b.hop[u] : 0;
+  const int B = given_hop ? given_hop : N - lmax + 1;
+  if (B < 1 || B + lmax - 1 > N) return -1.f;
+  const int I = b.n_src[u], Nx = b.src_len[u], J = b.J;
+  const float nbf = (float)((Nx + B - 1) / B);
+  return nbf * ((float)(I + J) * cf_ + (float)(I * J) * cm) + (float)(I * J) * cf_;
+}
+
+// The plan of utterance u: the forced size if the descriptor gives one, else
+// `batch_l2` if nonzero (one size for the whole batch), else its cheapest size.
+__device__ Sched plan_utterance(const BatchDev& b, const TuneDev& tune, int u, int batch_l2, int& err) {
+  Sched S = {0, 0, 0, 0, 0, 0};
+  const int lmax = utterance_lmax(b, u, err);
+  if (lmax <= 0) return S;
+  const int Nx = b.src_len[u];
+  const long long tu = (long long)Nx + lmax - 1;
   const int given_hop = b.hop ? b.hop[u] : 0;
   int l2 = 0;
   if (b.fft_log2n) {
     l2 = b.fft_log2n[u];
+  } else if (batch_l2) {
+    l2 = batch_l2;
   } else {
     float best = 0.f;
     for (int m = 9; m <= 15; ++m) {
-      const float cf_ = tune.cost_fft[m - 9], cm = tune.cost_mac[m - 9];
-      if (!(cf_ > 0.f)) continue;
-      const int N = 1 << m;
-      if (N < lmax) continue;
-      const int B = given_hop ? given_hop : N - lmax + 1;
-      if (B < 1 || B + lmax - 1 > N) continue;
-      const float nbf = (float)((Nx + B - 1) / B);
-      const float cost = nbf * ((float)(I + J) * cf_ + (float)(I * J) * cm) + (float)(I * J) * cf_;
+      const float cost = utterance_cost(b, tune, u, lmax, m);
+      if (cost < 0.f) continue;
       if (l2 == 0 || cost < best) {
         best = cost;
         l2 = m;
@@ -260,6 +271,43 @@ __global__ __launch_bounds__(kSchedThreads) void schedule_kernel(SchedArgs A) {
     s_base[t] = 0;
   }
   int err = 0;
+  // One size for the whole batch: the size with the smallest cost summed over
+  // the utterances, among the sizes every utterance with work can use.
+  __shared__ double s_cost[7];
+  __shared__ int s_bad[7];
+  __shared__ int s_l2;
+  int batch_l2 = 0;
+  if (tune.one_size && !b.fft_log2n) {
+    if (t < 7) {
+      s_cost[t] = 0.0;
+      s_bad[t] = 0;
+    }
+    __syncthreads();
+    for (int c0 = 0; c0 < b.U; c0 += kSchedThreads) {
+      const int u = c0 + t;
+      int e = 0;
+      const int lmax = u < b.U ? utterance_lmax(b, u, e) : 0;
+      for (int m = 9; m <= 15; ++m) {
+        const float c = lmax > 0 ? utterance_cost(b, tune, u, lmax, m) : 0.f;
+        const double cs = wave_sum_d(c > 0.f ? (double)c : 0.0);
+        const int bad = wave_or(lmax > 0 && c < 0.f);
+        if ((t & 63) == 0) {
+          atomicAdd(&s_cost[m - 9], cs);
+          if (bad) atomicOr(&s_bad[m - 9], 1);
+        }
+      }
+    }
+    __syncthreads();
+    if (t == 0) {
+      int best = 0;
+      for (int m = 9; m <= 15; ++m)
+        if (!s_bad[m - 9] && tune.cost_fft[m - 9] > 0.f && (best == 0 || s_cost[m - 9] < s_cost[best - 9]))
+          best = m;
+      s_l2 = best;  // 0: no common size, each utterance takes its own
+    }
+    __syncthreads();
+    batch_l2 = s_l2;
+  }
   __syncthreads();
   for (int c0 = 0; c0 < b.U; c0 += kSchedThreads) {
     const int idx = c0 + t;
@@ -270,7 +318,7 @@ __global__ __launch_bounds__(kSchedThreads) void schedule_kernel(SchedArgs A) {
         err |= RSIM_DEV_BADDESC;
         u = -1;
       } else {
-        const Sched S = plan_utterance(b, tune, u, err);
+        const Sched S = plan_utterance(b, tune, u, batch_l2, err);
         sched[u] = S;
         b.out_len[u] = S.tu;
         fam = S.nb > 0 ? family_of_log2n(S.log2n) : -1;
@@ -1063,6 +1111,7 @@ DevState g_dev[kMaxDev];
 struct Retired {
   hipGraphExec_t exec;
   hipEvent_t done;
+  bool seen_done;  // its event was observed complete by an earlier pass
 };
 std::deque<Retired> g_retired;
 
@@ -1180,6 +1229,7 @@ TuneDev default_tune() {
     t.cost_fft[m - 9] = (float)(2.5 * N * m);
     t.cost_mac[m - 9] = (float)(8.0 * (N / 2 + 1));
   }
+  t.one_size = 1;
   return t;
 }
 
@@ -1190,6 +1240,7 @@ TuneDev to_dev(const rsim_tune* tune) {
     t.cost_fft[k] = tune->cost_fft[k];
     t.cost_mac[k] = tune->cost_mac[k];
   }
+  t.one_size = tune->one_size;
   return t;
 }
 
@@ -1339,19 +1390,32 @@ rsim_status issue_eager(CallPlan& P, hipStream_t s) {
   return RSIM_OK;
 }
 
+// Executable graphs are destroyed late: one whose completion event has been
+// seen complete is destroyed only at a later call (two-phase), never in the
+// same pass that observed it.
 void gc_retired(bool wait) {
   while (!g_retired.empty()) {
     Retired& r = g_retired.front();
-    if (!wait) {
-      const hipError_t q = hipEventQuery(r.done);
-      if (q == hipErrorNotReady) (void)hipGetLastError();  // not an error: leave none behind
-      if (q != hipSuccess) break;
-    } else {
+    if (wait) {
       (void)hipEventSynchronize(r.done);
+    } else if (!r.seen_done) {
+      break;
     }
     (void)hipGraphExecDestroy(r.exec);
     (void)hipEventDestroy(r.done);
     g_retired.pop_front();
+  }
+  if (!wait) {
+    for (Retired& r : g_retired) {
+      if (r.seen_done) continue;
+      const hipError_t q = hipEventQuery(r.done);
+      if (q == hipErrorNotReady) {
+        (void)hipGetLastError();  // not an error: leave none behind
+        break;
+      }
+      if (q == hipSuccess) r.seen_done = true;
+      else break;
+    }
   }
 }
 
@@ -1375,11 +1439,20 @@ rsim_status issue_graph(CallPlan& P, hipStream_t s) {
     kp.extra = nullptr;
     return hipGraphAddKernelNode(out, g, deps, nd, &kp) == hipSuccess;
   };
-  hipGraphNode_t cut = nullptr, sch = nullptr, fam = nullptr;
+  // A chain: cut -> schedule -> family kernels one after another.  Graphs
+  // with parallel branches are not built: a run with them ended in a host
+  // segmentation fault whose cause is not identified (concurrent family
+  // kernels remain available on the eager path).
+  hipGraphNode_t prev = nullptr;
   bool ok = true;
-  if (P.has_cut) ok = add(P.cut, nullptr, 0, &cut);
-  ok = ok && add(P.sched, P.has_cut ? &cut : nullptr, P.has_cut ? 1 : 0, &sch);
-  for (int k = 0; ok && k < P.nf; ++k) ok = add(P.fam[k], &sch, 1, &fam);
+  if (P.has_cut) ok = add(P.cut, nullptr, 0, &prev);
+  hipGraphNode_t node = nullptr;
+  ok = ok && add(P.sched, prev ? &prev : nullptr, prev ? 1 : 0, &node);
+  prev = node;
+  for (int k = 0; ok && k < P.nf; ++k) {
+    ok = add(P.fam[k], &prev, 1, &node);
+    prev = node;
+  }
   hipGraphExec_t exec = nullptr;
   ok = ok && hipGraphInstantiate(&exec, g, nullptr, nullptr, 0) == hipSuccess;
   (void)hipGraphDestroy(g);
@@ -1400,7 +1473,7 @@ rsim_status issue_graph(CallPlan& P, hipStream_t s) {
   }
   std::lock_guard<std::mutex> lk(g_mu);
   gc_retired(false);
-  g_retired.push_back({exec, ev});
+  g_retired.push_back({exec, ev, false});
   if (g_retired.size() > 64) gc_retired(true);
   return RSIM_OK;
 }
@@ -1502,8 +1575,9 @@ float cut_scale(double eta) {
 void plan_truncate(Node& n, const float* h, long long h_len, const int64_t* off, const int32_t* len0,
                    int n_rir, float s, int32_t* n_c, int32_t* len) {
   const DevState& st = dev_state();
-  int grid = (st.cus > 0 ? st.cus : 256) * 8;
-  if (grid > n_rir) grid = n_rir;
+  long long grid = (long long)(st.cus > 0 ? st.cus : 256) * 16;
+  const long long need = ((long long)n_rir + kTruncWaves - 1) / kTruncWaves;
+  if (grid > need) grid = need;
   if (grid < 1) grid = 1;
   TruncArgs A;
   A.h = h;
@@ -1514,7 +1588,7 @@ void plan_truncate(Node& n, const float* h, long long h_len, const int64_t* off,
   A.s = s;
   A.n_c = n_c;
   A.len = len;
-  n.set(reinterpret_cast<const void*>(&truncate_kernel), dim3(grid), dim3(kTruncThreads), A);
+  n.set(reinterpret_cast<const void*>(&truncate_kernel), dim3((unsigned)grid), dim3(kTruncThreads), A);
 }
 
 int ilog2_exact(int n) {

@@ -49,7 +49,7 @@ class RsimBatch(ctypes.Structure):
 
 
 class RsimTune(ctypes.Structure):
-    _fields_ = [("cost_fft", ctypes.c_float * 7), ("cost_mac", ctypes.c_float * 7)]
+    _fields_ = [("cost_fft", ctypes.c_float * 7), ("cost_mac", ctypes.c_float * 7), ("one_size", ctypes.c_int32)]
 
 
 _LIB = None
@@ -195,11 +195,13 @@ def snr_gains(p_dry: Sequence[float], snr_db: Sequence[float], n_mic: int) -> np
     return a.reshape(I, n_mic)
 
 
-def tune_table(cost_fft: Sequence[float], cost_mac: Sequence[float]) -> RsimTune:
+def tune_table(cost_fft: Sequence[float], cost_mac: Sequence[float], one_size: bool = False) -> RsimTune:
+    """An FFT-size cost table (rsim_tune); one_size picks one N for the whole batch."""
     t = RsimTune()
     for k in range(7):
         t.cost_fft[k] = float(cost_fft[k])
         t.cost_mac[k] = float(cost_mac[k])
+    t.one_size = int(bool(one_size))
     return t
 
 

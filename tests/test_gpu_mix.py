@@ -226,3 +226,18 @@ def test_graph_and_eager_calls_agree_across_families():
             ref = outs[0][off + j * st: off + j * st + T]
             for k in range(1, len(outs)):
                 assert np.array_equal(outs[k][off + j * st: off + j * st + T], ref), (k, u, j)
+
+
+@pytest.mark.gpu
+def test_one_fft_size_for_the_batch():
+    # one N for every utterance (the smallest summed cost), eager and as a graph
+    torch = cuda()
+    from paper_1712_03439_amd import autotune, rsim
+
+    b = synth.make_config2(n_utt=24, epoch=5)
+    f, m = autotune.model_costs()
+    tune = rsim.tune_table(f, m, one_size=True)
+    for graph in (False, True):
+        db, alpha, y, rl, ol = _simulate(b, 20.0, tune=tune, use_graph=graph)
+        for u in range(b.n_utt):
+            _check_utterance(b, u, 20.0, y, rl, ol)
