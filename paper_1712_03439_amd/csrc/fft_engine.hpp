@@ -393,7 +393,13 @@ __device__ __forceinline__ void dispatch_plan(int l2, F&& f) {
   }
 }
 
-// Largest M and LDS footprint over the plans with T threads.
+// LDS available to one workgroup's exchanges (the rest of the 160 KB of a
+// CU is left for small shared arrays), and whether a plan of `lds` complex
+// entries gets two exchange buffers.
+constexpr int kLdsBudgetBytes = 160 * 1024 - 4096;
+constexpr bool double_exchange(int lds) { return 2 * lds * 8 <= kLdsBudgetBytes; }
+
+// Largest M and LDS footprint (exchange buffers) over the plans with T threads.
 template <int T, int L2 = kMinL2>
 constexpr int max_m_with_threads() {
   if constexpr (L2 > kMaxL2) return 0;
@@ -407,7 +413,8 @@ constexpr int max_lds_with_threads() {
   if constexpr (L2 > kMaxL2) return 0;
   else {
     constexpr int rest = max_lds_with_threads<T, L2 + 1>();
-    return PlanOf<L2>::T == T && PlanOf<L2>::LDS > rest ? PlanOf<L2>::LDS : rest;
+    constexpr int mine = (double_exchange(PlanOf<L2>::LDS) ? 2 : 1) * PlanOf<L2>::LDS;
+    return PlanOf<L2>::T == T && mine > rest ? mine : rest;
   }
 }
 
@@ -427,6 +434,29 @@ struct TwBase {
   cf mid[2];  // W_{R_p Ls_p}^{k}, k = t mod Ls_p, for middle passes p = 1, 2
   cf last;    // W_M^{kb}, kb = t (thread 0: T)
   cf post;    // W_N^{c}, c = t (thread 0: T)
+};
+
+// The LDS of a workgroup's data exchanges.  With room for two buffers
+// (every plan but N = 32768) consecutive exchanges alternate between them:
+// an exchange then needs one barrier (between its writes and its reads),
+// because the buffer it writes was last read before the previous exchange's
+// barrier.  With one buffer, a barrier also precedes the writes.  The parity
+// is uniform across the workgroup and starts at 0 for each work item (the
+// persistent loop's barriers separate items).
+template <class PL>
+struct Xch {
+  static constexpr bool kDouble = double_exchange(PL::LDS);
+  static constexpr int kEntries = (kDouble ? 2 : 1) * PL::LDS;
+  cf* base;
+  int par;
+  __device__ cf* buf() const { return kDouble ? base + par * PL::LDS : base; }
+  __device__ void before_write() const {
+    if constexpr (!kDouble) __syncthreads();
+  }
+  __device__ void before_read() const { __syncthreads(); }
+  __device__ void after_read() {
+    if constexpr (kDouble) par ^= 1;
+  }
 };
 
 template <class PL>
@@ -456,32 +486,37 @@ struct Fft {
   // Forward complex FFT.  In: v[r] = z[t + rT].  Out: slot layout (before the
   // real post-processing).  `lds` holds PL::LDS entries.  Contains barriers:
   // every thread of the workgroup must call it.
-  __device__ static __forceinline__ void forward(cf* v, cf* lds, const TwBase& B, int t_) {
+  __device__ static __forceinline__ void forward(cf* v, Xch<PL>& X, const TwBase& B, int t_) {
     const int t = opaque_v(t_);
     // pass 0 (Ls = 1): no twiddles; outputs of butterfly t go to t*R0 + r
     dft<PL::R[0], false>(v);
-    __syncthreads();  // previous users of lds are done
+    X.before_write();
     {
-      cf* dst = lds + t * (PL::R[0] + 1);
+      cf* dst = X.buf() + t * (PL::R[0] + 1);
 #pragma unroll
       for (int r = 0; r < PL::R[0]; ++r) dst[r] = v[r];
     }
-    __syncthreads();
+    X.before_read();
     sfor<NP - 2>([&](auto pc) {
       constexpr int p = decltype(pc)::value + 1;
       constexpr int R = PL::R[p], Ls = PL::ls(p), NB = P / R;
+      {
+        const cf* lds = X.buf();
 #pragma unroll
-      for (int b = 0; b < NB; ++b) {
-        const cf* src = lds + pad<PL>(t + T * b);
+        for (int b = 0; b < NB; ++b) {
+          const cf* src = lds + pad<PL>(t + T * b);
 #pragma unroll
-        for (int r = 0; r < R; ++r) v[b * R + r] = src[r * ps(M / R)];
+          for (int r = 0; r < R; ++r) v[b * R + r] = src[r * ps(M / R)];
+        }
       }
-      __syncthreads();
+      X.after_read();
+      X.before_write();
       for_powers<R>(opaque_c(B.mid[p - 1]), [&](auto rc, cf w) {
         constexpr int r = decltype(rc)::value;
 #pragma unroll
         for (int b = 0; b < NB; ++b) v[b * R + r] = cmul(v[b * R + r], w);
       });
+      cf* lds = X.buf();
 #pragma unroll
       for (int b = 0; b < NB; ++b) {
         const int j = t + T * b;
@@ -492,7 +527,7 @@ struct Fft {
 #pragma unroll
         for (int r = 0; r < R; ++r) dst[r * ps(Ls)] = u[r];
       }
-      __syncthreads();
+      X.before_read();
     });
     // last pass: butterflies ja, jb of radix RL, Ls = 2T.  Both use the
     // twiddles W_M^{r kb}: butterfly jb = 2T - t needs conj(W_M^{r t}) times
@@ -502,6 +537,7 @@ struct Fft {
     const bool t0 = t == 0;
     cf a[RL], b[RL];
     {
+      const cf* lds = X.buf();
       const cf* sa = lds + pad<PL>(ja);
       const cf* sb = lds + pad<PL>(jb);
 #pragma unroll
@@ -510,6 +546,7 @@ struct Fft {
         b[r] = sb[r * ps(2 * T)];
       }
     }
+    X.after_read();
     for_powers<RL>(opaque_c(B.last), [&](auto rc, cf w) {
       constexpr int r = decltype(rc)::value;
       const cf aw = cmul(a[r], w);
@@ -526,7 +563,7 @@ struct Fft {
   }
 
   // Adjoint of forward(): slot layout in, v[r] = M * z[t + rT] out.
-  __device__ static __forceinline__ void inverse(cf* v, cf* lds, const TwBase& B, int t_) {
+  __device__ static __forceinline__ void inverse(cf* v, Xch<PL>& X, const TwBase& B, int t_) {
     const int t = opaque_v(t_);
     const int ja = t, jb = t ? 2 * T - t : T;
     const bool t0 = t == 0;
@@ -544,8 +581,9 @@ struct Fft {
       a[r] = t0 ? a[r] : aw;
       b[r] = cmul(b[r], w);
     });
-    __syncthreads();  // previous users of lds are done
+    X.before_write();
     {
+      cf* lds = X.buf();
       cf* da = lds + pad<PL>(ja);
       cf* db = lds + pad<PL>(jb);
 #pragma unroll
@@ -554,19 +592,23 @@ struct Fft {
         db[r * ps(2 * T)] = b[r];
       }
     }
-    __syncthreads();
+    X.before_read();
     sfor<NP - 2>([&](auto pc) {
       constexpr int p = NP - 2 - decltype(pc)::value;
       constexpr int R = PL::R[p], Ls = PL::ls(p), NB = P / R;
+      {
+        const cf* lds = X.buf();
 #pragma unroll
-      for (int bb = 0; bb < NB; ++bb) {
-        const int j = t + T * bb;
-        const int k = j & (Ls - 1);
-        const cf* src = lds + pad<PL>((j - k) * R + k);
+        for (int bb = 0; bb < NB; ++bb) {
+          const int j = t + T * bb;
+          const int k = j & (Ls - 1);
+          const cf* src = lds + pad<PL>((j - k) * R + k);
 #pragma unroll
-        for (int r = 0; r < R; ++r) v[bb * R + r] = src[r * ps(Ls)];
+          for (int r = 0; r < R; ++r) v[bb * R + r] = src[r * ps(Ls)];
+        }
       }
-      __syncthreads();
+      X.after_read();
+      X.before_write();
 #pragma unroll
       for (int bb = 0; bb < NB; ++bb) dft<R, true>(v + bb * R);
       for_powers<R>(opaque_c(B.mid[p - 1]), [&](auto rc, cf w) {
@@ -574,6 +616,7 @@ struct Fft {
 #pragma unroll
         for (int bb = 0; bb < NB; ++bb) v[bb * R + r] = cmulc(v[bb * R + r], w);
       });
+      cf* lds = X.buf();
 #pragma unroll
       for (int bb = 0; bb < NB; ++bb) {
         const int j = t + T * bb;
@@ -582,13 +625,14 @@ struct Fft {
 #pragma unroll
         for (int r = 0; r < R; ++r) dst[r * ps(M / R)] = u[r];
       }
-      __syncthreads();
+      X.before_read();
     });
     {
-      const cf* src = lds + t * (PL::R[0] + 1);
+      const cf* src = X.buf() + t * (PL::R[0] + 1);
 #pragma unroll
       for (int r = 0; r < PL::R[0]; ++r) v[r] = src[r];
     }
+    X.after_read();
     dft<PL::R[0], true>(v);
   }
 

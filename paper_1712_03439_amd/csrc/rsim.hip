@@ -451,7 +451,7 @@ __device__ __forceinline__ void mac2(cf* Y0, cf* Y1, const cf* __restrict__ H0,
 // blocks (written by this workgroup) and are accumulated.  Both limits are
 // buffer range checks, so no element needs a branch.
 template <class PL>
-__device__ __forceinline__ void emit(cf* Yv, cf* lds, const TwBase& tw, float* __restrict__ yp, int lim,
+__device__ __forceinline__ void emit(cf* Yv, Xch<PL>& lds, const TwBase& tw, float* __restrict__ yp, int lim,
                                      int carry, int t_) {
   Fft<PL>::pre(Yv, tw, t_);
   Fft<PL>::inverse(Yv, lds, tw, t_);
@@ -485,7 +485,7 @@ __device__ __forceinline__ void load_carry(cf* c, const float* __restrict__ yp, 
 // Inverse-transform one mic spectrum, add the preloaded carry (first CR
 // slots) and store the samples below lim.
 template <class PL, int CR>
-__device__ __forceinline__ void emit_carried(cf* Yv, const cf* c, cf* lds, const TwBase& tw, float* __restrict__ yp,
+__device__ __forceinline__ void emit_carried(cf* Yv, const cf* c, Xch<PL>& lds, const TwBase& tw, float* __restrict__ yp,
                                              int lim, int t_) {
   Fft<PL>::pre(Yv, tw, t_);
   Fft<PL>::inverse(Yv, lds, tw, t_);
@@ -509,8 +509,10 @@ __device__ __forceinline__ const cf* plan_tw() {
 // of JG (1 or 2) accumulators; when J > JG the source spectra of the current
 // block are kept in the workgroup's scratch for the later mic groups.
 template <class PL, int JG, int MINW>
-__device__ __forceinline__ void mix_utterance(const MixArgs& A, int u, const Sched& S, cf* lds, cf* slot, int t) {
+__device__ __forceinline__ void mix_utterance(const MixArgs& A, int u, const Sched& S, cf* lds_raw, cf* slot,
+                                              int t) {
   constexpr int P = PL::P, M = PL::M;
+  Xch<PL> lds{lds_raw, 0};
   const TwBase tw = Fft<PL>::bases(plan_tw<PL>(), t);
   const BatchDev& b = A.b;
   const int I = uni(b.n_src[u]), J = b.J, NS = b.S, Nx = uni(b.src_len[u]);
@@ -679,14 +681,18 @@ __global__ __launch_bounds__(T, MINW) void mix_kernel(MixArgs A) {
   __shared__ int s_idx;
   const int t = threadIdx.x;
   cf* slot = A.scratch + (long long)blockIdx.x * A.slot_cf;
-  for (;;) {
+  // The first item of workgroup b is item b; later ones are popped from the
+  // family's counter (offset by the grid), so an empty family costs one load
+  // per workgroup and no atomic.
+  const int count = __builtin_amdgcn_readfirstlane(A.hdr->count[A.fam]);
+  for (int first = 1;; first = 0) {
     __syncthreads();
-    if (t == 0) s_idx = atomicAdd(&A.hdr->counter[A.fam], 1);
+    if (t == 0) s_idx = first ? (int)blockIdx.x : (int)gridDim.x + atomicAdd(&A.hdr->counter[A.fam], 1);
     __syncthreads();
     // Work-item values are uniform across the workgroup; saying so keeps the
     // descriptor loads scalar and the buffer resources in scalar registers.
     const int idx = __builtin_amdgcn_readfirstlane(s_idx);
-    if (idx >= A.hdr->count[A.fam]) break;
+    if (idx >= count) break;
     const int u = __builtin_amdgcn_readfirstlane(A.list[(long long)A.fam * A.b.U + idx]);
     Sched S = A.sched[u];
     S.log2n = __builtin_amdgcn_readfirstlane(S.log2n);
@@ -753,7 +759,7 @@ __device__ __forceinline__ void acc_corr(cf* __restrict__ Rm, const cf* X, const
 
 // Inverse-transform a spectrum and store the first `lim` samples at yp.
 template <class PL>
-__device__ __forceinline__ void emit_store(cf* Yv, cf* lds, const TwBase& tw, float* __restrict__ yp, int lim,
+__device__ __forceinline__ void emit_store(cf* Yv, Xch<PL>& lds, const TwBase& tw, float* __restrict__ yp, int lim,
                                            int t_) {
   Fft<PL>::pre(Yv, tw, t_);
   Fft<PL>::inverse(Yv, lds, tw, t_);
@@ -791,9 +797,10 @@ __device__ __forceinline__ double block_sum_d(double v, double* s_red, int t) {
 // Scratch: alpha-scaled RIR spectra (I J), this block's gradient spectra (J)
 // and the correlation accumulators (I J).
 template <class PL>
-__device__ __forceinline__ void bwd_utterance(const BwdArgs& A, int u, const Sched& S, cf* lds, double* s_red,
-                                              cf* slot, int t) {
+__device__ __forceinline__ void bwd_utterance(const BwdArgs& A, int u, const Sched& S, cf* lds_raw,
+                                              double* s_red, cf* slot, int t) {
   constexpr int P = PL::P, M = PL::M, N = PL::N;
+  Xch<PL> lds{lds_raw, 0};
   const TwBase tw = Fft<PL>::bases(plan_tw<PL>(), t);
   const BatchDev& b = A.b;
   const int I = uni(b.n_src[u]), J = b.J, NS = b.S, Nx = uni(b.src_len[u]);
@@ -882,12 +889,13 @@ __global__ __launch_bounds__(T, 2) void bwd_kernel(BwdArgs A) {
   __shared__ int s_idx;
   const int t = threadIdx.x;
   cf* slot = A.scratch + (long long)blockIdx.x * A.slot_cf;
-  for (;;) {
+  const int count = __builtin_amdgcn_readfirstlane(A.hdr->count[A.fam]);
+  for (int first = 1;; first = 0) {
     __syncthreads();
-    if (t == 0) s_idx = atomicAdd(&A.hdr->counter[A.fam], 1);
+    if (t == 0) s_idx = first ? (int)blockIdx.x : (int)gridDim.x + atomicAdd(&A.hdr->counter[A.fam], 1);
     __syncthreads();
     const int idx = __builtin_amdgcn_readfirstlane(s_idx);
-    if (idx >= A.hdr->count[A.fam]) break;
+    if (idx >= count) break;
     const int u = __builtin_amdgcn_readfirstlane(A.list[(long long)A.fam * A.b.U + idx]);
     Sched S = A.sched[u];
     S.log2n = __builtin_amdgcn_readfirstlane(S.log2n);
@@ -974,7 +982,8 @@ __device__ __forceinline__ int slot_bin(int q, int t) {
 
 template <class PL>
 __global__ __launch_bounds__(PL::T) void rfft_kernel(const float* __restrict__ x, float* __restrict__ spec) {
-  __shared__ cf lds[PL::LDS];
+  __shared__ cf lds_raw[Xch<PL>::kEntries];
+  Xch<PL> lds{lds_raw, 0};
   const int t = threadIdx.x;
   const long long sig = blockIdx.x;
   const TwBase tw = Fft<PL>::bases(plan_tw<PL>(), t);
@@ -996,7 +1005,8 @@ __global__ __launch_bounds__(PL::T) void rfft_kernel(const float* __restrict__ x
 
 template <class PL>
 __global__ __launch_bounds__(PL::T) void irfft_kernel(const float* __restrict__ spec, float* __restrict__ x) {
-  __shared__ cf lds[PL::LDS];
+  __shared__ cf lds_raw[Xch<PL>::kEntries];
+  Xch<PL> lds{lds_raw, 0};
   const int t = threadIdx.x;
   const long long sig = blockIdx.x;
   const TwBase tw = Fft<PL>::bases(plan_tw<PL>(), t);
