@@ -505,6 +505,34 @@ __device__ __forceinline__ const cf* plan_tw() {
   return g_tw + tw_off<ilog2c(PL::N)>();
 }
 
+// The RIR spectra of one utterance, once, scaled by alpha / (8M) (which also
+// carries the normalisation of the inverse transform); the next RIR is
+// requested while the current one is transformed.
+template <class PL>
+__device__ __forceinline__ void rir_spectra(const MixArgs& A, int u, int I, cf* Hs, Xch<PL>& lds, const TwBase& tw,
+                                            int t) {
+  constexpr int P = PL::P, M = PL::M;
+  const BatchDev& b = A.b;
+  const int J = b.J, NS = b.S;
+  const float cscale = 1.0f / (8.0f * (float)M);
+  const int n_rir = I * J;
+  const long long r0 = (long long)u * NS * J;  // slot of (i, j) is r0 + i J + j
+  cf vn[P];
+  if (n_rir > 0) load_real<PL>(vn, A.h + uni64(b.rir_off[r0]), uni(b.rir_len[r0]), t);
+  for (int k = 0; k < n_rir; ++k) {
+    cf v[P];
+#pragma unroll
+    for (int q = 0; q < P; ++q) v[q] = vn[q];
+    if (k + 1 < n_rir) load_real<PL>(vn, A.h + uni64(b.rir_off[r0 + k + 1]), uni(b.rir_len[r0 + k + 1]), t);
+    Fft<PL>::forward(v, lds, tw, t);
+    Fft<PL>::post(v, tw, t);
+    const float a = A.alpha[r0 + k] * cscale;
+#pragma unroll
+    for (int q = 0; q < P; ++q) v[q] = mk(v[q].x * a, v[q].y * a);
+    store_spec<PL>(Hs + (long long)k * M, v, t);
+  }
+}
+
 // One utterance: RIR spectra, then the blocks.  Mics are processed in groups
 // of JG (1 or 2) accumulators; when J > JG the source spectra of the current
 // block are kept in the workgroup's scratch for the later mic groups.
@@ -518,31 +546,11 @@ __device__ __forceinline__ void mix_utterance(const MixArgs& A, int u, const Sch
   const int I = uni(b.n_src[u]), J = b.J, NS = b.S, Nx = uni(b.src_len[u]);
   const int B = S.hop, nb = S.nb, tu = S.tu, lmax = S.lmax;
   const int span = B + lmax - 1;
-  const float cscale = 1.0f / (8.0f * (float)M);
   cf* Hs = slot;
   cf* Xs = slot + (long long)NS * J * M;
   const int ng = (J + JG - 1) / JG;
 
-  // RIR spectra, once per utterance, scaled by alpha / (8M); the next RIR
-  // is requested while the current one is transformed.
-  {
-    const int n_rir = I * J;
-    const long long r0 = (long long)u * NS * J;  // slot of (i, j) is r0 + i J + j
-    cf vn[P];
-    if (n_rir > 0) load_real<PL>(vn, A.h + uni64(b.rir_off[r0]), uni(b.rir_len[r0]), t);
-    for (int k = 0; k < n_rir; ++k) {
-      cf v[P];
-#pragma unroll
-      for (int q = 0; q < P; ++q) v[q] = vn[q];
-      if (k + 1 < n_rir) load_real<PL>(vn, A.h + uni64(b.rir_off[r0 + k + 1]), uni(b.rir_len[r0 + k + 1]), t);
-      Fft<PL>::forward(v, lds, tw, t);
-      Fft<PL>::post(v, tw, t);
-      const float a = A.alpha[r0 + k] * cscale;
-#pragma unroll
-      for (int q = 0; q < P; ++q) v[q] = mk(v[q].x * a, v[q].y * a);
-      store_spec<PL>(Hs + (long long)k * M, v, t);
-    }
-  }
+  rir_spectra<PL>(A, u, I, Hs, lds, tw, t);
 
   const long long yo = uni64(b.out_off[u]);
   const long long ys = uni(b.out_stride[u]);
