@@ -601,13 +601,23 @@ __device__ __forceinline__ void mix_utterance(const MixArgs& A, int u, const Sch
           }
 #pragma unroll
           for (int q = 0; q < P; ++q) X[q] = Xn[q];
+          // With one source, the next group's input is this item's own
+          // spectrum, not yet in the cache: it is handed over in registers.
+          const bool hand_over = g == 0 && I == 1 && ng > 1;
           if (i + 1 < I) fetch(bk, g, i + 1);
-          else if (g + 1 < ng) fetch(bk, g + 1, 0);
-          else if (bk + 1 < nb) fetch(bk + 1, 0, 0);
+          else if (g + 1 < ng) {
+            if (!hand_over) fetch(bk, g + 1, 0);
+          } else if (bk + 1 < nb) {
+            fetch(bk + 1, 0, 0);
+          }
           if (g == 0) {
             Fft<PL>::forward(X, lds, tw, t);
             Fft<PL>::post(X, tw, t);
             if (ng > 1) store_spec<PL>(Xs + (long long)i * M, X, t);
+            if (hand_over) {
+#pragma unroll
+              for (int q = 0; q < P; ++q) Xn[q] = X[q];
+            }
           }
           mac_regs<PL>(Y0, Hp0, X, t);
           if constexpr (JG == 2) {

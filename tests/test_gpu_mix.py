@@ -241,3 +241,96 @@ def test_one_fft_size_for_the_batch():
         db, alpha, y, rl, ol = _simulate(b, 20.0, tune=tune, use_graph=graph)
         for u in range(b.n_utt):
             _check_utterance(b, u, 20.0, y, rl, ol)
+
+
+def _sampled_check(b, eta, y, rl, ol, utts, n_samples, seed):
+    """Cut lengths bit-exact, out_len exact, and outputs at sampled indices
+    (each an independent direct sum of the oracle) within tolerance of the
+    sampled peak."""
+    rng = np.random.default_rng(seed)
+    J, S = b.n_mic, b.max_src
+    for u in utts:
+        xs, hs = b.sources(u), b.rirs(u)
+        I = len(xs)
+        cut = []
+        for i in range(I):
+            row = []
+            for j in range(J):
+                n_c, L, _ = oracle.cut_rir(hs[i][j], eta)
+                assert int(rl[(u * S + i) * J + j]) == L, (u, i, j)
+                row.append(np.asarray(hs[i][j], np.float32)[:L])
+            cut.append(row)
+        alpha = oracle.snr_gains([oracle.dry_power(x) for x in xs], b.snrs(u), J)
+        T = oracle.out_length(len(xs[0]) if I else 0, [[len(c) for c in row] for row in cut])
+        assert int(ol[u]) == T, u
+        if T == 0:
+            continue
+        idx = np.unique(np.concatenate([[0, 1, T // 2, T - 2, T - 1],
+                                        rng.integers(0, T, n_samples)]).clip(0, T - 1))
+        off, st = int(b.out_off[u]), int(b.out_stride[u])
+        for j in range(J):
+            ref = oracle.mix_at(xs, cut, alpha, j, idx)
+            got = y[off + j * st + idx]
+            peak = max(float(np.max(np.abs(ref))), 1e-30)
+            assert float(np.max(np.abs(got - ref))) <= 2 * TOL * peak, (u, j)
+
+
+def _large_subset(n_utt, eta_seed):
+    # the large workload's shapes: 1-20 s, up to 4 sources, 8 mics, T60 up to
+    # 1.0 s (L0 = ceil(T60 fs) <= 16000); utterance 0 is the extreme case
+    # (20 s, 4 sources, 16000-tap RIRs)
+    rng = synth.rng_for(4, 500 + eta_seed)
+    srcs, rirs, snrs = [], [], []
+    for u in range(n_utt):
+        n = 20 * synth.FS if u == 0 else int(rng.uniform(1.0, 20.0) * synth.FS)
+        I = 4 if u == 0 else int(1 + rng.integers(0, 4))
+        t60 = 1.0 if u == 0 else float(rng.uniform(0.1, 1.0))
+        L0 = min(int(math.ceil(t60 * synth.FS)), 16000)
+        srcs.append([synth.speech_like(rng, n)] + [synth.white_noise(rng, n) for _ in range(I - 1)])
+        rirs.append([[synth.rir(rng, L0, t60, int(rng.integers(20, 401))) for _ in range(8)] for _ in range(I)])
+        snrs.append([0.0] + [float(v) for v in rng.uniform(0, 30, I - 1)])
+    return synth.pack(srcs, rirs, snrs, 8)
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("eta", [math.inf, 30.0, 20.0, 10.0])
+def test_large_workload_subset_sampled(eta):
+    b = _large_subset(12, int(eta) if math.isfinite(eta) else 99)
+    db, alpha, y, rl, ol = _simulate(b, eta)
+    _sampled_check(b, eta, y, rl, ol, range(b.n_utt), 48, 7)
+
+
+@pytest.mark.gpu
+def test_batched_workload_full_size_sampled():
+    # the whole 2048-utterance epoch in the benchmark's launch configuration
+    # (one graph, LPT order, built-in cost model with one size per batch)
+    b = synth.make_config2(epoch=2)
+    order = np.argsort(-(b.src_len.astype(np.int64) * (b.n_src + b.n_mic)), kind="stable").astype(np.int32)
+    db, alpha, y, rl, ol = _simulate(b, 20.0, order=order, use_graph=True)
+    longest = int(np.argmax(b.src_len))
+    most_src = int(np.argmax(b.n_src))
+    longest_rir = int(np.argmax(b.rir_len0)) // (b.max_src * b.n_mic)
+    utts = sorted({0, longest, most_src, longest_rir} | set(range(0, b.n_utt, 97)))
+    _sampled_check(b, 20.0, y, rl, ol, utts, 24, 11)
+    # every cut length of the epoch, bit-exact
+    for r in range(0, len(b.rir_len0), 7):
+        h = b.h[b.rir_off[r]: b.rir_off[r] + b.rir_len0[r]]
+        assert int(rl[r]) == oracle.cut_rir(h, 20.0)[1], r
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("l2", [11, 13, 14, 15])
+def test_single_source_many_mics(l2):
+    # one source and several mic groups: every later group reuses the one
+    # source spectrum of the block
+    rng = synth.rng_for(14, l2)
+    srcs, rirs = [], []
+    for u in range(3):
+        n = int(rng.integers(3000, 40000))
+        srcs.append([synth.speech_like(rng, n)])
+        L0 = int(rng.integers(50, min(2 ** l2 // 2, 5000)))
+        rirs.append([[synth.rir(rng, L0, 0.3, 10) for _ in range(6)]])
+    b = synth.pack(srcs, rirs, [[0.0]] * 3, 6)
+    db, alpha, y, rl, ol = _simulate(b, math.inf, fft_log2n=np.full(3, l2, np.int32))
+    for u in range(3):
+        _check_utterance(b, u, math.inf, y, rl, ol)
