@@ -135,6 +135,63 @@ def cpu_baseline(base, eta, n_utt, max_workers=16):
                       f"FP64 direct convolution, {dt:.1f} s wall"}
 
 
+def differentiation(torch, rsim, synth, dev, reps: int = 10):
+    """Forward and adjoint of the mix on the differentiation workload: 64
+    utterances of 4 s, 3 sources, 4 mics, 8192-tap RIRs, no cut, N = 16384
+    (hop 8193, 8 blocks), loss sum_j sum_n w_j[n] y_j[n]^2 so g = 2 w y."""
+    b = synth.make_config3()
+    U, S, J = b.n_utt, b.max_src, b.n_mic
+    db = rsim.DeviceBatch(b, device=dev, fft_log2n=np.full(U, 14, np.int32))
+    alpha = torch.from_numpy(rsim.batch_gains(db, b.snr_db)).to(dev)
+    stream = torch.cuda.Stream()
+    stream.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(stream):
+        rsim.truncate_batch(db, math.inf, stream=stream)
+        y = torch.zeros(max(db.y_len, 1), dtype=torch.float32, device=dev)
+        ws_f = db.workspace(None)
+        ws_b = db.workspace(None, backward=True)
+        rsim.mix(db, alpha, y=y, ws=ws_f, stream=stream)
+        w = torch.from_numpy(synth.loss_weights(3, max(db.y_len, 1))).to(dev)
+        g = 2.0 * w * y
+        for _ in range(2):
+            rsim.mix(db, alpha, y=y, ws=ws_f, stream=stream)
+            rsim.mix_backward(db, alpha, g, ws=ws_b, stream=stream)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        ev[0].record(stream)
+        for _ in range(reps):
+            rsim.mix(db, alpha, y=y, ws=ws_f, stream=stream)
+        ev[1].record(stream)
+        for _ in range(reps):
+            rsim.mix_backward(db, alpha, g, ws=ws_b, stream=stream)
+        ev[2].record(stream)
+    torch.cuda.synchronize()
+    t_f = ev[0].elapsed_time(ev[1]) / reps
+    t_b = ev[1].elapsed_time(ev[2]) / reps
+    # algorithmic work of the adjoint: per block J gradient spectra, I source
+    # spectra, I inverse transforms (dx) and 2 I J spectral products; per
+    # utterance I J RIR spectra and I J inverse transforms (r)
+    N = 16384
+    c = 2.5 * N * math.log2(N)
+    mac = 8 * (N / 2 + 1)
+    flops, byts = 0.0, 0
+    L = db.rir_len.cpu().numpy().astype(np.int64).reshape(U, S * J)
+    T = db.out_len.cpu().numpy().astype(np.int64)
+    for u in range(U):
+        I, nx = int(b.n_src[u]), int(b.src_len[u])
+        lmax = int(L[u].max())
+        nb = -(-nx // (N - lmax + 1))
+        flops += nb * ((2 * I + J) * c + 2 * I * J * mac) + 2 * I * J * c
+        byts += 4 * (2 * I * nx + J * int(T[u]) + 2 * int(L[u].sum())) + 8 * I * J
+    achieved = flops / (t_b * 1e-3) / 1e12
+    return {"workload": "64 utterances of 4 s, 3 sources, 4 mics, 8192-tap RIRs, no cut, N = 16384",
+            "forward_ms": round(t_f, 4), "backward_ms": round(t_b, 4),
+            "audio_s_per_s": round(b.audio_seconds / ((t_f + t_b) * 1e-3), 1),
+            "backward_roofline": {"bound": "alu", "achieved": round(achieved, 2), "peak": FP32_PEAK_TFLOPS,
+                                  "unit": "TFLOP/s", "frac": round(achieved / FP32_PEAK_TFLOPS, 4)},
+            "backward_hbm": {"achieved": round(byts / (t_b * 1e-3) / 1e9, 1), "peak": HBM_PEAK_GBS,
+                             "unit": "GB/s", "frac": round(byts / (t_b * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -149,6 +206,7 @@ def main() -> int:
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--no-diff", action="store_true", help="skip the adjoint (differentiation workload) timing")
     ap.add_argument("--tune", default="auto", help="autotune table JSON, 'auto' or 'model'")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="before the warmup, fill and copy a buffer of this size (a reference "
@@ -305,6 +363,9 @@ def main() -> int:
         "hbm": {"achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4)},
         "kernel_ms": {"cut": round(float(np.mean(trunc_ms)), 4), "mix": round(float(np.mean(mix_ms)), 4)},
+        "cut_hbm": {"achieved": round(float(np.mean(byt_cut)) / (float(np.mean(trunc_ms)) * 1e-3) / 1e9, 1),
+                    "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(float(np.mean(byt_cut)) / (float(np.mean(trunc_ms)) * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
         "alu_model": "2.5 N log2 N per real FFT + 8 (N/2+1) per spectral MAC; peak = 256 CUs x 64 lanes x "
                      "2 FLOP (FMA) x 2.4 GHz",
         "bytes_per_step": {"mix": int(np.mean(byt)), "cut": int(np.mean(byt_cut))},
@@ -332,6 +393,12 @@ def main() -> int:
                                          f"synchronised per utterance"}
         result["speedup_vs_plain"] = round(value / plain, 2)
         log(f"plain per-utterance path: {plain:.4g} audio-s/s ({value / plain:.1f}x)")
+
+    if not args.no_diff:
+        result["differentiation"] = differentiation(torch, rsim, synth, dev)
+        d = result["differentiation"]
+        log(f"differentiation workload: forward {d['forward_ms']:.3f} ms, adjoint {d['backward_ms']:.3f} ms, "
+            f"adjoint at {d['backward_roofline']['frac']:.3f} of the FP32 peak")
 
     if not args.no_cpu:
         log("timing the FP64 oracle on the host cores ...")
