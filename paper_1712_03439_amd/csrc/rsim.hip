@@ -1152,7 +1152,8 @@ const void* mix_kernel_ptr_v(int fam) {
     case 2: return reinterpret_cast<const void*>(&mix_kernel<128, JG, MINW>);
     case 3: return reinterpret_cast<const void*>(&mix_kernel<256, JG, MINW>);
     case 4: return reinterpret_cast<const void*>(&mix_kernel<512, JG, MINW>);
-    default: return reinterpret_cast<const void*>(&mix_kernel<1024, JG, MINW>);
+    // 1024 threads leave 128 registers per thread: one mic accumulator
+    default: return reinterpret_cast<const void*>(&mix_kernel<1024, 1, 4>);
   }
 }
 const void* bwd_kernel_ptr(int fam) {
@@ -1183,7 +1184,8 @@ int kernel_variant() {
   }
   return g_var;
 }
-int mic_group() { return kVarJG[kernel_variant()]; }
+// Mic accumulators of family f's kernel under the current variant.
+int mic_group(int f) { return f == kNumFam - 1 ? 1 : kVarJG[kernel_variant()]; }
 
 rsim_status init_locked(int dev) {
   DevState& st = g_dev[dev];
@@ -1304,11 +1306,10 @@ WsLayout layout(const rsim_batch* b, const TuneDev& td, bool backward, const Dev
   bool used[kNumFam];
   families_used(b, td, used);
   const long long S = b->max_src, J = b->n_mic;
-  const int jg = mic_group();
   size_t off = L.scratch;
   for (int f = 0; f < kNumFam; ++f) {
     const long long M = kFamMaxM[f];
-    const long long spectra = backward ? (2 * S * J + J) : (S * J + (J > jg ? S : 0));
+    const long long spectra = backward ? (2 * S * J + J) : (S * J + (J > mic_group(f) ? S : 0));
     L.slot_cf[f] = spectra * M;
     // Without a device (size queries on a host) assume 256 CUs and the
     // largest occupancy used; the grid is capped at 8 workgroups per CU.
