@@ -88,6 +88,12 @@ struct BwdArgs {
   int fam;
   cf* scratch;
   long long slot_cf;
+  // Splitting of an utterance over several work items (for batches with few
+  // utterances): item (u, r), r < nsplit, covers a range of u's blocks and
+  // accumulates its share of the correlation spectra in `partial`
+  // ([U][nsplit][S J][M] for this family); a finishing pass sums them.
+  int nsplit;
+  cf* partial;
 };
 
 }  // namespace rsim

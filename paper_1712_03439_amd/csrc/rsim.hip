@@ -814,9 +814,49 @@ __device__ __forceinline__ double block_sum_d(double v, double* s_red, int t) {
 // block's dx and the block's share of r need (B + L_max - 1 <= N, no wrap).
 // Scratch: alpha-scaled RIR spectra (I J), this block's gradient spectra (J)
 // and the correlation accumulators (I J).
+// r_ij from its spectrum (sum of `nparts` accumulators `stride` entries
+// apart): dh = alpha r below L (zero from L to L0), dalpha = <h, r> in FP64.
 template <class PL>
-__device__ __forceinline__ void bwd_utterance(const BwdArgs& A, int u, const Sched& S, cf* lds_raw,
-                                              double* s_red, cf* slot, int t) {
+__device__ __forceinline__ void bwd_finish_rir(const BwdArgs& A, long long r, const cf* R, int nparts,
+                                               long long stride, Xch<PL>& lds, const TwBase& tw, double* s_red,
+                                               int t) {
+  constexpr int P = PL::P;
+  const BatchDev& b = A.b;
+  const int L = uni(b.rir_len[r]), L0 = uni(b.rir_len0[r]);
+  const long long ro = uni64(b.rir_off[r]);
+  const float a = A.alpha[r];
+  cf v[P];
+  load_spec<PL>(v, R, t);
+  for (int k = 1; k < nparts; ++k) {
+    cf w[P];
+    load_spec<PL>(w, R + k * stride, t);
+#pragma unroll
+    for (int q = 0; q < P; ++q) v[q] = mk(v[q].x + w[q].x, v[q].y + w[q].y);
+  }
+  Fft<PL>::pre(v, tw, t);
+  Fft<PL>::inverse(v, lds, tw, t);
+  // v[q] holds r at samples 2(t + qT), 2(t + qT) + 1.
+  const rsrc_t hr = make_rsrc(A.h + ro, L * 4);
+  const rsrc_t gw = make_rsrc(A.gh + ro, L * 4);
+  double part = 0.0;
+#pragma unroll
+  for (int q = 0; q < P; ++q) {
+    const int o = 8 * (t + q * PL::T);
+    const cf hv = ld2(hr, o);
+    part += (double)hv.x * (double)v[q].x + (double)hv.y * (double)v[q].y;
+    st2(gw, o, mk(a * v[q].x, a * v[q].y));
+  }
+  const double da = block_sum_d<PL::T>(part, s_red, t);
+  if (t == 0 && A.galpha) A.galpha[r] = (float)da;
+  for (int k = L + t; k < L0; k += PL::T) A.gh[ro + k] = 0.0f;
+}
+
+// Work item (u, part) of the adjoint: blocks [b0, b1) of utterance u.  With
+// one part per utterance it also finishes dh and dalpha; otherwise it leaves
+// its correlation spectra in A.partial for the finishing pass.
+template <class PL>
+__device__ __forceinline__ void bwd_utterance(const BwdArgs& A, int u, const Sched& S, int part, int nparts,
+                                              cf* lds_raw, double* s_red, cf* slot, int t) {
   constexpr int P = PL::P, M = PL::M, N = PL::N;
   Xch<PL> lds{lds_raw, 0};
   const TwBase tw = Fft<PL>::bases(plan_tw<PL>(), t);
@@ -826,7 +866,9 @@ __device__ __forceinline__ void bwd_utterance(const BwdArgs& A, int u, const Sch
   const float gscale = 1.0f / (8.0f * (float)M);
   cf* Hs = slot;
   cf* Gs = slot + (long long)NS * J * M;
-  cf* Rs = Gs + (long long)J * M;
+  cf* Rs = nparts == 1 ? Gs + (long long)J * M
+                       : A.partial + ((long long)u * A.nsplit + part) * NS * J * M;
+  const int b0 = (int)((long long)nb * part / nparts), b1 = (int)((long long)nb * (part + 1) / nparts);
   const long long yo = uni64(b.out_off[u]);
   const long long ys = uni(b.out_stride[u]);
 
@@ -844,7 +886,7 @@ __device__ __forceinline__ void bwd_utterance(const BwdArgs& A, int u, const Sch
     }
   }
 
-  for (int bk = 0; bk < nb; ++bk) {
+  for (int bk = b0; bk < b1; ++bk) {
     const int base = bk * B;
     const int nvalid = min(B, Nx - base);
     for (int j = 0; j < J; ++j) {
@@ -868,37 +910,28 @@ __device__ __forceinline__ void bwd_utterance(const BwdArgs& A, int u, const Sch
       Fft<PL>::forward(X, lds, tw, t);
       Fft<PL>::post(X, tw, t);
       for (int j = 0; j < J; ++j)
-        acc_corr<PL>(Rs + (long long)(i * J + j) * M, X, Gs + (long long)j * M, bk == 0, t);
+        acc_corr<PL>(Rs + (long long)(i * J + j) * M, X, Gs + (long long)j * M, bk == b0, t);
     }
   }
-
-  for (int i = 0; i < I; ++i) {
-    for (int j = 0; j < J; ++j) {
-      const long long r = ((long long)u * NS + i) * J + j;
-      const int L = uni(b.rir_len[r]), L0 = uni(b.rir_len0[r]);
-      const long long ro = uni64(b.rir_off[r]);
-      const float a = A.alpha[r];
-      cf v[P];
-      load_spec<PL>(v, Rs + (long long)(i * J + j) * M, t);
-      Fft<PL>::pre(v, tw, t);
-      Fft<PL>::inverse(v, lds, tw, t);
-      // v[q] holds r at samples 2(t + qT), 2(t + qT) + 1.
-      const rsrc_t hr = make_rsrc(A.h + ro, L * 4);
-      const rsrc_t gw = make_rsrc(A.gh + ro, L * 4);
-      double part = 0.0;
+  if (b1 == b0) {  // an empty part still defines its share: zero
+    for (int k = 0; k < I * J; ++k) {
+      cf z[P];
 #pragma unroll
-      for (int q = 0; q < P; ++q) {
-        const int o = 8 * (t + q * PL::T);
-        const cf hv = ld2(hr, o);
-        part += (double)hv.x * (double)v[q].x + (double)hv.y * (double)v[q].y;
-        st2(gw, o, mk(a * v[q].x, a * v[q].y));
-      }
-      const double da = block_sum_d<PL::T>(part, s_red, t);
-      if (t == 0 && A.galpha) A.galpha[r] = (float)da;
-      for (int k = L + t; k < L0; k += PL::T) A.gh[ro + k] = 0.0f;
+      for (int q = 0; q < P; ++q) z[q] = mk(0.f, 0.f);
+      store_spec<PL>(Rs + (long long)k * M, z, t);
     }
   }
+  if (nparts > 1) return;
+
+  for (int i = 0; i < I; ++i)
+    for (int j = 0; j < J; ++j)
+      bwd_finish_rir<PL>(A, ((long long)u * NS + i) * J + j, Rs + (long long)(i * J + j) * M, 1, 0, lds, tw,
+                         s_red, t);
 }
+
+// Work item of the adjoint: (list position, part).  nsplit parts per
+// utterance, capped by its block count (parts beyond it have no work).
+__device__ __forceinline__ int bwd_parts(int nsplit, int nb) { return nsplit < nb ? nsplit : nb; }
 
 template <int T>
 __global__ __launch_bounds__(T, 2) void bwd_kernel(BwdArgs A) {
@@ -907,23 +940,59 @@ __global__ __launch_bounds__(T, 2) void bwd_kernel(BwdArgs A) {
   __shared__ int s_idx;
   const int t = threadIdx.x;
   cf* slot = A.scratch + (long long)blockIdx.x * A.slot_cf;
-  const int count = __builtin_amdgcn_readfirstlane(A.hdr->count[A.fam]);
+  const int ns = A.nsplit;
+  const long long count = (long long)__builtin_amdgcn_readfirstlane(A.hdr->count[A.fam]) * ns;
   for (int first = 1;; first = 0) {
     __syncthreads();
     if (t == 0) s_idx = first ? (int)blockIdx.x : (int)gridDim.x + atomicAdd(&A.hdr->counter[A.fam], 1);
     __syncthreads();
     const int idx = __builtin_amdgcn_readfirstlane(s_idx);
     if (idx >= count) break;
-    const int u = __builtin_amdgcn_readfirstlane(A.list[(long long)A.fam * A.b.U + idx]);
+    const int pos = idx / ns, part = idx - pos * ns;
+    const int u = __builtin_amdgcn_readfirstlane(A.list[(long long)A.fam * A.b.U + pos]);
     Sched S = A.sched[u];
     S.log2n = __builtin_amdgcn_readfirstlane(S.log2n);
     S.hop = __builtin_amdgcn_readfirstlane(S.hop);
     S.nb = __builtin_amdgcn_readfirstlane(S.nb);
     S.tu = __builtin_amdgcn_readfirstlane(S.tu);
     S.lmax = __builtin_amdgcn_readfirstlane(S.lmax);
+    const int nparts = bwd_parts(ns, S.nb);
+    if (part >= nparts) continue;
     dispatch_plan<T>(S.log2n, [&](auto pl) __attribute__((always_inline)) {
       using PL = decltype(pl);
-      bwd_utterance<PL>(A, u, S, lds, s_red, slot, t);
+      bwd_utterance<PL>(A, u, S, part, nparts, lds, s_red, slot, t);
+    });
+  }
+}
+
+// Finishing pass of a split adjoint: for every utterance in more than one
+// part, sums the parts' correlation spectra and gives dh and dalpha.
+template <int T>
+__global__ __launch_bounds__(T, 2) void bwd_finish_kernel(BwdArgs A) {
+  __shared__ cf lds_raw[max_lds_with_threads<T>()];
+  __shared__ double s_red[T];
+  const int t = threadIdx.x;
+  const int count = __builtin_amdgcn_readfirstlane(A.hdr->count[A.fam]);
+  const BatchDev& b = A.b;
+  for (int pos = blockIdx.x; pos < count; pos += gridDim.x) {
+    const int u = __builtin_amdgcn_readfirstlane(A.list[(long long)A.fam * b.U + pos]);
+    Sched S = A.sched[u];
+    S.log2n = __builtin_amdgcn_readfirstlane(S.log2n);
+    S.nb = __builtin_amdgcn_readfirstlane(S.nb);
+    const int nparts = bwd_parts(A.nsplit, S.nb);
+    if (nparts <= 1) continue;
+    dispatch_plan<T>(S.log2n, [&](auto pl) __attribute__((always_inline)) {
+      using PL = decltype(pl);
+      constexpr int M = PL::M;
+      Xch<PL> lds{lds_raw, 0};
+      const TwBase tw = Fft<PL>::bases(plan_tw<PL>(), t);
+      const int I = uni(b.n_src[u]), J = b.J, NS = b.S;
+      const long long stride = (long long)NS * J * M;
+      const cf* R = A.partial + (long long)u * A.nsplit * stride;
+      for (int i = 0; i < I; ++i)
+        for (int j = 0; j < J; ++j)
+          bwd_finish_rir<PL>(A, ((long long)u * NS + i) * J + j, R + (long long)(i * J + j) * M, nparts,
+                             stride, lds, tw, s_red, t);
     });
   }
 }
@@ -1166,6 +1235,16 @@ const void* bwd_kernel_ptr(int fam) {
     default: return reinterpret_cast<const void*>(&bwd_kernel<1024>);
   }
 }
+const void* bwd_finish_kernel_ptr(int fam) {
+  switch (fam) {
+    case 0: return reinterpret_cast<const void*>(&bwd_finish_kernel<32>);
+    case 1: return reinterpret_cast<const void*>(&bwd_finish_kernel<64>);
+    case 2: return reinterpret_cast<const void*>(&bwd_finish_kernel<128>);
+    case 3: return reinterpret_cast<const void*>(&bwd_finish_kernel<256>);
+    case 4: return reinterpret_cast<const void*>(&bwd_finish_kernel<512>);
+    default: return reinterpret_cast<const void*>(&bwd_finish_kernel<1024>);
+  }
+}
 const void* mix_kernel_ptr(int fam, int var) {
   switch (var) {
     case 0: return mix_kernel_ptr_v<1, 2>(fam);
@@ -1283,6 +1362,8 @@ void families_used(const rsim_batch* b, const TuneDev& td, bool used[kNumFam]) {
 
 struct WsLayout {
   size_t hdr, sched, lists, scratch, total;
+  int nsplit;                   // adjoint: parts per utterance
+  size_t fam_partial[kNumFam];  // adjoint: byte offset of each family's part spectra (nsplit > 1)
   size_t fam_scratch[kNumFam];  // byte offset of each family's slots (families run concurrently)
   long long slot_cf[kNumFam];
   int grid[kNumFam];
@@ -1306,22 +1387,33 @@ WsLayout layout(const rsim_batch* b, const TuneDev& td, bool backward, const Dev
   bool used[kNumFam];
   families_used(b, td, used);
   const long long S = b->max_src, J = b->n_mic;
+  // Without a device (size queries on a host) assume 256 CUs.
+  const int cus = st.cus > 0 ? st.cus : 256;
+  // The adjoint splits utterances into parts when there are fewer of them
+  // than compute units (each part recomputes the RIR spectra).
+  L.nsplit = 1;
+  if (backward && U > 0 && (size_t)cus > U) L.nsplit = (int)std::min<size_t>(4, (cus + U - 1) / U);
+  const size_t items = U * (size_t)L.nsplit;
   size_t off = L.scratch;
   for (int f = 0; f < kNumFam; ++f) {
     const long long M = kFamMaxM[f];
     const long long spectra = backward ? (2 * S * J + J) : (S * J + (J > mic_group(f) ? S : 0));
     L.slot_cf[f] = spectra * M;
-    // Without a device (size queries on a host) assume 256 CUs and the
-    // largest occupancy used; the grid is capped at 8 workgroups per CU.
-    const int cus = st.cus > 0 ? st.cus : 256;
+    // the largest occupancy used without a device; at most 8 workgroups per
+    // CU and one per work item
     int occ = st.init ? (backward ? st.occ_bwd[f] : st.occ[kernel_variant()][f]) : 8;
     if (occ > 8) occ = 8;
     long long g = (long long)cus * occ;
-    if (g > (long long)U) g = (long long)U;
+    if (g > (long long)items) g = (long long)items;
     if (g < 1) g = 1;
     L.grid[f] = (int)g;
     L.fam_scratch[f] = off;
     if (used[f]) off += align256((size_t)g * (size_t)L.slot_cf[f] * sizeof(cf));
+  }
+  for (int f = 0; f < kNumFam; ++f) {
+    L.fam_partial[f] = off;
+    if (used[f] && L.nsplit > 1)
+      off += align256(U * (size_t)L.nsplit * (size_t)(S * J) * (size_t)kFamMaxM[f] * sizeof(cf));
   }
   L.total = off;
   return L;
@@ -1377,6 +1469,8 @@ struct CallPlan {
   Node cut, sched;
   Node fam[kNumFam + 1];  // the family kernels (and, for the adjoint, the zero fill)
   int nf = 0;
+  Node post[kNumFam];     // kernels that need every family kernel done (the adjoint's finishing pass)
+  int np = 0;
 };
 
 bool capturing(hipStream_t s) {
@@ -1415,6 +1509,10 @@ rsim_status issue_eager(CallPlan& P, hipStream_t s) {
           hipStreamWaitEvent(s, st.join[k - 1], 0) != hipSuccess)
         return RSIM_EDEVICE;
     }
+  }
+  for (int k = 0; k < P.np; ++k) {
+    Node& n = P.post[k];
+    if (hipLaunchKernel(n.fn, n.grid, n.block, n.p(), 0, s) != hipSuccess) return RSIM_EDEVICE;
   }
   return RSIM_OK;
 }
@@ -1480,6 +1578,10 @@ rsim_status issue_graph(CallPlan& P, hipStream_t s) {
   prev = node;
   for (int k = 0; ok && k < P.nf; ++k) {
     ok = add(P.fam[k], &prev, 1, &node);
+    prev = node;
+  }
+  for (int k = 0; ok && k < P.np; ++k) {
+    ok = add(P.post[k], &prev, 1, &node);
     prev = node;
   }
   hipGraphExec_t exec = nullptr;
@@ -1578,7 +1680,10 @@ void plan_bwd(CallPlan& P, const rsim_batch* b, const BatchDev& bd, const TuneDe
   A.fam = -1;
   A.scratch = nullptr;
   A.slot_cf = 0;
+  A.nsplit = L.nsplit;
+  A.partial = nullptr;
   P.nf = 0;
+  P.np = 0;
   const int cus = st.cus > 0 ? st.cus : 256;
   P.fam[P.nf++].set(reinterpret_cast<const void*>(&bwd_zero_kernel), dim3(std::min(b->n_utt, cus * 4)),
                     dim3(256), A);
@@ -1590,7 +1695,10 @@ void plan_bwd(CallPlan& P, const rsim_batch* b, const BatchDev& bd, const TuneDe
     A.fam = f;
     A.scratch = reinterpret_cast<cf*>(base + L.fam_scratch[f]);
     A.slot_cf = L.slot_cf[f];
+    A.partial = L.nsplit > 1 ? reinterpret_cast<cf*>(base + L.fam_partial[f]) : nullptr;
     P.fam[P.nf++].set(bwd_kernel_ptr(f), dim3(L.grid[f]), dim3(kFamT[f]), A);
+    if (L.nsplit > 1)
+      P.post[P.np++].set(bwd_finish_kernel_ptr(f), dim3(std::min(b->n_utt, cus * 2)), dim3(kFamT[f]), A);
   }
 }
 

@@ -212,3 +212,21 @@ def test_autograd_directional_derivative():
             fd = float((lp - lm) / 2)
             an = float(torch.sum(g.double() * d.double()))
         assert abs(fd - an) <= 1e-3 * max(abs(an), 1e-6), (k, fd, an)
+
+
+@pytest.mark.gpu
+def test_backward_many_utterances_one_part_each():
+    # more utterances than compute units: every utterance is one work item
+    rng = synth.rng_for(53, 0)
+    srcs, rirs, snrs = [], [], []
+    for u in range(300):
+        I = 1 + u % 3
+        n = int(rng.integers(1500, 6000))
+        srcs.append([synth.speech_like(rng, n)] + [synth.white_noise(rng, n) for _ in range(I - 1)])
+        L0 = int(rng.integers(50, 1200))
+        rirs.append([[synth.rir(rng, L0, 0.2, int(rng.integers(0, 40))) for _ in range(2)] for _ in range(I)])
+        snrs.append([0.0] + [float(v) for v in rng.uniform(0, 20, I - 1)])
+    b = synth.pack(srcs, rirs, snrs, 2)
+    gx, gh, ga, gys = _run(b, 20.0, 11)
+    for u in (0, 1, 2, 149, 299):
+        _check_full(b, 20.0, gx, gh, ga, gys, u)
