@@ -108,13 +108,19 @@ __global__ __launch_bounds__(kTruncThreads) void truncate_kernel(TruncArgs A) {
     const int vo = 16 * lane;
     float mx = 0.0f;
     int nf = 0;
-    for (int base = 0; base < L0; base += 256) {
-      const f4 v = ld4(rs, vo + 4 * base);  // whole offset range-checked
+    // four 128-bit loads in flight per lane (1024 taps per step)
+    for (int base = 0; base < L0; base += 1024) {
+      f4 v[4];
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const float q = v[k] * v[k];
-        nf |= !__builtin_isfinite(q);
-        mx = fmaxf(mx, q);
+      for (int c = 0; c < 4; ++c) v[c] = ld4(rs, vo + 4 * (base + 256 * c));  // whole offset range-checked
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const float q = v[c][k] * v[c][k];
+          nf |= !__builtin_isfinite(q);
+          mx = fmaxf(mx, q);
+        }
       }
     }
     mx = wave_max(mx);
