@@ -82,7 +82,12 @@ struct TruncArgs {
   int* len;
 };
 
+// Chunks of 1024 taps whose maxima a wave keeps in LDS (RIRs up to 32768
+// taps); past that the tail search reads the taps again, 256 at a time.
+constexpr int kTruncChunks = 32;
+
 __global__ __launch_bounds__(kTruncThreads) void truncate_kernel(TruncArgs A) {
+  __shared__ float s_cmax[kTruncWaves][kTruncChunks];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   for (int r0 = blockIdx.x * kTruncWaves; r0 < A.n_rir; r0 += gridDim.x * kTruncWaves) {
     const int r = r0 + w;
@@ -106,21 +111,28 @@ __global__ __launch_bounds__(kTruncThreads) void truncate_kernel(TruncArgs A) {
     }
     const rsrc_t rs = make_rsrc(A.h + o, L0 * 4);
     const int vo = 16 * lane;
+    // max pass: four 128-bit loads in flight per lane (one chunk of 1024
+    // taps per step); each chunk's maximum is kept for the tail search
     float mx = 0.0f;
     int nf = 0;
-    // four 128-bit loads in flight per lane (1024 taps per step)
-    for (int base = 0; base < L0; base += 1024) {
+    for (int base = 0, c = 0; base < L0; base += 1024, ++c) {
       f4 v[4];
 #pragma unroll
-      for (int c = 0; c < 4; ++c) v[c] = ld4(rs, vo + 4 * (base + 256 * c));  // whole offset range-checked
+      for (int k = 0; k < 4; ++k) v[k] = ld4(rs, vo + 4 * (base + 256 * k));  // whole offset range-checked
+      float cm = 0.0f;
 #pragma unroll
-      for (int c = 0; c < 4; ++c) {
+      for (int k = 0; k < 4; ++k) {
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          const float q = v[c][k] * v[c][k];
+        for (int e = 0; e < 4; ++e) {
+          const float q = v[k][e] * v[k][e];
           nf |= !__builtin_isfinite(q);
-          mx = fmaxf(mx, q);
+          cm = fmaxf(cm, q);
         }
+      }
+      mx = fmaxf(mx, cm);
+      if (c < kTruncChunks) {
+        cm = wave_max(cm);
+        if (lane == 0) s_cmax[w][c] = cm;
       }
     }
     mx = wave_max(mx);
@@ -134,19 +146,42 @@ __global__ __launch_bounds__(kTruncThreads) void truncate_kernel(TruncArgs A) {
       continue;
     }
     const float pth = mx * A.s;
+    const int nch = (L0 + 1023) / 1024;
     int found = -1;
-    for (int base = ((L0 - 1) / 256) * 256; base >= 0; base -= 256) {
-      const f4 v = ld4(rs, vo + 4 * base);  // whole offset range-checked
+    if (nch <= kTruncChunks) {
+      // the last chunk whose maximum reaches p_th holds the last such tap
+      // (wave-local LDS: the wave wrote these values itself)
+      const bool hit = lane < nch && s_cmax[w][lane] >= pth;
+      const unsigned long long m = __ballot(hit);
+      const int c = m ? 63 - __builtin_clzll(m) : 0;
+      const int base = c * 1024;
+      f4 v[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) v[k] = ld4(rs, vo + 4 * (base + 256 * k));
       int loc = -1;
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
-        const int idx = base + 4 * lane + k;
-        if (idx < L0 && v[k] * v[k] >= pth) loc = idx;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int idx = base + 256 * k + 4 * lane + e;
+          if (idx < L0 && v[k][e] * v[k][e] >= pth) loc = idx;
+        }
       }
-      loc = wave_max_i(loc);
-      if (loc >= 0) {
-        found = loc;
-        break;
+      found = wave_max_i(loc);
+    } else {
+      for (int base = ((L0 - 1) / 256) * 256; base >= 0; base -= 256) {
+        const f4 v = ld4(rs, vo + 4 * base);  // whole offset range-checked
+        int loc = -1;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const int idx = base + 4 * lane + k;
+          if (idx < L0 && v[k] * v[k] >= pth) loc = idx;
+        }
+        loc = wave_max_i(loc);
+        if (loc >= 0) {
+          found = loc;
+          break;
+        }
       }
     }
     if (lane == 0) {
