@@ -71,6 +71,9 @@ struct MixArgs {
   int fam;
   cf* scratch;          // per-workgroup scratch base
   long long slot_cf;    // complex entries per workgroup
+  // 1: a work item is an utterance; g > 1 (batches with few utterances): a
+  // work item is one mic group of an utterance, g items per utterance.
+  int gsplit;
 };
 
 struct BwdArgs {

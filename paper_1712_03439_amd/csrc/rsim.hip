@@ -550,27 +550,36 @@ __device__ __forceinline__ const cf* plan_tw() {
 // carries the normalisation of the inverse transform); the next RIR is
 // requested while the current one is transformed.
 template <class PL>
-__device__ __forceinline__ void rir_spectra(const MixArgs& A, int u, int I, cf* Hs, Xch<PL>& lds, const TwBase& tw,
-                                            int t) {
+__device__ __forceinline__ void rir_spectra(const MixArgs& A, int u, int I, int jlo, int jhi, cf* Hs, Xch<PL>& lds,
+                                            const TwBase& tw, int t) {
   constexpr int P = PL::P, M = PL::M;
   const BatchDev& b = A.b;
-  const int J = b.J, NS = b.S;
+  const int J = b.J, NS = b.S, JN = jhi - jlo;
   const float cscale = 1.0f / (8.0f * (float)M);
-  const int n_rir = I * J;
-  const long long r0 = (long long)u * NS * J;  // slot of (i, j) is r0 + i J + j
+  const int n_rir = I * JN;
+  // item k is RIR (i, j) = (k / JN, jlo + k % JN), slot r0 + i J + j
+  const long long r0 = (long long)u * NS * J;
+  auto slot_of = [&](int k) __attribute__((always_inline)) { return (k / JN) * J + jlo + k % JN; };
   cf vn[P];
-  if (n_rir > 0) load_real<PL>(vn, A.h + uni64(b.rir_off[r0]), uni(b.rir_len[r0]), t);
+  if (n_rir > 0) {
+    const long long r = r0 + slot_of(0);
+    load_real<PL>(vn, A.h + uni64(b.rir_off[r]), uni(b.rir_len[r]), t);
+  }
   for (int k = 0; k < n_rir; ++k) {
     cf v[P];
 #pragma unroll
     for (int q = 0; q < P; ++q) v[q] = vn[q];
-    if (k + 1 < n_rir) load_real<PL>(vn, A.h + uni64(b.rir_off[r0 + k + 1]), uni(b.rir_len[r0 + k + 1]), t);
+    if (k + 1 < n_rir) {
+      const long long rn = r0 + slot_of(k + 1);
+      load_real<PL>(vn, A.h + uni64(b.rir_off[rn]), uni(b.rir_len[rn]), t);
+    }
     Fft<PL>::forward(v, lds, tw, t);
     Fft<PL>::post(v, tw, t);
-    const float a = A.alpha[r0 + k] * cscale;
+    const int sl = slot_of(k);
+    const float a = A.alpha[r0 + sl] * cscale;
 #pragma unroll
     for (int q = 0; q < P; ++q) v[q] = mk(v[q].x * a, v[q].y * a);
-    store_spec<PL>(Hs + (long long)k * M, v, t);
+    store_spec<PL>(Hs + (long long)sl * M, v, t);
   }
 }
 
@@ -578,8 +587,8 @@ __device__ __forceinline__ void rir_spectra(const MixArgs& A, int u, int I, cf* 
 // of JG (1 or 2) accumulators; when J > JG the source spectra of the current
 // block are kept in the workgroup's scratch for the later mic groups.
 template <class PL, int JG, int MINW>
-__device__ __forceinline__ void mix_utterance(const MixArgs& A, int u, const Sched& S, cf* lds_raw, cf* slot,
-                                              int t) {
+__device__ __forceinline__ void mix_utterance(const MixArgs& A, int u, const Sched& S, int gsel, cf* lds_raw,
+                                              cf* slot, int t) {
   constexpr int P = PL::P, M = PL::M;
   Xch<PL> lds{lds_raw, 0};
   const TwBase tw = Fft<PL>::bases(plan_tw<PL>(), t);
@@ -589,9 +598,14 @@ __device__ __forceinline__ void mix_utterance(const MixArgs& A, int u, const Sch
   const int span = B + lmax - 1;
   cf* Hs = slot;
   cf* Xs = slot + (long long)NS * J * M;
-  const int ng = (J + JG - 1) / JG;
+  const int ng_all = (J + JG - 1) / JG;
+  // mic groups of this work item: all, or the one group gsel; the source
+  // spectra are cached for later groups only when one item does several
+  const int glo = gsel < 0 ? 0 : gsel, ghi = gsel < 0 ? ng_all : gsel + 1;
+  const int ng = ghi - glo;
+  const bool cache = ng > 1;
 
-  rir_spectra<PL>(A, u, I, Hs, lds, tw, t);
+  rir_spectra<PL>(A, u, I, glo * JG, min(J, ghi * JG), Hs, lds, tw, t);
 
   const long long yo = uni64(b.out_off[u]);
   const long long ys = uni(b.out_stride[u]);
@@ -611,19 +625,19 @@ __device__ __forceinline__ void mix_utterance(const MixArgs& A, int u, const Sch
     // live set is about (3 + 2 JG) arrays of P complex values.
     cf Xn[P];
     auto fetch = [&](int bk, int g, int i) __attribute__((always_inline)) {
-      if (g == 0) {
+      if (g == glo) {
         const int base = bk * B;
         load_real<PL>(Xn, A.x + uni64(b.src_off[(long long)u * NS + i]) + base, min(B, Nx - base), t);
       } else {
         load_spec<PL>(Xn, Xs + (long long)i * M, t);
       }
     };
-    fetch(0, 0, 0);
+    fetch(0, glo, 0);
     for (int bk = 0; bk < nb; ++bk) {
       const int base = bk * B;
       const int lim = min(span, tu - base);
       const int carry = bk == 0 ? 0 : lmax - 1;
-      for (int g = 0; g < ng; ++g) {
+      for (int g = glo; g < ghi; ++g) {
         const int j0 = g * JG;
         const bool two = JG == 2 && j0 + 1 < J;
         cf Y0[P], Y1[JG == 2 ? P : 1];
@@ -644,17 +658,17 @@ __device__ __forceinline__ void mix_utterance(const MixArgs& A, int u, const Sch
           for (int q = 0; q < P; ++q) X[q] = Xn[q];
           // With one source, the next group's input is this item's own
           // spectrum, not yet in the cache: it is handed over in registers.
-          const bool hand_over = g == 0 && I == 1 && ng > 1;
+          const bool hand_over = g == glo && I == 1 && cache;
           if (i + 1 < I) fetch(bk, g, i + 1);
-          else if (g + 1 < ng) {
+          else if (g + 1 < ghi) {
             if (!hand_over) fetch(bk, g + 1, 0);
           } else if (bk + 1 < nb) {
-            fetch(bk + 1, 0, 0);
+            fetch(bk + 1, glo, 0);
           }
-          if (g == 0) {
+          if (g == glo) {
             Fft<PL>::forward(X, lds, tw, t);
             Fft<PL>::post(X, tw, t);
-            if (ng > 1) store_spec<PL>(Xs + (long long)i * M, X, t);
+            if (cache) store_spec<PL>(Xs + (long long)i * M, X, t);
             if (hand_over) {
 #pragma unroll
               for (int q = 0; q < P; ++q) Xn[q] = X[q];
@@ -694,7 +708,7 @@ __device__ __forceinline__ void mix_utterance(const MixArgs& A, int u, const Sch
       const int nvalid = min(B, Nx - base);
       const int lim = min(span, tu - base);
       const int carry = bk == 0 ? 0 : lmax - 1;
-      for (int g = 0; g < ng; ++g) {
+      for (int g = glo; g < ghi; ++g) {
         const int j0 = g * JG;
         const bool two = JG == 2 && j0 + 1 < J;
         cf Y0[P], Y1[JG == 2 ? P : 1];
@@ -707,11 +721,11 @@ __device__ __forceinline__ void mix_utterance(const MixArgs& A, int u, const Sch
         for (int i = 0; i < I; ++i) {
           cf X[P];
           const cf* H0 = Hs + (long long)(i * J + j0) * M;
-          if (g == 0) {
+          if (g == glo) {
             load_real<PL>(X, A.x + uni64(b.src_off[(long long)u * NS + i]) + base, nvalid, t);
             Fft<PL>::forward(X, lds, tw, t);
             Fft<PL>::post(X, tw, t);
-            if (ng > 1) store_spec<PL>(Xs + (long long)i * M, X, t);
+            if (cache) store_spec<PL>(Xs + (long long)i * M, X, t);
           } else {
             load_spec<PL>(X, Xs + (long long)i * M, t);
           }
@@ -743,7 +757,8 @@ __global__ __launch_bounds__(T, MINW) void mix_kernel(MixArgs A) {
   // The first item of workgroup b is item b; later ones are popped from the
   // family's counter (offset by the grid), so an empty family costs one load
   // per workgroup and no atomic.
-  const int count = __builtin_amdgcn_readfirstlane(A.hdr->count[A.fam]);
+  const int gs = A.gsplit;
+  const int count = __builtin_amdgcn_readfirstlane(A.hdr->count[A.fam]) * gs;
   for (int first = 1;; first = 0) {
     __syncthreads();
     if (t == 0) s_idx = first ? (int)blockIdx.x : (int)gridDim.x + atomicAdd(&A.hdr->counter[A.fam], 1);
@@ -752,7 +767,8 @@ __global__ __launch_bounds__(T, MINW) void mix_kernel(MixArgs A) {
     // descriptor loads scalar and the buffer resources in scalar registers.
     const int idx = __builtin_amdgcn_readfirstlane(s_idx);
     if (idx >= count) break;
-    const int u = __builtin_amdgcn_readfirstlane(A.list[(long long)A.fam * A.b.U + idx]);
+    const int pos = idx / gs, gsel = gs > 1 ? idx - pos * gs : -1;
+    const int u = __builtin_amdgcn_readfirstlane(A.list[(long long)A.fam * A.b.U + pos]);
     Sched S = A.sched[u];
     S.log2n = __builtin_amdgcn_readfirstlane(S.log2n);
     S.hop = __builtin_amdgcn_readfirstlane(S.hop);
@@ -761,7 +777,8 @@ __global__ __launch_bounds__(T, MINW) void mix_kernel(MixArgs A) {
     S.lmax = __builtin_amdgcn_readfirstlane(S.lmax);
     dispatch_plan<T>(S.log2n, [&](auto pl) __attribute__((always_inline)) {
       using PL = decltype(pl);
-      mix_utterance<PL, JG, MINW>(A, u, S, lds, slot, t);
+      // a group past the utterance's mics has no work
+      if (gsel * JG < A.b.J) mix_utterance<PL, JG, MINW>(A, u, S, gsel, lds, slot, t);
     });
   }
 }
@@ -1403,6 +1420,7 @@ void families_used(const rsim_batch* b, const TuneDev& td, bool used[kNumFam]) {
 
 struct WsLayout {
   size_t hdr, sched, lists, scratch, total;
+  int gsplit[kNumFam];          // forward: work items per utterance (mic groups)
   int nsplit;                   // adjoint: parts per utterance
   size_t fam_partial[kNumFam];  // adjoint: byte offset of each family's part spectra (nsplit > 1)
   size_t fam_scratch[kNumFam];  // byte offset of each family's slots (families run concurrently)
@@ -1434,11 +1452,16 @@ WsLayout layout(const rsim_batch* b, const TuneDev& td, bool backward, const Dev
   // than compute units (each part recomputes the RIR spectra).
   L.nsplit = 1;
   if (backward && U > 0 && (size_t)cus > U) L.nsplit = (int)std::min<size_t>(4, (cus + U - 1) / U);
-  const size_t items = U * (size_t)L.nsplit;
   size_t off = L.scratch;
   for (int f = 0; f < kNumFam; ++f) {
     const long long M = kFamMaxM[f];
-    const long long spectra = backward ? (2 * S * J + J) : (S * J + (J > mic_group(f) ? S : 0));
+    // The forward splits utterances by mic group when there are fewer of
+    // them than compute units (each group then transforms the sources itself).
+    const int ngf = (int)((J + mic_group(f) - 1) / mic_group(f));
+    L.gsplit[f] = !backward && U > 0 && (size_t)cus > U && ngf > 1 ? ngf : 1;
+    const size_t items = U * (size_t)(backward ? L.nsplit : L.gsplit[f]);
+    const long long spectra =
+        backward ? (2 * S * J + J) : (S * J + (J > mic_group(f) && L.gsplit[f] == 1 ? S : 0));
     L.slot_cf[f] = spectra * M;
     // the largest occupancy used without a device; at most 8 workgroups per
     // CU and one per work item
@@ -1687,6 +1710,7 @@ void plan_mix(CallPlan& P, const rsim_batch* b, const BatchDev& bd, const TuneDe
     A.fam = f;
     A.scratch = reinterpret_cast<cf*>(base + L.fam_scratch[f]);
     A.slot_cf = L.slot_cf[f];
+    A.gsplit = L.gsplit[f];
     P.fam[P.nf++].set(mix_kernel_ptr(f, kernel_variant()), dim3(L.grid[f]), dim3(kFamT[f]), A);
   }
 }

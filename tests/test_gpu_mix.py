@@ -334,3 +334,26 @@ def test_single_source_many_mics(l2):
     db, alpha, y, rl, ol = _simulate(b, math.inf, fft_log2n=np.full(3, l2, np.int32))
     for u in range(3):
         _check_utterance(b, u, math.inf, y, rl, ol)
+
+
+@pytest.mark.gpu
+def test_many_utterances_several_mic_groups():
+    # more utterances than compute units with 5 mics: one work item per
+    # utterance, the source spectra cached for the later mic groups (one and
+    # several sources); with few utterances each mic group is its own item
+    rng = synth.rng_for(15, 0)
+    srcs, rirs = [], []
+    for u in range(300):
+        I = 1 + u % 3
+        n = int(rng.integers(1000, 5000))
+        srcs.append([synth.speech_like(rng, n)] + [synth.white_noise(rng, n) for _ in range(I - 1)])
+        L0 = int(rng.integers(30, 900))
+        rirs.append([[synth.rir(rng, L0, 0.2, int(rng.integers(0, 30))) for _ in range(5)] for _ in range(I)])
+    b = synth.pack(srcs, rirs, [[0.0] + [3.0] * (len(s) - 1) for s in srcs], 5)
+    db, alpha, y, rl, ol = _simulate(b, 20.0)
+    for u in (0, 1, 2, 150, 299):
+        _check_utterance(b, u, 20.0, y, rl, ol)
+    small = synth.subset(b, [0, 1, 2, 3])
+    db, alpha, y, rl, ol = _simulate(small, 20.0)
+    for u in range(4):
+        _check_utterance(small, u, 20.0, y, rl, ol)
