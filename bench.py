@@ -215,7 +215,7 @@ def main() -> int:
 
     if args.gpus != 1:
         print(f"bench.py: this build runs the hot path on one GPU; --gpus {args.gpus} is not "
-              f"supported (each GPU would take its own share of utterances, see DESIGN.md).",
+              f"supported (each GPU would take its own share of the utterances; this path runs on one GPU).",
               file=sys.stderr)
         return 2
 

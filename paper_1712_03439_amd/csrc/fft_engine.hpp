@@ -176,21 +176,6 @@ __device__ __forceinline__ cf twc(cf a) {
   return rot32<(INV ? -K : K) * (32 / R)>(a);
 }
 
-// wp[r] = w1^r for r = 1..R-1, by squaring (even r) or one product (odd r):
-// at most 2 log2 R roundings per power.
-template <int R>
-__device__ __forceinline__ void powers(cf* wp, cf w1) {
-  wp[1] = w1;
-  sfor<R - 2>([&](auto rc) {
-    constexpr int r = decltype(rc)::value + 2;
-    if constexpr (r % 2 == 0) {
-      wp[r] = csq(wp[r / 2]);
-    } else {
-      wp[r] = cmul(wp[r - 1], w1);
-    }
-  });
-}
-
 // Calls f(r, w^r) for r = 1..R-1 (r as a compile-time constant), forming the
 // powers on the fly from w, w^2, w^3, w^4 and the anchors w^{4m}: at most
 // about R/4 + 2 roundings per power and a handful of live registers.

@@ -357,3 +357,12 @@ def test_many_utterances_several_mic_groups():
     db, alpha, y, rl, ol = _simulate(small, 20.0)
     for u in range(4):
         _check_utterance(small, u, 20.0, y, rl, ol)
+
+
+@pytest.mark.gpu
+def test_differentiation_workload_forward_sampled():
+    # 64 utterances of 4 s, 3 sources, 4 mics, 8192-tap RIRs, no cut, N = 16384:
+    # fewer utterances than compute units, so each mic pair is its own work item
+    b = synth.make_config3()
+    db, alpha, y, rl, ol = _simulate(b, math.inf, fft_log2n=np.full(b.n_utt, 14, np.int32))
+    _sampled_check(b, math.inf, y, rl, ol, [0, 21, 42, 63], 32, 13)
