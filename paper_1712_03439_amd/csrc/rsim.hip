@@ -243,11 +243,11 @@ __device__ float utterance_cost(const BatchDev& b, const TuneDev& tune, int u, i
   return nbf * ((float)(I + J) * cf_ + (float)(I * J) * cm) + (float)(I * J) * cf_;
 }
 
-// The plan of utterance u: the forced size if the descriptor gives one, else
-// `batch_l2` if nonzero (one size for the whole batch), else its cheapest size.
-__device__ Sched plan_utterance(const BatchDev& b, const TuneDev& tune, int u, int batch_l2, int& err) {
+// The plan of utterance u with longest kept RIR lmax (> 0): the forced size
+// if the descriptor gives one, else `batch_l2` if nonzero (one size for the
+// whole batch), else its cheapest size.
+__device__ Sched plan_utterance(const BatchDev& b, const TuneDev& tune, int u, int lmax, int batch_l2, int& err) {
   Sched S = {0, 0, 0, 0, 0, 0};
-  const int lmax = utterance_lmax(b, u, err);
   if (lmax <= 0) return S;
   const int Nx = b.src_len[u];
   const long long tu = (long long)Nx + lmax - 1;
@@ -286,17 +286,37 @@ __device__ Sched plan_utterance(const BatchDev& b, const TuneDev& tune, int u, i
   return S;
 }
 
-// One workgroup of 1024 threads: plans every utterance and appends it to its
-// family's list, keeping the caller's order (a stable compaction per family).
-constexpr int kSchedThreads = 1024;
-
 struct SchedArgs {
   BatchDev b;
   TuneDev tune;
   Sched* sched;
   int* lists;
   WsHeader* hdr;
+  float* costs;  // [U][8]: per-size costs of each utterance (one size per batch)
 };
+
+// First step of the schedule, over every utterance in parallel: validates
+// its descriptor, records its longest kept RIR (or -1 for a bad descriptor)
+// in its plan slot and, for one size per batch, its cost at every size
+// (negative: that size cannot serve it).
+constexpr int kPrepThreads = 256;
+__global__ __launch_bounds__(kPrepThreads) void prepare_kernel(SchedArgs A) {
+  const BatchDev& b = A.b;
+  int err = 0;
+  for (int u = blockIdx.x * kPrepThreads + threadIdx.x; u < b.U; u += gridDim.x * kPrepThreads) {
+    const int lmax = utterance_lmax(b, u, err);
+    Sched S = {0, 0, 0, 0, lmax, 0};
+    A.sched[u] = S;
+    if (A.tune.one_size && !b.fft_log2n) {
+      for (int m = 9; m <= 15; ++m) A.costs[(long long)u * 8 + m - 9] = lmax > 0 ? utterance_cost(b, A.tune, u, lmax, m) : 0.f;
+    }
+  }
+  if (err) flag_status(err);
+}
+
+// One workgroup of 1024 threads: plans every utterance and appends it to its
+// family's list, keeping the caller's order (a stable compaction per family).
+constexpr int kSchedThreads = 1024;
 
 __global__ __launch_bounds__(kSchedThreads) void schedule_kernel(SchedArgs A) {
   const BatchDev& b = A.b;
@@ -326,10 +346,9 @@ __global__ __launch_bounds__(kSchedThreads) void schedule_kernel(SchedArgs A) {
     __syncthreads();
     for (int c0 = 0; c0 < b.U; c0 += kSchedThreads) {
       const int u = c0 + t;
-      int e = 0;
-      const int lmax = u < b.U ? utterance_lmax(b, u, e) : 0;
+      const int lmax = u < b.U ? sched[u].lmax : 0;
       for (int m = 9; m <= 15; ++m) {
-        const float c = lmax > 0 ? utterance_cost(b, tune, u, lmax, m) : 0.f;
+        const float c = lmax > 0 ? A.costs[(long long)u * 8 + m - 9] : 0.f;
         const double cs = wave_sum_d(c > 0.f ? (double)c : 0.0);
         const int bad = wave_or(lmax > 0 && c < 0.f);
         if ((t & 63) == 0) {
@@ -359,7 +378,7 @@ __global__ __launch_bounds__(kSchedThreads) void schedule_kernel(SchedArgs A) {
         err |= RSIM_DEV_BADDESC;
         u = -1;
       } else {
-        const Sched S = plan_utterance(b, tune, u, batch_l2, err);
+        const Sched S = plan_utterance(b, tune, u, sched[u].lmax, batch_l2, err);
         sched[u] = S;
         b.out_len[u] = S.tu;
         fam = S.nb > 0 ? family_of_log2n(S.log2n) : -1;
@@ -1419,7 +1438,7 @@ void families_used(const rsim_batch* b, const TuneDev& td, bool used[kNumFam]) {
 }
 
 struct WsLayout {
-  size_t hdr, sched, lists, scratch, total;
+  size_t hdr, sched, lists, costs, scratch, total;
   int gsplit[kNumFam];          // forward: work items per utterance (mic groups)
   int nsplit;                   // adjoint: parts per utterance
   size_t fam_partial[kNumFam];  // adjoint: byte offset of each family's part spectra (nsplit > 1)
@@ -1442,7 +1461,8 @@ WsLayout layout(const rsim_batch* b, const TuneDev& td, bool backward, const Dev
   L.hdr = 0;
   L.sched = align256(sizeof(WsHeader));
   L.lists = L.sched + align256(U * sizeof(Sched));
-  L.scratch = L.lists + align256((size_t)kNumFam * U * sizeof(int));
+  L.costs = L.lists + align256((size_t)kNumFam * U * sizeof(int));
+  L.scratch = L.costs + align256(U * 8 * sizeof(float));
   bool used[kNumFam];
   families_used(b, td, used);
   const long long S = b->max_src, J = b->n_mic;
@@ -1530,7 +1550,7 @@ struct Node {
 
 struct CallPlan {
   bool has_cut = false;
-  Node cut, sched;
+  Node cut, prep, sched;
   Node fam[kNumFam + 1];  // the family kernels (and, for the adjoint, the zero fill)
   int nf = 0;
   Node post[kNumFam];     // kernels that need every family kernel done (the adjoint's finishing pass)
@@ -1549,6 +1569,8 @@ bool capturing(hipStream_t s) {
 rsim_status issue_eager(CallPlan& P, hipStream_t s) {
   const DevState& st = dev_state();
   if (P.has_cut && hipLaunchKernel(P.cut.fn, P.cut.grid, P.cut.block, P.cut.p(), 0, s) != hipSuccess)
+    return RSIM_EDEVICE;
+  if (hipLaunchKernel(P.prep.fn, P.prep.grid, P.prep.block, P.prep.p(), 0, s) != hipSuccess)
     return RSIM_EDEVICE;
   if (hipLaunchKernel(P.sched.fn, P.sched.grid, P.sched.block, P.sched.p(), 0, s) != hipSuccess)
     return RSIM_EDEVICE;
@@ -1638,7 +1660,9 @@ rsim_status issue_graph(CallPlan& P, hipStream_t s) {
   bool ok = true;
   if (P.has_cut) ok = add(P.cut, nullptr, 0, &prev);
   hipGraphNode_t node = nullptr;
-  ok = ok && add(P.sched, prev ? &prev : nullptr, prev ? 1 : 0, &node);
+  ok = ok && add(P.prep, prev ? &prev : nullptr, prev ? 1 : 0, &node);
+  prev = node;
+  ok = ok && add(P.sched, &prev, 1, &node);
   prev = node;
   for (int k = 0; ok && k < P.nf; ++k) {
     ok = add(P.fam[k], &prev, 1, &node);
@@ -1691,6 +1715,13 @@ void plan_mix(CallPlan& P, const rsim_batch* b, const BatchDev& bd, const TuneDe
   SA.hdr = reinterpret_cast<WsHeader*>(base + L.hdr);
   SA.sched = reinterpret_cast<Sched*>(base + L.sched);
   SA.lists = reinterpret_cast<int*>(base + L.lists);
+  SA.costs = reinterpret_cast<float*>(base + L.costs);
+  {
+    const int cus = st.cus > 0 ? st.cus : 256;
+    const long long need = ((long long)b->n_utt + kPrepThreads - 1) / kPrepThreads;
+    const long long g = std::max(1LL, std::min(need, (long long)cus * 4));
+    P.prep.set(reinterpret_cast<const void*>(&prepare_kernel), dim3((unsigned)g), dim3(kPrepThreads), SA);
+  }
   P.sched.set(reinterpret_cast<const void*>(&schedule_kernel), dim3(1), dim3(kSchedThreads), SA);
   bool used[kNumFam];
   families_used(b, td, used);
@@ -1729,6 +1760,13 @@ void plan_bwd(CallPlan& P, const rsim_batch* b, const BatchDev& bd, const TuneDe
   SA.hdr = reinterpret_cast<WsHeader*>(base + L.hdr);
   SA.sched = reinterpret_cast<Sched*>(base + L.sched);
   SA.lists = reinterpret_cast<int*>(base + L.lists);
+  SA.costs = reinterpret_cast<float*>(base + L.costs);
+  {
+    const int cus = st.cus > 0 ? st.cus : 256;
+    const long long need = ((long long)b->n_utt + kPrepThreads - 1) / kPrepThreads;
+    const long long g = std::max(1LL, std::min(need, (long long)cus * 4));
+    P.prep.set(reinterpret_cast<const void*>(&prepare_kernel), dim3((unsigned)g), dim3(kPrepThreads), SA);
+  }
   P.sched.set(reinterpret_cast<const void*>(&schedule_kernel), dim3(1), dim3(kSchedThreads), SA);
   BwdArgs A;
   A.b = bd;
