@@ -168,7 +168,11 @@ rsim_status rsim_simulate(const rsim_batch* b, const float* x, const float* h,
  *   grad_x[i][n]  = sum_j alpha_ij sum_{k<L_ij} h_ij[k] g_j[n+k]        (n < Nx)
  *   grad_h[r][k]  = alpha_r sum_n x_i[n] g_j[n+k]   for k < L_r, 0 for L_r <= k < L0_r
  *   grad_alpha[r] = sum_n g_j[n] (h_r * x_i)[n]     (grad_alpha may be NULL)
- * in the layouts of x, h and alpha.  The cut index gets no gradient.
+ * in the layouts of x, h and alpha.  The cut index gets no gradient.  Entries
+ * that belong to no source or RIR slot of an utterance are not written.  The
+ * FFT size and hop are chosen as by rsim_mix with the same tune.  With fewer
+ * utterances than compute units, each utterance is split into block ranges
+ * whose correlation spectra are summed by a finishing pass (in ws).
  * ws must hold rsim_mix_workspace_bytes(b, tune, 1) bytes.
  */
 rsim_status rsim_mix_backward(const rsim_batch* b, const float* x, const float* h,
