@@ -565,12 +565,57 @@ __device__ __forceinline__ const cf* plan_tw() {
   return g_tw + tw_off<ilog2c(PL::N)>();
 }
 
+// An utterance's source and RIR descriptors, copied into LDS once per work
+// item: reading them later costs an LDS access instead of a scalar memory
+// round trip at the start of every source item.  Batches with more slots
+// than fit read the descriptor arrays directly.
+constexpr int kDescMax = 64;
+struct DescCache {
+  long long src_off[kDescMax];
+  long long rir_off[kDescMax];
+  int rir_len[kDescMax];
+};
+
+struct UttDesc {
+  const BatchDev& b;
+  const DescCache& c;
+  long long s0, r0;  // first source / RIR slot of the utterance
+  bool fast_src, fast_rir;
+  __device__ long long src_off(int i) const {
+    if (fast_src) return uni64(c.src_off[i]);
+    return uni64(b.src_off[s0 + i]);
+  }
+  __device__ long long rir_off(int k) const {
+    if (fast_rir) return uni64(c.rir_off[k]);
+    return uni64(b.rir_off[r0 + k]);
+  }
+  __device__ int rir_len(int k) const {
+    if (fast_rir) return uni(c.rir_len[k]);
+    return uni(b.rir_len[r0 + k]);
+  }
+};
+
+// Fills the cache for utterance u (I sources); contains a barrier.
+__device__ __forceinline__ UttDesc load_desc(const BatchDev& b, DescCache& c, int u, int I, int t, int nthreads) {
+  const long long s0 = (long long)u * b.S, r0 = s0 * b.J;
+  const bool fs = b.S <= kDescMax, fr = (long long)b.S * b.J <= kDescMax;
+  if (fs)
+    for (int i = t; i < I; i += nthreads) c.src_off[i] = b.src_off[s0 + i];
+  if (fr)
+    for (int k = t; k < I * b.J; k += nthreads) {
+      c.rir_off[k] = b.rir_off[r0 + k];
+      c.rir_len[k] = b.rir_len[r0 + k];
+    }
+  __syncthreads();
+  return UttDesc{b, c, s0, r0, fs, fr};
+}
+
 // The RIR spectra of one utterance, once, scaled by alpha / (8M) (which also
 // carries the normalisation of the inverse transform); the next RIR is
 // requested while the current one is transformed.
 template <class PL>
-__device__ __forceinline__ void rir_spectra(const MixArgs& A, int u, int I, int jlo, int jhi, cf* Hs, Xch<PL>& lds,
-                                            const TwBase& tw, int t) {
+__device__ __forceinline__ void rir_spectra(const MixArgs& A, const UttDesc& D, int u, int I, int jlo, int jhi,
+                                            cf* Hs, Xch<PL>& lds, const TwBase& tw, int t) {
   constexpr int P = PL::P, M = PL::M;
   const BatchDev& b = A.b;
   const int J = b.J, NS = b.S, JN = jhi - jlo;
@@ -581,16 +626,16 @@ __device__ __forceinline__ void rir_spectra(const MixArgs& A, int u, int I, int 
   auto slot_of = [&](int k) __attribute__((always_inline)) { return (k / JN) * J + jlo + k % JN; };
   cf vn[P];
   if (n_rir > 0) {
-    const long long r = r0 + slot_of(0);
-    load_real<PL>(vn, A.h + uni64(b.rir_off[r]), uni(b.rir_len[r]), t);
+    const int k0 = slot_of(0);
+    load_real<PL>(vn, A.h + D.rir_off(k0), D.rir_len(k0), t);
   }
   for (int k = 0; k < n_rir; ++k) {
     cf v[P];
 #pragma unroll
     for (int q = 0; q < P; ++q) v[q] = vn[q];
     if (k + 1 < n_rir) {
-      const long long rn = r0 + slot_of(k + 1);
-      load_real<PL>(vn, A.h + uni64(b.rir_off[rn]), uni(b.rir_len[rn]), t);
+      const int kn = slot_of(k + 1);
+      load_real<PL>(vn, A.h + D.rir_off(kn), D.rir_len(kn), t);
     }
     Fft<PL>::forward(v, lds, tw, t);
     Fft<PL>::post(v, tw, t);
@@ -607,7 +652,7 @@ __device__ __forceinline__ void rir_spectra(const MixArgs& A, int u, int I, int 
 // block are kept in the workgroup's scratch for the later mic groups.
 template <class PL, int JG, int MINW>
 __device__ __forceinline__ void mix_utterance(const MixArgs& A, int u, const Sched& S, int gsel, cf* lds_raw,
-                                              cf* slot, int t) {
+                                              DescCache& dc, cf* slot, int t) {
   constexpr int P = PL::P, M = PL::M;
   Xch<PL> lds{lds_raw, 0};
   const TwBase tw = Fft<PL>::bases(plan_tw<PL>(), t);
@@ -624,7 +669,8 @@ __device__ __forceinline__ void mix_utterance(const MixArgs& A, int u, const Sch
   const int ng = ghi - glo;
   const bool cache = ng > 1;
 
-  rir_spectra<PL>(A, u, I, glo * JG, min(J, ghi * JG), Hs, lds, tw, t);
+  const UttDesc D = load_desc(b, dc, u, I, t, PL::T);
+  rir_spectra<PL>(A, D, u, I, glo * JG, min(J, ghi * JG), Hs, lds, tw, t);
 
   const long long yo = uni64(b.out_off[u]);
   const long long ys = uni(b.out_stride[u]);
@@ -646,7 +692,7 @@ __device__ __forceinline__ void mix_utterance(const MixArgs& A, int u, const Sch
     auto fetch = [&](int bk, int g, int i) __attribute__((always_inline)) {
       if (g == glo) {
         const int base = bk * B;
-        load_real<PL>(Xn, A.x + uni64(b.src_off[(long long)u * NS + i]) + base, min(B, Nx - base), t);
+        load_real<PL>(Xn, A.x + D.src_off(i) + base, min(B, Nx - base), t);
       } else {
         load_spec<PL>(Xn, Xs + (long long)i * M, t);
       }
@@ -741,7 +787,7 @@ __device__ __forceinline__ void mix_utterance(const MixArgs& A, int u, const Sch
           cf X[P];
           const cf* H0 = Hs + (long long)(i * J + j0) * M;
           if (g == glo) {
-            load_real<PL>(X, A.x + uni64(b.src_off[(long long)u * NS + i]) + base, nvalid, t);
+            load_real<PL>(X, A.x + D.src_off(i) + base, nvalid, t);
             Fft<PL>::forward(X, lds, tw, t);
             Fft<PL>::post(X, tw, t);
             if (cache) store_spec<PL>(Xs + (long long)i * M, X, t);
@@ -770,6 +816,7 @@ __device__ __forceinline__ void mix_utterance(const MixArgs& A, int u, const Sch
 template <int T, int JG, int MINW>
 __global__ __launch_bounds__(T, MINW) void mix_kernel(MixArgs A) {
   __shared__ cf lds[max_lds_with_threads<T>()];
+  __shared__ DescCache s_desc;
   __shared__ int s_idx;
   const int t = threadIdx.x;
   cf* slot = A.scratch + (long long)blockIdx.x * A.slot_cf;
@@ -797,7 +844,7 @@ __global__ __launch_bounds__(T, MINW) void mix_kernel(MixArgs A) {
     dispatch_plan<T>(S.log2n, [&](auto pl) __attribute__((always_inline)) {
       using PL = decltype(pl);
       // a group past the utterance's mics has no work
-      if (gsel * JG < A.b.J) mix_utterance<PL, JG, MINW>(A, u, S, gsel, lds, slot, t);
+      if (gsel * JG < A.b.J) mix_utterance<PL, JG, MINW>(A, u, S, gsel, lds, s_desc, slot, t);
     });
   }
 }
