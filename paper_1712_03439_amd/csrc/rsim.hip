@@ -2,14 +2,20 @@
 //
 // Hot path (one call of rsim_mix / rsim_simulate):
 //   truncate_kernel  RIR tail cut-off, Sec. 2.3 eqs. (7)-(9)
-//   schedule_kernel  per-utterance FFT size / hop / block count (eq. (6) cost,
-//                    evaluated for every N = 2^m as the text after eq. (6) says),
-//                    grouped by workgroup size, in the caller's order
-//   mix_kernel<T>    persistent workgroups pop utterances; each computes the
-//                    I*J RIR spectra once (Sec. 2.2: the RIR FFT is not
-//                    repeated per block), then walks the blocks: FFT of each
-//                    source block, spectral multiply-accumulate over sources
-//                    per mic, inverse FFT, overlap-add (eq. (6)) into y (eq. (2)).
+//   prepare_kernel   per utterance, in parallel: descriptor checks, longest
+//                    kept RIR, cost of every FFT size N = 2^m (eq. (6))
+//   schedule_kernel  FFT size / hop / block count per utterance (one size for
+//                    the batch or each its own, as the text after eq. (6)
+//                    chooses per filtering), lists per workgroup size in the
+//                    caller's order
+//   mix_kernel<T>    persistent workgroups pop work items (an utterance, or
+//                    one mic group of it); each computes the RIR spectra once
+//                    (Sec. 2.2: the RIR FFT is not repeated per block), then
+//                    walks the blocks: FFT of each source block, spectral
+//                    multiply-accumulate over sources per mic, inverse FFT,
+//                    overlap-add (eq. (6)) into y (eq. (2)).
+// Adjoint (rsim_mix_backward): bwd_kernel<T> per utterance or block range,
+// bwd_finish_kernel<T> for split utterances, bwd_zero_kernel for idle ones.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
