@@ -128,3 +128,32 @@ def test_snr_gains_host_rule_matches_oracle():
     lib = rsim.lib()
     assert lib.rsim_snr_gains(None, None, 2, 2, None) == rsim.RSIM_EINVAL
     assert lib.rsim_snr_gains(None, None, 0, 2, None) == rsim.RSIM_OK
+
+
+def test_mix_backward_validation_codes():
+    lib = rsim.lib()
+    p = ctypes.c_void_p(8)
+    b = _host_batch()
+    need = lib.rsim_mix_workspace_bytes(ctypes.byref(b), None, 1)
+    args = lambda **k: [k.get(n, p) for n in ("x", "h", "alpha", "gy", "gx", "gh", "ga")]  # noqa: E731
+    # too small a workspace
+    assert lib.rsim_mix_backward(ctypes.byref(b), *args(), p, need - 1, None, None) == rsim.RSIM_EWORKSPACE
+    # every data pointer but grad_alpha is required
+    for name in ("x", "h", "alpha", "gy", "gx", "gh"):
+        assert lib.rsim_mix_backward(ctypes.byref(b), *args(**{name: None}), p, need, None, None) == \
+            rsim.RSIM_EINVAL, name
+    bad = _host_batch()
+    bad.n_mic = 0
+    assert lib.rsim_mix_backward(ctypes.byref(bad), *args(), p, need, None, None) == rsim.RSIM_EINVAL
+    empty = _host_batch(U=0)
+    assert lib.rsim_mix_backward(ctypes.byref(empty), *([None] * 7), None, 0, None, None) == rsim.RSIM_OK
+
+
+def test_one_size_tune_field_reaches_the_workspace_query():
+    # the tune table is accepted by the size query with either policy
+    lib = rsim.lib()
+    b = _host_batch()
+    f, m = [2.5 * (1 << k) * k for k in range(9, 16)], [8.0 * ((1 << k) / 2 + 1) for k in range(9, 16)]
+    for one in (False, True):
+        t = rsim.tune_table(f, m, one_size=one)
+        assert lib.rsim_mix_workspace_bytes(ctypes.byref(b), ctypes.byref(t), 0) > 0
