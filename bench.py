@@ -71,36 +71,13 @@ def lpt_order(b) -> np.ndarray:
     return np.argsort(-cost, kind="stable").astype(np.int32)
 
 
-def utt_cost(nx, I, J, lmax, m, tune_fft, tune_mac):
-    """The schedule's cost of one utterance at N = 2^m (None if N cannot serve it)."""
-    c = tune_fft[m - 9]
-    N = 1 << m
-    if not c > 0 or N < lmax:
-        return None
-    B = N - lmax + 1
-    nb = (nx + B - 1) // B
-    return nb * ((I + J) * c + I * J * tune_mac[m - 9]) + I * J * c
-
-
-def batch_log2n(shapes, tune_fft, tune_mac):
-    """The one size the schedule picks for a batch (smallest summed cost among
-    the sizes every utterance can use), or 0."""
-    tot = {}
-    for m in range(9, 16):
-        cs = [utt_cost(nx, I, J, lmax, m, tune_fft, tune_mac) for nx, I, J, lmax in shapes]
-        if all(c is not None for c in cs):
-            tot[m] = sum(cs)
-    return min(tot, key=tot.get) if tot else 0
-
-
 def host_plan(nx, I, J, lmax, tune_fft, tune_mac, l2=0):
-    """The FFT size the schedule kernel picks (same cost rule), for FLOP accounting."""
+    """N, hop and block count of an utterance under the schedule's rule (the
+    batch's one size l2, else the utterance's own choice), for FLOP accounting."""
+    from paper_1712_03439_amd import autotune
+
     if not l2:
-        best = None
-        for m in range(9, 16):
-            cost = utt_cost(nx, I, J, lmax, m, tune_fft, tune_mac)
-            if cost is not None and (best is None or cost < best):
-                best, l2 = cost, m
+        l2 = autotune.utterance_log2n(nx, I, J, lmax, tune_fft, tune_mac)
     N = 1 << l2
     B = N - lmax + 1
     return N, B, (nx + B - 1) // B
@@ -207,7 +184,10 @@ def main() -> int:
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-diff", action="store_true", help="skip the adjoint (differentiation workload) timing")
-    ap.add_argument("--tune", default="auto", help="autotune table JSON, 'auto' or 'model'")
+    ap.add_argument("--tune", default="measure",
+                    help="'measure' (time every FFT size and kernel variant on the first epoch's "
+                         "batch before the warmup), 'model' (the built-in cost model), 'auto' (this "
+                         "device's entry of the stored table) or a table JSON path")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="before the warmup, fill and copy a buffer of this size (a reference "
                          "for the HBM byte counters)")
@@ -235,8 +215,7 @@ def main() -> int:
     log(f"dataset: {base.n_utt} utterances, {base.audio_seconds:.0f} audio-s, "
         f"{base.x.nbytes / 1e9:.2f} GB of sources ({time.perf_counter() - t0:.1f} s)")
     order = lpt_order(base)
-    tune = autotune.load(args.tune)
-    tf, tm = autotune.costs(tune)
+    tune = None if args.tune == "measure" else autotune.load(args.tune)
 
     x_dev = torch.from_numpy(base.x).to(dev)
     epochs = []
@@ -252,10 +231,27 @@ def main() -> int:
         epochs.append((b, db, alpha))
         if e % 5 == 0:
             log(f"rooms for epoch {e} ready ({time.perf_counter() - t0:.1f} s)")
-    y = torch.empty(max(b.y_len for b, _, _ in epochs), dtype=torch.float32, device=dev)
-    ws = torch.empty(max(db.workspace_bytes(tune) for _, db, _ in epochs), dtype=torch.uint8, device=dev)
     stream = torch.cuda.Stream()
     stream.wait_stream(torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    tune_info = {"source": "built-in cost model" if tune is None else f"stored table ({args.tune})"}
+    if args.tune == "measure":
+        # The tuner times every FFT size and kernel variant on the first
+        # epoch's (cut) batch; its table then drives every epoch's schedule.
+        t1 = time.perf_counter()
+        _, db0, alpha0 = epochs[0]
+        rsim.truncate_batch(db0, args.eta, stream=stream)
+        stream.synchronize()
+        tune, entry = autotune.tune(db0, alpha0, stream=stream)
+        tune_info = {"source": "measured on the first epoch's batch", "variant": entry["variant"],
+                     "ms": {k: v["ms"] for k, v in entry["measured"]["sizes"].items()},
+                     "seconds": round(time.perf_counter() - t1, 2)}
+        log(f"tuned in {tune_info['seconds']} s: variants {entry['variant']}, "
+            + ", ".join(f"N=2^{k}: " + "/".join(f"{t:.3f}" for t in v.values()) + " ms"
+                        for k, v in tune_info["ms"].items()))
+    tf, tm = autotune.costs(tune)
+    y = torch.empty(max(b.y_len for b, _, _ in epochs), dtype=torch.float32, device=dev)
+    ws = torch.empty(max(db.workspace_bytes(tune) for _, db, _ in epochs), dtype=torch.uint8, device=dev)
     torch.cuda.synchronize()
     use_graph = not args.no_graph
 
@@ -318,7 +314,7 @@ def main() -> int:
         Lr = L.reshape(b.n_utt, b.max_src * J)
         shapes = [(int(b.src_len[u]), int(I[u]), J, int(Lr[u].max())) for u in range(b.n_utt)
                   if int(Lr[u].max()) > 0 and b.src_len[u] > 0]
-        l2b = batch_log2n(shapes, tf, tm) if one_size else 0
+        l2b = autotune.batch_log2n(shapes, tf, tm) if one_size else 0
         for nx, Iu, _, lmax in shapes:
             N, B, nb = host_plan(nx, Iu, J, lmax, tf, tm, l2b)
             c = 2.5 * N * math.log2(N)
@@ -357,8 +353,7 @@ def main() -> int:
                    "global_batch": base.n_utt, "audio_s_per_step": round(audio, 1),
                    "eta_db": args.eta, "hip_graph": use_graph,
                    "fft_sizes": {str(k): v // K for k, v in sorted(sizes.items())},
-                   "tune": ("measured table" if args.tune != "model" and tune is not None else "cost model")
-                           + (", one size per batch" if one_size else ", size per utterance")},
+                   "tune": dict(tune_info, policy="one size per batch" if one_size else "size per utterance")},
         "roofline": roof,
         "hbm": {"achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4)},

@@ -94,11 +94,23 @@ typedef struct rsim_batch {
  * smallest cost summed over the utterances among the sizes that every
  * utterance can use (each utterance keeps its own choice if there is none).
  * Sizes forced through rsim_batch.fft_log2n take precedence over both rules.
+ * variant[f] picks the work split of the filter-and-mix kernel of family f,
+ * the kernels of f = 0..5 running with 32 << f threads per workgroup (N = 512;
+ * 1024 and 2048; 4096; 8192; 16384; 32768):
+ *   0 the library default (2); 1 one mic per pass, registers sized for two
+ *   waves per SIMD; 2 two mics per pass, one wave per SIMD; 3 two mics per
+ *   pass, two waves per SIMD; 4 one mic per pass, four waves per SIMD (a
+ *   workgroup of 32 << f threads has at least (32 << f) / 256 waves per SIMD).
+ * Family 5 has variant 4 only; its entry is ignored.  Costs must be finite
+ * and >= 0 and variants in 0..4 (RSIM_EINVAL, or a workspace size of 0,
+ * otherwise).  The variant changes the order of no floating-point operation
+ * of an output sample.  A measured table comes from autotune.py.
  */
 typedef struct rsim_tune {
   float cost_fft[7];
   float cost_mac[7];
   int32_t one_size;
+  int32_t variant[6];
 } rsim_tune;
 
 /* Initialise the library on the current device (twiddle tables, launch

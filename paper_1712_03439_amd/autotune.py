@@ -7,8 +7,10 @@ smallest cost summed over the batch.  The paper's cost model counts multiplicati
 (eq. (6)); the kernels do I + J transforms per block (source spectra are shared
 across mics and the sum over sources is taken in the spectral domain), so the
 built-in model uses that count with 2.5 N log2 N per real FFT.  `tune()`
-replaces the model by measured times of the kernels themselves and stores the
-table next to this file, keyed by the device name.
+times the filter-and-mix kernels of every size and kernel variant on a batch
+(eager launches on one stream) and scales the model per size to the measured
+times; it also picks each kernel family's variant (the work split of
+rsim_tune.variant).  Tables are stored keyed by the device name.
 """
 from __future__ import annotations
 
@@ -63,95 +65,195 @@ def device_name() -> str:
         return "unknown"
 
 
-class _Probe:
-    """Descriptor of U identical utterances (I sources of Nx samples, J mics,
-    RIRs of L taps) with packed, non-overlapping offsets."""
-
-    def __init__(self, U: int, I: int, J: int, nx: int, L: int):
-        import numpy as np
-
-        self.n_utt, self.n_mic, self.max_src = U, J, I
-        self.n_src = np.full(U, I, np.int32)
-        self.src_len = np.full(U, nx, np.int32)
-        self.src_off = (np.arange(U * I, dtype=np.int64) * nx).reshape(U, I)
-        self.rir_len0 = np.full(U * I * J, L, np.int32)
-        self.rir_off = np.arange(U * I * J, dtype=np.int64) * L
-        T = nx + L - 1
-        self.out_stride = np.full(U, T, np.int32)
-        self.out_off = np.arange(U, dtype=np.int64) * (J * T)
-        self.y_len = U * J * T
-        self.x = np.zeros(0, np.float32)
-        self.h = np.zeros(0, np.float32)
-        self.x_len, self.h_len = U * I * nx, U * I * J * L
+# Kernel families (workgroup of 32 << f threads) of each log2 N, and the
+# kernel variants (rsim_tune.variant codes) each family has.
+FAMILY = {9: 0, 10: 1, 11: 1, 12: 2, 13: 3, 14: 4, 15: 5}
+VARIANTS = {0: (1, 2, 3, 4), 1: (1, 2, 3, 4), 2: (1, 2, 3, 4), 3: (1, 2, 3, 4), 4: (1, 2, 3, 4), 5: (4,)}
+DEFAULT_VARIANT = 2
 
 
-def tune(sizes=LOG2N, blocks: int = 8, reps: int = 3, save: bool = True, verbose: bool = False):
-    """Measure c_fft(N) and c_mac(N) (ns per transform and per spectral
-    product, whole-GPU throughput) with the mix kernels themselves.
+def utt_cost(nx: int, I: int, J: int, lmax: int, m: int, cost_fft, cost_mac) -> Optional[float]:
+    """The schedule's cost of one utterance at N = 2^m with the default hop
+    N - lmax + 1, or None if N cannot serve it (or the size is disabled)."""
+    c = cost_fft[m - 9]
+    N = 1 << m
+    if not c > 0 or N < lmax:
+        return None
+    B = N - lmax + 1
+    nb = (nx + B - 1) // B
+    return nb * ((I + J) * c + I * J * cost_mac[m - 9]) + I * J * c
 
-    For each N two probes of identical utterances run with N forced and hop
-    N/2 (so every probe has `blocks` blocks): (I, J) = (1, 1) and (3, 2).  The
-    time per utterance is modelled as blocks ((I + J) + I J k) c_f + I J c_f,
-    with c_m = k c_f and k the ratio of the flop counts 8 (N/2 + 1) and
-    2.5 N log2 N; c_f is the mean of the two probes' estimates."""
-    if True:  # switched off until the crash below is understood
-        raise RuntimeError("the measuring tuner is switched off: one of its runs ended in a host "
-                           "segmentation fault whose cause is not yet found; the built-in cost "
-                           "model is used instead")
+
+def batch_log2n(shapes, cost_fft, cost_mac) -> int:
+    """The one size the schedule picks for a batch of (nx, I, J, lmax): the
+    smallest summed cost among the sizes every utterance can use, else 0."""
+    tot = {}
+    for m in LOG2N:
+        cs = [utt_cost(nx, I, J, lmax, m, cost_fft, cost_mac) for nx, I, J, lmax in shapes]
+        if all(c is not None for c in cs):
+            tot[m] = sum(cs)
+    return min(tot, key=tot.get) if tot else 0
+
+
+def utterance_log2n(nx: int, I: int, J: int, lmax: int, cost_fft, cost_mac) -> int:
+    """The size the schedule picks for one utterance on its own (0 if none)."""
+    best, l2 = None, 0
+    for m in LOG2N:
+        c = utt_cost(nx, I, J, lmax, m, cost_fft, cost_mac)
+        if c is not None and (best is None or c < best):
+            best, l2 = c, m
+    return l2
+
+
+def batch_shapes(db) -> List[Tuple[int, int, int, int, int]]:
+    """(u, Nx, I, J, longest kept RIR) of every utterance with work, from the
+    batch's current (cut) RIR lengths."""
+    import numpy as np
+
+    n_src = db.n_src.cpu().numpy()
+    nx = db.src_len.cpu().numpy()
+    L = db.rir_len.cpu().numpy().reshape(db.U, db.S * db.J)
+    out = []
+    for u in range(db.U):
+        I = int(n_src[u])
+        lmax = int(L[u, : I * db.J].max()) if I else 0
+        if I and nx[u] > 0 and lmax > 0:
+            out.append((u, int(nx[u]), I, db.J, lmax))
+    return out
+
+
+def measure(db, alpha, sizes=LOG2N, reps: int = 3, min_probe: int = 64, stream=None,
+            verbose: bool = False) -> dict:
+    """Time the filter-and-mix kernels of every FFT size and kernel variant on
+    the caller's batch (already cut: rsim.truncate_batch).
+
+    The probe of size N is the batch's utterances whose longest kept RIR is at
+    most N/2 (so the hop N - L + 1 is at least half the block), all forced to
+    N with the default hop; a size with fewer than min_probe such utterances
+    (fewer than the batch's own count if smaller) is not measured.  Each
+    (size, variant) runs once untimed and then reps times eagerly on one
+    stream; the mean time per call is kept, with the built-in model's cost of
+    the same probe, so that the fit can scale the model per size."""
     import numpy as np
     import torch
 
     from . import rsim
 
-    dev = torch.device("cuda", torch.cuda.current_device())
-    stream = torch.cuda.Stream(device=dev)
-    cost_f, cost_m = [0.0] * 7, [0.0] * 7
+    shapes = batch_shapes(db)
+    if not shapes:
+        raise ValueError("the batch has no utterance with work to time")
     mf, mm = model_costs()
+    dev = db.device
+    if stream is None:
+        stream = torch.cuda.Stream(device=dev)
+    stream.wait_stream(torch.cuda.current_stream(dev))
+    y = db.new_output()
+    S, J = db.S, db.J
+    out = {"utterances": len(shapes), "reps": reps, "sizes": {}}
     for m in sizes:
         N = 1 << m
-        hop, L = N // 2, N // 2
-        nx = blocks * hop
-        U = max(2048, (1 << 24) // nx)
-        k = mm[m - 9] / mf[m - 9]
-        ratios = []
-        for I, J in ((1, 1), (3, 2)):
-            pr = _Probe(U, I, J, nx, L)
-            db = rsim.DeviceBatch(pr, device=dev, fft_log2n=np.full(U, m, np.int32),
-                                  hop=np.full(U, hop, np.int32), upload_data=False)
-            g = torch.Generator(device=dev)
-            g.manual_seed(1234 + m)
-            db.x = torch.randn(pr.x_len, device=dev, generator=g)
-            db.h = torch.randn(pr.h_len, device=dev, generator=g)
-            db.x_len, db.h_len = pr.x_len, pr.h_len
-            alpha = torch.ones(U * I * J, device=dev)
-            y = db.new_output()
-            ws = db.workspace(None)
+        rows = [sh for sh in shapes if sh[4] <= N // 2]
+        if not rows or len(rows) < min(min_probe, len(shapes)):
+            continue
+        idx = [sh[0] for sh in rows]
+        probe = db.select(idx)
+        probe.fft_log2n = torch.full((probe.U,), m, dtype=torch.int32, device=dev)
+        probe.hop = None
+        u = torch.as_tensor(np.asarray(idx, np.int64), device=dev)
+        slot = (u[:, None] * S + torch.arange(S, device=dev)[None, :]).reshape(-1)
+        a = alpha[(slot[:, None] * J + torch.arange(J, device=dev)[None, :]).reshape(-1)].contiguous()
+        model = float(sum(utt_cost(nx, I, Jm, lmax, m, mf, mm) for _, nx, I, Jm, lmax in rows))
+        f = FAMILY[m]
+        times = {}
+        for v in VARIANTS[f]:
+            var = [0] * 6
+            var[f] = v
+            t = rsim.tune_table(mf, mm, True, var)
+            ws = probe.workspace(t)
             with torch.cuda.stream(stream):
-                rsim.mix(db, alpha, y=y, ws=ws)
+                rsim.mix(probe, a, y=y, ws=ws, tune=t, stream=stream)
                 e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
                 e0.record(stream)
                 for _ in range(reps):
-                    rsim.mix(db, alpha, y=y, ws=ws)
+                    rsim.mix(probe, a, y=y, ws=ws, tune=t, stream=stream)
                 e1.record(stream)
             e1.synchronize()
-            t_utt = e0.elapsed_time(e1) / reps * 1e6 / U  # ns per utterance
-            units = blocks * ((I + J) + I * J * k) + I * J
-            ratios.append(t_utt / units)
-            del db, y, ws, alpha
-        cf_ = float(np.mean(ratios))
-        cost_f[m - 9], cost_m[m - 9] = cf_, cf_ * k
+            times[v] = e0.elapsed_time(e1) / reps
+            del ws
+        out["sizes"][m] = {"utterances": len(idx), "model": model, "ms": times}
         if verbose:
-            print(f"N={N}: c_fft={cf_:.2f} ns (probe ratios {ratios[0]:.2f}, {ratios[1]:.2f})", flush=True)
-    entry = {"cost_fft": cost_f, "cost_mac": cost_m, "unit": "ns"}
+            print(f"N={N}: {len(idx)} utterances, " +
+                  ", ".join(f"variant {v}: {ms:.3f} ms" for v, ms in times.items()), flush=True)
+    if rsim.device_status():
+        raise RuntimeError("a timing run set the device status word")
+    if not out["sizes"]:
+        raise ValueError("no FFT size had enough utterances to time")
+    return out
+
+
+def fit(measured: dict) -> dict:
+    """A tune-table entry from measure()'s times (or the "measured" field of
+    a stored entry).
+
+    Per family, the variant with the smallest time relative to the best
+    variant, summed over the family's measured sizes (the library default
+    wins ties).  Per measured size m, k(m) = the time with that variant / the
+    model's cost of the probe; a size not measured takes k of the nearest
+    measured size (the larger on a tie).  The costs are the built-in model's
+    scaled by k (ns per model unit), so the schedule's summed cost of a batch
+    approximates its time at each size and the one-size rule picks the size
+    that ran fastest."""
+    mf, mm = model_costs()
+    sizes = {}
+    for m, rec in measured["sizes"].items():
+        sizes[int(m)] = {"utterances": int(rec["utterances"]), "model": float(rec["model"]),
+                         "ms": {int(v): float(t) for v, t in rec["ms"].items()}}
+    if not sizes:
+        raise ValueError("no measured size")
+    variant = [0] * 6
+    for f in range(6):
+        ms = [m for m in sizes if FAMILY[m] == f]
+        common = [v for v in VARIANTS[f] if all(v in sizes[m]["ms"] for m in ms)]
+        if not ms or not common:
+            continue
+        score = {v: sum(sizes[m]["ms"][v] / min(sizes[m]["ms"].values()) for m in ms) for v in common}
+        variant[f] = min(score, key=lambda v: (score[v], v != DEFAULT_VARIANT))
+    k = {}
+    for m, rec in sizes.items():
+        v = variant[FAMILY[m]]
+        t = rec["ms"][v] if v else min(rec["ms"].values())
+        k[m] = t * 1e6 / rec["model"]
+    cost_fft, cost_mac = [], []
+    for m in LOG2N:
+        km = k[m] if m in k else k[min(k, key=lambda q: (abs(q - m), -q))]
+        cost_fft.append(km * mf[m - 9])
+        cost_mac.append(km * mm[m - 9])
+    return {"cost_fft": cost_fft, "cost_mac": cost_mac, "one_size": True, "variant": variant, "unit": "ns",
+            "measured": {"sizes": {str(m): {"utterances": r["utterances"], "model": r["model"],
+                                            "ms": {str(v): t for v, t in sorted(r["ms"].items())}}
+                                   for m, r in sorted(sizes.items())}}}
+
+
+def entry_to_tune(entry: dict):
+    from . import rsim
+
+    return rsim.tune_table(entry["cost_fft"], entry["cost_mac"], entry.get("one_size", True),
+                           entry.get("variant"))
+
+
+def tune(db, alpha, save: Optional[str] = None, **kw):
+    """measure() then fit(): the RsimTune for this GPU and the table entry.
+    With save, the entry is merged into that JSON file under device_name()."""
+    entry = fit(measure(db, alpha, **kw))
     if save:
         data = {}
-        if os.path.exists(TABLE):
-            with open(TABLE) as f:
+        if os.path.exists(save):
+            with open(save) as f:
                 data = json.load(f)
         data[device_name()] = entry
-        with open(TABLE, "w") as f:
+        with open(save, "w") as f:
             json.dump(data, f, indent=1)
-    return rsim.tune_table(cost_f, cost_m)
+    return entry_to_tune(entry), entry
 
 
 def load(which: str = "auto"):
@@ -169,21 +271,29 @@ def load(which: str = "auto"):
     entry = data if "cost_fft" in data else data.get(device_name())
     if not entry:
         return None
-    return rsim.tune_table(entry["cost_fft"], entry["cost_mac"], entry.get("one_size", True))
+    return entry_to_tune(entry)
 
 
 if __name__ == "__main__":
     import argparse
 
-    ap = argparse.ArgumentParser(description="measure the FFT-size cost table on this GPU")
+    ap = argparse.ArgumentParser(description="measure the FFT-size and kernel-variant table on this GPU "
+                                             "with a synthetic batched workload")
     ap.add_argument("--out", default=TABLE, help="JSON file to merge this device's entry into")
+    ap.add_argument("--n-utt", type=int, default=2048)
+    ap.add_argument("--eta", type=float, default=20.0)
     args = ap.parse_args()
     import torch
+
+    import synth
 
     from . import rsim
 
     torch.cuda.set_device(0)
     rsim.init()
-    TABLE = args.out
-    t = tune(save=True, verbose=True)
-    print(json.dumps({device_name(): {"cost_fft": list(t.cost_fft), "cost_mac": list(t.cost_mac)}}))
+    b = synth.make_config2(n_utt=args.n_utt)
+    db = rsim.DeviceBatch(b)
+    alpha = torch.from_numpy(rsim.batch_gains(db, b.snr_db)).cuda()
+    rsim.truncate_batch(db, args.eta)
+    _, e = tune(db, alpha, save=args.out, verbose=True)
+    print(json.dumps({device_name(): e}))

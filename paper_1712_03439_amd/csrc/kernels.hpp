@@ -51,6 +51,7 @@ struct TuneDev {
   float cost_fft[7];
   float cost_mac[7];
   int one_size;
+  int variant[kNumFam];  // host side only: kernel variant of each family (0..3)
 };
 
 // Workspace header shared by the schedule and mix launches of one call.

@@ -1310,7 +1310,7 @@ namespace {
 constexpr int kFamT[kNumFam] = {32, 64, 128, 256, 512, 1024};
 // Kernel variants: (mic accumulators JG, waves per SIMD the registers are
 // sized for).  0: JG 1 / 2 waves, 1: JG 2 / 1 wave, 2: JG 2 / 2 waves,
-// 3: JG 1 / 4 waves.
+// 3: JG 1 / 4 waves.  A tune table names one per family (code = index + 1).
 constexpr int kNumVar = 4;
 constexpr int kVarJG[kNumVar] = {1, 2, 2, 1};
 constexpr int kFamMaxM[kNumFam] = {max_m_with_threads<32>(),  max_m_with_threads<64>(),
@@ -1384,17 +1384,12 @@ const void* mix_kernel_ptr(int fam, int var) {
   }
 }
 
-// Variant used by every launch; RSIM_VARIANT (0..3) overrides it.
-int g_var = -1;
-int kernel_variant() {
-  if (g_var < 0) {
-    const char* e = std::getenv("RSIM_VARIANT");
-    g_var = (e && e[0] >= '0' && e[0] < '0' + kNumVar) ? e[0] - '0' : 1;
-  }
-  return g_var;
-}
-// Mic accumulators of family f's kernel under the current variant.
-int mic_group(int f) { return f == kNumFam - 1 ? 1 : kVarJG[kernel_variant()]; }
+// Variant of a family when the tune table names none: two mic accumulators
+// for every family but the 1024-thread one, which has a single variant.
+constexpr int kDefaultVar = 1;
+constexpr int kFam1024Var = 3;
+// Mic accumulators of family f's kernel.
+int mic_group(int f, const TuneDev& td) { return kVarJG[td.variant[f]]; }
 
 rsim_status init_locked(int dev) {
   DevState& st = g_dev[dev];
@@ -1469,17 +1464,33 @@ TuneDev default_tune() {
     t.cost_mac[m - 9] = (float)(8.0 * (N / 2 + 1));
   }
   t.one_size = 1;
+  for (int f = 0; f < kNumFam; ++f) t.variant[f] = f == kNumFam - 1 ? kFam1024Var : kDefaultVar;
   return t;
 }
 
+// A tune table is valid when every cost is finite and non-negative and every
+// variant code is 0 (the default) or 1..4.
+bool tune_ok(const rsim_tune* tune) {
+  if (!tune) return true;
+  for (int k = 0; k < 7; ++k)
+    if (!std::isfinite(tune->cost_fft[k]) || tune->cost_fft[k] < 0.f || !std::isfinite(tune->cost_mac[k]) ||
+        tune->cost_mac[k] < 0.f)
+      return false;
+  for (int f = 0; f < kNumFam; ++f)
+    if (tune->variant[f] < 0 || tune->variant[f] > kNumVar) return false;
+  return true;
+}
+
 TuneDev to_dev(const rsim_tune* tune) {
-  if (!tune) return default_tune();
-  TuneDev t;
+  TuneDev t = default_tune();
+  if (!tune) return t;
   for (int k = 0; k < 7; ++k) {
     t.cost_fft[k] = tune->cost_fft[k];
     t.cost_mac[k] = tune->cost_mac[k];
   }
   t.one_size = tune->one_size;
+  for (int f = 0; f < kNumFam - 1; ++f)
+    if (tune->variant[f] > 0) t.variant[f] = tune->variant[f] - 1;
   return t;
 }
 
@@ -1530,15 +1541,15 @@ WsLayout layout(const rsim_batch* b, const TuneDev& td, bool backward, const Dev
     const long long M = kFamMaxM[f];
     // The forward splits utterances by mic group when there are fewer of
     // them than compute units (each group then transforms the sources itself).
-    const int ngf = (int)((J + mic_group(f) - 1) / mic_group(f));
+    const int ngf = (int)((J + mic_group(f, td) - 1) / mic_group(f, td));
     L.gsplit[f] = !backward && U > 0 && (size_t)cus > U && ngf > 1 ? ngf : 1;
     const size_t items = U * (size_t)(backward ? L.nsplit : L.gsplit[f]);
     const long long spectra =
-        backward ? (2 * S * J + J) : (S * J + (J > mic_group(f) && L.gsplit[f] == 1 ? S : 0));
+        backward ? (2 * S * J + J) : (S * J + (J > mic_group(f, td) && L.gsplit[f] == 1 ? S : 0));
     L.slot_cf[f] = spectra * M;
     // the largest occupancy used without a device; at most 8 workgroups per
     // CU and one per work item
-    int occ = st.init ? (backward ? st.occ_bwd[f] : st.occ[kernel_variant()][f]) : 8;
+    int occ = st.init ? (backward ? st.occ_bwd[f] : st.occ[td.variant[f]][f]) : 8;
     if (occ > 8) occ = 8;
     long long g = (long long)cus * occ;
     if (g > (long long)items) g = (long long)items;
@@ -1795,7 +1806,7 @@ void plan_mix(CallPlan& P, const rsim_batch* b, const BatchDev& bd, const TuneDe
     A.scratch = reinterpret_cast<cf*>(base + L.fam_scratch[f]);
     A.slot_cf = L.slot_cf[f];
     A.gsplit = L.gsplit[f];
-    P.fam[P.nf++].set(mix_kernel_ptr(f, kernel_variant()), dim3(L.grid[f]), dim3(kFamT[f]), A);
+    P.fam[P.nf++].set(mix_kernel_ptr(f, td.variant[f]), dim3(L.grid[f]), dim3(kFamT[f]), A);
   }
 }
 
@@ -1932,7 +1943,7 @@ rsim_status rsim_truncate_rir(const float* h, int64_t h_len, const int64_t* off,
 }
 
 size_t rsim_mix_workspace_bytes(const rsim_batch* b, const rsim_tune* tune, int32_t backward) {
-  if (!batch_ok(b)) return 0;
+  if (!batch_ok(b) || !tune_ok(tune)) return 0;
   (void)ensure_init(nullptr);  // launch geometry of this device, when there is one
   const TuneDev td = to_dev(tune);
   return layout(b, td, backward != 0, dev_state()).total;
@@ -1941,7 +1952,7 @@ size_t rsim_mix_workspace_bytes(const rsim_batch* b, const rsim_tune* tune, int3
 rsim_status rsim_mix(const rsim_batch* b, const float* x, const float* h, const float* alpha, float* y,
                      void* ws, size_t ws_bytes, const rsim_tune* tune, int32_t use_graph,
                      hipStream_t stream) {
-  if (!batch_ok(b)) return RSIM_EINVAL;
+  if (!batch_ok(b) || !tune_ok(tune)) return RSIM_EINVAL;
   if (b->n_utt == 0) return RSIM_OK;
   if (!x || !h || !alpha || !y) return RSIM_EINVAL;
   const rsim_status e = ensure_init(stream);
@@ -1958,7 +1969,7 @@ rsim_status rsim_mix(const rsim_batch* b, const float* x, const float* h, const 
 rsim_status rsim_simulate(const rsim_batch* b, const float* x, const float* h, const float* alpha,
                           double eta_db, int32_t* rir_len_out, float* y, void* ws, size_t ws_bytes,
                           const rsim_tune* tune, int32_t use_graph, hipStream_t stream) {
-  if (!b || !eta_ok(eta_db) || !rir_len_out) return RSIM_EINVAL;
+  if (!b || !eta_ok(eta_db) || !rir_len_out || !tune_ok(tune)) return RSIM_EINVAL;
   rsim_batch bb = *b;
   bb.rir_len = rir_len_out;
   if (!batch_ok(&bb)) return RSIM_EINVAL;
@@ -2040,7 +2051,7 @@ rsim_status rsim_ola_convolve(const float* x, int32_t nx, const float* h, int32_
 rsim_status rsim_mix_backward(const rsim_batch* b, const float* x, const float* h, const float* alpha,
                               const float* grad_y, float* grad_x, float* grad_h, float* grad_alpha,
                               void* ws, size_t ws_bytes, const rsim_tune* tune, hipStream_t stream) {
-  if (!batch_ok(b)) return RSIM_EINVAL;
+  if (!batch_ok(b) || !tune_ok(tune)) return RSIM_EINVAL;
   if (b->n_utt == 0) return RSIM_OK;
   if (!x || !h || !alpha || !grad_y || !grad_x || !grad_h) return RSIM_EINVAL;
   const rsim_status e = ensure_init(stream);

@@ -49,7 +49,8 @@ class RsimBatch(ctypes.Structure):
 
 
 class RsimTune(ctypes.Structure):
-    _fields_ = [("cost_fft", ctypes.c_float * 7), ("cost_mac", ctypes.c_float * 7), ("one_size", ctypes.c_int32)]
+    _fields_ = [("cost_fft", ctypes.c_float * 7), ("cost_mac", ctypes.c_float * 7), ("one_size", ctypes.c_int32),
+                ("variant", ctypes.c_int32 * 6)]
 
 
 _LIB = None
@@ -195,13 +196,17 @@ def snr_gains(p_dry: Sequence[float], snr_db: Sequence[float], n_mic: int) -> np
     return a.reshape(I, n_mic)
 
 
-def tune_table(cost_fft: Sequence[float], cost_mac: Sequence[float], one_size: bool = False) -> RsimTune:
-    """An FFT-size cost table (rsim_tune); one_size picks one N for the whole batch."""
+def tune_table(cost_fft: Sequence[float], cost_mac: Sequence[float], one_size: bool = False,
+               variant: Optional[Sequence[int]] = None) -> RsimTune:
+    """An FFT-size cost table (rsim_tune); one_size picks one N for the whole
+    batch; variant[f] (0 = default, 1..4) is the kernel variant of family f."""
     t = RsimTune()
     for k in range(7):
         t.cost_fft[k] = float(cost_fft[k])
         t.cost_mac[k] = float(cost_mac[k])
     t.one_size = int(bool(one_size))
+    for f in range(6):
+        t.variant[f] = int(variant[f]) if variant is not None else 0
     return t
 
 
@@ -241,6 +246,44 @@ class DeviceBatch:
         self.y_len = int(b.y_len)
         self.max_rir_len0 = int(np.max(b.rir_len0)) if np.asarray(b.rir_len0).size else 0
         self.device = dev
+
+    def select(self, idx) -> "DeviceBatch":
+        """The utterances idx (host ints, distinct) as a batch of their own:
+        their descriptor rows (cut lengths included) gathered on the device, in
+        the parent's processing order; the sources, RIRs and output layout are
+        the parent's (x, h shared, outputs land where the parent's would)."""
+        torch = _torch()
+        dev = self.device
+        u = torch.as_tensor(np.asarray(idx, np.int64), device=dev)
+        S, J = self.S, self.J
+        slots = (u[:, None] * S + torch.arange(S, device=dev)[None, :]).reshape(-1)
+        rirs = (slots[:, None] * J + torch.arange(J, device=dev)[None, :]).reshape(-1)
+        sub = object.__new__(DeviceBatch)
+        sub.host = None
+        sub.U, sub.J, sub.S = int(u.numel()), J, S
+        sub.n_src = self.n_src[u].contiguous()
+        sub.src_len = self.src_len[u].contiguous()
+        sub.src_off = self.src_off[slots].contiguous()
+        sub.rir_off = self.rir_off[rirs].contiguous()
+        sub.rir_len0 = self.rir_len0[rirs].contiguous()
+        sub.rir_len = self.rir_len[rirs].contiguous()
+        sub.n_c = self.n_c[rirs].contiguous()
+        sub.out_off = self.out_off[u].contiguous()
+        sub.out_stride = self.out_stride[u].contiguous()
+        sub.out_len = torch.zeros(sub.U, dtype=torch.int32, device=dev)
+        sub.order = None
+        if self.order is not None:
+            # the parent's processing order restricted to idx
+            rank = torch.empty_like(self.order)
+            rank[self.order.long()] = torch.arange(self.U, dtype=rank.dtype, device=dev)
+            sub.order = torch.argsort(rank[u], stable=True).to(torch.int32)
+        sub.fft_log2n = None if self.fft_log2n is None else self.fft_log2n[u].contiguous()
+        sub.hop = None if self.hop is None else self.hop[u].contiguous()
+        sub.x, sub.h = self.x, self.h
+        sub.x_len, sub.h_len, sub.y_len = self.x_len, self.h_len, self.y_len
+        sub.max_rir_len0 = int(self.rir_len0[rirs].max().item()) if rirs.numel() else 0
+        sub.device = dev
+        return sub
 
     def struct(self, rir_len=None) -> RsimBatch:
         s = RsimBatch()

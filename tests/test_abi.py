@@ -157,3 +157,40 @@ def test_one_size_tune_field_reaches_the_workspace_query():
     for one in (False, True):
         t = rsim.tune_table(f, m, one_size=one)
         assert lib.rsim_mix_workspace_bytes(ctypes.byref(b), ctypes.byref(t), 0) > 0
+
+
+def test_tune_table_layout_and_validation():
+    # rsim_tune: 7 + 7 floats, one_size, variant[6] (int32), no padding
+    assert ctypes.sizeof(rsim.RsimTune) == 84
+    assert rsim.RsimTune.variant.offset == 60 and rsim.RsimTune.one_size.offset == 56
+    lib = rsim.lib()
+    p = ctypes.c_void_p(8)
+    b = _host_batch()
+    f, m = [2.5 * (1 << k) * k for k in range(9, 16)], [8.0 * ((1 << k) / 2 + 1) for k in range(9, 16)]
+    for code in range(5):
+        t = rsim.tune_table(f, m, True, [code] * 6)
+        assert lib.rsim_mix_workspace_bytes(ctypes.byref(b), ctypes.byref(t), 0) > 0, code
+    bad = []
+    for field, val in (("variant", 5), ("variant", -1), ("cost_fft", -1.0), ("cost_mac", math.nan),
+                       ("cost_fft", math.inf)):
+        t = rsim.tune_table(f, m, True)
+        getattr(t, field)[2] = val
+        bad.append(t)
+    for t in bad:
+        r = ctypes.byref(t)
+        assert lib.rsim_mix_workspace_bytes(ctypes.byref(b), r, 0) == 0
+        assert lib.rsim_mix(ctypes.byref(b), p, p, p, p, p, 1 << 30, r, 0, None) == rsim.RSIM_EINVAL
+        assert lib.rsim_simulate(ctypes.byref(b), p, p, p, 20.0, p, p, p, 1 << 30, r, 0, None) == rsim.RSIM_EINVAL
+        assert lib.rsim_mix_backward(ctypes.byref(b), p, p, p, p, p, p, p, p, 1 << 30, r, None) == rsim.RSIM_EINVAL
+
+
+def test_variant_sets_the_mic_split_of_the_workspace():
+    # with fewer utterances than compute units, one mic per pass splits an
+    # utterance of two mics into two work items; two mics per pass do not
+    lib = rsim.lib()
+    b = _host_batch(U=3, J=2)
+    f, m = [2.5 * (1 << k) * k for k in range(9, 16)], [8.0 * ((1 << k) / 2 + 1) for k in range(9, 16)]
+    one = lib.rsim_mix_workspace_bytes(ctypes.byref(b), ctypes.byref(rsim.tune_table(f, m, True, [1] * 6)), 0)
+    two = lib.rsim_mix_workspace_bytes(ctypes.byref(b), ctypes.byref(rsim.tune_table(f, m, True, [2] * 6)), 0)
+    dflt = lib.rsim_mix_workspace_bytes(ctypes.byref(b), ctypes.byref(rsim.tune_table(f, m, True)), 0)
+    assert dflt == two and one != two
