@@ -48,15 +48,30 @@ def source_digest() -> str:
     return h.hexdigest()
 
 
-def counter_traffic():
-    """HBM bytes per mix launch from the committed rocprofv3 counter summary,
-    or None when the kernels have changed since it was taken."""
+# rsim_tune.variant code -> (mic accumulators, waves per SIMD) of the kernel
+VARIANT_TEMPLATE = {1: (1, 2), 2: (2, 1), 3: (2, 2), 4: (1, 4)}
+
+
+def mix_kernel_name(log2n: int, variant) -> str:
+    """Symbol of the filter-and-mix kernel that runs size 2^log2n."""
+    from paper_1712_03439_amd import autotune
+
+    f = autotune.FAMILY[log2n]
+    code = (variant[f] if variant is not None and variant[f] else autotune.DEFAULT_VARIANT) if f < 5 else 4
+    jg, w = VARIANT_TEMPLATE[code]
+    return f"void rsim::mix_kernel<{32 << f}, {jg}, {w}>(rsim::MixArgs)"
+
+
+def counter_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary, or None when the kernels have changed since it was taken or it
+    covers another kernel."""
     try:
         with open(COUNTERS) as f:
             c = json.load(f)
     except (OSError, ValueError):
         return None
-    if c.get("source_sha256") != source_digest():
+    if c.get("source_sha256") != source_digest() or c.get("kernel") != kernel:
         return None
     return int(c["fetch_bytes_per_launch"] + c["write_bytes_per_launch"])
 
@@ -169,6 +184,69 @@ def differentiation(torch, rsim, synth, dev, reps: int = 10):
                              "unit": "GB/s", "frac": round(byts / (t_b * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}}
 
 
+def large_thresholds(torch, rsim, autotune, synth, dev, etas=(math.inf, 30.0, 20.0, 10.0), reps: int = 3):
+    """The large batched workload (4096 utterances of 1-20 s, up to 4 sources,
+    8 mics, T60 U(0.1, 1.0) s, RIRs up to 16000 taps) at each cut threshold:
+    per threshold the tuner runs on the cut batch, then cut + mix run as one
+    graph `reps` times (after one untimed run)."""
+    t0 = time.perf_counter()
+    b = synth.make_config4()
+    log(f"large workload: {b.n_utt} utterances, {b.audio_seconds:.0f} audio-s ({time.perf_counter() - t0:.1f} s)")
+    order = lpt_order(b)
+    db = rsim.DeviceBatch(b, device=dev, order=order)
+    alpha = torch.from_numpy(rsim.batch_gains(db, b.snr_db)).to(dev)
+    stream = torch.cuda.Stream()
+    stream.wait_stream(torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    y = db.new_output()
+    out = {"workload": f"{b.n_utt} utterances of 1-20 s, 1 + U{{0..3}} sources, 8 mics, T60 U(0.1,1.0) s, "
+                       f"L0 = ceil(T60 fs) <= 16000", "audio_s": round(b.audio_seconds, 1), "thresholds": {}}
+    for eta in etas:
+        with torch.cuda.stream(stream):
+            rsim.truncate_batch(db, eta, stream=stream)
+        stream.synchronize()
+        tune, entry = autotune.tune(db, alpha, stream=stream)
+        ws = db.workspace(tune)
+        with torch.cuda.stream(stream):
+            rsim.simulate(db, alpha, eta, y=y, ws=ws, tune=tune, use_graph=True, stream=stream)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(reps):
+                rsim.simulate(db, alpha, eta, y=y, ws=ws, tune=tune, use_graph=True, stream=stream)
+            e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        L = db.rir_len.cpu().numpy().astype(np.int64)
+        T = db.out_len.cpu().numpy().astype(np.int64)
+        I = b.n_src.astype(np.int64)
+        J = b.n_mic
+        byt = 4 * (np.sum(I * b.src_len) + np.sum(L) + J * np.sum(T)) + (4 * np.sum(b.rir_len0) if eta != math.inf else 0)
+        Lr = L.reshape(b.n_utt, b.max_src * J)
+        shapes = [(int(b.src_len[u]), int(I[u]), J, int(Lr[u].max())) for u in range(b.n_utt)
+                  if int(Lr[u].max()) > 0 and b.src_len[u] > 0]
+        tf, tm = autotune.costs(tune)
+        l2b = autotune.batch_log2n(shapes, tf, tm) if tune.one_size else 0
+        fl, sizes = 0.0, {}
+        for nx, Iu, _, lmax in shapes:
+            N, B, nb = host_plan(nx, Iu, J, lmax, tf, tm, l2b)
+            c = 2.5 * N * math.log2(N)
+            fl += nb * ((Iu + J) * c + Iu * J * 8 * (N / 2 + 1)) + Iu * J * c
+            sizes[N] = sizes.get(N, 0) + 1
+        key = "inf" if eta == math.inf else f"{eta:g}"
+        out["thresholds"][key] = {
+            "ms": round(ms, 3), "audio_s_per_s": round(b.audio_seconds / (ms * 1e-3), 1),
+            "mean_cut_len": round(float(L[L > 0].mean()), 1), "fft_sizes": {str(k): v for k, v in sorted(sizes.items())},
+            "variant": entry["variant"],
+            "alu": {"achieved": round(fl / (ms * 1e-3) / 1e12, 2), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                    "frac": round(fl / (ms * 1e-3) / 1e12 / FP32_PEAK_TFLOPS, 4)},
+            "hbm": {"achieved": round(byt / (ms * 1e-3) / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(byt / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}}
+        log(f"large workload, eta {key}: {ms:.2f} ms (cut + mix), {out['thresholds'][key]['audio_s_per_s']:.4g} "
+            f"audio-s/s, sizes {out['thresholds'][key]['fft_sizes']}")
+        del ws
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -184,10 +262,14 @@ def main() -> int:
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-diff", action="store_true", help="skip the adjoint (differentiation workload) timing")
+    ap.add_argument("--large", action="store_true",
+                    help="also time the large batched workload (4096 utterances, 8 mics) at eta = inf, 30, 20, "
+                         "10 dB (adds about a minute and 35 GB of GPU memory)")
     ap.add_argument("--tune", default="measure",
                     help="'measure' (time every FFT size and kernel variant on the first epoch's "
                          "batch before the warmup), 'model' (the built-in cost model), 'auto' (this "
                          "device's entry of the stored table) or a table JSON path")
+    ap.add_argument("--save-tune", default="", help="with --tune measure: merge the measured entry into this JSON")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="before the warmup, fill and copy a buffer of this size (a reference "
                          "for the HBM byte counters)")
@@ -242,7 +324,7 @@ def main() -> int:
         _, db0, alpha0 = epochs[0]
         rsim.truncate_batch(db0, args.eta, stream=stream)
         stream.synchronize()
-        tune, entry = autotune.tune(db0, alpha0, stream=stream)
+        tune, entry = autotune.tune(db0, alpha0, save=args.save_tune or None, stream=stream)
         tune_info = {"source": "measured on the first epoch's batch", "variant": entry["variant"],
                      "ms": {k: v["ms"] for k, v in entry["measured"]["sizes"].items()},
                      "seconds": round(time.perf_counter() - t1, 2)}
@@ -327,7 +409,9 @@ def main() -> int:
     # The binding bound of the mix is the one with the longer time at peak:
     # FP32 vector arithmetic (no packed FP32 in this build) or HBM.
     t_alu, t_hbm = float(np.mean(flops)) / (FP32_PEAK_TFLOPS * 1e12), float(np.mean(byt)) / (HBM_PEAK_GBS * 1e9)
-    traffic = counter_traffic()
+    dom_n = max(sizes, key=lambda n: sizes[n] * n * math.log2(n))
+    kernel = mix_kernel_name(int(math.log2(dom_n)), list(tune.variant) if tune is not None else None)
+    traffic = counter_traffic(kernel)
     if t_alu >= t_hbm:
         roof = {"bound": "alu", "achieved": round(alu, 2), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(alu / FP32_PEAK_TFLOPS, 4), "traffic": traffic}
@@ -357,6 +441,7 @@ def main() -> int:
         "roofline": roof,
         "hbm": {"achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4)},
+        "dominant_kernel": kernel,
         "kernel_ms": {"cut": round(float(np.mean(trunc_ms)), 4), "mix": round(float(np.mean(mix_ms)), 4)},
         "cut_hbm": {"achieved": round(float(np.mean(byt_cut)) / (float(np.mean(trunc_ms)) * 1e-3) / 1e9, 1),
                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -394,6 +479,12 @@ def main() -> int:
         d = result["differentiation"]
         log(f"differentiation workload: forward {d['forward_ms']:.3f} ms, adjoint {d['backward_ms']:.3f} ms, "
             f"adjoint at {d['backward_roofline']['frac']:.3f} of the FP32 peak")
+
+    if args.large:
+        del y, ws
+        epochs.clear()
+        torch.cuda.empty_cache()
+        result["large"] = large_thresholds(torch, rsim, autotune, synth, dev)
 
     if not args.no_cpu:
         log("timing the FP64 oracle on the host cores ...")

@@ -70,6 +70,7 @@ def device_name() -> str:
 FAMILY = {9: 0, 10: 1, 11: 1, 12: 2, 13: 3, 14: 4, 15: 5}
 VARIANTS = {0: (1, 2, 3, 4), 1: (1, 2, 3, 4), 2: (1, 2, 3, 4), 3: (1, 2, 3, 4), 4: (1, 2, 3, 4), 5: (4,)}
 DEFAULT_VARIANT = 2
+SAME_WITHIN = 0.02  # relative time difference taken as timing noise
 
 
 def utt_cost(nx: int, I: int, J: int, lmax: int, m: int, cost_fft, cost_mac) -> Optional[float]:
@@ -196,8 +197,8 @@ def fit(measured: dict) -> dict:
     a stored entry).
 
     Per family, the variant with the smallest time relative to the best
-    variant, summed over the family's measured sizes (the library default
-    wins ties).  Per measured size m, k(m) = the time with that variant / the
+    variant, summed over the family's measured sizes; the library default
+    is kept unless that sum is smaller by more than SAME_WITHIN per size.  Per measured size m, k(m) = the time with that variant / the
     model's cost of the probe; a size not measured takes k of the nearest
     measured size (the larger on a tie).  The costs are the built-in model's
     scaled by k (ns per model unit), so the schedule's summed cost of a batch
@@ -217,7 +218,12 @@ def fit(measured: dict) -> dict:
         if not ms or not common:
             continue
         score = {v: sum(sizes[m]["ms"][v] / min(sizes[m]["ms"].values()) for m in ms) for v in common}
-        variant[f] = min(score, key=lambda v: (score[v], v != DEFAULT_VARIANT))
+        best = min(score, key=lambda v: (score[v], v != DEFAULT_VARIANT))
+        # the default stays unless another variant is faster by more than the
+        # timing noise (SAME_WITHIN per size)
+        if DEFAULT_VARIANT in score and score[DEFAULT_VARIANT] <= score[best] + SAME_WITHIN * len(ms):
+            best = DEFAULT_VARIANT
+        variant[f] = best
     k = {}
     for m, rec in sizes.items():
         v = variant[FAMILY[m]]

@@ -56,6 +56,11 @@ def test_fit_variant_choice_and_default_on_ties():
     assert e["variant"][0] == 0 and e["variant"][1] == 0   # not measured: default
     e = autotune.fit(_measured(shapes, k_true, {1: 1.0, 2: 1.0, 3: 1.0, 4: 1.0}))
     assert e["variant"][3] == autotune.DEFAULT_VARIANT
+    # within the timing noise the default stays
+    e = autotune.fit(_measured(shapes, k_true, {1: 1.2, 2: 1.01, 3: 1.0, 4: 1.3}))
+    assert e["variant"][4] == autotune.DEFAULT_VARIANT
+    e = autotune.fit(_measured(shapes, k_true, {1: 1.2, 2: 1.05, 3: 1.0, 4: 1.3}))
+    assert e["variant"][4] == 3
     # the chosen variant's time sets the size's scale
     e = autotune.fit(_measured(shapes, {14: 2.0}, {1: 1.5, 2: 1.0, 3: 3.0, 4: 3.0}))
     k = e["cost_fft"][14 - 9] / MF[14 - 9]
