@@ -905,6 +905,54 @@ __device__ __forceinline__ void acc_corr(cf* __restrict__ Rm, const cf* X, const
   }
 }
 
+// One source against every mic for two blocks b, b + 1 (the second may be
+// absent: g1 then has a zero range and reads zeros, and X1 is zero):
+//   D0 += conj(H_ij) G_j,b,   D1 += conj(H_ij) G_j,b+1          (registers)
+//   R_ij = (first ? 0 : R_ij) + conj(X0) G_j,b + conj(X1) G_j,b+1   (memory)
+// so each RIR spectrum, gradient spectrum and accumulator is read once per
+// pair of blocks.  H_ij, G_j,b, G_j,b+1 and R_ij are spectra M apart.
+template <class PL>
+__device__ __forceinline__ void bwd_pair_pass(cf* D0, cf* D1, const cf* X0, const cf* X1,
+                                              const cf* __restrict__ Hi, const cf* __restrict__ G0,
+                                              const cf* __restrict__ G1, cf* __restrict__ Ri, int J, bool first,
+                                              bool two, int t_) {
+  constexpr int SP = Fft<PL>::SP, M = PL::M;
+  const int t = opaque_v(t_);
+  const int vo = 8 * t;
+  constexpr int bytes = PL::P * PL::T * 8;
+  for (int j = 0; j < J; ++j) {
+    const rsrc_t rh = make_rsrc(Hi + (long long)j * M, bytes);
+    const rsrc_t r0 = make_rsrc(G0 + (long long)j * M, bytes);
+    const rsrc_t r1 = make_rsrc(G1 + (long long)j * M, two ? bytes : 0);
+    const rsrc_t rr = make_rsrc(Ri + (long long)j * M, first ? 0 : bytes);
+    const rsrc_t rw = make_rsrc(Ri + (long long)j * M, bytes);
+#pragma unroll
+    for (int q = 0; q < PL::P; ++q) {
+      const cf h = ld2(rh, vo, 8 * q * PL::T);
+      const cf g0 = ld2(r0, vo, 8 * q * PL::T);
+      const cf g1 = ld2(r1, vo, 8 * q * PL::T);
+      const cf acc = ld2(rr, vo, 8 * q * PL::T);
+      cf o;
+      if (q == SP) {
+        const cf c0 = cmacc(D0[q], h, g0), c1 = cmacc(D1[q], h, g1);
+        const cf co = cmacc(cmacc(acc, X0[q], g0), X1[q], g1);
+        const cf d0 = mk(__builtin_fmaf(h.x, g0.x, D0[q].x), __builtin_fmaf(h.y, g0.y, D0[q].y));
+        const cf d1 = mk(__builtin_fmaf(h.x, g1.x, D1[q].x), __builtin_fmaf(h.y, g1.y, D1[q].y));
+        const cf dr = mk(__builtin_fmaf(X1[q].x, g1.x, __builtin_fmaf(X0[q].x, g0.x, acc.x)),
+                         __builtin_fmaf(X1[q].y, g1.y, __builtin_fmaf(X0[q].y, g0.y, acc.y)));
+        D0[q] = t == 0 ? d0 : c0;
+        D1[q] = t == 0 ? d1 : c1;
+        o = t == 0 ? dr : co;
+      } else {
+        D0[q] = cmacc(D0[q], h, g0);
+        D1[q] = cmacc(D1[q], h, g1);
+        o = cmacc(cmacc(acc, X0[q], g0), X1[q], g1);
+      }
+      st2(rw, vo, o, 8 * q * PL::T);
+    }
+  }
+}
+
 // Inverse-transform a spectrum and store the first `lim` samples at yp.
 template <class PL>
 __device__ __forceinline__ void emit_store(cf* Yv, Xch<PL>& lds, const TwBase& tw, float* __restrict__ yp, int lim,
@@ -996,7 +1044,7 @@ __device__ __forceinline__ void bwd_utterance(const BwdArgs& A, int u, const Sch
   const float gscale = 1.0f / (8.0f * (float)M);
   cf* Hs = slot;
   cf* Gs = slot + (long long)NS * J * M;
-  cf* Rs = nparts == 1 ? Gs + (long long)J * M
+  cf* Rs = nparts == 1 ? Gs + 2LL * J * M
                        : A.partial + ((long long)u * A.nsplit + part) * NS * J * M;
   const int b0 = (int)((long long)nb * part / nparts), b1 = (int)((long long)nb * (part + 1) / nparts);
   const long long yo = uni64(b.out_off[u]);
@@ -1016,31 +1064,75 @@ __device__ __forceinline__ void bwd_utterance(const BwdArgs& A, int u, const Sch
     }
   }
 
-  for (int bk = b0; bk < b1; ++bk) {
-    const int base = bk * B;
-    const int nvalid = min(B, Nx - base);
-    for (int j = 0; j < J; ++j) {
-      cf v[P];
-      load_real<PL>(v, A.gy + yo + (long long)j * ys + base, min(N, tu - base), t);
-      Fft<PL>::forward(v, lds, tw, t);
-      Fft<PL>::post(v, tw, t);
+  if constexpr (PL::T <= 512) {
+    // Two blocks per pass: the gradient spectra of both blocks are stored,
+    // then per source both source spectra are formed and one pass over the
+    // mics gives both blocks' dx spectra and their share of r.
+    for (int bk = b0; bk < b1; bk += 2) {
+      const bool two = bk + 1 < b1;
+      for (int hb = 0; hb < (two ? 2 : 1); ++hb) {
+        const int base = (bk + hb) * B;
+        for (int j = 0; j < J; ++j) {
+          cf v[P];
+          load_real<PL>(v, A.gy + yo + (long long)j * ys + base, min(N, tu - base), t);
+          Fft<PL>::forward(v, lds, tw, t);
+          Fft<PL>::post(v, tw, t);
 #pragma unroll
-      for (int q = 0; q < P; ++q) v[q] = mk(v[q].x * gscale, v[q].y * gscale);
-      store_spec<PL>(Gs + (long long)j * M, v, t);
+          for (int q = 0; q < P; ++q) v[q] = mk(v[q].x * gscale, v[q].y * gscale);
+          store_spec<PL>(Gs + (long long)(hb * J + j) * M, v, t);
+        }
+      }
+      for (int i = 0; i < I; ++i) {
+        const long long so = uni64(b.src_off[(long long)u * NS + i]);
+        const int base0 = bk * B, base1 = base0 + B;
+        const int nv0 = min(B, Nx - base0), nv1 = two ? min(B, Nx - base1) : 0;
+        cf X0[P], X1[P], D0[P], D1[P];
+        load_real<PL>(X0, A.x + so + base0, nv0, t);
+        Fft<PL>::forward(X0, lds, tw, t);
+        Fft<PL>::post(X0, tw, t);
+        if (two) {
+          load_real<PL>(X1, A.x + so + base1, nv1, t);
+          Fft<PL>::forward(X1, lds, tw, t);
+          Fft<PL>::post(X1, tw, t);
+        } else {
+#pragma unroll
+          for (int q = 0; q < P; ++q) X1[q] = mk(0.f, 0.f);
+        }
+#pragma unroll
+        for (int q = 0; q < P; ++q) D0[q] = D1[q] = mk(0.f, 0.f);
+        bwd_pair_pass<PL>(D0, D1, X0, X1, Hs + (long long)i * J * M, Gs, Gs + (long long)J * M,
+                          Rs + (long long)i * J * M, J, bk == b0, two, t);
+        emit_store<PL>(D0, lds, tw, A.gx + so + base0, nv0, t);
+        if (two) emit_store<PL>(D1, lds, tw, A.gx + so + base1, nv1, t);
+      }
     }
-    for (int i = 0; i < I; ++i) {
-      const long long so = uni64(b.src_off[(long long)u * NS + i]);
-      cf D[P];
+  } else {
+    for (int bk = b0; bk < b1; ++bk) {
+      const int base = bk * B;
+      const int nvalid = min(B, Nx - base);
+      for (int j = 0; j < J; ++j) {
+        cf v[P];
+        load_real<PL>(v, A.gy + yo + (long long)j * ys + base, min(N, tu - base), t);
+        Fft<PL>::forward(v, lds, tw, t);
+        Fft<PL>::post(v, tw, t);
 #pragma unroll
-      for (int q = 0; q < P; ++q) D[q] = mk(0.f, 0.f);
-      for (int j = 0; j < J; ++j) macc_mem<PL>(D, Hs + (long long)(i * J + j) * M, Gs + (long long)j * M, t);
-      emit_store<PL>(D, lds, tw, A.gx + so + base, nvalid, t);
-      cf X[P];
-      load_real<PL>(X, A.x + so + base, nvalid, t);
-      Fft<PL>::forward(X, lds, tw, t);
-      Fft<PL>::post(X, tw, t);
-      for (int j = 0; j < J; ++j)
-        acc_corr<PL>(Rs + (long long)(i * J + j) * M, X, Gs + (long long)j * M, bk == b0, t);
+        for (int q = 0; q < P; ++q) v[q] = mk(v[q].x * gscale, v[q].y * gscale);
+        store_spec<PL>(Gs + (long long)j * M, v, t);
+      }
+      for (int i = 0; i < I; ++i) {
+        const long long so = uni64(b.src_off[(long long)u * NS + i]);
+        cf D[P];
+#pragma unroll
+        for (int q = 0; q < P; ++q) D[q] = mk(0.f, 0.f);
+        for (int j = 0; j < J; ++j) macc_mem<PL>(D, Hs + (long long)(i * J + j) * M, Gs + (long long)j * M, t);
+        emit_store<PL>(D, lds, tw, A.gx + so + base, nvalid, t);
+        cf X[P];
+        load_real<PL>(X, A.x + so + base, nvalid, t);
+        Fft<PL>::forward(X, lds, tw, t);
+        Fft<PL>::post(X, tw, t);
+        for (int j = 0; j < J; ++j)
+          acc_corr<PL>(Rs + (long long)(i * J + j) * M, X, Gs + (long long)j * M, bk == b0, t);
+      }
     }
   }
   if (b1 == b0) {  // an empty part still defines its share: zero
@@ -1095,34 +1187,35 @@ __global__ __launch_bounds__(T, 2) void bwd_kernel(BwdArgs A) {
   }
 }
 
-// Finishing pass of a split adjoint: for every utterance in more than one
-// part, sums the parts' correlation spectra and gives dh and dalpha.
+// Finishing pass of a split adjoint: for every RIR slot (i, j) of an
+// utterance in more than one part, sums the parts' correlation spectra and
+// gives dh and dalpha.  One work item per slot, grid-stride.
 template <int T>
 __global__ __launch_bounds__(T, 2) void bwd_finish_kernel(BwdArgs A) {
   __shared__ cf lds_raw[max_lds_with_threads<T>()];
   __shared__ double s_red[T];
   const int t = threadIdx.x;
-  const int count = __builtin_amdgcn_readfirstlane(A.hdr->count[A.fam]);
   const BatchDev& b = A.b;
-  for (int pos = blockIdx.x; pos < count; pos += gridDim.x) {
+  const int NS = b.S, J = b.J;
+  const long long per = (long long)NS * J;
+  const long long items = (long long)__builtin_amdgcn_readfirstlane(A.hdr->count[A.fam]) * per;
+  for (long long k = blockIdx.x; k < items; k += gridDim.x) {
+    const int pos = (int)(k / per), i = (int)((k % per) / J), j = (int)(k % J);
     const int u = __builtin_amdgcn_readfirstlane(A.list[(long long)A.fam * b.U + pos]);
     Sched S = A.sched[u];
     S.log2n = __builtin_amdgcn_readfirstlane(S.log2n);
     S.nb = __builtin_amdgcn_readfirstlane(S.nb);
     const int nparts = bwd_parts(A.nsplit, S.nb);
-    if (nparts <= 1) continue;
+    if (nparts <= 1 || i >= uni(b.n_src[u])) continue;
     dispatch_plan<T>(S.log2n, [&](auto pl) __attribute__((always_inline)) {
       using PL = decltype(pl);
       constexpr int M = PL::M;
       Xch<PL> lds{lds_raw, 0};
       const TwBase tw = Fft<PL>::bases(plan_tw<PL>(), t);
-      const int I = uni(b.n_src[u]), J = b.J, NS = b.S;
-      const long long stride = (long long)NS * J * M;
+      const long long stride = per * M;
       const cf* R = A.partial + (long long)u * A.nsplit * stride;
-      for (int i = 0; i < I; ++i)
-        for (int j = 0; j < J; ++j)
-          bwd_finish_rir<PL>(A, ((long long)u * NS + i) * J + j, R + (long long)(i * J + j) * M, nparts,
-                             stride, lds, tw, s_red, t);
+      bwd_finish_rir<PL>(A, ((long long)u * NS + i) * J + j, R + (long long)(i * J + j) * M, nparts, stride,
+                         lds, tw, s_red, t);
     });
   }
 }
@@ -1545,7 +1638,7 @@ WsLayout layout(const rsim_batch* b, const TuneDev& td, bool backward, const Dev
     L.gsplit[f] = !backward && U > 0 && (size_t)cus > U && ngf > 1 ? ngf : 1;
     const size_t items = U * (size_t)(backward ? L.nsplit : L.gsplit[f]);
     const long long spectra =
-        backward ? (2 * S * J + J) : (S * J + (J > mic_group(f, td) && L.gsplit[f] == 1 ? S : 0));
+        backward ? (2 * S * J + 2 * J) : (S * J + (J > mic_group(f, td) && L.gsplit[f] == 1 ? S : 0));
     L.slot_cf[f] = spectra * M;
     // the largest occupancy used without a device; at most 8 workgroups per
     // CU and one per work item
@@ -1865,7 +1958,10 @@ void plan_bwd(CallPlan& P, const rsim_batch* b, const BatchDev& bd, const TuneDe
     A.partial = L.nsplit > 1 ? reinterpret_cast<cf*>(base + L.fam_partial[f]) : nullptr;
     P.fam[P.nf++].set(bwd_kernel_ptr(f), dim3(L.grid[f]), dim3(kFamT[f]), A);
     if (L.nsplit > 1)
-      P.post[P.np++].set(bwd_finish_kernel_ptr(f), dim3(std::min(b->n_utt, cus * 2)), dim3(kFamT[f]), A);
+      P.post[P.np++].set(bwd_finish_kernel_ptr(f),
+                         dim3((unsigned)std::min<long long>((long long)b->n_utt * b->max_src * b->n_mic,
+                                                            (long long)cus * 2)),
+                         dim3(kFamT[f]), A);
   }
 }
 
