@@ -183,8 +183,10 @@ rsim_status rsim_simulate(const rsim_batch* b, const float* x, const float* h,
  * in the layouts of x, h and alpha.  The cut index gets no gradient.  Entries
  * that belong to no source or RIR slot of an utterance are not written.  The
  * FFT size and hop are chosen as by rsim_mix with the same tune.  With fewer
- * utterances than compute units, each utterance is split into block ranges
- * whose correlation spectra are summed by a finishing pass (in ws).
+ * utterances than compute units, each utterance is split into block ranges:
+ * a first pass forms the RIR spectra once (in ws), the parts share them, and
+ * a finishing pass sums the parts' correlation spectra (in ws).  Runs eagerly
+ * on `stream` and the library's side streams (as rsim_mix with use_graph 0).
  * ws must hold rsim_mix_workspace_bytes(b, tune, 1) bytes.
  */
 rsim_status rsim_mix_backward(const rsim_batch* b, const float* x, const float* h,

@@ -95,9 +95,14 @@ struct BwdArgs {
   // Splitting of an utterance over several work items (for batches with few
   // utterances): item (u, r), r < nsplit, covers a range of u's blocks and
   // accumulates its share of the correlation spectra in `partial`
-  // ([U][nsplit][S J][M] for this family); a finishing pass sums them.
+  // ([U][nsplit][S J][mmax], mmax the family's largest M: the sizes of one
+  // family differ); a finishing pass sums them.
   int nsplit;
+  int mmax;
   cf* partial;
+  // With nsplit > 1, the alpha-scaled RIR spectra of every utterance of the
+  // family, formed once by a pass before the parts ([U][S J][mmax]).
+  cf* hspec;
 };
 
 }  // namespace rsim

@@ -1029,6 +1029,22 @@ __device__ __forceinline__ void bwd_finish_rir(const BwdArgs& A, long long r, co
   for (int k = L + t; k < L0; k += PL::T) A.gh[ro + k] = 0.0f;
 }
 
+// The alpha-scaled spectrum of RIR slot r (its kept taps) into dst.
+template <class PL>
+__device__ __forceinline__ void bwd_rir_spectrum(const BwdArgs& A, long long r, cf* dst, Xch<PL>& lds,
+                                                 const TwBase& tw, int t) {
+  constexpr int P = PL::P;
+  const BatchDev& b = A.b;
+  cf v[P];
+  load_real<PL>(v, A.h + uni64(b.rir_off[r]), uni(b.rir_len[r]), t);
+  Fft<PL>::forward(v, lds, tw, t);
+  Fft<PL>::post(v, tw, t);
+  const float a = A.alpha[r];
+#pragma unroll
+  for (int q = 0; q < P; ++q) v[q] = mk(v[q].x * a, v[q].y * a);
+  store_spec<PL>(dst, v, t);
+}
+
 // Work item (u, part) of the adjoint: blocks [b0, b1) of utterance u.  With
 // one part per utterance it also finishes dh and dalpha; otherwise it leaves
 // its correlation spectra in A.partial for the finishing pass.
@@ -1042,26 +1058,18 @@ __device__ __forceinline__ void bwd_utterance(const BwdArgs& A, int u, const Sch
   const int I = uni(b.n_src[u]), J = b.J, NS = b.S, Nx = uni(b.src_len[u]);
   const int B = S.hop, nb = S.nb, tu = S.tu;
   const float gscale = 1.0f / (8.0f * (float)M);
-  cf* Hs = slot;
+  cf* Hs = A.hspec ? A.hspec + (long long)u * NS * J * A.mmax : slot;
   cf* Gs = slot + (long long)NS * J * M;
   cf* Rs = nparts == 1 ? Gs + 2LL * J * M
-                       : A.partial + ((long long)u * A.nsplit + part) * NS * J * M;
+                       : A.partial + ((long long)u * A.nsplit + part) * NS * J * A.mmax;
   const int b0 = (int)((long long)nb * part / nparts), b1 = (int)((long long)nb * (part + 1) / nparts);
   const long long yo = uni64(b.out_off[u]);
   const long long ys = uni(b.out_stride[u]);
 
-  for (int i = 0; i < I; ++i) {
-    for (int j = 0; j < J; ++j) {
-      const long long r = ((long long)u * NS + i) * J + j;
-      cf v[P];
-      load_real<PL>(v, A.h + uni64(b.rir_off[r]), uni(b.rir_len[r]), t);
-      Fft<PL>::forward(v, lds, tw, t);
-      Fft<PL>::post(v, tw, t);
-      const float a = A.alpha[r];
-#pragma unroll
-      for (int q = 0; q < P; ++q) v[q] = mk(v[q].x * a, v[q].y * a);
-      store_spec<PL>(Hs + (long long)(i * J + j) * M, v, t);
-    }
+  if (!A.hspec) {
+    for (int i = 0; i < I; ++i)
+      for (int j = 0; j < J; ++j)
+        bwd_rir_spectrum<PL>(A, ((long long)u * NS + i) * J + j, Hs + (long long)(i * J + j) * M, lds, tw, t);
   }
 
   if constexpr (PL::T <= 512) {
@@ -1187,6 +1195,32 @@ __global__ __launch_bounds__(T, 2) void bwd_kernel(BwdArgs A) {
   }
 }
 
+// First pass of a split adjoint: the alpha-scaled spectrum of every RIR slot
+// of the family's utterances into A.hspec, one work item per slot, so that
+// the parts of an utterance share them.
+template <int T>
+__global__ __launch_bounds__(T, 2) void bwd_rir_kernel(BwdArgs A) {
+  __shared__ cf lds_raw[max_lds_with_threads<T>()];
+  const int t = threadIdx.x;
+  const BatchDev& b = A.b;
+  const int NS = b.S, J = b.J;
+  const long long per = (long long)NS * J;
+  const long long items = (long long)__builtin_amdgcn_readfirstlane(A.hdr->count[A.fam]) * per;
+  for (long long k = blockIdx.x; k < items; k += gridDim.x) {
+    const int pos = (int)(k / per), i = (int)((k % per) / J), j = (int)(k % J);
+    const int u = __builtin_amdgcn_readfirstlane(A.list[(long long)A.fam * b.U + pos]);
+    const int log2n = __builtin_amdgcn_readfirstlane(A.sched[u].log2n);
+    if (i >= uni(b.n_src[u])) continue;
+    dispatch_plan<T>(log2n, [&](auto pl) __attribute__((always_inline)) {
+      using PL = decltype(pl);
+      Xch<PL> lds{lds_raw, 0};
+      const TwBase tw = Fft<PL>::bases(plan_tw<PL>(), t);
+      bwd_rir_spectrum<PL>(A, ((long long)u * NS + i) * J + j,
+                           A.hspec + (long long)u * per * A.mmax + (long long)(i * J + j) * PL::M, lds, tw, t);
+    });
+  }
+}
+
 // Finishing pass of a split adjoint: for every RIR slot (i, j) of an
 // utterance in more than one part, sums the parts' correlation spectra and
 // gives dh and dalpha.  One work item per slot, grid-stride.
@@ -1212,7 +1246,7 @@ __global__ __launch_bounds__(T, 2) void bwd_finish_kernel(BwdArgs A) {
       constexpr int M = PL::M;
       Xch<PL> lds{lds_raw, 0};
       const TwBase tw = Fft<PL>::bases(plan_tw<PL>(), t);
-      const long long stride = per * M;
+      const long long stride = per * A.mmax;  // one part's spectra
       const cf* R = A.partial + (long long)u * A.nsplit * stride;
       bwd_finish_rir<PL>(A, ((long long)u * NS + i) * J + j, R + (long long)(i * J + j) * M, nparts, stride,
                          lds, tw, s_red, t);
@@ -1458,6 +1492,16 @@ const void* bwd_kernel_ptr(int fam) {
     default: return reinterpret_cast<const void*>(&bwd_kernel<1024>);
   }
 }
+const void* bwd_rir_kernel_ptr(int fam) {
+  switch (fam) {
+    case 0: return reinterpret_cast<const void*>(&bwd_rir_kernel<32>);
+    case 1: return reinterpret_cast<const void*>(&bwd_rir_kernel<64>);
+    case 2: return reinterpret_cast<const void*>(&bwd_rir_kernel<128>);
+    case 3: return reinterpret_cast<const void*>(&bwd_rir_kernel<256>);
+    case 4: return reinterpret_cast<const void*>(&bwd_rir_kernel<512>);
+    default: return reinterpret_cast<const void*>(&bwd_rir_kernel<1024>);
+  }
+}
 const void* bwd_finish_kernel_ptr(int fam) {
   switch (fam) {
     case 0: return reinterpret_cast<const void*>(&bwd_finish_kernel<32>);
@@ -1599,6 +1643,7 @@ struct WsLayout {
   int gsplit[kNumFam];          // forward: work items per utterance (mic groups)
   int nsplit;                   // adjoint: parts per utterance
   size_t fam_partial[kNumFam];  // adjoint: byte offset of each family's part spectra (nsplit > 1)
+  size_t fam_hspec[kNumFam];    // adjoint: byte offset of each family's shared RIR spectra (nsplit > 1)
   size_t fam_scratch[kNumFam];  // byte offset of each family's slots (families run concurrently)
   long long slot_cf[kNumFam];
   int grid[kNumFam];
@@ -1655,6 +1700,8 @@ WsLayout layout(const rsim_batch* b, const TuneDev& td, bool backward, const Dev
     L.fam_partial[f] = off;
     if (used[f] && L.nsplit > 1)
       off += align256(U * (size_t)L.nsplit * (size_t)(S * J) * (size_t)kFamMaxM[f] * sizeof(cf));
+    L.fam_hspec[f] = off;
+    if (used[f] && L.nsplit > 1) off += align256(U * (size_t)(S * J) * (size_t)kFamMaxM[f] * sizeof(cf));
   }
   L.total = off;
   return L;
@@ -1709,9 +1756,11 @@ struct CallPlan {
   bool has_cut = false;
   Node cut, prep, sched;
   Node fam[kNumFam + 1];  // the family kernels (and, for the adjoint, the zero fill)
+  // Optional kernels before and after fam[k] on its stream (the adjoint's
+  // RIR spectra and finishing pass of a family).
+  Node pre[kNumFam + 1], post[kNumFam + 1];
+  bool has_pre[kNumFam + 1] = {}, has_post[kNumFam + 1] = {};
   int nf = 0;
-  Node post[kNumFam];     // kernels that need every family kernel done (the adjoint's finishing pass)
-  int np = 0;
 };
 
 bool capturing(hipStream_t s) {
@@ -1721,8 +1770,9 @@ bool capturing(hipStream_t s) {
 }
 
 // Issues the plan on s.  Several families run concurrently on the library's
-// side streams (forked from s after the schedule and joined back into s);
-// when s is being captured by the caller they run one after the other on s.
+// side streams (forked from s after the schedule and joined back into s),
+// each with its kernels before and after it on the same stream; when s is
+// being captured by the caller they run one after the other on s.
 rsim_status issue_eager(CallPlan& P, hipStream_t s) {
   const DevState& st = dev_state();
   if (P.has_cut && hipLaunchKernel(P.cut.fn, P.cut.grid, P.cut.block, P.cut.p(), 0, s) != hipSuccess)
@@ -1745,17 +1795,21 @@ rsim_status issue_eager(CallPlan& P, hipStream_t s) {
       fs = st.side[k - 1];
       if (hipStreamWaitEvent(fs, st.fork, 0) != hipSuccess) return RSIM_EDEVICE;
     }
+    if (P.has_pre[k]) {
+      Node& pn = P.pre[k];
+      if (hipLaunchKernel(pn.fn, pn.grid, pn.block, pn.p(), 0, fs) != hipSuccess) return RSIM_EDEVICE;
+    }
     Node& n = P.fam[k];
     if (hipLaunchKernel(n.fn, n.grid, n.block, n.p(), 0, fs) != hipSuccess) return RSIM_EDEVICE;
+    if (P.has_post[k]) {
+      Node& qn = P.post[k];
+      if (hipLaunchKernel(qn.fn, qn.grid, qn.block, qn.p(), 0, fs) != hipSuccess) return RSIM_EDEVICE;
+    }
     if (fork && k > 0) {
       if (hipEventRecord(st.join[k - 1], fs) != hipSuccess ||
           hipStreamWaitEvent(s, st.join[k - 1], 0) != hipSuccess)
         return RSIM_EDEVICE;
     }
-  }
-  for (int k = 0; k < P.np; ++k) {
-    Node& n = P.post[k];
-    if (hipLaunchKernel(n.fn, n.grid, n.block, n.p(), 0, s) != hipSuccess) return RSIM_EDEVICE;
   }
   return RSIM_OK;
 }
@@ -1789,8 +1843,8 @@ void gc_retired(bool wait) {
   }
 }
 
-// Builds the plan into a graph (cut -> schedule -> the family kernels as
-// parallel branches), instantiates it and launches it on s.  The graph is
+// Builds the plan into a graph (a chain: cut -> schedule -> each family's
+// kernels), instantiates it and launches it on s.  The graph is
 // built node by node, not captured, so no stream other than s is involved.
 // The executable graph is destroyed once an event recorded after its launch
 // has completed.
@@ -1822,12 +1876,16 @@ rsim_status issue_graph(CallPlan& P, hipStream_t s) {
   ok = ok && add(P.sched, &prev, 1, &node);
   prev = node;
   for (int k = 0; ok && k < P.nf; ++k) {
-    ok = add(P.fam[k], &prev, 1, &node);
+    if (P.has_pre[k]) {
+      ok = add(P.pre[k], &prev, 1, &node);
+      prev = node;
+    }
+    ok = ok && add(P.fam[k], &prev, 1, &node);
     prev = node;
-  }
-  for (int k = 0; ok && k < P.np; ++k) {
-    ok = add(P.post[k], &prev, 1, &node);
-    prev = node;
+    if (ok && P.has_post[k]) {
+      ok = add(P.post[k], &prev, 1, &node);
+      prev = node;
+    }
   }
   hipGraphExec_t exec = nullptr;
   ok = ok && hipGraphInstantiate(&exec, g, nullptr, nullptr, 0) == hipSuccess;
@@ -1941,9 +1999,10 @@ void plan_bwd(CallPlan& P, const rsim_batch* b, const BatchDev& bd, const TuneDe
   A.scratch = nullptr;
   A.slot_cf = 0;
   A.nsplit = L.nsplit;
+  A.mmax = 0;
   A.partial = nullptr;
+  A.hspec = nullptr;
   P.nf = 0;
-  P.np = 0;
   const int cus = st.cus > 0 ? st.cus : 256;
   P.fam[P.nf++].set(reinterpret_cast<const void*>(&bwd_zero_kernel), dim3(std::min(b->n_utt, cus * 4)),
                     dim3(256), A);
@@ -1955,13 +2014,24 @@ void plan_bwd(CallPlan& P, const rsim_batch* b, const BatchDev& bd, const TuneDe
     A.fam = f;
     A.scratch = reinterpret_cast<cf*>(base + L.fam_scratch[f]);
     A.slot_cf = L.slot_cf[f];
+    A.mmax = kFamMaxM[f];
     A.partial = L.nsplit > 1 ? reinterpret_cast<cf*>(base + L.fam_partial[f]) : nullptr;
+    A.hspec = L.nsplit > 1 ? reinterpret_cast<cf*>(base + L.fam_hspec[f]) : nullptr;
+    if (L.nsplit > 1) {
+      P.pre[P.nf].set(bwd_rir_kernel_ptr(f),
+                      dim3((unsigned)std::min<long long>((long long)b->n_utt * b->max_src * b->n_mic,
+                                                         (long long)cus * 2)),
+                      dim3(kFamT[f]), A);
+      P.has_pre[P.nf] = true;
+    }
+    if (L.nsplit > 1) {
+      P.post[P.nf].set(bwd_finish_kernel_ptr(f),
+                       dim3((unsigned)std::min<long long>((long long)b->n_utt * b->max_src * b->n_mic,
+                                                          (long long)cus * 2)),
+                       dim3(kFamT[f]), A);
+      P.has_post[P.nf] = true;
+    }
     P.fam[P.nf++].set(bwd_kernel_ptr(f), dim3(L.grid[f]), dim3(kFamT[f]), A);
-    if (L.nsplit > 1)
-      P.post[P.np++].set(bwd_finish_kernel_ptr(f),
-                         dim3((unsigned)std::min<long long>((long long)b->n_utt * b->max_src * b->n_mic,
-                                                            (long long)cus * 2)),
-                         dim3(kFamT[f]), A);
   }
 }
 

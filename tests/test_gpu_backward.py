@@ -230,3 +230,23 @@ def test_backward_many_utterances_one_part_each():
     gx, gh, ga, gys = _run(b, 20.0, 11)
     for u in (0, 1, 2, 149, 299):
         _check_full(b, 20.0, gx, gh, ga, gys, u)
+
+
+@pytest.mark.gpu
+def test_backward_split_with_two_sizes_of_one_family():
+    # N = 1024 and 2048 run in one kernel family; with fewer utterances than
+    # compute units each is split into parts, whose correlation and RIR
+    # spectra live in per-family buffers laid out for the larger size
+    rng = synth.rng_for(54, 0)
+    srcs, rirs, snrs = [], [], []
+    for u in range(4):
+        I = 1 + u % 3
+        n = int(rng.integers(3000, 9000))
+        srcs.append([synth.speech_like(rng, n)] + [synth.pink_noise(rng, n) for _ in range(I - 1)])
+        L0 = int(rng.integers(50, 400))
+        rirs.append([[synth.rir(rng, L0, 0.2, int(rng.integers(0, 30))) for _ in range(2)] for _ in range(I)])
+        snrs.append([0.0] + [float(v) for v in rng.uniform(0, 20, I - 1)])
+    b = synth.pack(srcs, rirs, snrs, 2)
+    gx, gh, ga, gys = _run(b, 20.0, 12, fft_log2n=np.array([10, 11, 10, 11], np.int32))
+    for u in range(b.n_utt):
+        _check_full(b, 20.0, gx, gh, ga, gys, u)

@@ -302,11 +302,26 @@ def test_large_workload_subset_sampled(eta):
 
 @pytest.mark.gpu
 def test_batched_workload_full_size_sampled():
-    # the whole 2048-utterance epoch in the benchmark's launch configuration
-    # (one graph, LPT order, built-in cost model with one size per batch)
+    # the whole 2048-utterance epoch in the benchmark's launch configuration:
+    # LPT order, the tuner's table measured on the cut batch (FFT size and
+    # kernel variants), one graph for cut + mix
+    torch = cuda()
+    from paper_1712_03439_amd import autotune, rsim
+
     b = synth.make_config2(epoch=2)
     order = np.argsort(-(b.src_len.astype(np.int64) * (b.n_src + b.n_mic)), kind="stable").astype(np.int32)
-    db, alpha, y, rl, ol = _simulate(b, 20.0, order=order, use_graph=True)
+    db = rsim.DeviceBatch(b, order=order)
+    alpha_t = torch.from_numpy(rsim.batch_gains(db, b.snr_db)).cuda()
+    stream = torch.cuda.Stream()
+    stream.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(stream):
+        rsim.truncate_batch(db, 20.0, stream=stream)
+    stream.synchronize()
+    tune, _ = autotune.tune(db, alpha_t, stream=stream, reps=1)
+    with torch.cuda.stream(stream):
+        y = rsim.simulate(db, alpha_t, 20.0, tune=tune, use_graph=True, stream=stream)
+    torch.cuda.synchronize()
+    y, rl, ol = y.cpu().numpy(), db.rir_len.cpu().numpy(), db.out_len.cpu().numpy()
     longest = int(np.argmax(b.src_len))
     most_src = int(np.argmax(b.n_src))
     longest_rir = int(np.argmax(b.rir_len0)) // (b.max_src * b.n_mic)
