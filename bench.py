@@ -236,7 +236,8 @@ def large_thresholds(torch, rsim, autotune, synth, dev, etas=(math.inf, 30.0, 20
         out["thresholds"][key] = {
             "ms": round(ms, 3), "audio_s_per_s": round(b.audio_seconds / (ms * 1e-3), 1),
             "mean_cut_len": round(float(L[L > 0].mean()), 1), "fft_sizes": {str(k): v for k, v in sorted(sizes.items())},
-            "variant": entry["variant"],
+            "variant": entry["variant"], "policy": "one size per batch" if tune.one_size else "size per utterance",
+            "policy_ms": {k: round(v, 3) for k, v in entry.get("policy_ms", {}).items()},
             "alu": {"achieved": round(fl / (ms * 1e-3) / 1e12, 2), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                     "frac": round(fl / (ms * 1e-3) / 1e12 / FP32_PEAK_TFLOPS, 4)},
             "hbm": {"achieved": round(byt / (ms * 1e-3) / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -327,6 +328,7 @@ def main() -> int:
         tune, entry = autotune.tune(db0, alpha0, save=args.save_tune or None, stream=stream)
         tune_info = {"source": "measured on the first epoch's batch", "variant": entry["variant"],
                      "ms": {k: v["ms"] for k, v in entry["measured"]["sizes"].items()},
+                     "policy_ms": entry.get("policy_ms"),
                      "seconds": round(time.perf_counter() - t1, 2)}
         log(f"tuned in {tune_info['seconds']} s: variants {entry['variant']}, "
             + ", ".join(f"N=2^{k}: " + "/".join(f"{t:.3f}" for t in v.values()) + " ms"

@@ -10,7 +10,9 @@ built-in model uses that count with 2.5 N log2 N per real FFT.  `tune()`
 times the filter-and-mix kernels of every size and kernel variant on a batch
 (eager launches on one stream) and scales the model per size to the measured
 times; it also picks each kernel family's variant (the work split of
-rsim_tune.variant).  Tables are stored keyed by the device name.
+rsim_tune.variant) and, by timing the whole batch both ways, whether one size
+serves the batch or each utterance takes its own.  Tables are stored keyed by
+the device name.
 """
 from __future__ import annotations
 
@@ -240,6 +242,42 @@ def fit(measured: dict) -> dict:
                                    for m, r in sorted(sizes.items())}}}
 
 
+def choose_policy(ms_one_size: float, ms_per_utterance: float) -> bool:
+    """one_size for the table: one FFT size per batch unless choosing per
+    utterance ran faster by more than the timing noise."""
+    return not ms_per_utterance < ms_one_size * (1.0 - SAME_WITHIN)
+
+
+def measure_policy(db, alpha, entry: dict, reps: int = 3, stream=None) -> dict:
+    """Time the whole batch with the fitted table under both size policies
+    (one size per batch, a size per utterance): eager launches on one stream,
+    one untimed call then reps timed ones each."""
+    import torch
+
+    from . import rsim
+
+    dev = db.device
+    if stream is None:
+        stream = torch.cuda.Stream(device=dev)
+    stream.wait_stream(torch.cuda.current_stream(dev))
+    y = db.new_output()
+    out = {}
+    for key, one in (("one_size", True), ("per_utterance", False)):
+        t = entry_to_tune(dict(entry, one_size=one))
+        ws = db.workspace(t)
+        with torch.cuda.stream(stream):
+            rsim.mix(db, alpha, y=y, ws=ws, tune=t, stream=stream)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(reps):
+                rsim.mix(db, alpha, y=y, ws=ws, tune=t, stream=stream)
+            e1.record(stream)
+        e1.synchronize()
+        out[key] = e0.elapsed_time(e1) / reps
+        del ws
+    return out
+
+
 def entry_to_tune(entry: dict):
     from . import rsim
 
@@ -247,10 +285,15 @@ def entry_to_tune(entry: dict):
                            entry.get("variant"))
 
 
-def tune(db, alpha, save: Optional[str] = None, **kw):
-    """measure() then fit(): the RsimTune for this GPU and the table entry.
-    With save, the entry is merged into that JSON file under device_name()."""
+def tune(db, alpha, save: Optional[str] = None, policy: bool = True, **kw):
+    """measure() then fit(), then (policy) the size policy by measure_policy():
+    the RsimTune for this GPU and the table entry.  With save, the entry is
+    merged into that JSON file under device_name()."""
     entry = fit(measure(db, alpha, **kw))
+    if policy:
+        pm = measure_policy(db, alpha, entry, reps=kw.get("reps", 3), stream=kw.get("stream"))
+        entry["one_size"] = choose_policy(pm["one_size"], pm["per_utterance"])
+        entry["policy_ms"] = pm
     if save:
         data = {}
         if os.path.exists(save):

@@ -121,3 +121,10 @@ def test_sub_batch_rows_and_order():
     # parent order 5, 3, 11, 0, ...: of idx, 3 comes first, then 11, 0, 4
     assert [idx[k] for k in sub.order.numpy()] == [3, 11, 0, 4]
     assert sub.max_rir_len0 == int(b.rir_len0[rows].max())
+
+
+def test_policy_keeps_one_size_within_the_noise():
+    assert autotune.choose_policy(10.0, 10.0) is True
+    assert autotune.choose_policy(10.0, 9.9) is True     # 1 % faster: noise
+    assert autotune.choose_policy(10.0, 9.5) is False    # 5 % faster: per utterance
+    assert autotune.choose_policy(10.0, 11.0) is True
