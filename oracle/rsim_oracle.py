@@ -31,7 +31,7 @@ flag.  An empty RIR has n_c = -1 and L = 0.
 from __future__ import annotations
 
 import math
-from typing import List, Sequence, Tuple
+from typing import Sequence, Tuple
 
 import numpy as np
 

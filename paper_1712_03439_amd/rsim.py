@@ -8,7 +8,6 @@ there is no fallback of any kind when it is missing.
 from __future__ import annotations
 
 import ctypes
-import math
 import os
 from typing import Optional, Sequence
 
@@ -132,11 +131,6 @@ def device_status() -> int:
     st = ctypes.c_int32(0)
     _check(_lib().rsim_device_status(ctypes.byref(st)), "rsim_device_status")
     return int(st.value)
-
-
-def cut_scale_host(eta_db: float) -> float:
-    """Not used by the kernels (the C library computes the scale); kept for docs."""
-    return 0.0 if math.isinf(eta_db) else 10.0 ** (-eta_db / 10.0)
 
 
 def truncate_rir(h, off, len0, eta_db: float, n_c=None, length=None, stream=None):

@@ -6,7 +6,6 @@ import os
 import re
 
 import numpy as np
-import pytest
 
 from paper_1712_03439_amd import rsim
 
