@@ -210,6 +210,35 @@ rsim_status rsim_source_power(const rsim_batch* b, const float* x, double* power
 rsim_status rsim_snr_gains(const double* p_dry, const double* snr_db, int32_t I, int32_t J,
                            float* alpha);
 
+/*
+ * Image-method room impulse responses, Sec. 2.1 eq. (1): the room is mirrored
+ * across its walls into the (2K+1)^3 virtual rooms (a, b, c), |a|, |b|, |c| <= K
+ * (K = order; the paper uses K = 8, 4913 images), each holding one image of the
+ * source, and
+ *   h_r[n] = sum over the images of refl^g / d,  at n = ceil(d fs / c0) < len[r],
+ * g = |a| + |b| + |c| reflections, d the image-to-microphone distance, image
+ * x-coordinate a Lx + xs (a even) or a Lx + (Lx - xs) (a odd), likewise y, z.
+ * RIR r reads geom[9r .. 9r+9) = (Lx, Ly, Lz, source x, y, z, mic x, y, z) in
+ * metres and refl[r] (device arrays, binary64) and writes every tap of
+ * h[off[r] .. off[r] + len[r]).  Arithmetic in binary64 without fused
+ * multiply-add: d = sqrt((dx dx + dy dy) + dz dz), n = ceil((d fs) / c0),
+ * refl^g = refl multiplied g times from 1, amplitude refl^g / d; each amplitude
+ * is quantised to a multiple of 2^-40 (round half to even) and the taps sum
+ * these integers exactly, so the result does not depend on the order of the
+ * images; a tap is then converted to binary64, scaled by 2^-40 and rounded
+ * once to float32.  max_len >= every len[r] (host) sizes the launch.
+ * Validation: n_rir >= 0, 0 <= order <= 16, fs > 0, c0 > 0, max_len >= 0
+ * (RSIM_EINVAL).  Each RIR needs its source and microphone at least 5 mm
+ * inside every wall and at least 1 cm apart (so every image is at least 1 cm
+ * from the microphone and no tap's integer sum can overflow) and refl in
+ * [0, 1]; otherwise its taps are written as zeros and RSIM_DEV_BADDESC is
+ * set.  A RIR whose taps fall outside [0, h_len) or whose len exceeds
+ * max_len is not written (RSIM_DEV_BADDESC).
+ */
+rsim_status rsim_image_rir(const double* geom, const double* refl, int32_t n_rir, int32_t order, double fs,
+                           double c0, float* h, int64_t h_len, const int64_t* off, const int32_t* len,
+                           int32_t max_len, hipStream_t stream);
+
 /* Read and clear the device status word (synchronises the device). */
 rsim_status rsim_device_status(int32_t* status);
 

@@ -1310,6 +1310,108 @@ __global__ __launch_bounds__(256) void power_kernel(BatchDev b, const float* __r
   }
 }
 
+// ========================================================= image-method RIRs
+// Eq. (1): the RIR is the sum over the (2K+1)^3 images of the source in the
+// mirrored rooms (a, b, c) of refl^g / d at tap ceil(d fs / c0).  A work item
+// is one RIR and a window of kImgWindow taps: the workgroup evaluates every
+// image in binary64 (no contraction, so each product and sum is rounded on
+// its own, as the definition is written), quantises the amplitudes of the
+// images that fall in the window to multiples of 2^-40 and sums them exactly
+// with 64-bit integer atomics in LDS, so the result does not depend on the
+// order in which the images are added.
+constexpr int kImgThreads = 256;
+constexpr int kImgWindow = 4096;
+constexpr int kImgMaxOrder = 16;
+
+struct ImageArgs {
+  const double* geom;  // [n_rir][9]: room Lx Ly Lz, source xyz, mic xyz
+  const double* refl;  // [n_rir]
+  float* h;
+  long long h_len;
+  const long long* off;
+  const int* len;
+  int n_rir, order, nwin, max_len;
+  double fs, c0;
+};
+
+// Offset of the image in virtual room a from the microphone along one axis.
+__device__ __forceinline__ double image_delta(int a, double L, double s, double m) {
+#pragma clang fp contract(off)
+  const double base = (a & 1) ? (L - s) : s;
+  return ((double)a * L + base) - m;
+}
+
+// Source and microphone at least 5 mm inside every wall and 1 cm apart,
+// refl in [0, 1]: every image is then at least 1 cm from the microphone.
+__device__ __forceinline__ bool image_geometry_ok(const double* g, double refl) {
+#pragma clang fp contract(off)
+  bool ok = refl >= 0.0 && refl <= 1.0;
+  for (int ax = 0; ax < 3; ++ax) {
+    const double L = g[ax], s = g[3 + ax], m = g[6 + ax];
+    ok = ok && s >= 0.005 && s <= L - 0.005 && m >= 0.005 && m <= L - 0.005;
+  }
+  const double dx = g[3] - g[6], dy = g[4] - g[7], dz = g[5] - g[8];
+  return ok && ((dx * dx + dy * dy) + dz * dz) >= 1e-4;
+}
+
+__global__ __launch_bounds__(kImgThreads) void image_kernel(ImageArgs A) {
+#pragma clang fp contract(off)
+  __shared__ unsigned long long acc[kImgWindow];
+  __shared__ double sq[3][2 * kImgMaxOrder + 1];
+  __shared__ double pw[3 * kImgMaxOrder + 1];
+  const int t = threadIdx.x;
+  const int K = A.order, S = 2 * K + 1, V = S * S * S;
+  const long long items = (long long)A.n_rir * A.nwin;
+  int err = 0;
+  for (long long it = blockIdx.x; it < items; it += gridDim.x) {
+    const int r = (int)(it / A.nwin), w = (int)(it - (long long)r * A.nwin);
+    const int len = uni(A.len[r]);
+    const long long off = uni64(A.off[r]);
+    const int w0 = w * kImgWindow;
+    if (len < 0 || len > A.max_len || off < 0 || off + len > A.h_len) {
+      if (w == 0) err |= RSIM_DEV_BADDESC;
+      continue;
+    }
+    if (w0 >= len) continue;
+    const int wn = min(kImgWindow, len - w0);
+    const double* g = A.geom + 9LL * r;
+    const double refl = A.refl[r];
+    const bool ok = image_geometry_ok(g, refl);
+    if (!ok && w == 0) err |= RSIM_DEV_BADDESC;
+    __syncthreads();  // the previous item's readers of sq, pw and acc are done
+    if (t < 3 * S) {
+      const int ax = t / S, a = t - ax * S - K;
+      const double d = image_delta(a, g[ax], g[3 + ax], g[6 + ax]);
+      sq[ax][t - ax * S] = d * d;
+    }
+    if (t == 0) {
+      double p = 1.0;
+      for (int k = 0; k <= 3 * K; ++k) {
+        pw[k] = p;
+        p = p * refl;
+      }
+    }
+    for (int k = t; k < wn; k += kImgThreads) acc[k] = 0ull;
+    __syncthreads();
+    if (ok) {
+      for (int v = t; v < V; v += kImgThreads) {
+        const int ia = v / (S * S), ib = (v / S) % S, ic = v % S;
+        const double d = sqrt((sq[0][ia] + sq[1][ib]) + sq[2][ic]);
+        const double n = ceil((d * A.fs) / A.c0);
+        if (n >= (double)w0 && n < (double)(w0 + wn)) {
+          const int gg = abs(ia - K) + abs(ib - K) + abs(ic - K);
+          const double q = rint((pw[gg] / d) * 1099511627776.0);  // 2^40
+          atomicAdd(&acc[(int)n - w0], (unsigned long long)q);
+        }
+      }
+    }
+    __syncthreads();
+    for (int k = t; k < wn; k += kImgThreads)
+      A.h[off + w0 + k] = (float)((double)acc[k] * 9.094947017729282e-13);  // 2^-40
+  }
+  if (err && t == 0) flag_status(err);
+}
+
 // ================================================= FFT engine test kernels
 // Bin held by slot q of thread t (thread 0 permuted as in Fft::perm_t0; its
 // slot SP holds bins 0 and N/2).
@@ -2271,6 +2373,37 @@ rsim_status rsim_device_status(int32_t* status) {
   if (hipMemcpyToSymbol(HIP_SYMBOL(g_status), &zero, sizeof(int)) != hipSuccess) return RSIM_EDEVICE;
   *status = v;
   return RSIM_OK;
+}
+
+rsim_status rsim_image_rir(const double* geom, const double* refl, int32_t n_rir, int32_t order, double fs,
+                           double c0, float* h, int64_t h_len, const int64_t* off, const int32_t* len,
+                           int32_t max_len, hipStream_t stream) {
+  if (n_rir < 0 || order < 0 || order > kImgMaxOrder || !(fs > 0.0) || !(c0 > 0.0) || max_len < 0 || h_len < 0 ||
+      !std::isfinite(fs) || !std::isfinite(c0))
+    return RSIM_EINVAL;
+  if (n_rir == 0 || max_len == 0) return RSIM_OK;
+  if (!geom || !refl || !h || !off || !len) return RSIM_EINVAL;
+  const rsim_status e = ensure_init(stream);
+  if (e != RSIM_OK) return e;
+  ImageArgs A;
+  A.geom = geom;
+  A.refl = refl;
+  A.h = h;
+  A.h_len = h_len;
+  A.off = reinterpret_cast<const long long*>(off);
+  A.len = len;
+  A.n_rir = n_rir;
+  A.order = order;
+  A.nwin = (max_len + kImgWindow - 1) / kImgWindow;
+  A.max_len = max_len;
+  A.fs = fs;
+  A.c0 = c0;
+  const DevState& st = dev_state();
+  const int cus = st.cus > 0 ? st.cus : 256;
+  const long long items = (long long)n_rir * A.nwin;
+  const unsigned grid = (unsigned)std::min<long long>(items, (long long)cus * 8);
+  hipLaunchKernelGGL(image_kernel, dim3(grid), dim3(kImgThreads), 0, stream, A);
+  return hipGetLastError() == hipSuccess ? RSIM_OK : RSIM_EDEVICE;
 }
 
 rsim_status rsim_rfft(const float* x, int32_t n, int32_t count, float* spec, hipStream_t stream) {

@@ -24,7 +24,7 @@ EXPORTS = (
     "rsim_init", "rsim_strerror", "rsim_version", "rsim_truncate_rir",
     "rsim_ola_workspace_bytes", "rsim_ola_convolve", "rsim_mix_workspace_bytes", "rsim_mix",
     "rsim_simulate", "rsim_mix_backward", "rsim_source_power", "rsim_snr_gains",
-    "rsim_device_status", "rsim_rfft", "rsim_irfft",
+    "rsim_device_status", "rsim_rfft", "rsim_irfft", "rsim_image_rir",
 )
 
 
@@ -79,6 +79,7 @@ def _lib():
             "rsim_device_status": ([vp], i32),
             "rsim_rfft": ([vp, i32, i32, vp, vp], i32),
             "rsim_irfft": ([vp, i32, i32, vp, vp], i32),
+            "rsim_image_rir": ([vp, vp, i32, i32, f64, f64, vp, i64, vp, vp, i32, vp], i32),
         }
         for name, (args, res) in sig.items():
             fn = getattr(lib, name)
@@ -177,6 +178,26 @@ def irfft(spec, n: int, stream=None):
     x = torch.empty(count * n, dtype=torch.float32, device=spec.device)
     _check(_lib().rsim_irfft(_ptr(spec), int(n), count, _ptr(x), _stream(stream)), "rsim_irfft")
     return x.view(count, n)
+
+
+def image_rir(geom, refl, off, length, h, max_len: int, order: int = 8, fs: float = 16000.0,
+              c0: float = 343.0, stream=None):
+    """Image-method RIRs (eq. 1) written into h at off[r] .. off[r] + length[r].
+
+    geom: float64 [n_rir, 9] (room Lx Ly Lz, source xyz, mic xyz, metres),
+    refl: float64 [n_rir], off: int64 [n_rir], length: int32 [n_rir], all on the
+    GPU; max_len (host) >= every length."""
+    torch = _torch()
+    _require_cuda(geom, refl, off, length, h)
+    if geom.dtype != torch.float64 or refl.dtype != torch.float64 or h.dtype != torch.float32:
+        raise ValueError("rsim.image_rir: geom and refl are float64, h is float32")
+    n = int(refl.numel())
+    if geom.numel() != 9 * n or off.numel() != n or length.numel() != n:
+        raise ValueError("rsim.image_rir: geom [n, 9], refl, off and length [n]")
+    _check(_lib().rsim_image_rir(_ptr(geom), _ptr(refl), n, int(order), float(fs), float(c0), _ptr(h),
+                                 int(h.numel()), _ptr(off), _ptr(length), int(max_len), _stream(stream)),
+           "rsim_image_rir")
+    return h
 
 
 def snr_gains(p_dry: Sequence[float], snr_db: Sequence[float], n_mic: int) -> np.ndarray:

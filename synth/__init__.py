@@ -355,3 +355,36 @@ def subset(b: Batch, idx: Sequence[int]) -> Batch:
     return pack([b.sources(u) for u in idx], [b.rirs(u) for u in idx],
                 [list(b.snr_db[u * b.max_src:u * b.max_src + int(b.n_src[u])]) for u in idx],
                 b.n_mic)
+
+
+def image_geometry(b: Batch, seed_epoch: int = 0, cid: int = 70):
+    """Shoebox rooms for the image method (eq. 1), one per utterance of `b`,
+    for every RIR slot of `b`: geom [U*S*J, 9] (room Lx Ly Lz, source xyz,
+    mic xyz, metres, float64) and refl [U*S*J] (float64).  Recipe: sides
+    U(3, 10) x U(3, 8) x U(2.5, 4) m; reflection coefficient U(0.3, 0.9);
+    sources and mics uniform at least 0.5 m inside every wall; mics 10 cm
+    apart along a random horizontal direction from a random centre; a source
+    at least 0.2 m from every mic (redrawn otherwise).  Unused slots repeat
+    the utterance's first valid geometry (they have no taps)."""
+    rng = rng_for(cid, seed_epoch)
+    U, S, J = b.n_utt, b.max_src, b.n_mic
+    geom = np.zeros((U * S * J, 9))
+    refl = np.zeros(U * S * J)
+    for u in range(U):
+        room = np.array([rng.uniform(3.0, 10.0), rng.uniform(3.0, 8.0), rng.uniform(2.5, 4.0)])
+        r = rng.uniform(0.3, 0.9)
+        span = 0.1 * (J - 1)
+        centre = rng.uniform(0.5 + span, room - 0.5 - span)
+        phi = rng.uniform(0.0, 2 * np.pi)
+        step = 0.1 * np.array([np.cos(phi), np.sin(phi), 0.0])
+        mics = [centre + (j - (J - 1) / 2) * step for j in range(J)]
+        for i in range(S):
+            while True:
+                src = rng.uniform(0.5, room - 0.5)
+                if min(np.linalg.norm(src - m) for m in mics) >= 0.2:
+                    break
+            for j in range(J):
+                k = (u * S + i) * J + j
+                geom[k] = np.concatenate([room, src, mics[j]])
+                refl[k] = r
+    return geom, refl

@@ -193,3 +193,20 @@ def test_variant_sets_the_mic_split_of_the_workspace():
     two = lib.rsim_mix_workspace_bytes(ctypes.byref(b), ctypes.byref(rsim.tune_table(f, m, True, [2] * 6)), 0)
     dflt = lib.rsim_mix_workspace_bytes(ctypes.byref(b), ctypes.byref(rsim.tune_table(f, m, True)), 0)
     assert dflt == two and one != two
+
+
+def test_image_rir_validation_codes():
+    lib = rsim.lib()
+    p = ctypes.c_void_p(8)
+    ok = dict(n=4, order=8, fs=16000.0, c0=343.0, h_len=1000, max_len=100)
+
+    def call(**kw):
+        a = dict(ok, **kw)
+        return lib.rsim_image_rir(p, p, a["n"], a["order"], a["fs"], a["c0"], p, a["h_len"], p, p,
+                                  a["max_len"], None)
+
+    for bad in (dict(n=-1), dict(order=-1), dict(order=17), dict(fs=0.0), dict(fs=math.nan),
+                dict(c0=-343.0), dict(c0=math.inf), dict(max_len=-1), dict(h_len=-5)):
+        assert call(**bad) == rsim.RSIM_EINVAL, bad
+    assert call(n=0) == rsim.RSIM_OK and call(max_len=0) == rsim.RSIM_OK
+    assert lib.rsim_image_rir(None, p, 4, 8, 16000.0, 343.0, p, 1000, p, p, 100, None) == rsim.RSIM_EINVAL

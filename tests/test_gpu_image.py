@@ -1,0 +1,132 @@
+"""Image-method RIRs (eq. 1) on the GPU against the FP64 oracle.
+
+Bar: bit-exact.  Both sides evaluate every image with the same binary64
+operations, sum the amplitudes as exact multiples of 2^-40 and round once to
+float32, so every tap must be identical."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle.image_oracle as im
+import synth
+from tests.gpu_util import TOL, cuda, max_rel_err
+
+
+def _gpu_rirs(geom, refl, lens, order=8, max_len=None, h_len=None):
+    torch = cuda()
+    from paper_1712_03439_amd import rsim
+
+    lens = np.asarray(lens, np.int32)
+    off = np.concatenate([[0], np.cumsum(lens.astype(np.int64))[:-1]]).astype(np.int64)
+    total = int(lens.sum()) if h_len is None else h_len
+    h = torch.full((max(total, 1),), -7.0, dtype=torch.float32, device="cuda")
+    rsim.image_rir(torch.from_numpy(np.ascontiguousarray(geom, np.float64)).cuda(),
+                   torch.from_numpy(np.ascontiguousarray(refl, np.float64)).cuda(),
+                   torch.from_numpy(off).cuda(), torch.from_numpy(lens).cuda(), h,
+                   int(lens.max()) if max_len is None else max_len, order=order)
+    torch.cuda.synchronize()
+    return h.cpu().numpy(), off
+
+
+@pytest.mark.gpu
+def test_batch_of_rooms_bit_exact():
+    # RIR slots of a batched-workload batch (lengths ceil(T60 fs), T60 in
+    # 0.1..0.9 s: one to four windows of taps), order 8 (4913 images)
+    b = synth.make_config2(n_utt=24, epoch=3)
+    geom, refl = synth.image_geometry(b)
+    used = b.rir_len0 > 0
+    g, r, lens = geom[used], refl[used], b.rir_len0[used]
+    h, off = _gpu_rirs(g, r, lens)
+    for k in range(len(lens)):
+        ref = im.image_rir(g[k, :3], g[k, 3:6], g[k, 6:], r[k], int(lens[k]))
+        got = h[off[k]: off[k] + lens[k]]
+        assert np.array_equal(got, ref), (k, int(np.count_nonzero(got != ref)))
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("order", [0, 1, 3, 12, 16])
+def test_orders_bit_exact(order):
+    rng = np.random.default_rng(order)
+    geoms, refls, lens = [], [], []
+    for k in range(6):
+        room = rng.uniform([3.0, 3.0, 2.5], [9.0, 7.0, 4.0])
+        src = rng.uniform(0.3, room - 0.3)
+        mic = rng.uniform(0.3, room - 0.3)
+        geoms.append(np.concatenate([room, src, mic]))
+        refls.append(float(rng.uniform(0.0, 1.0)) if k else 1.0)
+        lens.append([1, 4095, 4096, 4097, 9000, 16000][k])
+    g, r = np.array(geoms), np.array(refls)
+    h, off = _gpu_rirs(g, r, lens, order=order)
+    for k in range(len(lens)):
+        ref = im.image_rir(g[k, :3], g[k, 3:6], g[k, 6:], r[k], lens[k], order=order)
+        assert np.array_equal(h[off[k]: off[k] + lens[k]], ref), (order, k)
+
+
+@pytest.mark.gpu
+def test_bad_geometry_and_ranges():
+    torch = cuda()
+    from paper_1712_03439_amd import rsim
+
+    rsim.device_status()  # clear
+    good = [6.0, 5.0, 3.0, 1.0, 1.0, 1.0, 4.0, 3.0, 2.0]
+    g = np.array([good,
+                  [6.0, 5.0, 3.0, 0.002, 1.0, 1.0, 4.0, 3.0, 2.0],   # source 2 mm from a wall
+                  [6.0, 5.0, 3.0, 1.0, 1.0, 1.0, 1.0, 1.0, 1.0],     # source at the mic
+                  good])
+    r = np.array([0.7, 0.7, 0.7, 1.2])                                # last: refl > 1
+    h, off = _gpu_rirs(g, r, [500, 500, 500, 500])
+    assert np.array_equal(h[:500], im.image_rir(good[:3], good[3:6], good[6:], 0.7, 500))
+    assert not np.any(h[500:])                                        # zeros, fully written
+    assert rsim.device_status() & rsim.DEV_BADDESC
+    # a RIR longer than max_len, or reaching past h, is not written
+    h, off = _gpu_rirs(g[:2], np.array([0.7, 0.7]), [300, 600], max_len=500)
+    assert np.all(h[300:900] == -7.0) and not np.all(h[:300] == -7.0)
+    assert rsim.device_status() & rsim.DEV_BADDESC
+    h, off = _gpu_rirs(g[:1], np.array([0.7]), [300], h_len=200)
+    assert np.all(h == -7.0)
+    assert rsim.device_status() & rsim.DEV_BADDESC
+    assert rsim.device_status() == 0
+
+
+@pytest.mark.gpu
+def test_image_rirs_through_the_simulator():
+    # RIRs generated on the GPU feed the cut + filter + mix of eq. (2); the
+    # oracle mixes its own image RIRs
+    torch = cuda()
+    import oracle
+    from paper_1712_03439_amd import rsim
+
+    b = synth.make_config2(n_utt=6, epoch=4)
+    geom, refl = synth.image_geometry(b, seed_epoch=1)
+    used = np.nonzero(b.rir_len0 > 0)[0]
+    db = rsim.DeviceBatch(b)
+    sel = torch.from_numpy(used).cuda()
+    rsim.image_rir(torch.from_numpy(geom[used]).cuda(), torch.from_numpy(refl[used]).cuda(),
+                   db.rir_off[sel].contiguous(), db.rir_len0[sel].contiguous(), db.h,
+                   int(b.rir_len0.max()))
+    alpha = torch.from_numpy(rsim.batch_gains(db, b.snr_db)).cuda()
+    y = rsim.simulate(db, alpha, 20.0).cpu().numpy()
+    rl, ol = db.rir_len.cpu().numpy(), db.out_len.cpu().numpy()
+    S, J = b.max_src, b.n_mic
+    for u in range(b.n_utt):
+        xs = b.sources(u)
+        I = len(xs)
+        hs = [[im.image_rir(geom[(u * S + i) * J + j, :3], geom[(u * S + i) * J + j, 3:6],
+                            geom[(u * S + i) * J + j, 6:], refl[(u * S + i) * J + j],
+                            int(b.rir_len0[(u * S + i) * J + j])) for j in range(J)] for i in range(I)]
+        cut = []
+        for i in range(I):
+            row = []
+            for j in range(J):
+                _, L, _ = oracle.cut_rir(hs[i][j], 20.0)
+                assert int(rl[(u * S + i) * J + j]) == L
+                row.append(hs[i][j][:L])
+            cut.append(row)
+        alpha_u = oracle.snr_gains([oracle.dry_power(x) for x in xs], b.snrs(u), J)
+        ref = oracle.mix(xs, cut, alpha_u)
+        T = ref.shape[1]
+        assert int(ol[u]) == T
+        off, st = int(b.out_off[u]), int(b.out_stride[u])
+        for j in range(J):
+            assert max_rel_err(y[off + j * st: off + j * st + T], ref[j]) <= TOL, (u, j)

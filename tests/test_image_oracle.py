@@ -108,6 +108,13 @@ def test_taps_beyond_the_length_are_dropped():
     assert im.image_rir(room, src, mic, r, 0).size == 0
 
 
-def test_source_at_the_microphone_is_rejected():
+@pytest.mark.parametrize("src,mic,r", [
+    ((1.0, 1.0, 1.0), (1.0, 1.0, 1.0), 0.5),        # source at the microphone
+    ((1.0, 1.0, 1.0), (1.005, 1.0, 1.0), 0.5),      # 5 mm apart
+    ((0.001, 1.0, 1.0), (2.0, 1.0, 1.0), 0.5),      # 1 mm from a wall
+    ((1.0, 1.0, 1.0), (2.0, 1.0, 2.999), 0.5),      # 1 mm from the ceiling
+    ((1.0, 1.0, 1.0), (2.0, 1.0, 1.0), 1.5),        # r outside [0, 1]
+])
+def test_invalid_geometry_is_rejected(src, mic, r):
     with pytest.raises(ValueError):
-        im.image_rir((5.0, 4.0, 3.0), (1.0, 1.0, 1.0), (1.0, 1.0, 1.0), 0.5, 100)
+        im.image_rir((5.0, 4.0, 3.0), src, mic, r, 100)
