@@ -184,6 +184,44 @@ def differentiation(torch, rsim, synth, dev, reps: int = 10):
                              "unit": "GB/s", "frac": round(byts / (t_b * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}}
 
 
+def rir_generation(torch, rsim, synth, dev, base, reps: int = 5, order: int = 8):
+    """The image-method RIRs (eq. 1, 17^3 virtual rooms) of every RIR slot of
+    the batched workload's epoch (its lengths ceil(T60 fs)), generated on the
+    GPU into a packed buffer: one untimed call, then `reps` timed ones."""
+    geom, refl = synth.image_geometry(base)
+    used = np.nonzero(base.rir_len0 > 0)[0]
+    lens = base.rir_len0[used].astype(np.int32)
+    off = base.rir_off[used].astype(np.int64)
+    g = torch.from_numpy(geom[used]).to(dev)
+    r = torch.from_numpy(refl[used]).to(dev)
+    o = torch.from_numpy(off).to(dev)
+    ln = torch.from_numpy(lens).to(dev)
+    h = torch.empty(int(base.h.size), dtype=torch.float32, device=dev)
+    stream = torch.cuda.Stream()
+    stream.wait_stream(torch.cuda.current_stream())
+    max_len = int(lens.max())
+    with torch.cuda.stream(stream):
+        rsim.image_rir(g, r, o, ln, h, max_len, order=order, stream=stream)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            rsim.image_rir(g, r, o, ln, h, max_len, order=order, stream=stream)
+        e1.record(stream)
+    torch.cuda.synchronize()
+    if rsim.device_status():
+        raise RuntimeError("image-method generation flagged a bad descriptor")
+    ms = e0.elapsed_time(e1) / reps
+    taps = int(lens.astype(np.int64).sum())
+    images = len(lens) * (2 * order + 1) ** 3
+    gbs = 4.0 * taps / (ms * 1e-3) / 1e9
+    return {"workload": f"{len(lens)} RIRs of the batched epoch ({taps} taps, lengths ceil(T60 fs)), "
+                        f"{(2 * order + 1) ** 3} images each",
+            "ms": round(ms, 4), "rirs_per_s": round(len(lens) / (ms * 1e-3), 1),
+            "images_per_s": round(images / (ms * 1e-3), 1),
+            "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(gbs / HBM_PEAK_GBS, 4)}}
+
+
 def large_thresholds(torch, rsim, autotune, synth, dev, etas=(math.inf, 30.0, 20.0, 10.0), reps: int = 3):
     """The large batched workload (4096 utterances of 1-20 s, up to 4 sources,
     8 mics, T60 U(0.1, 1.0) s, RIRs up to 16000 taps) at each cut threshold:
@@ -263,6 +301,7 @@ def main() -> int:
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-diff", action="store_true", help="skip the adjoint (differentiation workload) timing")
+    ap.add_argument("--no-rirgen", action="store_true", help="skip the image-method RIR generation timing")
     ap.add_argument("--large", action="store_true",
                     help="also time the large batched workload (4096 utterances, 8 mics) at eta = inf, 30, 20, "
                          "10 dB (adds about a minute and 35 GB of GPU memory)")
@@ -481,6 +520,12 @@ def main() -> int:
         d = result["differentiation"]
         log(f"differentiation workload: forward {d['forward_ms']:.3f} ms, adjoint {d['backward_ms']:.3f} ms, "
             f"adjoint at {d['backward_roofline']['frac']:.3f} of the FP32 peak")
+
+    if not args.no_rirgen:
+        result["rir_generation"] = rir_generation(torch, rsim, synth, dev, base)
+        d = result["rir_generation"]
+        log(f"image-method RIRs: {d['ms']:.3f} ms for one epoch's RIRs, {d['rirs_per_s']:.4g} RIRs/s, "
+            f"{d['roofline']['frac']:.3f} of the HBM peak")
 
     if args.large:
         del y, ws

@@ -16,9 +16,9 @@ Readings where the paper is silent:
   x = a Lx + xs for even a and a Lx + (Lx - xs) for odd a (likewise y, z),
   reached after g = |a| + |b| + |c| reflections.
 * Taps at or beyond the requested length are dropped.
-* Geometry: source and microphone at least 5 mm inside every wall and at
-  least 1 cm apart, so every image is at least 1 cm from the microphone;
-  0 <= r <= 1.
+* Geometry: sides below 10 km, source and microphone at least 5 mm inside
+  every wall and at least 1 cm apart, so every image is at least 1 cm from
+  the microphone; 0 <= r <= 1.
 * Arithmetic: binary64, no fused multiply-add, in this order:
   d = sqrt((dx dx + dy dy) + dz dz); n = ceil((d fs) / c0);
   r^g = r multiplied g times starting from 1; amplitude (r^g) / d.
@@ -60,8 +60,8 @@ def image_taps(room: Sequence[float], src: Sequence[float], mic: Sequence[float]
     d = np.sqrt(d2).reshape(-1)
     # source and microphone at least 5 mm inside every wall and 1 cm apart
     for ax in range(3):
-        if not (0.005 <= s[ax] <= L[ax] - 0.005 and 0.005 <= m[ax] <= L[ax] - 0.005):
-            raise ValueError("source and microphone must lie at least 5 mm inside the room")
+        if not (L[ax] < 1e4 and 0.005 <= s[ax] <= L[ax] - 0.005 and 0.005 <= m[ax] <= L[ax] - 0.005):
+            raise ValueError("sides below 10 km; source and microphone at least 5 mm inside the room")
     if ((s[0] - m[0]) * (s[0] - m[0]) + (s[1] - m[1]) * (s[1] - m[1])) + (s[2] - m[2]) * (s[2] - m[2]) < 1e-4:
         raise ValueError("source and microphone must be at least 1 cm apart")
     if not 0.0 <= float(refl) <= 1.0:

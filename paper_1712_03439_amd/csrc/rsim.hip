@@ -1312,16 +1312,23 @@ __global__ __launch_bounds__(256) void power_kernel(BatchDev b, const float* __r
 
 // ========================================================= image-method RIRs
 // Eq. (1): the RIR is the sum over the (2K+1)^3 images of the source in the
-// mirrored rooms (a, b, c) of refl^g / d at tap ceil(d fs / c0).  A work item
-// is one RIR and a window of kImgWindow taps: the workgroup evaluates every
-// image in binary64 (no contraction, so each product and sum is rounded on
-// its own, as the definition is written), quantises the amplitudes of the
-// images that fall in the window to multiples of 2^-40 and sums them exactly
-// with 64-bit integer atomics in LDS, so the result does not depend on the
-// order in which the images are added.
+// mirrored rooms (a, b, c) of refl^g / d at tap ceil(d fs / c0).  One
+// workgroup per RIR: every image is evaluated in binary64 (no contraction, so
+// each product and sum is rounded on its own, as the definition is written),
+// its amplitude quantised to a multiple of 2^-40 and added with a 64-bit
+// integer atomic to an LDS window of kImgWindow taps, so the sums are exact
+// and do not depend on the order of the images.  The taps are produced one
+// window at a time; a first pass sorts the images into per-window lists by a
+// float32 estimate of their distance (with margins far wider than its
+// rounding), so each window evaluates only its own images, with every lane
+// busy.  RIRs with more list entries than fit (orders above 10) take every
+// image in every window instead.
 constexpr int kImgThreads = 256;
-constexpr int kImgWindow = 4096;
+constexpr int kImgWindow = 2048;
 constexpr int kImgMaxOrder = 16;
+constexpr int kImgMaxWin = 16;     // windows per RIR: up to 32768 taps
+constexpr int kImgListOrder = 10;  // orders with per-window lists (5-bit indices)
+constexpr int kImgListMax = 10240;
 
 struct ImageArgs {
   const double* geom;  // [n_rir][9]: room Lx Ly Lz, source xyz, mic xyz
@@ -1330,7 +1337,7 @@ struct ImageArgs {
   long long h_len;
   const long long* off;
   const int* len;
-  int n_rir, order, nwin, max_len;
+  int n_rir, order, max_len;
   double fs, c0;
 };
 
@@ -1341,48 +1348,93 @@ __device__ __forceinline__ double image_delta(int a, double L, double s, double 
   return ((double)a * L + base) - m;
 }
 
-// Source and microphone at least 5 mm inside every wall and 1 cm apart,
-// refl in [0, 1]: every image is then at least 1 cm from the microphone.
+// Sides below 10 km, source and microphone at least 5 mm inside every wall
+// and 1 cm apart, refl in [0, 1] (NaN fails every test): every image is then
+// at least 1 cm from the microphone.
 __device__ __forceinline__ bool image_geometry_ok(const double* g, double refl) {
 #pragma clang fp contract(off)
   bool ok = refl >= 0.0 && refl <= 1.0;
   for (int ax = 0; ax < 3; ++ax) {
     const double L = g[ax], s = g[3 + ax], m = g[6 + ax];
-    ok = ok && s >= 0.005 && s <= L - 0.005 && m >= 0.005 && m <= L - 0.005;
+    ok = ok && L < 1e4 && s >= 0.005 && s <= L - 0.005 && m >= 0.005 && m <= L - 0.005;
   }
   const double dx = g[3] - g[6], dy = g[4] - g[7], dz = g[5] - g[8];
   return ok && ((dx * dx + dy * dy) + dz * dz) >= 1e-4;
 }
 
+// Windows [wlo, whi] an image with float32 squared-distance estimate d2f can
+// reach: its tap, ceil(d fs / c0), lies within two taps of the estimate.
+__device__ __forceinline__ void image_windows(float d2f, float taps_per_m, int nw, int& wlo, int& whi) {
+  const float nlo = sqrtf(d2f * 0.999f) * taps_per_m - 2.0f;
+  const float nhi = sqrtf(d2f * 1.001f) * taps_per_m + 2.0f;
+  const float end = (float)(nw * kImgWindow);
+  wlo = nlo <= 0.0f ? 0 : (nlo >= end ? nw : (int)(nlo * (1.0f / kImgWindow)));
+  whi = nhi >= end ? nw - 1 : (int)(nhi * (1.0f / kImgWindow));
+}
+
+// Adds image (ia, ib, ic) to window [w0, w0 + wn) if its tap falls there.
+__device__ __forceinline__ void image_add(const double (*sq)[2 * kImgMaxOrder + 1], const double* pw, int K,
+                                          int ia, int ib, int ic, double fs, double c0, int w0, int wn,
+                                          unsigned long long* acc) {
+#pragma clang fp contract(off)
+  const double d = sqrt((sq[0][ia] + sq[1][ib]) + sq[2][ic]);
+  const double n = ceil((d * fs) / c0);
+  if (n >= (double)w0 && n < (double)(w0 + wn)) {
+    const int g = abs(ia - K) + abs(ib - K) + abs(ic - K);
+    const double q = rint((pw[g] / d) * 1099511627776.0);  // 2^40
+    atomicAdd(&acc[(int)n - w0], (unsigned long long)q);
+  }
+}
+
+// Image v = (ia S + ib) S + ic, stepped by kImgThreads = (q2 S + q1) S + q0.
+struct ImageIter {
+  int ia, ib, ic;
+  __device__ __forceinline__ void step(int S, int q2, int q1, int q0) {
+    ic += q0;
+    const int cc = ic >= S;
+    ic -= cc ? S : 0;
+    ib += q1 + cc;
+    const int cb = ib >= S;
+    ib -= cb ? S : 0;
+    ia += q2 + cb;
+  }
+};
+
 __global__ __launch_bounds__(kImgThreads) void image_kernel(ImageArgs A) {
 #pragma clang fp contract(off)
   __shared__ unsigned long long acc[kImgWindow];
+  __shared__ unsigned short list[kImgListMax];  // (ia << 10) | (ib << 5) | ic
   __shared__ double sq[3][2 * kImgMaxOrder + 1];
+  __shared__ float sqf[3][2 * kImgMaxOrder + 1];
   __shared__ double pw[3 * kImgMaxOrder + 1];
-  const int t = threadIdx.x;
-  const int K = A.order, S = 2 * K + 1, V = S * S * S;
-  const long long items = (long long)A.n_rir * A.nwin;
+  __shared__ int s_cnt[kImgMaxWin], s_base[kImgMaxWin + 1], s_fill[kImgMaxWin];
+  const int t = threadIdx.x, lane = t & 63;
+  const unsigned long long below = (1ull << lane) - 1ull;
+  const int K = A.order, S = 2 * K + 1, S2 = S * S, V = S2 * S;
+  const int q2 = kImgThreads / S2, q1 = (kImgThreads % S2) / S, q0 = kImgThreads % S;
+  const ImageIter it0{t / S2, (t % S2) / S, t % S};
+  const float taps_per_m = (float)(A.fs / A.c0);
+  const bool can_list = K <= kImgListOrder;
   int err = 0;
-  for (long long it = blockIdx.x; it < items; it += gridDim.x) {
-    const int r = (int)(it / A.nwin), w = (int)(it - (long long)r * A.nwin);
+  for (int r = blockIdx.x; r < A.n_rir; r += gridDim.x) {
     const int len = uni(A.len[r]);
     const long long off = uni64(A.off[r]);
-    const int w0 = w * kImgWindow;
     if (len < 0 || len > A.max_len || off < 0 || off + len > A.h_len) {
-      if (w == 0) err |= RSIM_DEV_BADDESC;
+      err |= RSIM_DEV_BADDESC;
       continue;
     }
-    if (w0 >= len) continue;
-    const int wn = min(kImgWindow, len - w0);
+    if (len == 0) continue;
+    const int nw = (len + kImgWindow - 1) / kImgWindow;
     const double* g = A.geom + 9LL * r;
     const double refl = A.refl[r];
     const bool ok = image_geometry_ok(g, refl);
-    if (!ok && w == 0) err |= RSIM_DEV_BADDESC;
-    __syncthreads();  // the previous item's readers of sq, pw and acc are done
+    if (!ok) err |= RSIM_DEV_BADDESC;
+    __syncthreads();  // the previous RIR's readers of the shared arrays are done
     if (t < 3 * S) {
       const int ax = t / S, a = t - ax * S - K;
       const double d = image_delta(a, g[ax], g[3 + ax], g[6 + ax]);
       sq[ax][t - ax * S] = d * d;
+      sqf[ax][t - ax * S] = (float)(d * d);
     }
     if (t == 0) {
       double p = 1.0;
@@ -1391,23 +1443,73 @@ __global__ __launch_bounds__(kImgThreads) void image_kernel(ImageArgs A) {
         p = p * refl;
       }
     }
-    for (int k = t; k < wn; k += kImgThreads) acc[k] = 0ull;
+    if (t < kImgMaxWin) s_cnt[t] = 0;
     __syncthreads();
-    if (ok) {
+    // Pass 1: list entries per window (one LDS atomic per wave and window).
+    if (ok && can_list) {
+      ImageIter im = it0;
       for (int v = t; v < V; v += kImgThreads) {
-        const int ia = v / (S * S), ib = (v / S) % S, ic = v % S;
-        const double d = sqrt((sq[0][ia] + sq[1][ib]) + sq[2][ic]);
-        const double n = ceil((d * A.fs) / A.c0);
-        if (n >= (double)w0 && n < (double)(w0 + wn)) {
-          const int gg = abs(ia - K) + abs(ib - K) + abs(ic - K);
-          const double q = rint((pw[gg] / d) * 1099511627776.0);  // 2^40
-          atomicAdd(&acc[(int)n - w0], (unsigned long long)q);
+        int wlo, whi;
+        image_windows((sqf[0][im.ia] + sqf[1][im.ib]) + sqf[2][im.ic], taps_per_m, nw, wlo, whi);
+        for (int wi = 0; wi < nw; ++wi) {
+          const unsigned long long m = __ballot(wlo <= wi && wi <= whi);
+          if (m && lane == __ffsll((long long)m) - 1) atomicAdd(&s_cnt[wi], __popcll(m));
         }
+        im.step(S, q2, q1, q0);
       }
     }
     __syncthreads();
-    for (int k = t; k < wn; k += kImgThreads)
-      A.h[off + w0 + k] = (float)((double)acc[k] * 9.094947017729282e-13);  // 2^-40
+    if (t == 0) {
+      int o = 0;
+      for (int wi = 0; wi < nw; ++wi) {
+        s_base[wi] = o;
+        s_fill[wi] = o;
+        o += s_cnt[wi];
+      }
+      s_base[nw] = o;
+    }
+    __syncthreads();
+    const bool listed = can_list && s_base[nw] <= kImgListMax;
+    // Pass 2: the lists (same estimate, so the same windows).
+    if (ok && listed) {
+      ImageIter im = it0;
+      for (int v = t; v < V; v += kImgThreads) {
+        int wlo, whi;
+        image_windows((sqf[0][im.ia] + sqf[1][im.ib]) + sqf[2][im.ic], taps_per_m, nw, wlo, whi);
+        for (int wi = 0; wi < nw; ++wi) {
+          const bool in = wlo <= wi && wi <= whi;
+          const unsigned long long m = __ballot(in);
+          if (!m) continue;
+          const int leader = __ffsll((long long)m) - 1;
+          int e0 = 0;
+          if (lane == leader) e0 = atomicAdd(&s_fill[wi], __popcll(m));
+          const int e = __shfl(e0, leader) + __popcll(m & below);
+          if (in && e < s_base[wi + 1]) list[e] = (unsigned short)((im.ia << 10) | (im.ib << 5) | im.ic);
+        }
+        im.step(S, q2, q1, q0);
+      }
+    }
+    for (int wi = 0; wi < nw; ++wi) {
+      const int w0 = wi * kImgWindow, wn = min(kImgWindow, len - w0);
+      for (int k = t; k < wn; k += kImgThreads) acc[k] = 0ull;
+      __syncthreads();  // zeroed window and complete lists
+      if (ok && listed) {
+        for (int e = s_base[wi] + t; e < s_base[wi + 1]; e += kImgThreads) {
+          const unsigned c = list[e];
+          image_add(sq, pw, K, (int)(c >> 10), (int)((c >> 5) & 31), (int)(c & 31), A.fs, A.c0, w0, wn, acc);
+        }
+      } else if (ok) {
+        ImageIter im = it0;
+        for (int v = t; v < V; v += kImgThreads) {
+          image_add(sq, pw, K, im.ia, im.ib, im.ic, A.fs, A.c0, w0, wn, acc);
+          im.step(S, q2, q1, q0);
+        }
+      }
+      __syncthreads();
+      for (int k = t; k < wn; k += kImgThreads)
+        A.h[off + w0 + k] = (float)((double)acc[k] * 9.094947017729282e-13);  // 2^-40
+      __syncthreads();  // the window's readers are done before the next zeroing
+    }
   }
   if (err && t == 0) flag_status(err);
 }
@@ -2381,6 +2483,7 @@ rsim_status rsim_image_rir(const double* geom, const double* refl, int32_t n_rir
   if (n_rir < 0 || order < 0 || order > kImgMaxOrder || !(fs > 0.0) || !(c0 > 0.0) || max_len < 0 || h_len < 0 ||
       !std::isfinite(fs) || !std::isfinite(c0))
     return RSIM_EINVAL;
+  if (max_len > kImgMaxWin * kImgWindow) return RSIM_EUNSUPPORTED;
   if (n_rir == 0 || max_len == 0) return RSIM_OK;
   if (!geom || !refl || !h || !off || !len) return RSIM_EINVAL;
   const rsim_status e = ensure_init(stream);
@@ -2394,14 +2497,12 @@ rsim_status rsim_image_rir(const double* geom, const double* refl, int32_t n_rir
   A.len = len;
   A.n_rir = n_rir;
   A.order = order;
-  A.nwin = (max_len + kImgWindow - 1) / kImgWindow;
   A.max_len = max_len;
   A.fs = fs;
   A.c0 = c0;
   const DevState& st = dev_state();
   const int cus = st.cus > 0 ? st.cus : 256;
-  const long long items = (long long)n_rir * A.nwin;
-  const unsigned grid = (unsigned)std::min<long long>(items, (long long)cus * 8);
+  const unsigned grid = (unsigned)std::min<long long>(n_rir, (long long)cus * 8);
   hipLaunchKernelGGL(image_kernel, dim3(grid), dim3(kImgThreads), 0, stream, A);
   return hipGetLastError() == hipSuccess ? RSIM_OK : RSIM_EDEVICE;
 }

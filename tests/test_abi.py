@@ -209,4 +209,5 @@ def test_image_rir_validation_codes():
                 dict(c0=-343.0), dict(c0=math.inf), dict(max_len=-1), dict(h_len=-5)):
         assert call(**bad) == rsim.RSIM_EINVAL, bad
     assert call(n=0) == rsim.RSIM_OK and call(max_len=0) == rsim.RSIM_OK
+    assert call(max_len=32769) == rsim.RSIM_EUNSUPPORTED
     assert lib.rsim_image_rir(None, p, 4, 8, 16000.0, 343.0, p, 1000, p, p, 100, None) == rsim.RSIM_EINVAL
