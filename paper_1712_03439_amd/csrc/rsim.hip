@@ -1402,19 +1402,23 @@ struct ImageIter {
 
 __global__ __launch_bounds__(kImgThreads) void image_kernel(ImageArgs A) {
 #pragma clang fp contract(off)
+  // acc holds a window's tap sums; before the windows it holds the list
+  // counters cnt[wi * kImgThreads + t] (thread t's images in window wi).
   __shared__ unsigned long long acc[kImgWindow];
   __shared__ unsigned short list[kImgListMax];  // (ia << 10) | (ib << 5) | ic
   __shared__ double sq[3][2 * kImgMaxOrder + 1];
   __shared__ float sqf[3][2 * kImgMaxOrder + 1];
   __shared__ double pw[3 * kImgMaxOrder + 1];
-  __shared__ int s_cnt[kImgMaxWin], s_base[kImgMaxWin + 1], s_fill[kImgMaxWin];
-  const int t = threadIdx.x, lane = t & 63;
-  const unsigned long long below = (1ull << lane) - 1ull;
+  __shared__ int s_base[kImgMaxWin + 1], s_wsum[kImgThreads / 64];
+  static_assert(kImgMaxWin * kImgThreads * sizeof(unsigned short) <= sizeof(acc), "counters fit in acc");
+  unsigned short* cnt = reinterpret_cast<unsigned short*>(acc);
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int K = A.order, S = 2 * K + 1, S2 = S * S, V = S2 * S;
   const int q2 = kImgThreads / S2, q1 = (kImgThreads % S2) / S, q0 = kImgThreads % S;
   const ImageIter it0{t / S2, (t % S2) / S, t % S};
   const float taps_per_m = (float)(A.fs / A.c0);
   const bool can_list = K <= kImgListOrder;
+  constexpr int kPer = kImgMaxWin * kImgThreads / kImgThreads;  // counters scanned per thread
   int err = 0;
   for (int r = blockIdx.x; r < A.n_rir; r += gridDim.x) {
     const int len = uni(A.len[r]);
@@ -1429,6 +1433,7 @@ __global__ __launch_bounds__(kImgThreads) void image_kernel(ImageArgs A) {
     const double refl = A.refl[r];
     const bool ok = image_geometry_ok(g, refl);
     if (!ok) err |= RSIM_DEV_BADDESC;
+    const bool listing = ok && can_list;
     __syncthreads();  // the previous RIR's readers of the shared arrays are done
     if (t < 3 * S) {
       const int ax = t / S, a = t - ax * S - K;
@@ -1443,57 +1448,66 @@ __global__ __launch_bounds__(kImgThreads) void image_kernel(ImageArgs A) {
         p = p * refl;
       }
     }
-    if (t < kImgMaxWin) s_cnt[t] = 0;
+    if (listing)
+      for (int wi = 0; wi < kImgMaxWin; ++wi) cnt[wi * kImgThreads + t] = 0;
     __syncthreads();
-    // Pass 1: list entries per window (one LDS atomic per wave and window).
-    if (ok && can_list) {
+    bool listed = false;
+    if (listing) {
+      // Pass 1: each thread counts its images per window in its own counters.
       ImageIter im = it0;
       for (int v = t; v < V; v += kImgThreads) {
         int wlo, whi;
         image_windows((sqf[0][im.ia] + sqf[1][im.ib]) + sqf[2][im.ic], taps_per_m, nw, wlo, whi);
-        for (int wi = 0; wi < nw; ++wi) {
-          const unsigned long long m = __ballot(wlo <= wi && wi <= whi);
-          if (m && lane == __ffsll((long long)m) - 1) atomicAdd(&s_cnt[wi], __popcll(m));
-        }
+        for (int wi = wlo; wi <= whi; ++wi) cnt[wi * kImgThreads + t] += 1;
         im.step(S, q2, q1, q0);
       }
-    }
-    __syncthreads();
-    if (t == 0) {
-      int o = 0;
-      for (int wi = 0; wi < nw; ++wi) {
-        s_base[wi] = o;
-        s_fill[wi] = o;
-        o += s_cnt[wi];
+      __syncthreads();
+      // Exclusive scan of the counters in (window, thread) order: thread t
+      // takes kPer consecutive counters, the threads' sums are scanned
+      // within each wave and across the waves.
+      int part = 0;
+      for (int k = 0; k < kPer; ++k) part += cnt[t * kPer + k];
+      int x = part;
+      for (int d = 1; d < 64; d <<= 1) {
+        const int y = __shfl_up(x, d);
+        if (lane >= d) x += y;
       }
-      s_base[nw] = o;
-    }
-    __syncthreads();
-    const bool listed = can_list && s_base[nw] <= kImgListMax;
-    // Pass 2: the lists (same estimate, so the same windows).
-    if (ok && listed) {
-      ImageIter im = it0;
-      for (int v = t; v < V; v += kImgThreads) {
-        int wlo, whi;
-        image_windows((sqf[0][im.ia] + sqf[1][im.ib]) + sqf[2][im.ic], taps_per_m, nw, wlo, whi);
-        for (int wi = 0; wi < nw; ++wi) {
-          const bool in = wlo <= wi && wi <= whi;
-          const unsigned long long m = __ballot(in);
-          if (!m) continue;
-          const int leader = __ffsll((long long)m) - 1;
-          int e0 = 0;
-          if (lane == leader) e0 = atomicAdd(&s_fill[wi], __popcll(m));
-          const int e = __shfl(e0, leader) + __popcll(m & below);
-          if (in && e < s_base[wi + 1]) list[e] = (unsigned short)((im.ia << 10) | (im.ib << 5) | im.ic);
+      if (lane == 63) s_wsum[wave] = x;
+      __syncthreads();
+      int before = x - part;
+      for (int w = 0; w < wave; ++w) before += s_wsum[w];
+      const int total = s_wsum[0] + s_wsum[1] + s_wsum[2] + s_wsum[3];
+      for (int k = 0; k < kPer; ++k) {
+        const int c = cnt[t * kPer + k];
+        cnt[t * kPer + k] = (unsigned short)(total <= kImgListMax ? before : 0);
+        before += c;
+      }
+      __syncthreads();
+      if (t <= nw) s_base[t] = t < nw ? (int)cnt[t * kImgThreads] : total;
+      listed = total <= kImgListMax;
+      __syncthreads();  // window starts read before pass 2 advances the counters
+      // Pass 2: each thread writes its images at its own positions (same
+      // estimate as pass 1, so the same windows).
+      if (listed) {
+        ImageIter jm = it0;
+        for (int v = t; v < V; v += kImgThreads) {
+          int wlo, whi;
+          image_windows((sqf[0][jm.ia] + sqf[1][jm.ib]) + sqf[2][jm.ic], taps_per_m, nw, wlo, whi);
+          for (int wi = wlo; wi <= whi; ++wi) {
+            const int e = cnt[wi * kImgThreads + t];
+            cnt[wi * kImgThreads + t] = (unsigned short)(e + 1);
+            list[e] = (unsigned short)((jm.ia << 10) | (jm.ib << 5) | jm.ic);
+          }
+          jm.step(S, q2, q1, q0);
         }
-        im.step(S, q2, q1, q0);
       }
     }
     for (int wi = 0; wi < nw; ++wi) {
       const int w0 = wi * kImgWindow, wn = min(kImgWindow, len - w0);
+      __syncthreads();  // lists complete; the counters (or the previous window) no longer read
       for (int k = t; k < wn; k += kImgThreads) acc[k] = 0ull;
-      __syncthreads();  // zeroed window and complete lists
-      if (ok && listed) {
+      __syncthreads();
+      if (listed) {
         for (int e = s_base[wi] + t; e < s_base[wi + 1]; e += kImgThreads) {
           const unsigned c = list[e];
           image_add(sq, pw, K, (int)(c >> 10), (int)((c >> 5) & 31), (int)(c & 31), A.fs, A.c0, w0, wn, acc);
@@ -1508,7 +1522,6 @@ __global__ __launch_bounds__(kImgThreads) void image_kernel(ImageArgs A) {
       __syncthreads();
       for (int k = t; k < wn; k += kImgThreads)
         A.h[off + w0 + k] = (float)((double)acc[k] * 9.094947017729282e-13);  // 2^-40
-      __syncthreads();  // the window's readers are done before the next zeroing
     }
   }
   if (err && t == 0) flag_status(err);
