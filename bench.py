@@ -184,10 +184,11 @@ def differentiation(torch, rsim, synth, dev, reps: int = 10):
                              "unit": "GB/s", "frac": round(byts / (t_b * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}}
 
 
-def rir_generation(torch, rsim, synth, dev, base, reps: int = 5, order: int = 8):
+def rir_generation(torch, rsim, synth, dev, base, db, alpha, y, ws, tune, eta, reps: int = 5, order: int = 8):
     """The image-method RIRs (eq. 1, 17^3 virtual rooms) of every RIR slot of
     the batched workload's epoch (its lengths ceil(T60 fs)), generated on the
-    GPU into a packed buffer: one untimed call, then `reps` timed ones."""
+    GPU into a packed buffer: one untimed call, then `reps` timed ones; and
+    whole epochs with those rooms (generation, cut and mix as one graph)."""
     geom, refl = synth.image_geometry(base)
     used = np.nonzero(base.rir_len0 > 0)[0]
     lens = base.rir_len0[used].astype(np.int32)
@@ -214,12 +215,33 @@ def rir_generation(torch, rsim, synth, dev, base, reps: int = 5, order: int = 8)
     taps = int(lens.astype(np.int64).sum())
     images = len(lens) * (2 * order + 1) ** 3
     gbs = 4.0 * taps / (ms * 1e-3) / 1e9
+    # whole epochs: rooms -> RIRs -> cut -> mix, one graph per epoch
+    gall, rall = torch.from_numpy(geom).to(dev), torch.from_numpy(refl).to(dev)
+    h_saved = db.h
+    db.h = h
+    with torch.cuda.stream(stream):
+        rsim.simulate_rooms(db, gall, rall, alpha, eta, order=order, y=y, ws=ws, tune=tune, use_graph=True,
+                            stream=stream)
+        e2, e3 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e2.record(stream)
+        for _ in range(reps):
+            rsim.simulate_rooms(db, gall, rall, alpha, eta, order=order, y=y, ws=ws, tune=tune, use_graph=True,
+                                stream=stream)
+        e3.record(stream)
+    torch.cuda.synchronize()
+    db.h = h_saved
+    if rsim.device_status():
+        raise RuntimeError("an image-method epoch flagged a bad descriptor")
+    ms_epoch = e2.elapsed_time(e3) / reps
     return {"workload": f"{len(lens)} RIRs of the batched epoch ({taps} taps, lengths ceil(T60 fs)), "
                         f"{(2 * order + 1) ** 3} images each",
             "ms": round(ms, 4), "rirs_per_s": round(len(lens) / (ms * 1e-3), 1),
             "images_per_s": round(images / (ms * 1e-3), 1),
             "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": round(gbs / HBM_PEAK_GBS, 4)}}
+                         "frac": round(gbs / HBM_PEAK_GBS, 4)},
+            "epoch_with_rooms": {"ms": round(ms_epoch, 4),
+                                 "audio_s_per_s": round(base.audio_seconds / (ms_epoch * 1e-3), 1),
+                                 "steps": "image-method RIRs, cut, mix as one graph"}}
 
 
 def large_thresholds(torch, rsim, autotune, synth, dev, etas=(math.inf, 30.0, 20.0, 10.0), reps: int = 3):
@@ -522,10 +544,12 @@ def main() -> int:
             f"adjoint at {d['backward_roofline']['frac']:.3f} of the FP32 peak")
 
     if not args.no_rirgen:
-        result["rir_generation"] = rir_generation(torch, rsim, synth, dev, base)
+        _, db0, alpha0 = epochs[0]
+        result["rir_generation"] = rir_generation(torch, rsim, synth, dev, base, db0, alpha0, y, ws, tune, args.eta)
         d = result["rir_generation"]
         log(f"image-method RIRs: {d['ms']:.3f} ms for one epoch's RIRs, {d['rirs_per_s']:.4g} RIRs/s, "
-            f"{d['roofline']['frac']:.3f} of the HBM peak")
+            f"{d['roofline']['frac']:.3f} of the HBM peak; epochs with image-method rooms "
+            f"{d['epoch_with_rooms']['ms']:.3f} ms ({d['epoch_with_rooms']['audio_s_per_s']:.4g} audio-s/s)")
 
     if args.large:
         del y, ws

@@ -239,6 +239,20 @@ rsim_status rsim_image_rir(const double* geom, const double* refl, int32_t n_rir
                            double c0, float* h, int64_t h_len, const int64_t* off, const int32_t* len,
                            int32_t max_len, hipStream_t stream);
 
+/*
+ * One epoch with image-method rooms: rsim_image_rir into every RIR slot of
+ * the batch (slot r = (u*S + i)*J + j reads geom[9r ..] and refl[r] and
+ * writes h[rir_off[r] .. + rir_len0[r]); slots of length 0 are skipped, and
+ * max_rir_len0 sizes the launch), then the cut and the mix of rsim_simulate
+ * on those RIRs.  With use_graph != 0 the three steps form one HIP graph (a
+ * chain).  Validation as rsim_simulate and rsim_image_rir (max_rir_len0 <=
+ * 32768).
+ */
+rsim_status rsim_simulate_rooms(const rsim_batch* b, const float* x, float* h, const double* geom,
+                                const double* refl, int32_t order, double fs, double c0, const float* alpha,
+                                double eta_db, int32_t* rir_len_out, float* y, void* ws, size_t ws_bytes,
+                                const rsim_tune* tune, int32_t use_graph, hipStream_t stream);
+
 /* Read and clear the device status word (synchronises the device). */
 rsim_status rsim_device_status(int32_t* status);
 

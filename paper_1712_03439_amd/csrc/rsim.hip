@@ -1970,6 +1970,8 @@ struct Node {
 };
 
 struct CallPlan {
+  bool has_gen = false;  // image-method RIRs before the cut
+  Node gen;
   bool has_cut = false;
   Node cut, prep, sched;
   Node fam[kNumFam + 1];  // the family kernels (and, for the adjoint, the zero fill)
@@ -1992,6 +1994,8 @@ bool capturing(hipStream_t s) {
 // being captured by the caller they run one after the other on s.
 rsim_status issue_eager(CallPlan& P, hipStream_t s) {
   const DevState& st = dev_state();
+  if (P.has_gen && hipLaunchKernel(P.gen.fn, P.gen.grid, P.gen.block, P.gen.p(), 0, s) != hipSuccess)
+    return RSIM_EDEVICE;
   if (P.has_cut && hipLaunchKernel(P.cut.fn, P.cut.grid, P.cut.block, P.cut.p(), 0, s) != hipSuccess)
     return RSIM_EDEVICE;
   if (hipLaunchKernel(P.prep.fn, P.prep.grid, P.prep.block, P.prep.p(), 0, s) != hipSuccess)
@@ -2086,7 +2090,12 @@ rsim_status issue_graph(CallPlan& P, hipStream_t s) {
   // kernels remain available on the eager path).
   hipGraphNode_t prev = nullptr;
   bool ok = true;
-  if (P.has_cut) ok = add(P.cut, nullptr, 0, &prev);
+  if (P.has_gen) ok = add(P.gen, nullptr, 0, &prev);
+  if (ok && P.has_cut) {
+    hipGraphNode_t cn = nullptr;
+    ok = add(P.cut, prev ? &prev : nullptr, prev ? 1 : 0, &cn);
+    prev = cn;
+  }
   hipGraphNode_t node = nullptr;
   ok = ok && add(P.prep, prev ? &prev : nullptr, prev ? 1 : 0, &node);
   prev = node;
@@ -2283,6 +2292,35 @@ int ilog2_exact(int n) {
   int l = 0;
   while ((1 << l) < n) ++l;
   return l;
+}
+
+rsim_status image_args_ok(int n_rir, int order, double fs, double c0, int max_len, long long h_len) {
+  if (n_rir < 0 || order < 0 || order > kImgMaxOrder || !(fs > 0.0) || !(c0 > 0.0) || max_len < 0 || h_len < 0 ||
+      !std::isfinite(fs) || !std::isfinite(c0))
+    return RSIM_EINVAL;
+  if (max_len > kImgMaxWin * kImgWindow) return RSIM_EUNSUPPORTED;
+  return RSIM_OK;
+}
+
+// One workgroup per RIR, at most 8 per compute unit.
+void plan_image(Node& n, const double* geom, const double* refl, int n_rir, int order, double fs, double c0, float* h,
+                long long h_len, const int64_t* off, const int32_t* len, int max_len) {
+  ImageArgs A;
+  A.geom = geom;
+  A.refl = refl;
+  A.h = h;
+  A.h_len = h_len;
+  A.off = reinterpret_cast<const long long*>(off);
+  A.len = len;
+  A.n_rir = n_rir;
+  A.order = order;
+  A.max_len = max_len;
+  A.fs = fs;
+  A.c0 = c0;
+  const DevState& st = dev_state();
+  const int cus = st.cus > 0 ? st.cus : 256;
+  n.set(reinterpret_cast<const void*>(&image_kernel),
+        dim3((unsigned)std::max<long long>(1, std::min<long long>(n_rir, (long long)cus * 8))), dim3(kImgThreads), A);
 }
 
 }  // namespace
@@ -2493,31 +2531,47 @@ rsim_status rsim_device_status(int32_t* status) {
 rsim_status rsim_image_rir(const double* geom, const double* refl, int32_t n_rir, int32_t order, double fs,
                            double c0, float* h, int64_t h_len, const int64_t* off, const int32_t* len,
                            int32_t max_len, hipStream_t stream) {
-  if (n_rir < 0 || order < 0 || order > kImgMaxOrder || !(fs > 0.0) || !(c0 > 0.0) || max_len < 0 || h_len < 0 ||
-      !std::isfinite(fs) || !std::isfinite(c0))
-    return RSIM_EINVAL;
-  if (max_len > kImgMaxWin * kImgWindow) return RSIM_EUNSUPPORTED;
+  const rsim_status v = image_args_ok(n_rir, order, fs, c0, max_len, h_len);
+  if (v != RSIM_OK) return v;
   if (n_rir == 0 || max_len == 0) return RSIM_OK;
   if (!geom || !refl || !h || !off || !len) return RSIM_EINVAL;
   const rsim_status e = ensure_init(stream);
   if (e != RSIM_OK) return e;
-  ImageArgs A;
-  A.geom = geom;
-  A.refl = refl;
-  A.h = h;
-  A.h_len = h_len;
-  A.off = reinterpret_cast<const long long*>(off);
-  A.len = len;
-  A.n_rir = n_rir;
-  A.order = order;
-  A.max_len = max_len;
-  A.fs = fs;
-  A.c0 = c0;
-  const DevState& st = dev_state();
-  const int cus = st.cus > 0 ? st.cus : 256;
-  const unsigned grid = (unsigned)std::min<long long>(n_rir, (long long)cus * 8);
-  hipLaunchKernelGGL(image_kernel, dim3(grid), dim3(kImgThreads), 0, stream, A);
-  return hipGetLastError() == hipSuccess ? RSIM_OK : RSIM_EDEVICE;
+  Node n;
+  plan_image(n, geom, refl, n_rir, order, fs, c0, h, h_len, off, len, max_len);
+  if (hipLaunchKernel(n.fn, n.grid, n.block, n.p(), 0, stream) != hipSuccess) return clear_error(RSIM_EDEVICE);
+  return RSIM_OK;
+}
+
+rsim_status rsim_simulate_rooms(const rsim_batch* b, const float* x, float* h, const double* geom,
+                                const double* refl, int32_t order, double fs, double c0, const float* alpha,
+                                double eta_db, int32_t* rir_len_out, float* y, void* ws, size_t ws_bytes,
+                                const rsim_tune* tune, int32_t use_graph, hipStream_t stream) {
+  if (!b || !eta_ok(eta_db) || !rir_len_out || !tune_ok(tune)) return RSIM_EINVAL;
+  rsim_batch bb = *b;
+  bb.rir_len = rir_len_out;
+  if (!batch_ok(&bb)) return RSIM_EINVAL;
+  const long long n_rir = (long long)bb.n_utt * bb.max_src * bb.n_mic;
+  if (n_rir > 0x7fffffffLL) return RSIM_EINVAL;
+  const rsim_status v = image_args_ok((int)n_rir, order, fs, c0, bb.max_rir_len0, bb.h_len);
+  if (v != RSIM_OK) return v;
+  if (bb.n_utt == 0) return RSIM_OK;
+  if (!x || !h || !geom || !refl || !alpha || !y) return RSIM_EINVAL;
+  const rsim_status e = ensure_init(stream);
+  const TuneDev td = to_dev(tune);
+  const WsLayout L = layout(&bb, td, false, dev_state());
+  if (!ws || ws_bytes < L.total) return RSIM_EWORKSPACE;
+  if (e != RSIM_OK) return e;
+  const BatchDev bd = to_dev(&bb);
+  CallPlan P;
+  P.has_gen = bb.max_rir_len0 > 0;
+  if (P.has_gen)
+    plan_image(P.gen, geom, refl, (int)n_rir, order, fs, c0, h, bb.h_len, bb.rir_off, bb.rir_len0,
+               bb.max_rir_len0);
+  P.has_cut = true;
+  plan_truncate(P.cut, h, bb.h_len, bb.rir_off, bb.rir_len0, (int)n_rir, cut_scale(eta_db), nullptr, rir_len_out);
+  plan_mix(P, &bb, bd, td, x, h, alpha, y, ws);
+  return issue(P, stream, use_graph);
 }
 
 rsim_status rsim_rfft(const float* x, int32_t n, int32_t count, float* spec, hipStream_t stream) {

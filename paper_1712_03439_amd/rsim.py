@@ -24,7 +24,7 @@ EXPORTS = (
     "rsim_init", "rsim_strerror", "rsim_version", "rsim_truncate_rir",
     "rsim_ola_workspace_bytes", "rsim_ola_convolve", "rsim_mix_workspace_bytes", "rsim_mix",
     "rsim_simulate", "rsim_mix_backward", "rsim_source_power", "rsim_snr_gains",
-    "rsim_device_status", "rsim_rfft", "rsim_irfft", "rsim_image_rir",
+    "rsim_device_status", "rsim_rfft", "rsim_irfft", "rsim_image_rir", "rsim_simulate_rooms",
 )
 
 
@@ -80,6 +80,8 @@ def _lib():
             "rsim_rfft": ([vp, i32, i32, vp, vp], i32),
             "rsim_irfft": ([vp, i32, i32, vp, vp], i32),
             "rsim_image_rir": ([vp, vp, i32, i32, f64, f64, vp, i64, vp, vp, i32, vp], i32),
+            "rsim_simulate_rooms": ([bp, vp, vp, vp, vp, i32, f64, f64, vp, f64, vp, vp, vp, sz, tp, i32, vp],
+                                    i32),
         }
         for name, (args, res) in sig.items():
             fn = getattr(lib, name)
@@ -198,6 +200,26 @@ def image_rir(geom, refl, off, length, h, max_len: int, order: int = 8, fs: floa
                                  int(h.numel()), _ptr(off), _ptr(length), int(max_len), _stream(stream)),
            "rsim_image_rir")
     return h
+
+
+def simulate_rooms(db: DeviceBatch, geom, refl, alpha, eta_db: float, order: int = 8, fs: float = 16000.0,
+                   c0: float = 343.0, y=None, ws=None, tune: Optional[RsimTune] = None, use_graph: bool = False,
+                   stream=None):
+    """Image-method RIRs (eq. 1) into db.h for every RIR slot (geom float64
+    [U*S*J, 9], refl float64 [U*S*J] on the GPU), then cut + mix, as one call
+    (one graph with use_graph)."""
+    _require_cuda(geom, refl, alpha)
+    if y is None:
+        y = db.new_output()
+    if ws is None:
+        ws = db.workspace(tune)
+    s = db.struct()
+    _check(_lib().rsim_simulate_rooms(ctypes.byref(s), _ptr(db.x), _ptr(db.h), _ptr(geom), _ptr(refl), int(order),
+                                      float(fs), float(c0), _ptr(alpha), float(eta_db), _ptr(db.rir_len), _ptr(y),
+                                      _ptr(ws), int(ws.numel()), ctypes.byref(tune) if tune else None,
+                                      int(bool(use_graph)), _stream(stream)),
+           "rsim_simulate_rooms")
+    return y
 
 
 def snr_gains(p_dry: Sequence[float], snr_db: Sequence[float], n_mic: int) -> np.ndarray:

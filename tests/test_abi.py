@@ -211,3 +211,22 @@ def test_image_rir_validation_codes():
     assert call(n=0) == rsim.RSIM_OK and call(max_len=0) == rsim.RSIM_OK
     assert call(max_len=32769) == rsim.RSIM_EUNSUPPORTED
     assert lib.rsim_image_rir(None, p, 4, 8, 16000.0, 343.0, p, 1000, p, p, 100, None) == rsim.RSIM_EINVAL
+
+
+def test_simulate_rooms_validation_codes():
+    lib = rsim.lib()
+    p = ctypes.c_void_p(8)
+    b = _host_batch()
+    need = lib.rsim_mix_workspace_bytes(ctypes.byref(b), None, 0)
+
+    def call(bb=b, order=8, fs=16000.0, c0=343.0, eta=20.0, x=p, ws_bytes=need):
+        return lib.rsim_simulate_rooms(ctypes.byref(bb) if bb is not None else None, x, p, p, p, order, fs, c0,
+                                       p, eta, p, p, p, ws_bytes, None, 0, None)
+
+    assert call(bb=None) == rsim.RSIM_EINVAL
+    assert call(order=17) == rsim.RSIM_EINVAL and call(fs=-1.0) == rsim.RSIM_EINVAL
+    assert call(eta=-1.0) == rsim.RSIM_EINVAL and call(x=None) == rsim.RSIM_EINVAL
+    assert call(ws_bytes=need - 1) == rsim.RSIM_EWORKSPACE
+    long = _host_batch()
+    long.max_rir_len0 = 40000
+    assert call(bb=long) == rsim.RSIM_EUNSUPPORTED

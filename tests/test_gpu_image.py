@@ -130,3 +130,38 @@ def test_image_rirs_through_the_simulator():
         off, st = int(b.out_off[u]), int(b.out_stride[u])
         for j in range(J):
             assert max_rel_err(y[off + j * st: off + j * st + T], ref[j]) <= TOL, (u, j)
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("graph", [False, True])
+def test_rooms_epoch_matches_separate_calls(graph):
+    # generation + cut + mix in one call (one graph) gives the bits of the
+    # separate calls
+    torch = cuda()
+    from paper_1712_03439_amd import rsim
+
+    b = synth.make_config2(n_utt=40, epoch=6)
+    geom, refl = synth.image_geometry(b, seed_epoch=2)
+    g = torch.from_numpy(geom).cuda()
+    r = torch.from_numpy(refl).cuda()
+    db1 = rsim.DeviceBatch(b)
+    alpha = torch.from_numpy(rsim.batch_gains(db1, b.snr_db)).cuda()
+    used = torch.from_numpy(np.nonzero(b.rir_len0 > 0)[0]).cuda()
+    rsim.image_rir(g[used].contiguous(), r[used].contiguous(), db1.rir_off[used].contiguous(),
+                   db1.rir_len0[used].contiguous(), db1.h, int(b.rir_len0.max()))
+    y1 = rsim.simulate(db1, alpha, 20.0)
+    db2 = rsim.DeviceBatch(b)
+    db2.h.zero_()
+    stream = torch.cuda.Stream()
+    stream.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(stream):
+        y2 = rsim.simulate_rooms(db2, g, r, alpha, 20.0, use_graph=graph, stream=stream)
+    torch.cuda.synchronize()
+    assert torch.equal(db1.h, db2.h)
+    assert torch.equal(db1.rir_len, db2.rir_len) and torch.equal(db1.out_len, db2.out_len)
+    y1, y2 = y1.cpu().numpy(), y2.cpu().numpy()
+    ol = db1.out_len.cpu().numpy()
+    for u in range(b.n_utt):
+        off, st, T = int(b.out_off[u]), int(b.out_stride[u]), int(ol[u])
+        for j in range(b.n_mic):
+            assert np.array_equal(y1[off + j * st: off + j * st + T], y2[off + j * st: off + j * st + T]), (u, j)
