@@ -15,5 +15,7 @@ from .rsim_oracle import (  # noqa: F401
     mix_backward,
     mix_backward_at,
     out_length,
+    reverb_energy,
+    snr_gains_reverb,
     simulate,
 )

@@ -19,6 +19,9 @@ What it computes, with the passage each function follows:
                   up to rounding, so the oracle is the definition itself.
 * mix, mix_at  -- eq. (2): y_j[n] = sum_i alpha_ij (h_ij * x_i)[n].
 * mix_backward -- the adjoint of eq. (2) with respect to x, h and alpha.
+* reverb_energy,
+  snr_gains_reverb -- the other reading of eq. (2)'s per-(i, j) gains: the
+                  SNR measured at each mic on the reverberant signals.
 
 Precision rule for the cut (float32, round to nearest even, no flush of
 subnormals): q[n] = fl32(h[n]^2); P = max q; s = fl32(10^(-eta/10)) computed in
@@ -99,6 +102,36 @@ def snr_gains(p_dry: Sequence[float], snr_db: Sequence[float], n_mic: int) -> np
     for i in range(1, I):
         pi = float(p_dry[i])
         a[i, :] = 0.0 if pi <= 0.0 else math.sqrt(p0 / (pi * 10.0 ** (float(snr_db[i]) / 10.0)))
+    return a
+
+
+def reverb_energy(x: np.ndarray, h: np.ndarray) -> float:
+    """Energy of a reverberant source at a mic, E = sum_n ((h * x)[n])^2, in
+    FP64 from the direct convolution (h is the cut RIR)."""
+    c = convolve(x, h)
+    return float(np.dot(c, c))
+
+
+def snr_gains_reverb(energy: np.ndarray, snr_db: Sequence[float]) -> np.ndarray:
+    """alpha [I, J] of eq. (2) under the reverberant-at-mic SNR rule.
+
+    The paper names alpha_ij per source and mic but gives no rule; this is
+    the rule that measures the SNR at each mic on the reverberant signals:
+    alpha_0j = 1 and, for a noise source i >= 1 with energy E_ij = ||h_ij * x_i||^2
+    at mic j and requested SNR s_i dB, alpha_ij = sqrt(E_0j / (E_ij 10^(s_i/10))),
+    so that 10 log10(E_0j / (alpha_ij^2 E_ij)) = s_i at every mic.  A silent
+    noise (E_ij = 0) or a silent target at that mic (E_0j = 0) gives 0.
+    """
+    E = np.asarray(energy, np.float64)
+    I, J = E.shape if E.size else (0, 0)
+    a = np.zeros((I, J), np.float64)
+    if I == 0:
+        return a
+    a[0, :] = 1.0
+    for i in range(1, I):
+        for j in range(J):
+            e0, ei = float(E[0, j]), float(E[i, j])
+            a[i, j] = 0.0 if ei <= 0.0 or e0 <= 0.0 else math.sqrt(e0 / (ei * 10.0 ** (float(snr_db[i]) / 10.0)))
     return a
 
 

@@ -355,3 +355,48 @@ def test_sampled_adjoint_agrees_with_central_differences():
     assert abs(fd - da) <= 1e-6 * max(1.0, abs(fd))
     # a tap index beyond the RIR has no gradient
     assert O.mix_backward_at(xs, hs, a, g, 1, 2, [], [len(hs[1][2]) + 3])[1][0] == 0.0
+
+
+# --------------------------------------------------- reverberant-at-mic gains
+def test_reverb_energy_of_a_scaled_delay():
+    # h = a delta[n - d]: (h * x)[n] = a x[n - d], so E = a^2 sum x^2
+    rng = np.random.default_rng(31)
+    x = rng.standard_normal(3000).astype(np.float32)
+    h = np.zeros(700, np.float32)
+    h[321] = np.float32(0.375)
+    e = oracle.reverb_energy(x, h)
+    ref = 0.375 ** 2 * float(np.sum(x.astype(np.float64) ** 2))
+    assert abs(e - ref) <= 1e-12 * ref
+
+
+def test_reverb_energy_by_parseval_and_by_autocorrelation():
+    # Parseval on a transform long enough for the whole convolution, and the
+    # identity E = sum_l r_hh[l] r_xx[l] with both autocorrelations from
+    # numpy.correlate: three routes to the same number
+    rng = np.random.default_rng(32)
+    for nx, L in ((1, 1), (50, 7), (4000, 900), (2500, 2600)):
+        x = rng.standard_normal(nx)
+        h = rng.standard_normal(L) * np.exp(-np.arange(L) / (L / 3 + 1))
+        e = oracle.reverb_energy(x, h)
+        n = 1 << int(np.ceil(np.log2(nx + L - 1)))
+        pars = float(np.sum(np.abs(np.fft.fft(x, n) * np.fft.fft(h, n)) ** 2) / n)
+        rxx = np.correlate(x, x, "full")[nx - 1:]
+        rhh = np.correlate(h, h, "full")[L - 1:]
+        m = min(L, nx)
+        auto = float(rhh[0] * rxx[0] + 2.0 * np.dot(rhh[1:m], rxx[1:m]))
+        assert abs(pars - e) <= 1e-9 * e and abs(auto - e) <= 1e-9 * e
+
+
+def test_reverb_gains_give_the_snr_at_every_mic():
+    rng = np.random.default_rng(33)
+    E = rng.uniform(0.1, 50.0, (4, 3))
+    snr = [0.0, 3.5, 12.0, 27.25]
+    a = oracle.snr_gains_reverb(E, snr)
+    assert np.all(a[0] == 1.0)
+    for i in range(1, 4):
+        for j in range(3):
+            assert abs(10 * math.log10(E[0, j] / (a[i, j] ** 2 * E[i, j])) - snr[i]) <= 1e-9
+    E[2, 1] = 0.0
+    E[0, 2] = 0.0
+    a = oracle.snr_gains_reverb(E, snr)
+    assert a[2, 1] == 0.0 and np.all(a[1:, 2] == 0.0)
