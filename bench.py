@@ -244,6 +244,49 @@ def rir_generation(torch, rsim, synth, dev, base, db, alpha, y, ws, tune, eta, r
                                  "steps": "image-method RIRs, cut, mix as one graph"}}
 
 
+def reverb_gains(torch, rsim, dev, base, db, reps: int = 5):
+    """Energies of every reverberant source at every mic of the batched epoch
+    (the reverberant-at-mic gain rule), after that epoch's cut: one untimed
+    call, then `reps` timed ones."""
+    stream = torch.cuda.Stream()
+    stream.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(stream):
+        rsim.reverb_energy(db, stream=stream)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            e = rsim.reverb_energy(db, stream=stream)
+        e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    if not bool(torch.isfinite(e).all()) or rsim.device_status():
+        raise RuntimeError("energy computation flagged a slot")
+    # algorithmic work: per source, blocks of hop N - Lmax + 1 with two
+    # transforms each, one inverse, one transform of the window and one per RIR
+    L = db.rir_len.cpu().numpy().astype(np.int64).reshape(base.n_utt, base.max_src, base.n_mic)
+    flops, byts = 0.0, 0
+    for u in range(base.n_utt):
+        nx = int(base.src_len[u])
+        for i in range(int(base.n_src[u])):
+            lmax = int(L[u, i].max())
+            if lmax <= 0 or nx <= 0:
+                continue
+            m = 14
+            while (1 << m) < 2 * lmax:
+                m += 1
+            N = 1 << m
+            nb = -(-nx // (N - lmax + 1))
+            c = 2.5 * N * m
+            flops += nb * (2 * c + 8 * (N / 2 + 1)) + 2 * c + base.n_mic * (c + 4 * (N / 2 + 1))
+            byts += 4 * (nx + int(L[u, i].sum()))
+    tf = flops / (ms * 1e-3) / 1e12
+    return {"workload": "energies of every (source, mic) pair of the batched epoch after its cut",
+            "ms": round(ms, 4), "audio_s_per_s": round(base.audio_seconds / (ms * 1e-3), 1),
+            "roofline": {"bound": "alu", "achieved": round(tf, 2), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                         "frac": round(tf / FP32_PEAK_TFLOPS, 4)},
+            "hbm": {"achieved": round(byts / (ms * 1e-3) / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s"}}
+
+
 def large_thresholds(torch, rsim, autotune, synth, dev, etas=(math.inf, 30.0, 20.0, 10.0), reps: int = 3):
     """The large batched workload (4096 utterances of 1-20 s, up to 4 sources,
     8 mics, T60 U(0.1, 1.0) s, RIRs up to 16000 taps) at each cut threshold:
@@ -324,6 +367,7 @@ def main() -> int:
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-diff", action="store_true", help="skip the adjoint (differentiation workload) timing")
     ap.add_argument("--no-rirgen", action="store_true", help="skip the image-method RIR generation timing")
+    ap.add_argument("--no-reverb", action="store_true", help="skip the reverberant-energy (gain rule) timing")
     ap.add_argument("--large", action="store_true",
                     help="also time the large batched workload (4096 utterances, 8 mics) at eta = inf, 30, 20, "
                          "10 dB (adds about a minute and 35 GB of GPU memory)")
@@ -550,6 +594,13 @@ def main() -> int:
         log(f"image-method RIRs: {d['ms']:.3f} ms for one epoch's RIRs, {d['rirs_per_s']:.4g} RIRs/s, "
             f"{d['roofline']['frac']:.3f} of the HBM peak; epochs with image-method rooms "
             f"{d['epoch_with_rooms']['ms']:.3f} ms ({d['epoch_with_rooms']['audio_s_per_s']:.4g} audio-s/s)")
+
+    if not args.no_reverb:
+        b0, db0, _ = epochs[0]
+        rsim.truncate_batch(db0, args.eta)
+        result["reverb_gains"] = reverb_gains(torch, rsim, dev, b0, db0)
+        d = result["reverb_gains"]
+        log(f"reverberant energies: {d['ms']:.3f} ms per epoch, {d['roofline']['frac']:.3f} of the FP32 peak")
 
     if args.large:
         del y, ws

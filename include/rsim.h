@@ -253,6 +253,28 @@ rsim_status rsim_simulate_rooms(const rsim_batch* b, const float* x, float* h, c
                                 double eta_db, int32_t* rir_len_out, float* y, void* ws, size_t ws_bytes,
                                 const rsim_tune* tune, int32_t use_graph, hipStream_t stream);
 
+/*
+ * Energies of the reverberant sources at the mics, for the reverberant-at-mic
+ * reading of eq. (2)'s gains: energy[r] = sum_n ((h_r * x_i)[n])^2 (binary64,
+ * device array of U*S*J) for RIR slot r = (u*S + i)*J + j with its kept
+ * length b->rir_len[r] (call after the cut).  Computed from the identity
+ * E = sum_{|l| < L} r_hh[l] r_xx[l] of the autocorrelations, in the frequency
+ * domain with transforms of N = max(16384, 2^ceil(log2(2 Lmax))) points
+ * (float32 transforms, binary64 sums).  Unused slots get 0; a bad descriptor NaN and RSIM_DEV_BADDESC; a
+ * kept RIR longer than 16384 taps NaN and RSIM_DEV_BADPLAN.
+ */
+rsim_status rsim_reverb_energy(const rsim_batch* b, const float* x, const float* h, double* energy,
+                               hipStream_t stream);
+
+/*
+ * Gains of the reverberant-at-mic rule (host arrays): alpha[i*J + j] from the
+ * energies energy[i*J + j] of one utterance: alpha_0j = 1 and, for i >= 1,
+ * alpha_ij = sqrt(E_0j / (E_ij 10^(snr_db[i]/10))), so the SNR is snr_db[i]
+ * at every mic; 0 if E_ij <= 0 or E_0j <= 0.
+ */
+rsim_status rsim_snr_gains_reverb(const double* energy, const double* snr_db, int32_t I, int32_t J,
+                                  float* alpha);
+
 /* Read and clear the device status word (synchronises the device). */
 rsim_status rsim_device_status(int32_t* status);
 

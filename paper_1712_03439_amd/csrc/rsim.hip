@@ -1279,6 +1279,164 @@ __global__ __launch_bounds__(256) void bwd_zero_kernel(BwdArgs A) {
   }
 }
 
+// ======================================= reverberant energies (gain rule)
+// E_ij = sum_n ((h_ij * x_i)[n])^2 for the cut RIRs, from the identity
+// E = sum_{|l| < L} r_hh[l] r_xx[l] (r the autocorrelations) evaluated in the
+// frequency domain: with N >= 2 Lmax (Lmax the longest kept RIR of source i),
+// E_ij = (1/N) sum_k |H_ij[k]|^2 S_i[k], S_i the transform of r_xx
+// windowed to |l| < Lmax and made periodic with period N (no aliasing since
+// L + Lmax - 1 <= N).  r_xx up to lag Lmax - 1 is accumulated over blocks of
+// hop N - Lmax + 1: block b correlates x[bB, bB + B) with x[bB, bB + N),
+// which holds every sample its lags need.  One work item per source slot.
+struct EnergyArgs {
+  BatchDev b;
+  const float* x;
+  const float* h;
+  double* energy;  // [U*S*J]
+  int fam;
+};
+
+// log2 of the transform size for a longest kept RIR of lmax taps: at least
+// 2 lmax points, and at least 16384 (long blocks, the most efficient plan).
+__host__ __device__ constexpr int energy_log2n(int lmax) {
+  int l2 = 14;
+  while (l2 < 16 && (1 << l2) < 2 * lmax) ++l2;
+  return l2;
+}
+
+template <class PL>
+__device__ __forceinline__ void energy_source(const EnergyArgs& A, int u, int i, int lmax, cf* lds_raw,
+                                              double* s_red, int t) {
+#pragma clang fp contract(off)
+  constexpr int P = PL::P, M = PL::M, N = PL::N, T = PL::T, SP = Fft<PL>::SP;
+  Xch<PL> lds{lds_raw, 0};
+  const TwBase tw = Fft<PL>::bases(plan_tw<PL>(), t);
+  const BatchDev& b = A.b;
+  const int Nx = uni(b.src_len[u]), J = b.J;
+  const long long so = uni64(b.src_off[(long long)u * b.S + i]);
+  const int B = N - lmax + 1, nb = (Nx + B - 1) / B;
+  // With 1024 threads (128 registers each) the next window is not held
+  // while the current one is transformed.
+  constexpr bool kPrefetch = T <= 512;
+  cf R[P], Zn[P];
+#pragma unroll
+  for (int q = 0; q < P; ++q) R[q] = mk(0.f, 0.f);
+  if (kPrefetch) load_real<PL>(Zn, A.x + so, min(N, Nx), t);
+  for (int bk = 0; bk < nb; ++bk) {
+    // Z: the block's window x[bB, bB + N); X: its first B samples (the same
+    // registers with the rest zeroed).  The next window is loaded meanwhile.
+    if (!kPrefetch) load_real<PL>(Zn, A.x + so + bk * B, min(N, Nx - bk * B), t);
+    cf X[P], Z[P];
+#pragma unroll
+    for (int q = 0; q < P; ++q) {
+      Z[q] = Zn[q];
+      const int n0 = 2 * (t + q * T);
+      X[q] = mk(n0 < B ? Zn[q].x : 0.f, n0 + 1 < B ? Zn[q].y : 0.f);
+    }
+    if (kPrefetch && bk + 1 < nb) {
+      const int nbase = (bk + 1) * B;
+      load_real<PL>(Zn, A.x + so + nbase, min(N, Nx - nbase), t);
+    }
+    Fft<PL>::forward(X, lds, tw, t);
+    Fft<PL>::post(X, tw, t);
+    Fft<PL>::forward(Z, lds, tw, t);
+    Fft<PL>::post(Z, tw, t);
+#pragma unroll
+    for (int q = 0; q < P; ++q) {
+      const cf c = cmacc(R[q], X[q], Z[q]);
+      const cf d = mk(__builtin_fmaf(X[q].x, Z[q].x, R[q].x), __builtin_fmaf(X[q].y, Z[q].y, R[q].y));
+      R[q] = (q == SP && t == 0) ? d : c;
+    }
+  }
+  // Both spectra carry a factor 2 and the inverse 2 M: R -> 8 M r_xx.
+  Fft<PL>::pre(R, tw, t);
+  Fft<PL>::inverse(R, lds, tw, t);
+  float* rl = reinterpret_cast<float*>(lds_raw);
+  const float sc = 1.0f / (8.0f * (float)M);
+  __syncthreads();  // every read of the exchange buffers is done
+#pragma unroll
+  for (int q = 0; q < P; ++q) {
+    const int n0 = 2 * (t + q * T);
+    if (n0 < lmax) rl[n0] = R[q].x * sc;
+    if (n0 + 1 < lmax) rl[n0 + 1] = R[q].y * sc;
+  }
+  __syncthreads();
+  cf sv[P];
+#pragma unroll
+  for (int q = 0; q < P; ++q) {
+    const int n0 = 2 * (t + q * T), n1 = n0 + 1;
+    const float a = n0 < lmax ? rl[n0] : (n0 > N - lmax ? rl[N - n0] : 0.f);
+    const float c = n1 < lmax ? rl[n1] : (n1 > N - lmax ? rl[N - n1] : 0.f);
+    sv[q] = mk(a, c);
+  }
+  __syncthreads();  // the windowed autocorrelation is read before the exchanges reuse the LDS
+  Fft<PL>::forward(sv, lds, tw, t);
+  Fft<PL>::post(sv, tw, t);  // 2 S, real (s is real and even)
+  for (int j = 0; j < J; ++j) {
+    const long long r = ((long long)u * b.S + i) * J + j;
+    cf Hv[P];
+    load_real<PL>(Hv, A.h + uni64(b.rir_off[r]), uni(b.rir_len[r]), t);
+    Fft<PL>::forward(Hv, lds, tw, t);
+    Fft<PL>::post(Hv, tw, t);  // 2 H
+    double part = 0.0;
+#pragma unroll
+    for (int q = 0; q < P; ++q) {
+      const double hx = Hv[q].x, hy = Hv[q].y;
+      if (q == SP && t == 0)
+        part += hx * hx * (double)sv[q].x + hy * hy * (double)sv[q].y;  // bins 0 and N/2
+      else
+        part += 2.0 * (hx * hx + hy * hy) * (double)sv[q].x;           // bins k and N - k
+    }
+    const double e = block_sum_d<T>(part, s_red, t);
+    if (t == 0) A.energy[r] = e / (8.0 * (double)N);
+  }
+}
+
+template <int T>
+__global__ __launch_bounds__(T, 2) void energy_kernel(EnergyArgs A) {
+  __shared__ cf lds[max_lds_with_threads<T>()];
+  __shared__ double s_red[T];
+  const int t = threadIdx.x;
+  const BatchDev& b = A.b;
+  const long long items = (long long)b.U * b.S;
+  int err = 0;
+  for (long long k = blockIdx.x; k < items; k += gridDim.x) {
+    const int u = (int)(k / b.S), i = (int)(k - (long long)u * b.S);
+    const int I = uni(b.n_src[u]), Nx = uni(b.src_len[u]), J = b.J;
+    int lmax = 0;
+    bool ok = I >= 0 && I <= b.S && Nx >= 0;
+    if (ok && i < I) {
+      for (int j = 0; j < J; ++j) {
+        const long long r = ((long long)u * b.S + i) * J + j;
+        const int L = uni(b.rir_len[r]);
+        const long long ro = uni64(b.rir_off[r]);
+        ok = ok && L >= 0 && ro >= 0 && ro + L <= b.h_len;
+        lmax = L > lmax ? L : lmax;
+      }
+      const long long so = uni64(b.src_off[k]);
+      ok = ok && so >= 0 && so + Nx <= b.x_len;
+    }
+    const bool work = ok && i < I && Nx > 0 && lmax > 0;
+    const int l2 = work ? energy_log2n(lmax) : 0;
+    // Slots without work (and unusable ones) are written by family 0.
+    const int fam = work && l2 <= 15 ? family_of_log2n(l2) : 0;
+    if (fam != A.fam) continue;
+    if (!work || l2 > 15) {
+      // no work: 0; a bad descriptor or a kept RIR longer than 16384 taps: NaN
+      const bool bad = !ok || l2 > 15;
+      if (!ok) err |= RSIM_DEV_BADDESC;
+      else if (l2 > 15) err |= RSIM_DEV_BADPLAN;
+      for (int jj = t; jj < J; jj += T) A.energy[k * J + jj] = bad ? __builtin_nan("") : 0.0;
+      continue;
+    }
+    dispatch_plan<T>(l2, [&](auto pl) __attribute__((always_inline)) {
+      using PL = decltype(pl);
+      energy_source<PL>(A, u, i, lmax, lds, s_red, t);
+    });
+  }
+  if (err && t == 0) flag_status(err);
+}
+
 // ================================================================ dry power
 __global__ __launch_bounds__(256) void power_kernel(BatchDev b, const float* __restrict__ x,
                                                    double* __restrict__ power) {
@@ -1717,6 +1875,16 @@ const void* bwd_rir_kernel_ptr(int fam) {
     case 3: return reinterpret_cast<const void*>(&bwd_rir_kernel<256>);
     case 4: return reinterpret_cast<const void*>(&bwd_rir_kernel<512>);
     default: return reinterpret_cast<const void*>(&bwd_rir_kernel<1024>);
+  }
+}
+const void* energy_kernel_ptr(int fam) {
+  switch (fam) {
+    case 0: return reinterpret_cast<const void*>(&energy_kernel<32>);
+    case 1: return reinterpret_cast<const void*>(&energy_kernel<64>);
+    case 2: return reinterpret_cast<const void*>(&energy_kernel<128>);
+    case 3: return reinterpret_cast<const void*>(&energy_kernel<256>);
+    case 4: return reinterpret_cast<const void*>(&energy_kernel<512>);
+    default: return reinterpret_cast<const void*>(&energy_kernel<1024>);
   }
 }
 const void* bwd_finish_kernel_ptr(int fam) {
@@ -2572,6 +2740,46 @@ rsim_status rsim_simulate_rooms(const rsim_batch* b, const float* x, float* h, c
   plan_truncate(P.cut, h, bb.h_len, bb.rir_off, bb.rir_len0, (int)n_rir, cut_scale(eta_db), nullptr, rir_len_out);
   plan_mix(P, &bb, bd, td, x, h, alpha, y, ws);
   return issue(P, stream, use_graph);
+}
+
+rsim_status rsim_reverb_energy(const rsim_batch* b, const float* x, const float* h, double* energy,
+                               hipStream_t stream) {
+  if (!batch_ok(b)) return RSIM_EINVAL;
+  if (b->n_utt == 0) return RSIM_OK;
+  if (!x || !h || !energy) return RSIM_EINVAL;
+  const rsim_status e = ensure_init(stream);
+  if (e != RSIM_OK) return e;
+  const BatchDev bd = to_dev(b);
+  const DevState& st = dev_state();
+  const int cus = st.cus > 0 ? st.cus : 256;
+  const long long items = (long long)b->n_utt * b->max_src;
+  for (int f = 0; f < kNumFam; ++f) {
+    EnergyArgs A;
+    A.b = bd;
+    A.x = x;
+    A.h = h;
+    A.energy = energy;
+    A.fam = f;
+    void* args[] = {&A};
+    const unsigned grid = (unsigned)std::max<long long>(1, std::min<long long>(items, (long long)cus * 2));
+    if (hipLaunchKernel(energy_kernel_ptr(f), dim3(grid), dim3(kFamT[f]), args, 0, stream) != hipSuccess)
+      return clear_error(RSIM_EDEVICE);
+  }
+  return RSIM_OK;
+}
+
+rsim_status rsim_snr_gains_reverb(const double* energy, const double* snr_db, int32_t I, int32_t J, float* alpha) {
+  if (I < 0 || J < 1 || (I > 0 && (!energy || !snr_db || !alpha))) return RSIM_EINVAL;
+  for (int i = 0; i < I; ++i)
+    for (int j = 0; j < J; ++j) {
+      double a = 1.0;
+      if (i > 0) {
+        const double e0 = energy[j], ei = energy[i * J + j];
+        a = (ei > 0.0 && e0 > 0.0) ? std::sqrt(e0 / (ei * std::pow(10.0, snr_db[i] / 10.0))) : 0.0;
+      }
+      alpha[i * J + j] = (float)a;
+    }
+  return RSIM_OK;
 }
 
 rsim_status rsim_rfft(const float* x, int32_t n, int32_t count, float* spec, hipStream_t stream) {

@@ -25,6 +25,7 @@ EXPORTS = (
     "rsim_ola_workspace_bytes", "rsim_ola_convolve", "rsim_mix_workspace_bytes", "rsim_mix",
     "rsim_simulate", "rsim_mix_backward", "rsim_source_power", "rsim_snr_gains",
     "rsim_device_status", "rsim_rfft", "rsim_irfft", "rsim_image_rir", "rsim_simulate_rooms",
+    "rsim_reverb_energy", "rsim_snr_gains_reverb",
 )
 
 
@@ -82,6 +83,8 @@ def _lib():
             "rsim_image_rir": ([vp, vp, i32, i32, f64, f64, vp, i64, vp, vp, i32, vp], i32),
             "rsim_simulate_rooms": ([bp, vp, vp, vp, vp, i32, f64, f64, vp, f64, vp, vp, vp, sz, tp, i32, vp],
                                     i32),
+            "rsim_reverb_energy": ([bp, vp, vp, vp, vp], i32),
+            "rsim_snr_gains_reverb": ([vp, vp, i32, i32, vp], i32),
         }
         for name, (args, res) in sig.items():
             fn = getattr(lib, name)
@@ -220,6 +223,42 @@ def simulate_rooms(db: DeviceBatch, geom, refl, alpha, eta_db: float, order: int
                                       int(bool(use_graph)), _stream(stream)),
            "rsim_simulate_rooms")
     return y
+
+
+def reverb_energy(db: DeviceBatch, x=None, h=None, stream=None):
+    """Energies of the reverberant sources at the mics, float64 [U*S*J] on the
+    GPU (rsim_reverb_energy; call after the cut)."""
+    torch = _torch()
+    e = torch.empty(db.U * db.S * db.J, dtype=torch.float64, device=db.device)
+    s = db.struct()
+    _check(_lib().rsim_reverb_energy(ctypes.byref(s), _ptr(db.x if x is None else x), _ptr(db.h if h is None else h),
+                                     _ptr(e), _stream(stream)), "rsim_reverb_energy")
+    return e
+
+
+def snr_gains_reverb(energy: np.ndarray, snr_db: Sequence[float]) -> np.ndarray:
+    """Host gain rule of the reverberant-at-mic reading (rsim_snr_gains_reverb):
+    energy [I, J] -> alpha [I, J]."""
+    E = np.ascontiguousarray(energy, np.float64)
+    I, J = E.shape
+    s = np.ascontiguousarray(snr_db, np.float64)
+    a = np.zeros(I * J, np.float32)
+    _check(_lib().rsim_snr_gains_reverb(E.ctypes.data, s.ctypes.data, I, J, a.ctypes.data), "rsim_snr_gains_reverb")
+    return a.reshape(I, J)
+
+
+def batch_gains_reverb(db: DeviceBatch, snr_db: np.ndarray, energy: np.ndarray) -> np.ndarray:
+    """alpha [U*S*J] (float32, host) of the reverberant-at-mic rule from the
+    energies (reverb_energy, copied to the host)."""
+    U, S, J = db.U, db.S, db.J
+    a = np.zeros(U * S * J, np.float32)
+    n_src = db.host.n_src
+    E = np.asarray(energy, np.float64).reshape(U, S, J)
+    for u in range(U):
+        I = int(n_src[u])
+        if I:
+            a[u * S * J:(u * S + I) * J] = snr_gains_reverb(E[u, :I], snr_db[u * S:u * S + I]).reshape(-1)
+    return a
 
 
 def snr_gains(p_dry: Sequence[float], snr_db: Sequence[float], n_mic: int) -> np.ndarray:

@@ -230,3 +230,22 @@ def test_simulate_rooms_validation_codes():
     long = _host_batch()
     long.max_rir_len0 = 40000
     assert call(bb=long) == rsim.RSIM_EUNSUPPORTED
+
+
+def test_reverb_energy_and_gain_validation():
+    lib = rsim.lib()
+    p = ctypes.c_void_p(8)
+    b = _host_batch()
+    assert lib.rsim_reverb_energy(None, p, p, p, None) == rsim.RSIM_EINVAL
+    assert lib.rsim_reverb_energy(ctypes.byref(b), None, p, p, None) == rsim.RSIM_EINVAL
+    assert lib.rsim_reverb_energy(ctypes.byref(_host_batch(U=0)), None, None, None, None) == rsim.RSIM_OK
+    assert lib.rsim_snr_gains_reverb(None, None, 2, 0, None) == rsim.RSIM_EINVAL
+    # the host rule against the oracle's
+    import oracle
+    rng = np.random.default_rng(3)
+    E = rng.uniform(0.01, 9.0, (3, 2))
+    E[2, 1] = 0.0
+    snr = [0.0, 4.0, 17.0]
+    got = rsim.snr_gains_reverb(E, snr)
+    ref = oracle.snr_gains_reverb(E, snr).astype(np.float32)
+    assert np.allclose(got, ref, rtol=2e-7, atol=0)
