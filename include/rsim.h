@@ -275,6 +275,24 @@ rsim_status rsim_reverb_energy(const rsim_batch* b, const float* x, const float*
 rsim_status rsim_snr_gains_reverb(const double* energy, const double* snr_db, int32_t I, int32_t J,
                                   float* alpha);
 
+/*
+ * The log-Mel front end the paper trains on (Sec. 4): for every utterance u
+ * and mic j, 128 log-Mel features per frame of the output y (after rsim_mix,
+ * which writes out_len): frame t covers samples [160 t, 160 t + 512) of
+ * y_j, whole frames only (F_u = 1 + (out_len[u] - 512) / 160 when
+ * out_len[u] >= 512); periodic Hann window; power spectrum of the 512-point
+ * transform; 128 triangular filters over 130 edges equally spaced in
+ * m(f) = 2595 log10(1 + f/700) from 125 to 7500 Hz; natural log of
+ * (energy + 1e-6).  Frame t of (u, j) goes to
+ * feat[feat_off[u] + (j C_u + t) * 128 .. + 128) with C_u the frame count of
+ * out_stride[u] samples (frames t >= F_u are not written).  max_frames >=
+ * every C_u (host) sizes the launch.  (Stacking four frames and keeping every
+ * third, as the paper does next, is a view of these rows.)  A slot whose
+ * features would leave [0, feat_len) is skipped with RSIM_DEV_BADDESC.
+ */
+rsim_status rsim_logmel(const rsim_batch* b, const float* y, float* feat, const int64_t* feat_off, int64_t feat_len,
+                        int32_t max_frames, hipStream_t stream);
+
 /* Read and clear the device status word (synchronises the device). */
 rsim_status rsim_device_status(int32_t* status);
 

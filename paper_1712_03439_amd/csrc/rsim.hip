@@ -32,6 +32,13 @@ namespace rsim {
 
 __device__ cf g_tw[kTwTotal];
 __device__ int g_status;
+// Log-Mel front end: periodic Hann window of 512 samples and the 128
+// triangular Mel filters over the 257 bins of a 512-point transform (bands
+// as bin ranges with their weights), filled at init from binary64 values.
+constexpr int kMelWin = 512, kMelHop = 160, kMelBands = 128, kMelBins = kMelWin / 2 + 1, kMelWMax = 2 * kMelBins;
+__device__ float g_hann[kMelWin];
+__device__ int g_mel_first[kMelBands], g_mel_count[kMelBands], g_mel_off[kMelBands];
+__device__ float g_mel_w[kMelWMax];
 
 __device__ __forceinline__ void flag_status(int bits) { atomicOr(&g_status, bits); }
 
@@ -1752,6 +1759,92 @@ __global__ __launch_bounds__(PL::T) void irfft_kernel(const float* __restrict__ 
   }
 }
 
+// ======================================================= log-Mel front end
+// The paper's acoustic-model features (Sec. 4): 128 log-Mel bands of 512-sample
+// (32 ms) Hann windows every 160 samples (10 ms), the filterbank spanning
+// 125..7500 Hz.  A workgroup holds kMelGroups groups of 32 threads, each
+// group one frame through the 512-point plan (its own LDS exchange buffers;
+// the plan's barriers are the workgroup's, so every group runs the same
+// steps, on zeros when it has no frame).  Power |X_k|^2 goes to LDS and each
+// thread sums four bands over their bins in a fixed order.
+constexpr int kMelGroups = 8;
+
+struct MelArgs {
+  BatchDev b;
+  const float* y;
+  float* feat;
+  const long long* feat_off;  // [U]
+  long long feat_len;
+  int chunks;                 // work items per (utterance, mic): frames / kMelGroups, rounded up
+};
+
+__device__ __forceinline__ int mel_frames(int T) { return T >= kMelWin ? 1 + (T - kMelWin) / kMelHop : 0; }
+
+__global__ __launch_bounds__(kMelGroups * 32) void logmel_kernel(MelArgs A) {
+  using PL = PlanOf<9>;
+  static_assert(PL::T == 32 && PL::N == kMelWin, "one 512-point plan per group of 32 threads");
+  __shared__ cf lds_raw[kMelGroups][Xch<PL>::kEntries];
+  __shared__ float pw[kMelGroups][kMelBins + 7];
+  const int tid = threadIdx.x, grp = tid >> 5, t = tid & 31;
+  const BatchDev& b = A.b;
+  const TwBase tw = Fft<PL>::bases(plan_tw<PL>(), t);
+  const long long items = (long long)b.U * b.J * A.chunks;
+  int err = 0;
+  for (long long it = blockIdx.x; it < items; it += gridDim.x) {
+    const int c = (int)(it % A.chunks);
+    const long long uj = it / A.chunks;
+    const int u = (int)(uj / b.J), j = (int)(uj - (long long)u * b.J);
+    const int T = uni(b.out_len[u]), stride = uni(b.out_stride[u]);
+    const int F = mel_frames(T), cap = mel_frames(stride);
+    if (c * kMelGroups >= F) continue;
+    const long long yo = uni64(b.out_off[u]) + (long long)j * stride;
+    const long long fo = uni64(A.feat_off[u]);
+    if (T > stride || yo < 0 || yo + T > b.y_len || fo < 0 || fo + (long long)b.J * cap * kMelBands > A.feat_len) {
+      if (c == 0) err |= RSIM_DEV_BADDESC;
+      continue;
+    }
+    const int fr = c * kMelGroups + grp;
+    const bool live = fr < F;
+    cf v[PL::P];
+    {
+      const int f0 = live ? fr * kMelHop : 0;
+      load_real<PL>(v, A.y + yo + f0, live ? kMelWin : 0, t);
+#pragma unroll
+      for (int r = 0; r < PL::P; ++r) {
+        const int n = 2 * (t + r * PL::T);
+        v[r] = mk(v[r].x * g_hann[n], v[r].y * g_hann[n + 1]);
+      }
+    }
+    Xch<PL> lds{lds_raw[grp], 0};
+    Fft<PL>::forward(v, lds, tw, t);
+    Fft<PL>::post(v, tw, t);  // 2 X
+#pragma unroll
+    for (int q = 0; q < PL::P; ++q) {
+      if (t == 0 && q == Fft<PL>::SP) {
+        pw[grp][0] = 0.25f * v[q].x * v[q].x;
+        pw[grp][PL::M] = 0.25f * v[q].y * v[q].y;
+      } else {
+        pw[grp][slot_bin<PL>(q, t)] = 0.25f * (v[q].x * v[q].x + v[q].y * v[q].y);
+      }
+    }
+    __syncthreads();
+    if (live) {
+      float* out = A.feat + fo + ((long long)j * cap + fr) * kMelBands;
+#pragma unroll
+      for (int k = 0; k < kMelBands / 32; ++k) {
+        const int band = t + 32 * k;
+        const int first = g_mel_first[band], n = g_mel_count[band], o = g_mel_off[band];
+        float m = 0.f;
+        for (int i = 0; i < n; ++i) m = __builtin_fmaf(g_mel_w[o + i], pw[grp][first + i], m);
+        out[band] = logf(m + 1e-6f);
+      }
+    }
+    __syncthreads();  // pw is read before the next item writes it
+  }
+  if (err && tid == 0) flag_status(err);
+}
+
+
 // ================================================================ host side
 template <class PL>
 static void fill_plan(std::vector<float2>& tw, int base) {
@@ -1913,6 +2006,45 @@ constexpr int kFam1024Var = 3;
 // Mic accumulators of family f's kernel.
 int mic_group(int f, const TuneDev& td) { return kVarJG[td.variant[f]]; }
 
+// The log-Mel tables in binary64, rounded once to float32: the periodic Hann
+// window and, per band b, the nonzero weights of the triangle over the Mel
+// edges b, b+1, b+2 (130 edges equally spaced in m(f) = 2595 log10(1 + f/700)
+// from 125 to 7500 Hz) at the bin frequencies k * 16000 / 512.
+bool upload_mel_tables() {
+  std::vector<float> hann(kMelWin);
+  for (int n = 0; n < kMelWin; ++n) hann[n] = (float)(0.5 - 0.5 * std::cos(2.0 * M_PI * n / kMelWin));
+  auto mel = [](double f) { return 2595.0 * std::log10(1.0 + f / 700.0); };
+  auto hz = [](double m) { return 700.0 * (std::pow(10.0, m / 2595.0) - 1.0); };
+  double edges[kMelBands + 2];
+  const double m0 = mel(125.0), m1 = mel(7500.0);
+  for (int e = 0; e < kMelBands + 2; ++e)
+    edges[e] = e == kMelBands + 1 ? hz(m1) : hz(m0 + (m1 - m0) * e / (double)(kMelBands + 1));
+  int first[kMelBands], count[kMelBands], off[kMelBands];
+  std::vector<float> w;
+  for (int b = 0; b < kMelBands; ++b) {
+    const double lo = edges[b], c = edges[b + 1], hi = edges[b + 2];
+    first[b] = 0;
+    count[b] = 0;
+    off[b] = (int)w.size();
+    for (int k = 0; k < kMelBins; ++k) {
+      const double f = k * 16000.0 / kMelWin;
+      const double v = std::max(0.0, std::min((f - lo) / (c - lo), (hi - f) / (hi - c)));
+      if (v > 0.0) {
+        if (count[b] == 0) first[b] = k;
+        w.push_back((float)v);
+        ++count[b];
+      }
+    }
+  }
+  if ((int)w.size() > kMelWMax) return false;
+  w.resize(kMelWMax, 0.f);
+  return hipMemcpyToSymbol(HIP_SYMBOL(g_hann), hann.data(), sizeof(float) * kMelWin) == hipSuccess &&
+         hipMemcpyToSymbol(HIP_SYMBOL(g_mel_first), first, sizeof(first)) == hipSuccess &&
+         hipMemcpyToSymbol(HIP_SYMBOL(g_mel_count), count, sizeof(count)) == hipSuccess &&
+         hipMemcpyToSymbol(HIP_SYMBOL(g_mel_off), off, sizeof(off)) == hipSuccess &&
+         hipMemcpyToSymbol(HIP_SYMBOL(g_mel_w), w.data(), sizeof(float) * kMelWMax) == hipSuccess;
+}
+
 rsim_status init_locked(int dev) {
   DevState& st = g_dev[dev];
   if (st.init) return RSIM_OK;
@@ -1922,6 +2054,7 @@ rsim_status init_locked(int dev) {
     return RSIM_EDEVICE;
   const int zero = 0;
   if (hipMemcpyToSymbol(HIP_SYMBOL(g_status), &zero, sizeof(int)) != hipSuccess) return RSIM_EDEVICE;
+  if (!upload_mel_tables()) return RSIM_EDEVICE;
   if (hipDeviceGetAttribute(&st.cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
     return RSIM_EDEVICE;
   for (int v = 0; v < kNumVar; ++v)
@@ -2780,6 +2913,28 @@ rsim_status rsim_snr_gains_reverb(const double* energy, const double* snr_db, in
       alpha[i * J + j] = (float)a;
     }
   return RSIM_OK;
+}
+
+rsim_status rsim_logmel(const rsim_batch* b, const float* y, float* feat, const int64_t* feat_off, int64_t feat_len,
+                        int32_t max_frames, hipStream_t stream) {
+  if (!batch_ok(b) || max_frames < 0 || feat_len < 0) return RSIM_EINVAL;
+  if (b->n_utt == 0 || max_frames == 0) return RSIM_OK;
+  if (!y || !feat || !feat_off) return RSIM_EINVAL;
+  const rsim_status e = ensure_init(stream);
+  if (e != RSIM_OK) return e;
+  MelArgs A;
+  A.b = to_dev(b);
+  A.y = y;
+  A.feat = feat;
+  A.feat_off = reinterpret_cast<const long long*>(feat_off);
+  A.feat_len = feat_len;
+  A.chunks = (max_frames + kMelGroups - 1) / kMelGroups;
+  const DevState& st = dev_state();
+  const int cus = st.cus > 0 ? st.cus : 256;
+  const long long items = (long long)b->n_utt * b->n_mic * A.chunks;
+  const unsigned grid = (unsigned)std::max<long long>(1, std::min<long long>(items, (long long)cus * 4));
+  hipLaunchKernelGGL(logmel_kernel, dim3(grid), dim3(kMelGroups * 32), 0, stream, A);
+  return hipGetLastError() == hipSuccess ? RSIM_OK : clear_error(RSIM_EDEVICE);
 }
 
 rsim_status rsim_rfft(const float* x, int32_t n, int32_t count, float* spec, hipStream_t stream) {

@@ -25,7 +25,7 @@ EXPORTS = (
     "rsim_ola_workspace_bytes", "rsim_ola_convolve", "rsim_mix_workspace_bytes", "rsim_mix",
     "rsim_simulate", "rsim_mix_backward", "rsim_source_power", "rsim_snr_gains",
     "rsim_device_status", "rsim_rfft", "rsim_irfft", "rsim_image_rir", "rsim_simulate_rooms",
-    "rsim_reverb_energy", "rsim_snr_gains_reverb",
+    "rsim_reverb_energy", "rsim_snr_gains_reverb", "rsim_logmel",
 )
 
 
@@ -85,6 +85,7 @@ def _lib():
                                     i32),
             "rsim_reverb_energy": ([bp, vp, vp, vp, vp], i32),
             "rsim_snr_gains_reverb": ([vp, vp, i32, i32, vp], i32),
+            "rsim_logmel": ([bp, vp, vp, vp, i64, i32, vp], i32),
         }
         for name, (args, res) in sig.items():
             fn = getattr(lib, name)
@@ -259,6 +260,35 @@ def batch_gains_reverb(db: DeviceBatch, snr_db: np.ndarray, energy: np.ndarray) 
         if I:
             a[u * S * J:(u * S + I) * J] = snr_gains_reverb(E[u, :I], snr_db[u * S:u * S + I]).reshape(-1)
     return a
+
+
+MEL_WIN, MEL_HOP, MEL_BANDS = 512, 160, 128
+
+
+def mel_frames(T) -> np.ndarray:
+    """Whole 512-sample frames every 160 samples in T samples."""
+    T = np.asarray(T, np.int64)
+    return np.where(T >= MEL_WIN, 1 + (T - MEL_WIN) // MEL_HOP, 0)
+
+
+def logmel(db: DeviceBatch, y, stream=None):
+    """128 log-Mel features per frame of every (utterance, mic) output
+    (rsim_logmel; call after the mix).  Returns (feat, off, cap): frame t of
+    (u, j) is feat[off[u] + (j cap[u] + t) * 128 : + 128] for
+    t < mel_frames(out_len[u])."""
+    torch = _torch()
+    _require_cuda(y)
+    cap = mel_frames(db.host.out_stride)
+    sizes = cap * db.J * MEL_BANDS
+    off = np.concatenate([[0], np.cumsum(sizes)[:-1]]).astype(np.int64)
+    total = int(sizes.sum())
+    feat = torch.empty(max(total, 1), dtype=torch.float32, device=db.device)
+    # the device copy of the offsets stays referenced by db until the next call
+    db.mel_off = torch.from_numpy(off).to(db.device)
+    s = db.struct()
+    _check(_lib().rsim_logmel(ctypes.byref(s), _ptr(y), _ptr(feat), _ptr(db.mel_off), int(feat.numel()),
+                              int(cap.max()) if cap.size else 0, _stream(stream)), "rsim_logmel")
+    return feat, off, cap
 
 
 def snr_gains(p_dry: Sequence[float], snr_db: Sequence[float], n_mic: int) -> np.ndarray:

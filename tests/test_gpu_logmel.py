@@ -1,0 +1,74 @@
+"""The log-Mel front end on the GPU (rsim_logmel) against the FP64 oracle.
+
+Bar, derived from the arithmetic: float32 512-point transforms and sums give
+band energies within a small multiple of float32 rounding of the frame's
+total power; the test allows 1e-5 of it (|exp(f_gpu) - exp(f_ref)|, the
+floor included on both sides)."""
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import logmel_oracle as lm
+from tests.gpu_util import cuda
+
+
+def _run(b, eta=20.0):
+    torch = cuda()
+    from paper_1712_03439_amd import rsim
+
+    db = rsim.DeviceBatch(b)
+    alpha = torch.from_numpy(rsim.batch_gains(db, b.snr_db)).cuda()
+    y = rsim.simulate(db, alpha, eta)
+    feat, off, cap = rsim.logmel(db, y)
+    torch.cuda.synchronize()
+    return y.cpu().numpy(), feat.cpu().numpy(), off, cap, db.out_len.cpu().numpy()
+
+
+def _check(b, y, feat, off, cap, ol, utts):
+    for u in utts:
+        T = int(ol[u])
+        F = lm.n_frames(T)
+        st, yo = int(b.out_stride[u]), int(b.out_off[u])
+        assert F <= cap[u]
+        for j in range(b.n_mic):
+            yj = y[yo + j * st: yo + j * st + T].astype(np.float64)
+            ref = lm.logmel(yj)
+            got = feat[off[u] + j * cap[u] * 128: off[u] + (j * cap[u] + F) * 128].reshape(F, 128)
+            power = lm.power_spectra(yj)
+            total = power[:, 0] + power[:, 256] + 2 * power[:, 1:256].sum(axis=1)
+            err = np.abs(np.exp(got.astype(np.float64)) - np.exp(ref))
+            assert np.all(err <= 1e-5 * total[:, None] + 1e-9), (u, j, float(np.max(err / (total[:, None] + 1e-30))))
+
+
+@pytest.mark.gpu
+def test_logmel_of_a_batch():
+    b = synth.make_config2(n_utt=12, epoch=9)
+    y, feat, off, cap, ol = _run(b)
+    _check(b, y, feat, off, cap, ol, range(b.n_utt))
+
+
+@pytest.mark.gpu
+def test_logmel_edges_and_a_tone():
+    # outputs of 511 (no frame), 512 (one), 672 (two) samples and a long one;
+    # the frames of a pure tone on a bin peak in the band holding that bin
+    torch = cuda()
+    from paper_1712_03439_amd import rsim
+
+    rng = synth.rng_for(63, 0)
+    n = np.arange(20000)
+    tone = (0.3 * np.cos(2 * math.pi * 64 * n / 512)).astype(np.float32)   # 2000 Hz
+    srcs = [[synth.speech_like(rng, 511)], [synth.speech_like(rng, 512)], [synth.speech_like(rng, 672)], [tone]]
+    delta = np.zeros(1, np.float32)
+    delta[0] = 1.0
+    rirs = [[[delta]], [[delta]], [[delta]], [[delta]]]
+    b = synth.pack(srcs, rirs, [[0.0]] * 4, 1)
+    y, feat, off, cap, ol = _run(b, math.inf)
+    assert [int(v) for v in ol] == [511, 512, 672, 20000]
+    assert [lm.n_frames(int(v)) for v in ol[:3]] == [0, 1, 2]
+    _check(b, y, feat, off, cap, ol, range(4))
+    F = lm.n_frames(20000)
+    f3 = feat[off[3]: off[3] + F * 128].reshape(F, 128)
+    W = lm.filterbank()
+    assert np.all(np.argmax(f3, axis=1) == np.argmax(W[:, 64]))
