@@ -287,6 +287,38 @@ def reverb_gains(torch, rsim, dev, base, db, reps: int = 5):
             "hbm": {"achieved": round(byts / (ms * 1e-3) / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s"}}
 
 
+def front_end(torch, rsim, base, db, y, reps: int = 5):
+    """The log-Mel features (Sec. 4) of every mic output of the batched epoch:
+    one untimed call, then `reps` timed ones."""
+    stream = torch.cuda.Stream()
+    stream.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(stream):
+        rsim.logmel(db, y, stream=stream)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            rsim.logmel(db, y, stream=stream)
+        e1.record(stream)
+    torch.cuda.synchronize()
+    if rsim.device_status():
+        raise RuntimeError("the front end flagged a bad descriptor")
+    ms = e0.elapsed_time(e1) / reps
+    T = db.out_len.cpu().numpy().astype(np.int64)
+    frames = int(rsim.mel_frames(T).sum()) * base.n_mic
+    byts = 4 * base.n_mic * int(T.sum()) + frames * 128 * 4
+    m = 9
+    flops = frames * (2.5 * 512 * m + 4 * 257 + 2 * 2 * 257 + 128 * 8)
+    tf = flops / (ms * 1e-3) / 1e12
+    gbs = byts / (ms * 1e-3) / 1e9
+    return {"workload": f"128 log-Mel bands of every mic output of the batched epoch ({frames} frames)",
+            "ms": round(ms, 4), "frames_per_s": round(frames / (ms * 1e-3), 1),
+            "audio_s_per_s": round(base.audio_seconds / (ms * 1e-3), 1),
+            "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(gbs / HBM_PEAK_GBS, 4)},
+            "alu": {"achieved": round(tf, 2), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                    "frac": round(tf / FP32_PEAK_TFLOPS, 4)}}
+
+
 def large_thresholds(torch, rsim, autotune, synth, dev, etas=(math.inf, 30.0, 20.0, 10.0), reps: int = 3):
     """The large batched workload (4096 utterances of 1-20 s, up to 4 sources,
     8 mics, T60 U(0.1, 1.0) s, RIRs up to 16000 taps) at each cut threshold:
@@ -368,6 +400,7 @@ def main() -> int:
     ap.add_argument("--no-diff", action="store_true", help="skip the adjoint (differentiation workload) timing")
     ap.add_argument("--no-rirgen", action="store_true", help="skip the image-method RIR generation timing")
     ap.add_argument("--no-reverb", action="store_true", help="skip the reverberant-energy (gain rule) timing")
+    ap.add_argument("--no-frontend", action="store_true", help="skip the log-Mel front-end timing")
     ap.add_argument("--large", action="store_true",
                     help="also time the large batched workload (4096 utterances, 8 mics) at eta = inf, 30, 20, "
                          "10 dB (adds about a minute and 35 GB of GPU memory)")
@@ -557,6 +590,14 @@ def main() -> int:
                      "2 FLOP (FMA) x 2.4 GHz",
         "bytes_per_step": {"mix": int(np.mean(byt)), "cut": int(np.mean(byt_cut))},
     }
+
+    # the front end reads the last timed epoch's output, still in y
+    if not args.no_frontend:
+        b_last, db_last, _ = epochs[(W + K - 1) % E]
+        result["front_end"] = front_end(torch, rsim, b_last, db_last, y)
+        d = result["front_end"]
+        log(f"log-Mel front end: {d['ms']:.3f} ms per epoch, {d['frames_per_s']:.4g} frames/s, "
+            f"{d['roofline']['frac']:.3f} of the HBM peak")
 
     if not args.no_plain:
         # Plain per-utterance path: the same kernels, one utterance per call, no

@@ -1767,7 +1767,8 @@ __global__ __launch_bounds__(PL::T) void irfft_kernel(const float* __restrict__ 
 // the plan's barriers are the workgroup's, so every group runs the same
 // steps, on zeros when it has no frame).  Power |X_k|^2 goes to LDS and each
 // thread sums four bands over their bins in a fixed order.
-constexpr int kMelGroups = 8;
+constexpr int kMelGroups = 2;  // one wave: its barriers cost little
+constexpr int kMelChunksPerItem = 16;
 
 struct MelArgs {
   BatchDev b;
@@ -1775,7 +1776,7 @@ struct MelArgs {
   float* feat;
   const long long* feat_off;  // [U]
   long long feat_len;
-  int chunks;                 // work items per (utterance, mic): frames / kMelGroups, rounded up
+  int chunks;                 // chunks of kMelGroups frames per (utterance, mic), at most
 };
 
 __device__ __forceinline__ int mel_frames(int T) { return T >= kMelWin ? 1 + (T - kMelWin) / kMelHop : 0; }
@@ -1785,61 +1786,83 @@ __global__ __launch_bounds__(kMelGroups * 32) void logmel_kernel(MelArgs A) {
   static_assert(PL::T == 32 && PL::N == kMelWin, "one 512-point plan per group of 32 threads");
   __shared__ cf lds_raw[kMelGroups][Xch<PL>::kEntries];
   __shared__ float pw[kMelGroups][kMelBins + 7];
+  __shared__ float s_w[kMelWMax];
+  __shared__ int s_first[kMelBands], s_count[kMelBands], s_off[kMelBands];
   const int tid = threadIdx.x, grp = tid >> 5, t = tid & 31;
+  // the filterbank in LDS: the band sums below read it in dependent steps
+  for (int k = tid; k < kMelWMax; k += kMelGroups * 32) s_w[k] = g_mel_w[k];
+  for (int k = tid; k < kMelBands; k += kMelGroups * 32) {
+    s_first[k] = g_mel_first[k];
+    s_count[k] = g_mel_count[k];
+    s_off[k] = g_mel_off[k];
+  }
+  __syncthreads();
   const BatchDev& b = A.b;
   const TwBase tw = Fft<PL>::bases(plan_tw<PL>(), t);
-  const long long items = (long long)b.U * b.J * A.chunks;
+  // A work item is up to kMelChunksPerItem chunks of kMelGroups frames of one
+  // (utterance, mic); the next chunk's frames load while one is transformed.
+  const int per_item = (A.chunks + kMelChunksPerItem - 1) / kMelChunksPerItem;
+  const long long items = (long long)b.U * b.J * per_item;
   int err = 0;
   for (long long it = blockIdx.x; it < items; it += gridDim.x) {
-    const int c = (int)(it % A.chunks);
-    const long long uj = it / A.chunks;
+    const int cb = (int)(it % per_item);
+    const long long uj = it / per_item;
     const int u = (int)(uj / b.J), j = (int)(uj - (long long)u * b.J);
     const int T = uni(b.out_len[u]), stride = uni(b.out_stride[u]);
     const int F = mel_frames(T), cap = mel_frames(stride);
-    if (c * kMelGroups >= F) continue;
+    const int c0 = cb * kMelChunksPerItem;
+    if (c0 * kMelGroups >= F) continue;
     const long long yo = uni64(b.out_off[u]) + (long long)j * stride;
     const long long fo = uni64(A.feat_off[u]);
     if (T > stride || yo < 0 || yo + T > b.y_len || fo < 0 || fo + (long long)b.J * cap * kMelBands > A.feat_len) {
-      if (c == 0) err |= RSIM_DEV_BADDESC;
+      if (cb == 0) err |= RSIM_DEV_BADDESC;
       continue;
     }
-    const int fr = c * kMelGroups + grp;
-    const bool live = fr < F;
-    cf v[PL::P];
+    const int c1 = min(c0 + kMelChunksPerItem, (F + kMelGroups - 1) / kMelGroups);
+    cf vn[PL::P];
     {
-      const int f0 = live ? fr * kMelHop : 0;
-      load_real<PL>(v, A.y + yo + f0, live ? kMelWin : 0, t);
+      const int fr = c0 * kMelGroups + grp;
+      load_real<PL>(vn, A.y + yo + (fr < F ? fr * kMelHop : 0), fr < F ? kMelWin : 0, t);
+    }
+    for (int c = c0; c < c1; ++c) {
+      const int fr = c * kMelGroups + grp;
+      const bool live = fr < F;
+      cf v[PL::P];
 #pragma unroll
       for (int r = 0; r < PL::P; ++r) {
         const int n = 2 * (t + r * PL::T);
-        v[r] = mk(v[r].x * g_hann[n], v[r].y * g_hann[n + 1]);
+        v[r] = mk(vn[r].x * g_hann[n], vn[r].y * g_hann[n + 1]);
       }
-    }
-    Xch<PL> lds{lds_raw[grp], 0};
-    Fft<PL>::forward(v, lds, tw, t);
-    Fft<PL>::post(v, tw, t);  // 2 X
+      if (c + 1 < c1) {
+        const int fn = fr + kMelGroups;
+        load_real<PL>(vn, A.y + yo + (fn < F ? fn * kMelHop : 0), fn < F ? kMelWin : 0, t);
+      }
+      Xch<PL> lds{lds_raw[grp], 0};
+      Fft<PL>::forward(v, lds, tw, t);
+      Fft<PL>::post(v, tw, t);  // 2 X
 #pragma unroll
-    for (int q = 0; q < PL::P; ++q) {
-      if (t == 0 && q == Fft<PL>::SP) {
-        pw[grp][0] = 0.25f * v[q].x * v[q].x;
-        pw[grp][PL::M] = 0.25f * v[q].y * v[q].y;
-      } else {
-        pw[grp][slot_bin<PL>(q, t)] = 0.25f * (v[q].x * v[q].x + v[q].y * v[q].y);
+      for (int q = 0; q < PL::P; ++q) {
+        if (t == 0 && q == Fft<PL>::SP) {
+          pw[grp][0] = 0.25f * v[q].x * v[q].x;
+          pw[grp][PL::M] = 0.25f * v[q].y * v[q].y;
+        } else {
+          pw[grp][slot_bin<PL>(q, t)] = 0.25f * (v[q].x * v[q].x + v[q].y * v[q].y);
+        }
       }
-    }
-    __syncthreads();
-    if (live) {
-      float* out = A.feat + fo + ((long long)j * cap + fr) * kMelBands;
+      __syncthreads();
+      if (live) {
+        float* out = A.feat + fo + ((long long)j * cap + fr) * kMelBands;
 #pragma unroll
-      for (int k = 0; k < kMelBands / 32; ++k) {
-        const int band = t + 32 * k;
-        const int first = g_mel_first[band], n = g_mel_count[band], o = g_mel_off[band];
-        float m = 0.f;
-        for (int i = 0; i < n; ++i) m = __builtin_fmaf(g_mel_w[o + i], pw[grp][first + i], m);
-        out[band] = logf(m + 1e-6f);
+        for (int k = 0; k < kMelBands / 32; ++k) {
+          const int band = t + 32 * k;
+          const int first = s_first[band], n = s_count[band], o = s_off[band];
+          float m = 0.f;
+          for (int i = 0; i < n; ++i) m = __builtin_fmaf(s_w[o + i], pw[grp][first + i], m);
+          out[band] = logf(m + 1e-6f);
+        }
       }
+      __syncthreads();  // pw is read before the next chunk writes it
     }
-    __syncthreads();  // pw is read before the next item writes it
   }
   if (err && tid == 0) flag_status(err);
 }
@@ -2932,7 +2955,7 @@ rsim_status rsim_logmel(const rsim_batch* b, const float* y, float* feat, const 
   const DevState& st = dev_state();
   const int cus = st.cus > 0 ? st.cus : 256;
   const long long items = (long long)b->n_utt * b->n_mic * A.chunks;
-  const unsigned grid = (unsigned)std::max<long long>(1, std::min<long long>(items, (long long)cus * 4));
+  const unsigned grid = (unsigned)std::max<long long>(1, std::min<long long>(items, (long long)cus * 16));
   hipLaunchKernelGGL(logmel_kernel, dim3(grid), dim3(kMelGroups * 32), 0, stream, A);
   return hipGetLastError() == hipSuccess ? RSIM_OK : clear_error(RSIM_EDEVICE);
 }
