@@ -293,6 +293,22 @@ rsim_status rsim_snr_gains_reverb(const double* energy, const double* snr_db, in
 rsim_status rsim_logmel(const rsim_batch* b, const float* y, float* feat, const int64_t* feat_off, int64_t feat_len,
                         int32_t max_frames, hipStream_t stream);
 
+/*
+ * Full-length FFT filtering, Sec. 2.2 eqs. 4-5 (the method the paper starts
+ * from; overlap-add replaces it): for every utterance and mic,
+ *   y_j = IFFT_N( sum_i alpha_ij FFT_N(h_ij) FFT_N(x_i) )[0, T_u),
+ * N = 2^fft_log2n >= Nx + Lmax - 1 (the caller's bound for the whole batch;
+ * an utterance it does not fit, or whose T_u exceeds its output stride, is
+ * skipped with RSIM_DEV_BADPLAN and out_len 0), with the cut lengths in
+ * b->rir_len (call after the cut).  The transforms are batched global-memory
+ * passes over `chunk` utterances at a time; ws must hold
+ * rsim_fft_filter_workspace_bytes(b, fft_log2n, chunk) bytes.  Writes y and
+ * out_len like rsim_mix.  1 <= fft_log2n <= 20, chunk >= 1 (RSIM_EINVAL).
+ */
+size_t rsim_fft_filter_workspace_bytes(const rsim_batch* b, int32_t fft_log2n, int32_t chunk);
+rsim_status rsim_fft_filter(const rsim_batch* b, const float* x, const float* h, const float* alpha, float* y,
+                            int32_t fft_log2n, int32_t chunk, void* ws, size_t ws_bytes, hipStream_t stream);
+
 /* Read and clear the device status word (synchronises the device). */
 rsim_status rsim_device_status(int32_t* status);
 

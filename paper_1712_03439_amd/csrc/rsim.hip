@@ -1692,6 +1692,157 @@ __global__ __launch_bounds__(kImgThreads) void image_kernel(ImageArgs A) {
   if (err && t == 0) flag_status(err);
 }
 
+// ============================================ full-length FFT filtering
+// Eqs. 4-5: every signal is transformed whole, with N = 2^m >= Nx + L - 1
+// points (up to 2^20), beyond what one workgroup holds in LDS, so the
+// transform is a sequence of batched Stockham passes over global memory
+// (radix 4, and one radix 2 when m is odd): pass s with span Ls reads
+// butterfly j's inputs at j + r N/R, twists them by W^(r (j mod Ls)) with
+// W = exp(-/+ 2 pi i / (R Ls)) and writes its outputs at
+// (j - j mod Ls) R + (j mod Ls) + r Ls; after the last pass the spectrum is in
+// natural order.  Real signals go in as complex with zero imaginary part.
+// Per utterance and mic the spectra are summed over sources (linearity), so
+// one inverse per mic.  This is the paper's slower rung, kept for comparison.
+constexpr int kFfThreads = 256;
+
+template <int R, bool INV>
+__global__ __launch_bounds__(kFfThreads) void ff_pass_kernel(const cf* __restrict__ in, cf* __restrict__ out, int log2n,
+                                                            int Ls, int count) {
+  const long long N = 1LL << log2n;
+  const long long nbf = N / R;
+  const long long total = nbf * count;
+  for (long long g = (long long)blockIdx.x * kFfThreads + threadIdx.x; g < total;
+       g += (long long)gridDim.x * kFfThreads) {
+    const long long c = g / nbf, j = g - c * nbf;
+    const cf* src = in + c * N;
+    cf* dst = out + c * N;
+    const long long k = j & (Ls - 1);
+    cf v[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[r] = src[j + r * nbf];
+    // twiddles W^(r k), angle -/+ 2 pi r k / (R Ls) from an exact ratio
+#pragma unroll
+    for (int r = 1; r < R; ++r) {
+      const float a = (float)(r * k) / (float)(R * Ls);  // r k < 2^24: exact
+      float sn, cs;
+      sincospif(2.0f * a, &sn, &cs);
+      if (!INV) sn = -sn;
+      v[r] = mk(v[r].x * cs - v[r].y * sn, v[r].x * sn + v[r].y * cs);
+    }
+    cf o[R];
+    if constexpr (R == 2) {
+      o[0] = mk(v[0].x + v[1].x, v[0].y + v[1].y);
+      o[1] = mk(v[0].x - v[1].x, v[0].y - v[1].y);
+    } else {
+      const cf s0 = mk(v[0].x + v[2].x, v[0].y + v[2].y), d0 = mk(v[0].x - v[2].x, v[0].y - v[2].y);
+      const cf s1 = mk(v[1].x + v[3].x, v[1].y + v[3].y), d1 = mk(v[1].x - v[3].x, v[1].y - v[3].y);
+      // -i d1 forward, +i d1 inverse
+      const cf e1 = INV ? mk(-d1.y, d1.x) : mk(d1.y, -d1.x);
+      o[0] = mk(s0.x + s1.x, s0.y + s1.y);
+      o[2] = mk(s0.x - s1.x, s0.y - s1.y);
+      o[1] = mk(d0.x + e1.x, d0.y + e1.y);
+      o[3] = mk(d0.x - e1.x, d0.y - e1.y);
+    }
+    const long long base = (j - k) * R + k;
+#pragma unroll
+    for (int r = 0; r < R; ++r) dst[base + (long long)r * Ls] = o[r];
+  }
+}
+
+struct FfArgs {
+  BatchDev b;
+  const float* x;
+  const float* h;
+  const float* alpha;
+  float* y;
+  cf* X;    // [C][S][N] source spectra
+  cf* H;    // [C][S][N] RIR spectra of one mic
+  cf* Y;    // [C][N] one mic's spectrum
+  int u0, nu, log2n, j;
+};
+
+// Real signals into complex arrays: kind 0 the sources, 1 the cut RIRs of mic
+// A.j; slots without a signal are zero.  Also checks N >= Nx + Lmax - 1.
+__global__ __launch_bounds__(kFfThreads) void ff_load_kernel(FfArgs A, int kind) {
+  const BatchDev& b = A.b;
+  const long long N = 1LL << A.log2n;
+  const long long total = (long long)A.nu * b.S * N;
+  cf* dst = kind == 0 ? A.X : A.H;
+  for (long long g = (long long)blockIdx.x * kFfThreads + threadIdx.x; g < total;
+       g += (long long)gridDim.x * kFfThreads) {
+    const long long slot = g / N, n = g - slot * N;
+    const int cu = (int)(slot / b.S), i = (int)(slot - (long long)cu * b.S);
+    const int u = A.u0 + cu;
+    const int I = b.n_src[u];
+    float v = 0.f;
+    if (i < I && I <= b.S) {
+      if (kind == 0) {
+        const long long so = b.src_off[(long long)u * b.S + i];
+        const int Nx = b.src_len[u];
+        if (n < Nx && so >= 0 && so + Nx <= b.x_len) v = A.x[so + n];
+      } else {
+        const long long r = ((long long)u * b.S + i) * b.J + A.j;
+        const long long ro = b.rir_off[r];
+        const int L = b.rir_len[r];
+        if (n < L && ro >= 0 && ro + L <= b.h_len) v = A.h[ro + n];
+      }
+    }
+    dst[g] = mk(v, 0.f);
+  }
+}
+
+// Y[c] = sum_i alpha_ij H[c][i] X[c][i] for mic A.j.
+__global__ __launch_bounds__(kFfThreads) void ff_mac_kernel(FfArgs A) {
+  const BatchDev& b = A.b;
+  const long long N = 1LL << A.log2n;
+  const long long total = (long long)A.nu * N;
+  for (long long g = (long long)blockIdx.x * kFfThreads + threadIdx.x; g < total;
+       g += (long long)gridDim.x * kFfThreads) {
+    const int cu = (int)(g / N);
+    const long long k = g - (long long)cu * N;
+    const int u = A.u0 + cu;
+    const int I = min(b.n_src[u], b.S);
+    float re = 0.f, im = 0.f;
+    for (int i = 0; i < I; ++i) {
+      const float a = A.alpha[((long long)u * b.S + i) * b.J + A.j];
+      const cf hv = A.H[((long long)cu * b.S + i) * N + k], xv = A.X[((long long)cu * b.S + i) * N + k];
+      const float pr = hv.x * xv.x - hv.y * xv.y, pi = hv.x * xv.y + hv.y * xv.x;
+      re = __builtin_fmaf(a, pr, re);
+      im = __builtin_fmaf(a, pi, im);
+    }
+    A.Y[g] = mk(re, im);
+  }
+}
+
+// y_j[n] = Re(Y[n]) / N for n < T_u = Nx + Lmax - 1 (written to out_len with
+// mic 0); an utterance whose T_u exceeds N or its output stride is skipped
+// with RSIM_DEV_BADPLAN.
+__global__ __launch_bounds__(kFfThreads) void ff_store_kernel(FfArgs A) {
+  const BatchDev& b = A.b;
+  const long long N = 1LL << A.log2n;
+  const float sc = 1.0f / (float)N;
+  for (int cu = blockIdx.x; cu < A.nu; cu += gridDim.x) {
+    const int u = A.u0 + cu;
+    const int I = b.n_src[u], Nx = b.src_len[u];
+    int lmax = 0;
+    for (int i = 0; i < min(I, b.S); ++i)
+      for (int j = 0; j < b.J; ++j) lmax = max(lmax, b.rir_len[((long long)u * b.S + i) * b.J + j]);
+    const long long T = (I > 0 && Nx > 0 && lmax > 0) ? (long long)Nx + lmax - 1 : 0;
+    const int stride = b.out_stride[u];
+    if (T > N || T > stride) {
+      if (threadIdx.x == 0 && A.j == 0) {
+        flag_status(RSIM_DEV_BADPLAN);
+        b.out_len[u] = 0;
+      }
+      continue;
+    }
+    if (threadIdx.x == 0 && A.j == 0) b.out_len[u] = (int)T;
+    float* yj = A.y + b.out_off[u] + (long long)A.j * stride;
+    const cf* Y = A.Y + (long long)cu * N;
+    for (long long n = threadIdx.x; n < T; n += kFfThreads) yj[n] = Y[n].x * sc;
+  }
+}
+
 // ================================================= FFT engine test kernels
 // Bin held by slot q of thread t (thread 0 permuted as in Fft::perm_t0; its
 // slot SP holds bins 0 and N/2).
@@ -2957,6 +3108,88 @@ rsim_status rsim_logmel(const rsim_batch* b, const float* y, float* feat, const 
   const long long items = (long long)b->n_utt * b->n_mic * A.chunks;
   const unsigned grid = (unsigned)std::max<long long>(1, std::min<long long>(items, (long long)cus * 16));
   hipLaunchKernelGGL(logmel_kernel, dim3(grid), dim3(kMelGroups * 32), 0, stream, A);
+  return hipGetLastError() == hipSuccess ? RSIM_OK : clear_error(RSIM_EDEVICE);
+}
+
+size_t rsim_fft_filter_workspace_bytes(const rsim_batch* b, int32_t fft_log2n, int32_t chunk) {
+  if (!batch_ok(b) || fft_log2n < 1 || fft_log2n > 20 || chunk < 1) return 0;
+  const size_t N = (size_t)1 << fft_log2n, C = (size_t)chunk, S = (size_t)b->max_src;
+  return (3 * S + 2) * C * N * sizeof(cf);
+}
+
+rsim_status rsim_fft_filter(const rsim_batch* b, const float* x, const float* h, const float* alpha, float* y,
+                            int32_t fft_log2n, int32_t chunk, void* ws, size_t ws_bytes, hipStream_t stream) {
+  if (!batch_ok(b) || fft_log2n < 1 || fft_log2n > 20 || chunk < 1) return RSIM_EINVAL;
+  if (b->n_utt == 0) return RSIM_OK;
+  if (!x || !h || !alpha || !y) return RSIM_EINVAL;
+  const size_t need = rsim_fft_filter_workspace_bytes(b, fft_log2n, chunk);
+  if (!ws || ws_bytes < need) return RSIM_EWORKSPACE;
+  const rsim_status e = ensure_init(stream);
+  if (e != RSIM_OK) return e;
+  const long long N = 1LL << fft_log2n, C = chunk, S = b->max_src;
+  cf* base = static_cast<cf*>(ws);
+  FfArgs A;
+  A.b = to_dev(b);
+  A.x = x;
+  A.h = h;
+  A.alpha = alpha;
+  A.y = y;
+  A.X = base;
+  A.H = A.X + C * S * N;
+  cf* tmp = A.H + C * S * N;
+  A.Y = tmp + C * S * N;
+  A.log2n = fft_log2n;
+  const int passes = fft_log2n / 2 + (fft_log2n & 1);
+  const DevState& st = dev_state();
+  const int cus = st.cus > 0 ? st.cus : 256;
+  auto grid_for = [&](long long work) {
+    return dim3((unsigned)std::max<long long>(1, std::min<long long>((work + kFfThreads - 1) / kFfThreads,
+                                                                      (long long)cus * 16)));
+  };
+  // passes over `count` transforms; the data starts in `first` and ends in
+  // `first` after an even number of passes, else in `second`
+  auto fft = [&](cf* first, cf* second, int count, bool inv) {
+    cf* src = first;
+    cf* dst = second;
+    long long Ls = 1;
+    for (int q = 0; q < passes; ++q) {
+      const bool radix2 = (fft_log2n & 1) && q == passes - 1;
+      const long long bf = (N / (radix2 ? 2 : 4)) * count;
+      const void* fn = radix2 ? (inv ? reinterpret_cast<const void*>(&ff_pass_kernel<2, true>)
+                                     : reinterpret_cast<const void*>(&ff_pass_kernel<2, false>))
+                              : (inv ? reinterpret_cast<const void*>(&ff_pass_kernel<4, true>)
+                                     : reinterpret_cast<const void*>(&ff_pass_kernel<4, false>));
+      int ls = (int)Ls, l2 = fft_log2n, cnt = count;
+      void* args[] = {&src, &dst, &l2, &ls, &cnt};
+      if (hipLaunchKernel(fn, grid_for(bf), dim3(kFfThreads), args, 0, stream) != hipSuccess) return false;
+      Ls *= radix2 ? 2 : 4;
+      std::swap(src, dst);
+    }
+    return true;
+  };
+  const bool even = (passes % 2) == 0;
+  for (int u0 = 0; u0 < b->n_utt; u0 += chunk) {
+    A.u0 = u0;
+    A.nu = std::min(chunk, b->n_utt - u0);
+    const int cs = (int)(A.nu * S);
+    // sources: loaded where the passes end in X
+    FfArgs L = A;
+    L.X = even ? A.X : tmp;
+    hipLaunchKernelGGL(ff_load_kernel, grid_for((long long)cs * N), dim3(kFfThreads), 0, stream, L, 0);
+    if (!fft(L.X, even ? tmp : A.X, cs, false)) return clear_error(RSIM_EDEVICE);
+    for (int j = 0; j < b->n_mic; ++j) {
+      A.j = j;
+      L = A;
+      L.H = even ? A.H : tmp;
+      hipLaunchKernelGGL(ff_load_kernel, grid_for((long long)cs * N), dim3(kFfThreads), 0, stream, L, 1);
+      if (!fft(L.H, even ? tmp : A.H, cs, false)) return clear_error(RSIM_EDEVICE);
+      L = A;
+      L.Y = even ? A.Y : tmp;
+      hipLaunchKernelGGL(ff_mac_kernel, grid_for((long long)A.nu * N), dim3(kFfThreads), 0, stream, L);
+      if (!fft(L.Y, even ? tmp : A.Y, A.nu, true)) return clear_error(RSIM_EDEVICE);
+      hipLaunchKernelGGL(ff_store_kernel, dim3((unsigned)A.nu), dim3(kFfThreads), 0, stream, A);
+    }
+  }
   return hipGetLastError() == hipSuccess ? RSIM_OK : clear_error(RSIM_EDEVICE);
 }
 

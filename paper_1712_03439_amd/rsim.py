@@ -8,6 +8,7 @@ there is no fallback of any kind when it is missing.
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 from typing import Optional, Sequence
 
@@ -25,7 +26,8 @@ EXPORTS = (
     "rsim_ola_workspace_bytes", "rsim_ola_convolve", "rsim_mix_workspace_bytes", "rsim_mix",
     "rsim_simulate", "rsim_mix_backward", "rsim_source_power", "rsim_snr_gains",
     "rsim_device_status", "rsim_rfft", "rsim_irfft", "rsim_image_rir", "rsim_simulate_rooms",
-    "rsim_reverb_energy", "rsim_snr_gains_reverb", "rsim_logmel",
+    "rsim_reverb_energy", "rsim_snr_gains_reverb", "rsim_logmel", "rsim_fft_filter_workspace_bytes",
+    "rsim_fft_filter",
 )
 
 
@@ -86,6 +88,8 @@ def _lib():
             "rsim_reverb_energy": ([bp, vp, vp, vp, vp], i32),
             "rsim_snr_gains_reverb": ([vp, vp, i32, i32, vp], i32),
             "rsim_logmel": ([bp, vp, vp, vp, i64, i32, vp], i32),
+            "rsim_fft_filter_workspace_bytes": ([bp, i32, i32], sz),
+            "rsim_fft_filter": ([bp, vp, vp, vp, vp, i32, i32, vp, sz, vp], i32),
         }
         for name, (args, res) in sig.items():
             fn = getattr(lib, name)
@@ -289,6 +293,33 @@ def logmel(db: DeviceBatch, y, stream=None):
     _check(_lib().rsim_logmel(ctypes.byref(s), _ptr(y), _ptr(feat), _ptr(db.mel_off), int(feat.numel()),
                               int(cap.max()) if cap.size else 0, _stream(stream)), "rsim_logmel")
     return feat, off, cap
+
+
+def fft_filter_log2n(db: DeviceBatch) -> int:
+    """The smallest transform size (log2) that holds every utterance's whole
+    convolution with its uncut RIRs (a bound for any cut)."""
+    b = db.host
+    L0 = np.asarray(b.rir_len0, np.int64).reshape(db.U, db.S * db.J).max(axis=1) if db.U else np.zeros(0)
+    need = int(np.max(np.asarray(b.src_len, np.int64) + L0 - 1)) if db.U else 1
+    return max(1, int(math.ceil(math.log2(max(need, 2)))))
+
+
+def fft_filter(db: DeviceBatch, alpha, y=None, fft_log2n: Optional[int] = None, chunk: int = 16, ws=None,
+               stream=None):
+    """Eqs. 4-5: full-length FFT filtering and mixing of the batch (after the
+    cut), for comparison with the overlap-add path."""
+    torch = _torch()
+    _require_cuda(alpha)
+    if y is None:
+        y = db.new_output()
+    l2 = fft_filter_log2n(db) if fft_log2n is None else int(fft_log2n)
+    s = db.struct()
+    n = int(_lib().rsim_fft_filter_workspace_bytes(ctypes.byref(s), l2, int(chunk)))
+    if ws is None or ws.numel() < n:
+        ws = torch.empty(max(n, 1), dtype=torch.uint8, device=db.device)
+    _check(_lib().rsim_fft_filter(ctypes.byref(s), _ptr(db.x), _ptr(db.h), _ptr(alpha), _ptr(y), l2, int(chunk),
+                                  _ptr(ws), int(ws.numel()), _stream(stream)), "rsim_fft_filter")
+    return y
 
 
 def snr_gains(p_dry: Sequence[float], snr_db: Sequence[float], n_mic: int) -> np.ndarray:

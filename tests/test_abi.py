@@ -249,3 +249,16 @@ def test_reverb_energy_and_gain_validation():
     got = rsim.snr_gains_reverb(E, snr)
     ref = oracle.snr_gains_reverb(E, snr).astype(np.float32)
     assert np.allclose(got, ref, rtol=2e-7, atol=0)
+
+
+def test_fft_filter_validation_codes():
+    lib = rsim.lib()
+    p = ctypes.c_void_p(8)
+    b = _host_batch()
+    need = lib.rsim_fft_filter_workspace_bytes(ctypes.byref(b), 12, 4)
+    assert need == (3 * 2 + 2) * 4 * 4096 * 8
+    for l2, chunk in ((0, 4), (21, 4), (12, 0)):
+        assert lib.rsim_fft_filter_workspace_bytes(ctypes.byref(b), l2, chunk) == 0
+        assert lib.rsim_fft_filter(ctypes.byref(b), p, p, p, p, l2, chunk, p, need, None) == rsim.RSIM_EINVAL
+    assert lib.rsim_fft_filter(ctypes.byref(b), p, p, p, p, 12, 4, p, need - 1, None) == rsim.RSIM_EWORKSPACE
+    assert lib.rsim_fft_filter(ctypes.byref(b), None, p, p, p, 12, 4, p, need, None) == rsim.RSIM_EINVAL

@@ -1,0 +1,83 @@
+"""Full-length FFT filtering (eqs. 4-5) on the GPU against the FP64 oracle.
+
+Bar: per (utterance, mic), max |y_gpu - y_ref| <= 1e-5 max |y_ref| (float32
+transforms of up to 2^18 points: about log2 N roundings of float32 per sample
+relative to the peak)."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests.gpu_util import TOL, cuda, max_rel_err
+
+
+def _run(b, eta, fft_log2n=None, chunk=3):
+    torch = cuda()
+    from paper_1712_03439_amd import rsim
+
+    db = rsim.DeviceBatch(b)
+    alpha = torch.from_numpy(rsim.batch_gains(db, b.snr_db)).cuda()
+    rsim.truncate_batch(db, eta)
+    y = rsim.fft_filter(db, alpha, fft_log2n=fft_log2n, chunk=chunk)
+    torch.cuda.synchronize()
+    return y.cpu().numpy(), db.rir_len.cpu().numpy(), db.out_len.cpu().numpy(), alpha.cpu().numpy()
+
+
+def _check(b, eta, y, rl, ol, alpha, utts):
+    S, J = b.max_src, b.n_mic
+    for u in utts:
+        xs, hs = b.sources(u), b.rirs(u)
+        I = len(xs)
+        cut = [[np.asarray(hs[i][j], np.float32)[: int(rl[(u * S + i) * J + j])] for j in range(J)] for i in range(I)]
+        a = alpha[u * S * J:(u * S + I) * J].reshape(I, J).astype(np.float64)
+        ref = oracle.mix(xs, cut, a)
+        T = ref.shape[1]
+        assert int(ol[u]) == T
+        off, st = int(b.out_off[u]), int(b.out_stride[u])
+        for j in range(J):
+            assert max_rel_err(y[off + j * st: off + j * st + T], ref[j]) <= TOL, (u, j)
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("eta", [20.0, math.inf])
+def test_fft_filter_small_batch(eta):
+    # utterances of 0.1-2 s, 1-4 sources, 3 mics; chunks of 3 (a ragged last one)
+    rng = synth.rng_for(64, int(eta) if eta != math.inf else 1)
+    srcs, rirs, snrs = [], [], []
+    for u in range(7):
+        I = 1 + u % 4
+        n = int(rng.integers(1600, 32000))
+        srcs.append([synth.speech_like(rng, n)] + [synth.pink_noise(rng, n) for _ in range(I - 1)])
+        L0 = int(rng.integers(1, 6000))
+        rirs.append([[synth.rir(rng, L0, 0.4, int(rng.integers(0, 30))) for _ in range(3)] for _ in range(I)])
+        snrs.append([0.0] + [float(v) for v in rng.uniform(0, 30, I - 1)])
+    b = synth.pack(srcs, rirs, snrs, 3)
+    y, rl, ol, alpha = _run(b, eta)
+    _check(b, eta, y, rl, ol, alpha, range(b.n_utt))
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("l2", [15, 16, 18])
+def test_fft_filter_sizes(l2):
+    # an odd and even number of radix-4 passes, and the paper's 2^17-2^18 range
+    rng = synth.rng_for(65, l2)
+    n = (1 << l2) - 9000
+    srcs = [[synth.speech_like(rng, n), synth.white_noise(rng, n)]]
+    rirs = [[[synth.rir(rng, 8000, 0.5, 40)] * 2, [synth.rir(rng, 3000, 0.3, 10)] * 2]]
+    b = synth.pack(srcs, rirs, [[0.0, 10.0]], 2)
+    y, rl, ol, alpha = _run(b, 20.0, fft_log2n=l2, chunk=1)
+    _check(b, 20.0, y, rl, ol, alpha, [0])
+
+
+@pytest.mark.gpu
+def test_fft_filter_too_small_a_transform_is_flagged():
+    torch = cuda()
+    from paper_1712_03439_amd import rsim
+
+    rng = synth.rng_for(66, 0)
+    b = synth.pack([[synth.speech_like(rng, 5000)]], [[[synth.rir(rng, 200, 0.2, 3)]]], [[0.0]], 1)
+    rsim.device_status()
+    y, rl, ol, alpha = _run(b, math.inf, fft_log2n=12)   # 4096 < 5199
+    assert int(ol[0]) == 0 and rsim.device_status() & rsim.DEV_BADPLAN
