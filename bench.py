@@ -319,6 +319,30 @@ def front_end(torch, rsim, base, db, y, reps: int = 5):
                     "frac": round(tf / FP32_PEAK_TFLOPS, 4)}}
 
 
+def ladder(torch, rsim, base, db, alpha, y, mix_ms, reps: int = 3):
+    """The paper's filtering ladder on the same epoch (Table 1): the
+    full-length FFT filtering of eqs. 4-5 (one transform per signal, batched
+    global-memory passes) against the overlap-add mix timed above."""
+    stream = torch.cuda.Stream()
+    stream.wait_stream(torch.cuda.current_stream())
+    l2 = rsim.fft_filter_log2n(db)
+    with torch.cuda.stream(stream):
+        rsim.fft_filter(db, alpha, y=y, stream=stream)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            rsim.fft_filter(db, alpha, y=y, stream=stream)
+        e1.record(stream)
+    torch.cuda.synchronize()
+    if rsim.device_status():
+        raise RuntimeError("full-length filtering flagged an utterance")
+    ms = e0.elapsed_time(e1) / reps
+    sizes = {f"2^{k}": int(v) for k, v in zip(*np.unique(l2, return_counts=True))}
+    return {"workload": "the batched epoch, each utterance at its own transform size", "fft_sizes": sizes,
+            "full_length_fft_ms": round(ms, 3), "overlap_add_ms": round(mix_ms, 3),
+            "overlap_add_speedup": round(ms / mix_ms, 2)}
+
+
 def large_thresholds(torch, rsim, autotune, synth, dev, etas=(math.inf, 30.0, 20.0, 10.0), reps: int = 3):
     """The large batched workload (4096 utterances of 1-20 s, up to 4 sources,
     8 mics, T60 U(0.1, 1.0) s, RIRs up to 16000 taps) at each cut threshold:
@@ -401,6 +425,7 @@ def main() -> int:
     ap.add_argument("--no-rirgen", action="store_true", help="skip the image-method RIR generation timing")
     ap.add_argument("--no-reverb", action="store_true", help="skip the reverberant-energy (gain rule) timing")
     ap.add_argument("--no-frontend", action="store_true", help="skip the log-Mel front-end timing")
+    ap.add_argument("--no-ladder", action="store_true", help="skip the full-length FFT filtering timing")
     ap.add_argument("--large", action="store_true",
                     help="also time the large batched workload (4096 utterances, 8 mics) at eta = inf, 30, 20, "
                          "10 dB (adds about a minute and 35 GB of GPU memory)")
@@ -635,6 +660,14 @@ def main() -> int:
         log(f"image-method RIRs: {d['ms']:.3f} ms for one epoch's RIRs, {d['rirs_per_s']:.4g} RIRs/s, "
             f"{d['roofline']['frac']:.3f} of the HBM peak; epochs with image-method rooms "
             f"{d['epoch_with_rooms']['ms']:.3f} ms ({d['epoch_with_rooms']['audio_s_per_s']:.4g} audio-s/s)")
+
+    if not args.no_ladder:
+        b_last, db_last, alpha_last = epochs[(W + K - 1) % E]
+        rsim.truncate_batch(db_last, args.eta)
+        result["ladder"] = ladder(torch, rsim, b_last, db_last, alpha_last, y, float(np.mean(mix_ms)))
+        d = result["ladder"]
+        log(f"full-length FFT filtering: {d['full_length_fft_ms']:.2f} ms per epoch "
+            f"(overlap-add {d['overlap_add_ms']:.2f} ms, {d['overlap_add_speedup']:.1f}x)")
 
     if not args.no_reverb:
         b0, db0, _ = epochs[0]

@@ -295,30 +295,44 @@ def logmel(db: DeviceBatch, y, stream=None):
     return feat, off, cap
 
 
-def fft_filter_log2n(db: DeviceBatch) -> int:
-    """The smallest transform size (log2) that holds every utterance's whole
+def fft_filter_log2n(db: DeviceBatch) -> np.ndarray:
+    """Per utterance, the smallest transform size (log2) that holds its whole
     convolution with its uncut RIRs (a bound for any cut)."""
     b = db.host
-    L0 = np.asarray(b.rir_len0, np.int64).reshape(db.U, db.S * db.J).max(axis=1) if db.U else np.zeros(0)
-    need = int(np.max(np.asarray(b.src_len, np.int64) + L0 - 1)) if db.U else 1
-    return max(1, int(math.ceil(math.log2(max(need, 2)))))
+    if not db.U:
+        return np.zeros(0, np.int64)
+    L0 = np.asarray(b.rir_len0, np.int64).reshape(db.U, db.S * db.J).max(axis=1)
+    need = np.maximum(np.asarray(b.src_len, np.int64) + L0 - 1, 2)
+    return np.ceil(np.log2(need)).astype(np.int64)
 
 
-def fft_filter(db: DeviceBatch, alpha, y=None, fft_log2n: Optional[int] = None, chunk: int = 16, ws=None,
-               stream=None):
+def fft_filter(db: DeviceBatch, alpha, y=None, chunk: int = 16, stream=None):
     """Eqs. 4-5: full-length FFT filtering and mixing of the batch (after the
-    cut), for comparison with the overlap-add path."""
+    cut), for comparison with the overlap-add path.  Utterances are grouped
+    by their transform size (fft_filter_log2n); each group is one call."""
     torch = _torch()
     _require_cuda(alpha)
     if y is None:
         y = db.new_output()
-    l2 = fft_filter_log2n(db) if fft_log2n is None else int(fft_log2n)
-    s = db.struct()
-    n = int(_lib().rsim_fft_filter_workspace_bytes(ctypes.byref(s), l2, int(chunk)))
-    if ws is None or ws.numel() < n:
+    l2s = fft_filter_log2n(db)
+    S, J = db.S, db.J
+    for l2 in np.unique(l2s):
+        idx = np.nonzero(l2s == l2)[0]
+        sub = db if idx.size == db.U else db.select(idx)
+        if sub is db:
+            a = alpha
+        else:
+            u = torch.as_tensor(idx, device=db.device)
+            rows = ((u[:, None] * S + torch.arange(S, device=db.device)[None, :])[:, :, None] * J
+                    + torch.arange(J, device=db.device)[None, None, :]).reshape(-1)
+            a = alpha[rows].contiguous()
+        s = sub.struct()
+        n = int(_lib().rsim_fft_filter_workspace_bytes(ctypes.byref(s), int(l2), int(chunk)))
         ws = torch.empty(max(n, 1), dtype=torch.uint8, device=db.device)
-    _check(_lib().rsim_fft_filter(ctypes.byref(s), _ptr(db.x), _ptr(db.h), _ptr(alpha), _ptr(y), l2, int(chunk),
-                                  _ptr(ws), int(ws.numel()), _stream(stream)), "rsim_fft_filter")
+        _check(_lib().rsim_fft_filter(ctypes.byref(s), _ptr(db.x), _ptr(db.h), _ptr(a), _ptr(y), int(l2), int(chunk),
+                                      _ptr(ws), int(ws.numel()), _stream(stream)), "rsim_fft_filter")
+        if sub is not db:
+            db.out_len[torch.as_tensor(idx, device=db.device)] = sub.out_len
     return y
 
 

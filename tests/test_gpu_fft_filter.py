@@ -20,7 +20,19 @@ def _run(b, eta, fft_log2n=None, chunk=3):
     db = rsim.DeviceBatch(b)
     alpha = torch.from_numpy(rsim.batch_gains(db, b.snr_db)).cuda()
     rsim.truncate_batch(db, eta)
-    y = rsim.fft_filter(db, alpha, fft_log2n=fft_log2n, chunk=chunk)
+    if fft_log2n is None:
+        y = rsim.fft_filter(db, alpha, chunk=chunk)   # grouped by transform size
+    else:
+        import ctypes
+
+        y = db.new_output()
+        s = db.struct()
+        n = int(rsim.lib().rsim_fft_filter_workspace_bytes(ctypes.byref(s), fft_log2n, chunk))
+        ws = torch.empty(max(n, 1), dtype=torch.uint8, device="cuda")
+        code = rsim.lib().rsim_fft_filter(ctypes.byref(s), db.x.data_ptr(), db.h.data_ptr(), alpha.data_ptr(),
+                                          y.data_ptr(), fft_log2n, chunk, ws.data_ptr(), ws.numel(),
+                                          torch.cuda.current_stream().cuda_stream)
+        assert code == rsim.RSIM_OK
     torch.cuda.synchronize()
     return y.cpu().numpy(), db.rir_len.cpu().numpy(), db.out_len.cpu().numpy(), alpha.cpu().numpy()
 
