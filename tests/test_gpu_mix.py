@@ -301,6 +301,25 @@ def test_large_workload_subset_sampled(eta):
 
 
 @pytest.mark.gpu
+@pytest.mark.parametrize("graph", [True, False])
+def test_large_workload_sizes_per_utterance(graph):
+    # the large workload without a cut takes a size per utterance (16384 for
+    # the shorter RIRs, 32768 for the longest), several kernel families in
+    # one graph or concurrently on the side streams
+    from paper_1712_03439_amd import autotune, rsim
+
+    b = _large_subset(16, 77)
+    f, m = autotune.model_costs()
+    tune = rsim.tune_table(f, m, one_size=False)
+    db, alpha, y, rl, ol = _simulate(b, math.inf, tune=tune, use_graph=graph)
+    L = rl.reshape(b.n_utt, -1).max(axis=1)
+    shapes = [(int(b.src_len[u]), int(b.n_src[u]), b.n_mic, int(L[u])) for u in range(b.n_utt)]
+    sizes = {autotune.utterance_log2n(*sh, f, m) for sh in shapes}
+    assert len(sizes) >= 2, sizes
+    _sampled_check(b, math.inf, y, rl, ol, range(b.n_utt), 32, 8)
+
+
+@pytest.mark.gpu
 def test_batched_workload_full_size_sampled():
     # the whole 2048-utterance epoch in the benchmark's launch configuration:
     # LPT order, the tuner's table measured on the cut batch (FFT size and
