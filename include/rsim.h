@@ -79,6 +79,12 @@ typedef struct rsim_batch {
   const int32_t* order;   /* [U] or NULL: processing order, longest work first */
   const int32_t* fft_log2n; /* [U] or NULL: forced log2 FFT size per utterance (9..15) */
   const int32_t* hop;     /* [U] or NULL: forced block hop; default N - max L + 1 */
+  int32_t fft_sizes;      /* (host) with fft_log2n: bit m set for every forced size
+                           * 2^m that occurs (m = 9..15), so that only those kernel
+                           * families are sized and launched; an utterance forced to
+                           * a size whose bit is clear is skipped with
+                           * RSIM_DEV_BADPLAN.  0: not stated, every size is
+                           * provided for.  Ignored without fft_log2n. */
 } rsim_batch;
 
 /*

@@ -161,6 +161,7 @@ def measure(db, alpha, sizes=LOG2N, reps: int = 3, min_probe: int = 64, stream=N
         idx = [sh[0] for sh in rows]
         probe = db.select(idx)
         probe.fft_log2n = torch.full((probe.U,), m, dtype=torch.int32, device=dev)
+        probe.fft_sizes = 1 << m
         probe.hop = None
         u = torch.as_tensor(np.asarray(idx, np.int64), device=dev)
         slot = (u[:, None] * S + torch.arange(S, device=dev)[None, :]).reshape(-1)

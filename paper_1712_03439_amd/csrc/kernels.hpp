@@ -45,6 +45,7 @@ struct BatchDev {
   const int* order;
   const int* fft_log2n;
   const int* hop;
+  int fft_sizes;  // bit m: forced size 2^m provided for; 0 = every size
 };
 
 struct TuneDev {

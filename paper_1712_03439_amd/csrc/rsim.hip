@@ -268,6 +268,8 @@ __device__ Sched plan_utterance(const BatchDev& b, const TuneDev& tune, int u, i
   int l2 = 0;
   if (b.fft_log2n) {
     l2 = b.fft_log2n[u];
+    // a forced size outside the stated set has no kernel family launched
+    if (b.fft_sizes && l2 >= 9 && l2 <= 15 && !((b.fft_sizes >> l2) & 1)) l2 = 0;
   } else if (batch_l2) {
     l2 = batch_l2;
   } else {
@@ -2326,8 +2328,10 @@ TuneDev to_dev(const rsim_tune* tune) {
 // Families that may receive work.
 void families_used(const rsim_batch* b, const TuneDev& td, bool used[kNumFam]) {
   for (int f = 0; f < kNumFam; ++f) used[f] = false;
-  for (int m = 9; m <= 15; ++m)
-    if (b->fft_log2n || td.cost_fft[m - 9] > 0.f) used[family_of_log2n(m)] = true;
+  for (int m = 9; m <= 15; ++m) {
+    const bool on = b->fft_log2n ? (b->fft_sizes == 0 || ((b->fft_sizes >> m) & 1)) : td.cost_fft[m - 9] > 0.f;
+    if (on) used[family_of_log2n(m)] = true;
+  }
 }
 
 struct WsLayout {
@@ -2419,6 +2423,7 @@ BatchDev to_dev(const rsim_batch* b) {
   d.order = b->order;
   d.fft_log2n = b->fft_log2n;
   d.hop = b->hop;
+  d.fft_sizes = b->fft_sizes;
   return d;
 }
 
@@ -2897,6 +2902,7 @@ size_t rsim_ola_workspace_bytes(int32_t fft_n) {
   b.max_src = 1;
   int32_t dummy = 0;
   b.fft_log2n = &dummy;  // marks a forced size
+  b.fft_sizes = 1 << l2;
   (void)ensure_init(nullptr);
   return align256(sizeof(OlaDesc)) + layout(&b, default_tune(), false, dev_state()).total;
 }
@@ -2936,6 +2942,7 @@ rsim_status rsim_ola_convolve(const float* x, int32_t nx, const float* h, int32_
   b.out_len = &d->out_len;
   b.order = nullptr;
   b.fft_log2n = &d->log2n;
+  b.fft_sizes = 1 << l2;
   b.hop = &d->hop;
   const TuneDev td = default_tune();
   const BatchDev bd = to_dev(&b);

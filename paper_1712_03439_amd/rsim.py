@@ -47,6 +47,7 @@ class RsimBatch(ctypes.Structure):
         ("rir_off", ctypes.c_void_p), ("rir_len0", ctypes.c_void_p), ("rir_len", ctypes.c_void_p),
         ("out_off", ctypes.c_void_p), ("out_stride", ctypes.c_void_p), ("out_len", ctypes.c_void_p),
         ("order", ctypes.c_void_p), ("fft_log2n", ctypes.c_void_p), ("hop", ctypes.c_void_p),
+        ("fft_sizes", ctypes.c_int32),
     ]
 
 
@@ -389,6 +390,7 @@ class DeviceBatch:
         self.out_len = torch.zeros(self.U, dtype=torch.int32, device=dev)
         self.order = None if order is None else t(order, torch.int32)
         self.fft_log2n = None if fft_log2n is None else t(fft_log2n, torch.int32)
+        self.fft_sizes = size_bits(fft_log2n)
         self.hop = None if hop is None else t(hop, torch.int32)
         self.x = t(b.x, torch.float32) if upload_data else None
         self.h = t(b.h, torch.float32) if upload_data else None
@@ -429,6 +431,7 @@ class DeviceBatch:
             rank[self.order.long()] = torch.arange(self.U, dtype=rank.dtype, device=dev)
             sub.order = torch.argsort(rank[u], stable=True).to(torch.int32)
         sub.fft_log2n = None if self.fft_log2n is None else self.fft_log2n[u].contiguous()
+        sub.fft_sizes = self.fft_sizes
         sub.hop = None if self.hop is None else self.hop[u].contiguous()
         sub.x, sub.h = self.x, self.h
         sub.x_len, sub.h_len, sub.y_len = self.x_len, self.h_len, self.y_len
@@ -445,6 +448,7 @@ class DeviceBatch:
         s.rir_len = _ptr(self.rir_len if rir_len is None else rir_len)
         s.out_off, s.out_stride, s.out_len = _ptr(self.out_off), _ptr(self.out_stride), _ptr(self.out_len)
         s.order, s.fft_log2n, s.hop = _ptr(self.order), _ptr(self.fft_log2n), _ptr(self.hop)
+        s.fft_sizes = self.fft_sizes if self.fft_log2n is not None else 0
         return s
 
     def workspace_bytes(self, tune: Optional[RsimTune] = None, backward: bool = False) -> int:
@@ -460,6 +464,19 @@ class DeviceBatch:
     def new_output(self):
         torch = _torch()
         return torch.empty(max(self.y_len, 1), dtype=torch.float32, device=self.device)
+
+
+def size_bits(fft_log2n) -> int:
+    """The descriptor's fft_sizes word for forced sizes given on the host: bit
+    m for every log2 size m in 9..15 that occurs (0 when none is given, which
+    leaves every size provided for)."""
+    if fft_log2n is None:
+        return 0
+    bits = 0
+    for m in np.unique(np.asarray(fft_log2n)):
+        if 9 <= int(m) <= 15:
+            bits |= 1 << int(m)
+    return bits
 
 
 def _one(db: DeviceBatch, u: int) -> RsimBatch:

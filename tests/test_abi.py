@@ -262,3 +262,49 @@ def test_fft_filter_validation_codes():
         assert lib.rsim_fft_filter(ctypes.byref(b), p, p, p, p, l2, chunk, p, need, None) == rsim.RSIM_EINVAL
     assert lib.rsim_fft_filter(ctypes.byref(b), p, p, p, p, 12, 4, p, need - 1, None) == rsim.RSIM_EWORKSPACE
     assert lib.rsim_fft_filter(ctypes.byref(b), None, p, p, p, 12, 4, p, need, None) == rsim.RSIM_EINVAL
+
+
+def test_binding_structs_match_the_header(tmp_path):
+    # every field offset and the size of the ctypes mirrors of rsim_batch and
+    # rsim_tune, as the C compiler lays out the declarations in include/
+    import shutil
+    import subprocess
+
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("no C compiler")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    lines = []
+    for cname, cls in (("rsim_batch", rsim.RsimBatch), ("rsim_tune", rsim.RsimTune)):
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in cls._fields_:
+            lines.append(f'printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    src = tmp_path / "layout.c"
+    src.write_text('#include <stdio.h>\n#include "rsim.h"\nint main(void) {\n' + "\n".join(lines) +
+                   "\nreturn 0;\n}\n")
+    exe = tmp_path / "layout"
+    subprocess.run([gcc, "-std=c99", "-D__HIP_PLATFORM_AMD__", "-I", os.path.join(root, "include"),
+                    "-I", "/opt/rocm/include", str(src), "-o", str(exe)], check=True)
+    got = dict(l.rsplit(" ", 1) for l in subprocess.run([str(exe)], check=True, capture_output=True,
+                                                          text=True).stdout.splitlines())
+    for cname, cls in (("rsim_batch", rsim.RsimBatch), ("rsim_tune", rsim.RsimTune)):
+        assert int(got[f"{cname} size"]) == ctypes.sizeof(cls), cname
+        for fname, _ in cls._fields_:
+            assert int(got[f"{cname} {fname}"]) == getattr(cls, fname).offset, (cname, fname)
+
+
+def test_forced_sizes_hint_limits_the_workspace():
+    # with forced sizes, fft_sizes names the sizes in use: only their kernel
+    # families get scratch; 0 provides for every size
+    lib = rsim.lib()
+    b = _host_batch()
+    b.fft_log2n = ctypes.c_void_p(8).value
+    b.fft_sizes = 0
+    every = lib.rsim_mix_workspace_bytes(ctypes.byref(b), None, 0)
+    b.fft_sizes = 1 << 14
+    one = lib.rsim_mix_workspace_bytes(ctypes.byref(b), None, 0)
+    assert 0 < one < every
+    b.fft_sizes = (1 << 14) | (1 << 12)
+    two = lib.rsim_mix_workspace_bytes(ctypes.byref(b), None, 0)
+    assert one < two < every
+    assert rsim.size_bits(None) == 0 and rsim.size_bits(np.array([14, 12, 14, 16, 8])) == (1 << 14) | (1 << 12)

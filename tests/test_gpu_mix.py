@@ -226,6 +226,26 @@ def test_graph_and_eager_calls_agree_across_families():
             ref = outs[0][off + j * st: off + j * st + T]
             for k in range(1, len(outs)):
                 assert np.array_equal(outs[k][off + j * st: off + j * st + T], ref), (k, u, j)
+    # the descriptor states the forced sizes (binding default): launching
+    # every family instead gives the same bits; a size left out of the stated
+    # set skips its utterance with BADPLAN and leaves the others as they were
+    assert db.fft_sizes == sum(1 << m for m in set(sizes))
+    rsim.device_status()
+    for bits, skip in ((0, None), (db.fft_sizes & ~(1 << 15), sizes.index(15))):
+        db.fft_sizes = bits
+        y = torch.full((max(db.y_len, 1),), float("nan"), device="cuda")
+        rsim.mix(db, alpha, y=y)
+        torch.cuda.synchronize()
+        y = y.cpu().numpy()
+        assert bool(rsim.device_status() & rsim.DEV_BADPLAN) == (skip is not None)
+        ol2 = db.out_len.cpu().numpy()
+        for u in range(b.n_utt):
+            off, st, T = int(b.out_off[u]), int(b.out_stride[u]), int(ol[u])
+            if u == skip:
+                assert ol2[u] == 0 and np.all(np.isnan(y[off: off + b.n_mic * st]))
+                continue
+            for j in range(b.n_mic):
+                assert np.array_equal(y[off + j * st: off + j * st + T], outs[0][off + j * st: off + j * st + T]), (bits, u, j)
 
 
 @pytest.mark.gpu
