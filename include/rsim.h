@@ -294,7 +294,8 @@ rsim_status rsim_snr_gains_reverb(const double* energy, const double* snr_db, in
  * out_stride[u] samples (frames t >= F_u are not written).  max_frames >=
  * every C_u (host) sizes the launch.  (Stacking four frames and keeping every
  * third, as the paper does next, is a view of these rows.)  A slot whose
- * features would leave [0, feat_len) is skipped with RSIM_DEV_BADDESC.
+ * features would leave [0, feat_len), or whose T_u is 2^29 samples or more,
+ * is skipped with RSIM_DEV_BADDESC.
  */
 rsim_status rsim_logmel(const rsim_batch* b, const float* y, float* feat, const int64_t* feat_off, int64_t feat_len,
                         int32_t max_frames, hipStream_t stream);

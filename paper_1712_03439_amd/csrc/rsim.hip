@@ -35,10 +35,16 @@ __device__ int g_status;
 // Log-Mel front end: periodic Hann window of 512 samples and the 128
 // triangular Mel filters over the 257 bins of a 512-point transform (bands
 // as bin ranges with their weights), filled at init from binary64 values.
-constexpr int kMelWin = 512, kMelHop = 160, kMelBands = 128, kMelBins = kMelWin / 2 + 1, kMelWMax = 2 * kMelBins;
+constexpr int kMelWin = 512, kMelHop = 160, kMelBands = 128, kMelBins = kMelWin / 2 + 1;
+// Nonzero weights of a band, at most, for bands 0-31, 32-63, 64-95, 96-127
+// (the triangles widen with frequency: 2, 3, 6 and 9 bins for this scale).
+constexpr int kMelCap0 = 3, kMelCap1 = 4, kMelCap2 = 7, kMelCap3 = 10, kMelCapMax = 10;
+__device__ __host__ constexpr int mel_cap(int quarter) {
+  return quarter == 0 ? kMelCap0 : quarter == 1 ? kMelCap1 : quarter == 2 ? kMelCap2 : kMelCap3;
+}
 __device__ float g_hann[kMelWin];
-__device__ int g_mel_first[kMelBands], g_mel_count[kMelBands], g_mel_off[kMelBands];
-__device__ float g_mel_w[kMelWMax];
+__device__ int g_mel_first[kMelBands], g_mel_count[kMelBands];
+__device__ float g_mel_w[kMelBands * kMelCapMax];  // band b's weights at [b * kMelCapMax, + count), zero after
 
 __device__ __forceinline__ void flag_status(int bits) { atomicOr(&g_status, bits); }
 
@@ -1918,9 +1924,15 @@ __global__ __launch_bounds__(PL::T) void irfft_kernel(const float* __restrict__ 
 // 125..7500 Hz.  A workgroup holds kMelGroups groups of 32 threads, each
 // group one frame through the 512-point plan (its own LDS exchange buffers;
 // the plan's barriers are the workgroup's, so every group runs the same
-// steps, on zeros when it has no frame).  Power |X_k|^2 goes to LDS and each
-// thread sums four bands over their bins in a fixed order.
+// steps, on zeros when it has no frame).  Power |X_k|^2 goes to LDS (over the
+// group's exchange buffer, free once the transform has its result in
+// registers) and thread t sums bands t, t + 32, t + 64, t + 96 over their
+// bins in bin order.  A thread's window samples and band weights are the same
+// for every frame: they are loaded into registers once, and the band loops
+// have compile-time trip counts (the widest band of each quarter), so all
+// power reads of a frame are in flight together.
 constexpr int kMelGroups = 2;  // one wave: its barriers cost little
+constexpr int kMelMaxT = 1 << 29;  // mic signals shorter than this (byte offsets fit 31 bits)
 constexpr int kMelChunksPerItem = 16;
 
 struct MelArgs {
@@ -1934,24 +1946,48 @@ struct MelArgs {
 
 __device__ __forceinline__ int mel_frames(int T) { return T >= kMelWin ? 1 + (T - kMelWin) / kMelHop : 0; }
 
+// Band energy sum_i w[i] pw[first + i] over i < count (<= CAP), in bin order.
+template <int CAP>
+__device__ __forceinline__ float mel_band(const float* w, const float* pw, int first, int count) {
+  float p[CAP];
+#pragma unroll
+  for (int i = 0; i < CAP; ++i) p[i] = pw[first + i];
+  float m = 0.f;
+#pragma unroll
+  for (int i = 0; i < CAP; ++i) m = i < count ? __builtin_fmaf(w[i], p[i], m) : m;
+  return m;
+}
+
 __global__ __launch_bounds__(kMelGroups * 32) void logmel_kernel(MelArgs A) {
   using PL = PlanOf<9>;
   static_assert(PL::T == 32 && PL::N == kMelWin, "one 512-point plan per group of 32 threads");
   __shared__ cf lds_raw[kMelGroups][Xch<PL>::kEntries];
-  __shared__ float pw[kMelGroups][kMelBins + 7];
-  __shared__ float s_w[kMelWMax];
-  __shared__ int s_first[kMelBands], s_count[kMelBands], s_off[kMelBands];
+  static_assert(2 * Xch<PL>::kEntries >= kMelBins + kMelCapMax, "the power spectrum fits the exchange buffer");
   const int tid = threadIdx.x, grp = tid >> 5, t = tid & 31;
-  // the filterbank in LDS: the band sums below read it in dependent steps
-  for (int k = tid; k < kMelWMax; k += kMelGroups * 32) s_w[k] = g_mel_w[k];
-  for (int k = tid; k < kMelBands; k += kMelGroups * 32) {
-    s_first[k] = g_mel_first[k];
-    s_count[k] = g_mel_count[k];
-    s_off[k] = g_mel_off[k];
+  float hw[2 * PL::P];
+#pragma unroll
+  for (int r = 0; r < PL::P; ++r) {
+    hw[2 * r] = g_hann[2 * (t + r * PL::T)];
+    hw[2 * r + 1] = g_hann[2 * (t + r * PL::T) + 1];
   }
-  __syncthreads();
+  float w0[kMelCap0], w1[kMelCap1], w2[kMelCap2], w3[kMelCap3];
+  int first[4], count[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    first[k] = g_mel_first[t + 32 * k];
+    count[k] = g_mel_count[t + 32 * k];
+  }
+#pragma unroll
+  for (int i = 0; i < kMelCap0; ++i) w0[i] = g_mel_w[(t + 0) * kMelCapMax + i];
+#pragma unroll
+  for (int i = 0; i < kMelCap1; ++i) w1[i] = g_mel_w[(t + 32) * kMelCapMax + i];
+#pragma unroll
+  for (int i = 0; i < kMelCap2; ++i) w2[i] = g_mel_w[(t + 64) * kMelCapMax + i];
+#pragma unroll
+  for (int i = 0; i < kMelCap3; ++i) w3[i] = g_mel_w[(t + 96) * kMelCapMax + i];
   const BatchDev& b = A.b;
   const TwBase tw = Fft<PL>::bases(plan_tw<PL>(), t);
+  float* pw = reinterpret_cast<float*>(lds_raw[grp]);
   // A work item is up to kMelChunksPerItem chunks of kMelGroups frames of one
   // (utterance, mic); the next chunk's frames load while one is transformed.
   const int per_item = (A.chunks + kMelChunksPerItem - 1) / kMelChunksPerItem;
@@ -1967,54 +2003,57 @@ __global__ __launch_bounds__(kMelGroups * 32) void logmel_kernel(MelArgs A) {
     if (c0 * kMelGroups >= F) continue;
     const long long yo = uni64(b.out_off[u]) + (long long)j * stride;
     const long long fo = uni64(A.feat_off[u]);
-    if (T > stride || yo < 0 || yo + T > b.y_len || fo < 0 || fo + (long long)b.J * cap * kMelBands > A.feat_len) {
+    if (T > stride || T >= kMelMaxT || yo < 0 || yo + T > b.y_len || fo < 0 ||
+        fo + (long long)b.J * cap * kMelBands > A.feat_len) {
       if (cb == 0) err |= RSIM_DEV_BADDESC;
       continue;
     }
     const int c1 = min(c0 + kMelChunksPerItem, (F + kMelGroups - 1) / kMelGroups);
+    // One buffer resource for the mic's signal, the same for both groups of
+    // the wave (a per-group base would make the compiler serialise every
+    // load over the groups); a frame is a lane offset into it.  A group
+    // without a frame reads frame 0 (in range, results unused).
+    const rsrc_t ys = make_rsrc(A.y + yo, T * 4);
+    auto load_frame = [&](cf* dst, int fr) __attribute__((always_inline)) {
+      const int vo = opaque_v((fr < F ? fr * kMelHop * 4 : 0) + 8 * t);
+#pragma unroll
+      for (int r = 0; r < PL::P; ++r) dst[r] = ld2(ys, vo, 8 * r * PL::T);
+    };
     cf vn[PL::P];
-    {
-      const int fr = c0 * kMelGroups + grp;
-      load_real<PL>(vn, A.y + yo + (fr < F ? fr * kMelHop : 0), fr < F ? kMelWin : 0, t);
-    }
+    load_frame(vn, c0 * kMelGroups + grp);
     for (int c = c0; c < c1; ++c) {
       const int fr = c * kMelGroups + grp;
       const bool live = fr < F;
       cf v[PL::P];
 #pragma unroll
-      for (int r = 0; r < PL::P; ++r) {
-        const int n = 2 * (t + r * PL::T);
-        v[r] = mk(vn[r].x * g_hann[n], vn[r].y * g_hann[n + 1]);
-      }
-      if (c + 1 < c1) {
-        const int fn = fr + kMelGroups;
-        load_real<PL>(vn, A.y + yo + (fn < F ? fn * kMelHop : 0), fn < F ? kMelWin : 0, t);
-      }
+      for (int r = 0; r < PL::P; ++r) v[r] = mk(vn[r].x * hw[2 * r], vn[r].y * hw[2 * r + 1]);
+      if (c + 1 < c1) load_frame(vn, fr + kMelGroups);
+      __syncthreads();  // the previous chunk's band sums have read pw
       Xch<PL> lds{lds_raw[grp], 0};
       Fft<PL>::forward(v, lds, tw, t);
       Fft<PL>::post(v, tw, t);  // 2 X
+      __syncthreads();  // every exchange read is done before pw overwrites the buffer
 #pragma unroll
       for (int q = 0; q < PL::P; ++q) {
         if (t == 0 && q == Fft<PL>::SP) {
-          pw[grp][0] = 0.25f * v[q].x * v[q].x;
-          pw[grp][PL::M] = 0.25f * v[q].y * v[q].y;
+          pw[0] = 0.25f * v[q].x * v[q].x;
+          pw[PL::M] = 0.25f * v[q].y * v[q].y;
         } else {
-          pw[grp][slot_bin<PL>(q, t)] = 0.25f * (v[q].x * v[q].x + v[q].y * v[q].y);
+          pw[slot_bin<PL>(q, t)] = 0.25f * (v[q].x * v[q].x + v[q].y * v[q].y);
         }
       }
       __syncthreads();
       if (live) {
         float* out = A.feat + fo + ((long long)j * cap + fr) * kMelBands;
-#pragma unroll
-        for (int k = 0; k < kMelBands / 32; ++k) {
-          const int band = t + 32 * k;
-          const int first = s_first[band], n = s_count[band], o = s_off[band];
-          float m = 0.f;
-          for (int i = 0; i < n; ++i) m = __builtin_fmaf(s_w[o + i], pw[grp][first + i], m);
-          out[band] = logf(m + 1e-6f);
-        }
+        const float m0 = mel_band<kMelCap0>(w0, pw, first[0], count[0]);
+        const float m1 = mel_band<kMelCap1>(w1, pw, first[1], count[1]);
+        const float m2 = mel_band<kMelCap2>(w2, pw, first[2], count[2]);
+        const float m3 = mel_band<kMelCap3>(w3, pw, first[3], count[3]);
+        out[t] = logf(m0 + 1e-6f);
+        out[t + 32] = logf(m1 + 1e-6f);
+        out[t + 64] = logf(m2 + 1e-6f);
+        out[t + 96] = logf(m3 + 1e-6f);
       }
-      __syncthreads();  // pw is read before the next chunk writes it
     }
   }
   if (err && tid == 0) flag_status(err);
@@ -2195,30 +2234,28 @@ bool upload_mel_tables() {
   const double m0 = mel(125.0), m1 = mel(7500.0);
   for (int e = 0; e < kMelBands + 2; ++e)
     edges[e] = e == kMelBands + 1 ? hz(m1) : hz(m0 + (m1 - m0) * e / (double)(kMelBands + 1));
-  int first[kMelBands], count[kMelBands], off[kMelBands];
-  std::vector<float> w;
+  int first[kMelBands], count[kMelBands];
+  std::vector<float> w((size_t)kMelBands * kMelCapMax, 0.f);
   for (int b = 0; b < kMelBands; ++b) {
     const double lo = edges[b], c = edges[b + 1], hi = edges[b + 2];
     first[b] = 0;
     count[b] = 0;
-    off[b] = (int)w.size();
     for (int k = 0; k < kMelBins; ++k) {
       const double f = k * 16000.0 / kMelWin;
       const double v = std::max(0.0, std::min((f - lo) / (c - lo), (hi - f) / (hi - c)));
       if (v > 0.0) {
         if (count[b] == 0) first[b] = k;
-        w.push_back((float)v);
+        // the weights of a band are consecutive bins
+        if (count[b] != k - first[b] || count[b] >= mel_cap(b / 32)) return false;
+        w[(size_t)b * kMelCapMax + count[b]] = (float)v;
         ++count[b];
       }
     }
   }
-  if ((int)w.size() > kMelWMax) return false;
-  w.resize(kMelWMax, 0.f);
   return hipMemcpyToSymbol(HIP_SYMBOL(g_hann), hann.data(), sizeof(float) * kMelWin) == hipSuccess &&
          hipMemcpyToSymbol(HIP_SYMBOL(g_mel_first), first, sizeof(first)) == hipSuccess &&
          hipMemcpyToSymbol(HIP_SYMBOL(g_mel_count), count, sizeof(count)) == hipSuccess &&
-         hipMemcpyToSymbol(HIP_SYMBOL(g_mel_off), off, sizeof(off)) == hipSuccess &&
-         hipMemcpyToSymbol(HIP_SYMBOL(g_mel_w), w.data(), sizeof(float) * kMelWMax) == hipSuccess;
+         hipMemcpyToSymbol(HIP_SYMBOL(g_mel_w), w.data(), sizeof(float) * w.size()) == hipSuccess;
 }
 
 rsim_status init_locked(int dev) {
