@@ -261,8 +261,9 @@ def reverb_gains(torch, rsim, dev, base, db, reps: int = 5):
     ms = e0.elapsed_time(e1) / reps
     if not bool(torch.isfinite(e).all()) or rsim.device_status():
         raise RuntimeError("energy computation flagged a slot")
-    # algorithmic work: per source, blocks of hop N - Lmax + 1 with two
-    # transforms each, one inverse, one transform of the window and one per RIR
+    # algorithmic work: per source, one transform per half block of N/2
+    # samples and its spectral product (an add and a multiply-add per bin),
+    # one inverse, one transform of the windowed autocorrelation and one per RIR
     L = db.rir_len.cpu().numpy().astype(np.int64).reshape(base.n_utt, base.max_src, base.n_mic)
     flops, byts = 0.0, 0
     for u in range(base.n_utt):
@@ -275,9 +276,9 @@ def reverb_gains(torch, rsim, dev, base, db, reps: int = 5):
             while (1 << m) < 2 * lmax:
                 m += 1
             N = 1 << m
-            nb = -(-nx // (N - lmax + 1))
+            nb = -(-nx // (N // 2))
             c = 2.5 * N * m
-            flops += nb * (2 * c + 8 * (N / 2 + 1)) + 2 * c + base.n_mic * (c + 4 * (N / 2 + 1))
+            flops += nb * (c + 10 * (N / 2 + 1)) + 2 * c + base.n_mic * (c + 4 * (N / 2 + 1))
             byts += 4 * (nx + int(L[u, i].sum()))
     tf = flops / (ms * 1e-3) / 1e12
     return {"workload": "energies of every (source, mic) pair of the batched epoch after its cut",

@@ -1300,9 +1300,12 @@ __global__ __launch_bounds__(256) void bwd_zero_kernel(BwdArgs A) {
 // frequency domain: with N >= 2 Lmax (Lmax the longest kept RIR of source i),
 // E_ij = (1/N) sum_k |H_ij[k]|^2 S_i[k], S_i the transform of r_xx
 // windowed to |l| < Lmax and made periodic with period N (no aliasing since
-// L + Lmax - 1 <= N).  r_xx up to lag Lmax - 1 is accumulated over blocks of
-// hop N - Lmax + 1: block b correlates x[bB, bB + B) with x[bB, bB + N),
-// which holds every sample its lags need.  One work item per source slot.
+// L + Lmax - 1 <= N).  r_xx up to lag Lmax - 1 is accumulated over half
+// blocks x_b = x[b N/2, (b + 1) N/2): lag l < Lmax <= N/2 pairs a sample of
+// x_b with one of x_b or x_{b+1}, and the window x[b N/2, b N/2 + N) has the
+// spectrum X_b + (-1)^k X_{b+1}, so each half block is transformed once and
+// r_xx = IFFT(sum_b conj(X_b) (X_b + (-1)^k X_{b+1})) on lags [0, Lmax).
+// One work item per source slot.
 struct EnergyArgs {
   BatchDev b;
   const float* x;
@@ -1329,38 +1332,41 @@ __device__ __forceinline__ void energy_source(const EnergyArgs& A, int u, int i,
   const BatchDev& b = A.b;
   const int Nx = uni(b.src_len[u]), J = b.J;
   const long long so = uni64(b.src_off[(long long)u * b.S + i]);
-  const int B = N - lmax + 1, nb = (Nx + B - 1) / B;
-  // With 1024 threads (128 registers each) the next window is not held
+  const int nb = (Nx + M - 1) / M;  // half blocks of M = N/2 samples
+  // (-1)^k for every bin k this thread holds: its bins have the parity of t
+  const float sgn = (t & 1) ? -1.f : 1.f;
+  // With 1024 threads (128 registers each) the next half block is not held
   // while the current one is transformed.
   constexpr bool kPrefetch = T <= 512;
-  cf R[P], Zn[P];
+  cf R[P], Xc[P], Xn[P];
 #pragma unroll
   for (int q = 0; q < P; ++q) R[q] = mk(0.f, 0.f);
-  if (kPrefetch) load_real<PL>(Zn, A.x + so, min(N, Nx), t);
+  load_real<PL>(Xc, A.x + so, min(M, Nx), t);
+  if (kPrefetch && nb > 1) load_real<PL>(Xn, A.x + so + M, min(M, Nx - M), t);
+  Fft<PL>::forward(Xc, lds, tw, t);
+  Fft<PL>::post(Xc, tw, t);
   for (int bk = 0; bk < nb; ++bk) {
-    // Z: the block's window x[bB, bB + N); X: its first B samples (the same
-    // registers with the rest zeroed).  The next window is loaded meanwhile.
-    if (!kPrefetch) load_real<PL>(Zn, A.x + so + bk * B, min(N, Nx - bk * B), t);
-    cf X[P], Z[P];
+    // X: the spectrum of half block bk + 1 (zero past the end)
+    cf X[P];
+    if (bk + 1 < nb) {
+      const int base = (bk + 1) * M;
+      if (!kPrefetch) load_real<PL>(Xn, A.x + so + base, min(M, Nx - base), t);
+#pragma unroll
+      for (int q = 0; q < P; ++q) X[q] = Xn[q];
+      if (kPrefetch && bk + 2 < nb) load_real<PL>(Xn, A.x + so + base + M, min(M, Nx - base - M), t);
+      Fft<PL>::forward(X, lds, tw, t);
+      Fft<PL>::post(X, tw, t);
+    } else {
+#pragma unroll
+      for (int q = 0; q < P; ++q) X[q] = mk(0.f, 0.f);
+    }
 #pragma unroll
     for (int q = 0; q < P; ++q) {
-      Z[q] = Zn[q];
-      const int n0 = 2 * (t + q * T);
-      X[q] = mk(n0 < B ? Zn[q].x : 0.f, n0 + 1 < B ? Zn[q].y : 0.f);
-    }
-    if (kPrefetch && bk + 1 < nb) {
-      const int nbase = (bk + 1) * B;
-      load_real<PL>(Zn, A.x + so + nbase, min(N, Nx - nbase), t);
-    }
-    Fft<PL>::forward(X, lds, tw, t);
-    Fft<PL>::post(X, tw, t);
-    Fft<PL>::forward(Z, lds, tw, t);
-    Fft<PL>::post(Z, tw, t);
-#pragma unroll
-    for (int q = 0; q < P; ++q) {
-      const cf c = cmacc(R[q], X[q], Z[q]);
-      const cf d = mk(__builtin_fmaf(X[q].x, Z[q].x, R[q].x), __builtin_fmaf(X[q].y, Z[q].y, R[q].y));
+      const cf Z = mk(Xc[q].x + sgn * X[q].x, Xc[q].y + sgn * X[q].y);
+      const cf c = cmacc(R[q], Xc[q], Z);
+      const cf d = mk(__builtin_fmaf(Xc[q].x, Z.x, R[q].x), __builtin_fmaf(Xc[q].y, Z.y, R[q].y));
       R[q] = (q == SP && t == 0) ? d : c;
+      Xc[q] = X[q];
     }
   }
   // Both spectra carry a factor 2 and the inverse 2 M: R -> 8 M r_xx.
@@ -1385,12 +1391,23 @@ __device__ __forceinline__ void energy_source(const EnergyArgs& A, int u, int i,
     sv[q] = mk(a, c);
   }
   __syncthreads();  // the windowed autocorrelation is read before the exchanges reuse the LDS
+  // the taps of the first RIR are requested before the transform of s, each
+  // next RIR's before the current one is transformed
+  const long long r0 = ((long long)u * b.S + i) * J;
+  cf Hn[kPrefetch ? P : 1];
+  if constexpr (kPrefetch) load_real<PL>(Hn, A.h + uni64(b.rir_off[r0]), uni(b.rir_len[r0]), t);
   Fft<PL>::forward(sv, lds, tw, t);
   Fft<PL>::post(sv, tw, t);  // 2 S, real (s is real and even)
   for (int j = 0; j < J; ++j) {
-    const long long r = ((long long)u * b.S + i) * J + j;
+    const long long r = r0 + j;
     cf Hv[P];
-    load_real<PL>(Hv, A.h + uni64(b.rir_off[r]), uni(b.rir_len[r]), t);
+    if constexpr (kPrefetch) {
+#pragma unroll
+      for (int q = 0; q < P; ++q) Hv[q] = Hn[q];
+      if (j + 1 < J) load_real<PL>(Hn, A.h + uni64(b.rir_off[r + 1]), uni(b.rir_len[r + 1]), t);
+    } else {
+      load_real<PL>(Hv, A.h + uni64(b.rir_off[r]), uni(b.rir_len[r]), t);
+    }
     Fft<PL>::forward(Hv, lds, tw, t);
     Fft<PL>::post(Hv, tw, t);  // 2 H
     double part = 0.0;
@@ -1407,47 +1424,141 @@ __device__ __forceinline__ void energy_source(const EnergyArgs& A, int u, int i,
   }
 }
 
+// Source slot k of the batch: whether its descriptors are usable, whether it
+// has work, its longest kept RIR, transform size and kernel family.  Slots
+// without work (and unusable ones) belong to the family of the 16384-point
+// transforms, which writes them.
+struct EnergyItem {
+  bool ok, work;
+  int u, i, nx, lmax, l2, fam;
+};
+
+__device__ __forceinline__ EnergyItem energy_item(const BatchDev& b, long long k) {
+  EnergyItem e;
+  e.u = (int)(k / b.S);
+  e.i = (int)(k - (long long)e.u * b.S);
+  const int I = b.n_src[e.u], J = b.J;
+  e.nx = b.src_len[e.u];
+  e.lmax = 0;
+  e.ok = I >= 0 && I <= b.S && e.nx >= 0;
+  if (e.ok && e.i < I) {
+    for (int j = 0; j < J; ++j) {
+      const long long r = ((long long)e.u * b.S + e.i) * J + j;
+      const int L = b.rir_len[r];
+      const long long ro = b.rir_off[r];
+      e.ok = e.ok && L >= 0 && ro >= 0 && ro + L <= b.h_len;
+      e.lmax = L > e.lmax ? L : e.lmax;
+    }
+    const long long so = b.src_off[k];
+    e.ok = e.ok && so >= 0 && so + e.nx <= b.x_len;
+  }
+  e.work = e.ok && e.i < I && e.nx > 0 && e.lmax > 0;
+  e.l2 = e.work ? energy_log2n(e.lmax) : 0;
+  e.fam = family_of_log2n(e.work && e.l2 <= 15 ? e.l2 : 14);
+  return e;
+}
+
+// Transforms an item of family `fam` costs (half blocks, the inverse, s and
+// one per mic); 1 for a slot that is only written; 0 for other families.
+__device__ __forceinline__ double energy_cost(const BatchDev& b, long long k, int fam) {
+  const EnergyItem e = energy_item(b, k);
+  if (e.fam != fam) return 0.0;
+  if (!e.work || e.l2 > 15) return 1.0;
+  const int half = 1 << (e.l2 - 1);
+  return (double)((e.nx + half - 1) / half + 2 + b.J);
+}
+
+// Each workgroup takes a contiguous range of the slots with about 1/G of the
+// family's transforms: slot k goes to workgroup floor(G m_k / C), m_k the
+// midpoint of its cost in the running sum and C the total (every workgroup
+// computes the same sums).  No counter is needed, and the longest sources do
+// not pile up on the workgroups that a fixed stride would give them.
+// The costs are kept in `cache` (the exchange buffers, idle until the first
+// transform) when the batch's slots fit it.
+template <int T>
+__device__ __forceinline__ void energy_range(const BatchDev& b, int fam, double* s_red, float* cache, long long cap,
+                                             long long& lo, long long& hi, int t) {
+  const long long items = (long long)b.U * b.S;
+  const bool cached = items <= cap;
+  const long long per = (items + T - 1) / T;
+  const long long k0 = min(items, (long long)t * per), k1 = min(items, k0 + per);
+  double c = 0.0;
+  for (long long k = k0; k < k1; ++k) {
+    const double ck = energy_cost(b, k, fam);
+    if (cached) cache[k] = (float)ck;  // small integers: exact
+    c += ck;
+  }
+  // inclusive scan of the per-thread sums (Hillis-Steele)
+  __syncthreads();
+  s_red[t] = c;
+  __syncthreads();
+  for (int d = 1; d < T; d <<= 1) {
+    const double v = t >= d ? s_red[t - d] : 0.0;
+    __syncthreads();
+    s_red[t] += v;
+    __syncthreads();
+  }
+  const double total = s_red[T - 1];
+  const double base = s_red[t] - c;
+  const double G = (double)gridDim.x;
+  const double a = total * (double)blockIdx.x / G, z = total * (double)(blockIdx.x + 1) / G;
+  // slots of this thread's chunk whose midpoint lies below a (resp. z)
+  double below_a = 0.0, below_z = 0.0, p = base;
+  for (long long k = k0; k < k1; ++k) {
+    const double ck = cached ? (double)cache[k] : energy_cost(b, k, fam);
+    const double mid = p + 0.5 * ck;
+    below_a += mid < a ? 1.0 : 0.0;
+    below_z += mid < z ? 1.0 : 0.0;
+    p += ck;
+  }
+  const double na = block_sum_d<T>(below_a, s_red, t);
+  const double nz = block_sum_d<T>(below_z, s_red, t);
+  // every slot of positive cost has its midpoint below the total, so the
+  // ranges of consecutive workgroups tile all of them
+  lo = (long long)na;
+  hi = (long long)nz;
+}
+
 template <int T>
 __global__ __launch_bounds__(T, 2) void energy_kernel(EnergyArgs A) {
   __shared__ cf lds[max_lds_with_threads<T>()];
   __shared__ double s_red[T];
+  __shared__ int s_list[T];
+  __shared__ int s_n;
   const int t = threadIdx.x;
   const BatchDev& b = A.b;
-  const long long items = (long long)b.U * b.S;
+  long long lo, hi;
+  energy_range<T>(b, A.fam, s_red, reinterpret_cast<float*>(lds), 2LL * max_lds_with_threads<T>(), lo, hi, t);
   int err = 0;
-  for (long long k = blockIdx.x; k < items; k += gridDim.x) {
-    const int u = (int)(k / b.S), i = (int)(k - (long long)u * b.S);
-    const int I = uni(b.n_src[u]), Nx = uni(b.src_len[u]), J = b.J;
-    int lmax = 0;
-    bool ok = I >= 0 && I <= b.S && Nx >= 0;
-    if (ok && i < I) {
-      for (int j = 0; j < J; ++j) {
-        const long long r = ((long long)u * b.S + i) * J + j;
-        const int L = uni(b.rir_len[r]);
-        const long long ro = uni64(b.rir_off[r]);
-        ok = ok && L >= 0 && ro >= 0 && ro + L <= b.h_len;
-        lmax = L > lmax ? L : lmax;
+  // The range is walked T slots at a time: the slots of this family in the
+  // window are found in parallel (one per thread) and listed, so slots of
+  // other families cost no serial descriptor reads.
+  for (long long w = lo; w < hi; w += T) {
+    __syncthreads();  // the previous window's list has been read
+    if (t == 0) s_n = 0;
+    __syncthreads();
+    if (w + t < hi && energy_item(b, w + t).fam == A.fam) s_list[atomicAdd(&s_n, 1)] = t;
+    __syncthreads();
+    const int n = s_n;
+    for (int q = 0; q < n; ++q) {
+      const long long k = w + s_list[q];
+      const EnergyItem e = energy_item(b, k);
+      const int J = b.J;
+      if (!e.work || e.l2 > 15) {
+        // no work: 0; a bad descriptor or a kept RIR longer than 16384 taps: NaN
+        const bool bad = !e.ok || e.l2 > 15;
+        if (!e.ok) err |= RSIM_DEV_BADDESC;
+        else if (e.l2 > 15) err |= RSIM_DEV_BADPLAN;
+        for (int jj = t; jj < J; jj += T) A.energy[k * J + jj] = bad ? __builtin_nan("") : 0.0;
+        continue;
       }
-      const long long so = uni64(b.src_off[k]);
-      ok = ok && so >= 0 && so + Nx <= b.x_len;
+      const int u = __builtin_amdgcn_readfirstlane(e.u), i = __builtin_amdgcn_readfirstlane(e.i);
+      const int lmax = __builtin_amdgcn_readfirstlane(e.lmax), l2 = __builtin_amdgcn_readfirstlane(e.l2);
+      dispatch_plan<T>(l2, [&](auto pl) __attribute__((always_inline)) {
+        using PL = decltype(pl);
+        energy_source<PL>(A, u, i, lmax, lds, s_red, t);
+      });
     }
-    const bool work = ok && i < I && Nx > 0 && lmax > 0;
-    const int l2 = work ? energy_log2n(lmax) : 0;
-    // Slots without work (and unusable ones) are written by family 0.
-    const int fam = work && l2 <= 15 ? family_of_log2n(l2) : 0;
-    if (fam != A.fam) continue;
-    if (!work || l2 > 15) {
-      // no work: 0; a bad descriptor or a kept RIR longer than 16384 taps: NaN
-      const bool bad = !ok || l2 > 15;
-      if (!ok) err |= RSIM_DEV_BADDESC;
-      else if (l2 > 15) err |= RSIM_DEV_BADPLAN;
-      for (int jj = t; jj < J; jj += T) A.energy[k * J + jj] = bad ? __builtin_nan("") : 0.0;
-      continue;
-    }
-    dispatch_plan<T>(l2, [&](auto pl) __attribute__((always_inline)) {
-      using PL = decltype(pl);
-      energy_source<PL>(A, u, i, lmax, lds, s_red, t);
-    });
   }
   if (err && t == 0) flag_status(err);
 }
@@ -3104,7 +3215,8 @@ rsim_status rsim_reverb_energy(const rsim_batch* b, const float* x, const float*
   const DevState& st = dev_state();
   const int cus = st.cus > 0 ? st.cus : 256;
   const long long items = (long long)b->n_utt * b->max_src;
-  for (int f = 0; f < kNumFam; ++f) {
+  // transforms of 2^14 and 2^15 points only (energy_log2n)
+  for (int f : {family_of_log2n(14), family_of_log2n(15)}) {
     EnergyArgs A;
     A.b = bd;
     A.x = x;
@@ -3112,7 +3224,9 @@ rsim_status rsim_reverb_energy(const rsim_batch* b, const float* x, const float*
     A.energy = energy;
     A.fam = f;
     void* args[] = {&A};
-    const unsigned grid = (unsigned)std::max<long long>(1, std::min<long long>(items, (long long)cus * 2));
+    // one workgroup per CU (the exchange buffers take most of its LDS), each
+    // with a balanced range of the family's slots
+    const unsigned grid = (unsigned)std::max<long long>(1, std::min<long long>(items, (long long)cus));
     if (hipLaunchKernel(energy_kernel_ptr(f), dim3(grid), dim3(kFamT[f]), args, 0, stream) != hipSuccess)
       return clear_error(RSIM_EDEVICE);
   }
