@@ -710,15 +710,28 @@ __device__ __forceinline__ void mix_utterance(const MixArgs& A, int u, const Sch
     // The RIR spectra of a source are requested when its item starts.  The
     // live set is about (3 + 2 JG) arrays of P complex values.
     cf Xn[P];
-    auto fetch = [&](int bk, int g, int i) __attribute__((always_inline)) {
+    // The input of item (bk, g, i): source i's block bk for the first group,
+    // else its cached spectrum.  Both are element q T + t of the thread's
+    // slots, so one load site serves every case (the source and the valid
+    // count are chosen first, in scalar registers): the prefetched values
+    // then always land in the same registers, and no register copy has to
+    // wait for them before they are used.
+    auto input_of = [&](int bk, int g, int i, const float*& src, int& nvalid) __attribute__((always_inline)) {
       if (g == glo) {
         const int base = bk * B;
-        load_real<PL>(Xn, A.x + D.src_off(i) + base, min(B, Nx - base), t);
+        src = A.x + D.src_off(i) + base;
+        nvalid = min(B, Nx - base);
       } else {
-        load_spec<PL>(Xn, Xs + (long long)i * M, t);
+        src = reinterpret_cast<const float*>(Xs + (long long)i * M);
+        nvalid = 2 * M;
       }
     };
-    fetch(0, glo, 0);
+    {
+      const float* src;
+      int nv;
+      input_of(0, glo, 0, src, nv);
+      load_real<PL>(Xn, src, nv, t);
+    }
     for (int bk = 0; bk < nb; ++bk) {
       const int base = bk * B;
       const int lim = min(span, tu - base);
@@ -736,21 +749,28 @@ __device__ __forceinline__ void mix_utterance(const MixArgs& A, int u, const Sch
         for (int i = 0; i < I; ++i) {
           const cf* H0 = Hs + (long long)(i * J + j0) * M;
           cf X[P], Hp0[P], Hp1[JG == 2 ? P : 1];
+          // The prefetched input is taken into X before this item's loads
+          // are issued: the wait for it then leaves no later load behind it
+          // (the counter of outstanding loads drains in issue order), so the
+          // RIR spectra stay in flight through the transform.
+#pragma unroll
+          for (int q = 0; q < P; ++q) X[q] = opaque_c(Xn[q]);
+          asm volatile("" ::: "memory");
           load_spec<PL>(Hp0, H0, t);
           if constexpr (JG == 2) {
             if (two) load_spec<PL>(Hp1, H0 + M, t);
           }
-#pragma unroll
-          for (int q = 0; q < P; ++q) X[q] = Xn[q];
           // With one source, the next group's input is this item's own
           // spectrum, not yet in the cache: it is handed over in registers.
           const bool hand_over = g == glo && I == 1 && cache;
-          if (i + 1 < I) fetch(bk, g, i + 1);
-          else if (g + 1 < ghi) {
-            if (!hand_over) fetch(bk, g + 1, 0);
-          } else if (bk + 1 < nb) {
-            fetch(bk + 1, glo, 0);
-          }
+          const float* fsrc = A.x;
+          int fn = 0;
+          bool fetch = true;
+          if (i + 1 < I) input_of(bk, g, i + 1, fsrc, fn);
+          else if (g + 1 < ghi && !hand_over) input_of(bk, g + 1, 0, fsrc, fn);
+          else if (g + 1 >= ghi && bk + 1 < nb) input_of(bk + 1, glo, 0, fsrc, fn);
+          else fetch = false;
+          if (fetch) load_real<PL>(Xn, fsrc, fn, t);
           if (g == glo) {
             Fft<PL>::forward(X, lds, tw, t);
             Fft<PL>::post(X, tw, t);
