@@ -1833,58 +1833,145 @@ __global__ __launch_bounds__(kImgThreads) void image_kernel(ImageArgs A) {
 
 // ============================================ full-length FFT filtering
 // Eqs. 4-5: every signal is transformed whole, with N = 2^m >= Nx + L - 1
-// points (up to 2^20), beyond what one workgroup holds in LDS, so the
-// transform is a sequence of batched Stockham passes over global memory
-// (radix 4, and one radix 2 when m is odd): pass s with span Ls reads
-// butterfly j's inputs at j + r N/R, twists them by W^(r (j mod Ls)) with
-// W = exp(-/+ 2 pi i / (R Ls)) and writes its outputs at
-// (j - j mod Ls) R + (j mod Ls) + r Ls; after the last pass the spectrum is in
-// natural order.  Real signals go in as complex with zero imaginary part.
-// Per utterance and mic the spectra are summed over sources (linearity), so
-// one inverse per mic.  This is the paper's slower rung, kept for comparison.
+// points (up to 2^20), beyond what one workgroup holds in LDS.  The transform
+// is split in four steps (N = N1 N2, n = N2 n1 + n2, k = k1 + N1 k2):
+//   A  for every n2, the N1-point DFT over n1 of x[N2 n1 + n2], times
+//      W_N^(n2 k1), stored at [k1 N2 + n2];
+//   B  for every k1, the N2-point DFT over n2 of that row, stored at
+//      X[k1 + N1 k2] (natural order).
+// Each step is one kernel: a workgroup loads C sequences of L points (a tile
+// of C L <= kFfTile complex values) into LDS, transforms them there by
+// radix-4 Stockham passes (and one radix 2 when log2 L is odd: pass s with
+// span Ls reads butterfly j's inputs at j + r L/R, twists them by
+// W_(R Ls)^(r (j mod Ls)) and writes its outputs at
+// (j - j mod Ls) R + (j mod Ls) + r Ls) and stores them, so each transform
+// reads and writes global memory twice.  Real signals go in as complex with
+// zero imaginary part.  Per utterance and mic the spectra are summed over
+// sources (linearity), so one inverse per mic.  This is the paper's slower
+// rung, kept for comparison.
 constexpr int kFfThreads = 256;
+constexpr int kFfStepThreads = 512;
+constexpr int kFfTile = 8192;   // complex values of one workgroup's sequences
+constexpr int kFfMaxL = 1024;   // points of one sequence, at most
+
+struct FfStep {
+  const cf* in;
+  cf* out;
+  long long sig_len;         // N: distance between consecutive signals
+  int count;                 // signals
+  int log2l, log2c;          // L = 2^log2l points per sequence, C = 2^log2c per workgroup
+  int cols;                  // sequences per signal (a multiple of C)
+  long long in_cs, in_ns;    // input (c, n) of a signal at c in_cs + n in_ns
+  long long out_cs, out_ks;  // output (c, k) at c out_cs + k out_ks
+  int n_fast;                // load with n varying fastest (in_ns == 1)
+  int log2n, twiddle;        // outputs times W_N^(c k) when twiddle != 0
+  const int* n_src;          // signals are source slots (u0 + sig / S, sig mod S): those
+  int u0, S;                 // past n_src[u] are skipped (left unwritten); NULL: none
+};
 
 template <int R, bool INV>
-__global__ __launch_bounds__(kFfThreads) void ff_pass_kernel(const cf* __restrict__ in, cf* __restrict__ out, int log2n,
-                                                            int Ls, int count) {
-  const long long N = 1LL << log2n;
-  const long long nbf = N / R;
-  const long long total = nbf * count;
-  for (long long g = (long long)blockIdx.x * kFfThreads + threadIdx.x; g < total;
-       g += (long long)gridDim.x * kFfThreads) {
-    const long long c = g / nbf, j = g - c * nbf;
-    const cf* src = in + c * N;
-    cf* dst = out + c * N;
-    const long long k = j & (Ls - 1);
-    cf v[R];
+__device__ __forceinline__ void ff_butterfly(cf* v) {
+  if constexpr (R == 2) {
+    const cf a = v[0], b = v[1];
+    v[0] = mk(a.x + b.x, a.y + b.y);
+    v[1] = mk(a.x - b.x, a.y - b.y);
+  } else {
+    const cf s0 = mk(v[0].x + v[2].x, v[0].y + v[2].y), d0 = mk(v[0].x - v[2].x, v[0].y - v[2].y);
+    const cf s1 = mk(v[1].x + v[3].x, v[1].y + v[3].y), d1 = mk(v[1].x - v[3].x, v[1].y - v[3].y);
+    // -i d1 forward, +i d1 inverse
+    const cf e1 = INV ? mk(-d1.y, d1.x) : mk(d1.y, -d1.x);
+    v[0] = mk(s0.x + s1.x, s0.y + s1.y);
+    v[2] = mk(s0.x - s1.x, s0.y - s1.y);
+    v[1] = mk(d0.x + e1.x, d0.y + e1.y);
+    v[3] = mk(d0.x - e1.x, d0.y - e1.y);
+  }
+}
+
+// One radix-R Stockham pass over the C sequences in buf (sequence c, point n
+// at n CP + c).  Every thread reads all its butterflies' inputs before the
+// barrier and writes after it, so the pass runs in place.
+template <int R, bool INV>
+__device__ __forceinline__ void ff_lds_pass(cf* buf, const cf* tw, int log2l, int log2c, int CP, int Ls, int t) {
+  constexpr int NB = kFfTile / R / kFfStepThreads;  // butterflies per thread, at most
+  const int L = 1 << log2l, C = 1 << log2c;
+  const int nb = (C * L) / R;
+  const int stride = L / R;
+  const int tws = L / (R * Ls);  // W_(R Ls)^e = W_L^(e tws)
+  cf v[NB][R];
 #pragma unroll
-    for (int r = 0; r < R; ++r) v[r] = src[j + r * nbf];
-    // twiddles W^(r k), angle -/+ 2 pi r k / (R Ls) from an exact ratio
+  for (int s = 0; s < NB; ++s) {
+    const int b = t + s * kFfStepThreads;
+    if (b < nb) {
+      const int c = b & (C - 1), j = b >> log2c, k = j & (Ls - 1);
 #pragma unroll
-    for (int r = 1; r < R; ++r) {
-      const float a = (float)(r * k) / (float)(R * Ls);  // r k < 2^24: exact
-      float sn, cs;
-      sincospif(2.0f * a, &sn, &cs);
-      if (!INV) sn = -sn;
-      v[r] = mk(v[r].x * cs - v[r].y * sn, v[r].x * sn + v[r].y * cs);
+      for (int r = 0; r < R; ++r) v[s][r] = buf[(j + r * stride) * CP + c];
+#pragma unroll
+      for (int r = 1; r < R; ++r) v[s][r] = cmul(v[s][r], tw[r * k * tws]);
+      ff_butterfly<R, INV>(v[s]);
     }
-    cf o[R];
-    if constexpr (R == 2) {
-      o[0] = mk(v[0].x + v[1].x, v[0].y + v[1].y);
-      o[1] = mk(v[0].x - v[1].x, v[0].y - v[1].y);
-    } else {
-      const cf s0 = mk(v[0].x + v[2].x, v[0].y + v[2].y), d0 = mk(v[0].x - v[2].x, v[0].y - v[2].y);
-      const cf s1 = mk(v[1].x + v[3].x, v[1].y + v[3].y), d1 = mk(v[1].x - v[3].x, v[1].y - v[3].y);
-      // -i d1 forward, +i d1 inverse
-      const cf e1 = INV ? mk(-d1.y, d1.x) : mk(d1.y, -d1.x);
-      o[0] = mk(s0.x + s1.x, s0.y + s1.y);
-      o[2] = mk(s0.x - s1.x, s0.y - s1.y);
-      o[1] = mk(d0.x + e1.x, d0.y + e1.y);
-      o[3] = mk(d0.x - e1.x, d0.y - e1.y);
-    }
-    const long long base = (j - k) * R + k;
+  }
+  __syncthreads();
 #pragma unroll
-    for (int r = 0; r < R; ++r) dst[base + (long long)r * Ls] = o[r];
+  for (int s = 0; s < NB; ++s) {
+    const int b = t + s * kFfStepThreads;
+    if (b < nb) {
+      const int c = b & (C - 1), j = b >> log2c, k = j & (Ls - 1);
+      const int base = (j - k) * R + k;
+#pragma unroll
+      for (int r = 0; r < R; ++r) buf[(base + r * Ls) * CP + c] = v[s][r];
+    }
+  }
+  __syncthreads();
+}
+
+template <bool INV>
+__global__ __launch_bounds__(kFfStepThreads) void ff_step_kernel(FfStep S) {
+  __shared__ cf buf[kFfTile + kFfMaxL];  // C sequences, row stride C + 1
+  __shared__ cf tw[kFfMaxL];             // W_L^m, m < L
+  const int t = threadIdx.x;
+  const int L = 1 << S.log2l, C = 1 << S.log2c, CP = C + 1;
+  for (int m = t; m < L; m += kFfStepThreads) {
+    float sn, cs;
+    sincospif(2.0f * (float)m / (float)L, &sn, &cs);  // m / L exact
+    tw[m] = mk(cs, INV ? sn : -sn);
+  }
+  const int tiles = S.cols >> S.log2c;
+  const long long items = (long long)S.count * tiles;
+  const float inv_n = 1.0f / (float)(1LL << S.log2n);
+  for (long long it = blockIdx.x; it < items; it += gridDim.x) {
+    const long long sig = it / tiles;
+    const int c0 = (int)(it - sig * tiles) << S.log2c;
+    if (S.n_src && (int)(sig % S.S) >= S.n_src[S.u0 + sig / S.S]) continue;  // uniform
+    const cf* src = S.in + sig * S.sig_len + (long long)c0 * S.in_cs;
+    cf* dst = S.out + sig * S.sig_len + (long long)c0 * S.out_cs;
+    __syncthreads();  // the table is written; the previous tile is stored
+    for (int e = t; e < C * L; e += kFfStepThreads) {
+      int c, n;
+      if (S.n_fast) {
+        n = e & (L - 1);
+        c = e >> S.log2l;
+      } else {
+        c = e & (C - 1);
+        n = e >> S.log2c;
+      }
+      buf[n * CP + c] = src[(long long)c * S.in_cs + (long long)n * S.in_ns];
+    }
+    __syncthreads();
+    int Ls = 1, l = S.log2l;
+    for (; l >= 2; l -= 2, Ls *= 4) ff_lds_pass<4, INV>(buf, tw, S.log2l, S.log2c, CP, Ls, t);
+    if (l == 1) ff_lds_pass<2, INV>(buf, tw, S.log2l, S.log2c, CP, Ls, t);
+    for (int e = t; e < C * L; e += kFfStepThreads) {
+      const int c = e & (C - 1), k = e >> S.log2c;
+      cf z = buf[k * CP + c];
+      if (S.twiddle) {
+        // W_N^(n2 k1) with n2 k1 < N <= 2^20: the ratio is exact
+        const float a = (float)((unsigned)(c0 + c) * (unsigned)k) * inv_n;
+        float sn, cs;
+        sincospif(2.0f * a, &sn, &cs);
+        z = cmul(z, mk(cs, INV ? sn : -sn));
+      }
+      dst[(long long)c * S.out_cs + (long long)k * S.out_ks] = z;
+    }
   }
 }
 
@@ -1913,8 +2000,9 @@ __global__ __launch_bounds__(kFfThreads) void ff_load_kernel(FfArgs A, int kind)
     const int cu = (int)(slot / b.S), i = (int)(slot - (long long)cu * b.S);
     const int u = A.u0 + cu;
     const int I = b.n_src[u];
+    if (i >= I) continue;  // an unused slot is neither transformed nor read
     float v = 0.f;
-    if (i < I && I <= b.S) {
+    if (I <= b.S) {
       if (kind == 0) {
         const long long so = b.src_off[(long long)u * b.S + i];
         const int Nx = b.src_len[u];
@@ -1955,31 +2043,32 @@ __global__ __launch_bounds__(kFfThreads) void ff_mac_kernel(FfArgs A) {
 
 // y_j[n] = Re(Y[n]) / N for n < T_u = Nx + Lmax - 1 (written to out_len with
 // mic 0); an utterance whose T_u exceeds N or its output stride is skipped
-// with RSIM_DEV_BADPLAN.
+// with RSIM_DEV_BADPLAN.  Grid: (sample chunks, utterances of the chunk).
 __global__ __launch_bounds__(kFfThreads) void ff_store_kernel(FfArgs A) {
   const BatchDev& b = A.b;
   const long long N = 1LL << A.log2n;
   const float sc = 1.0f / (float)N;
-  for (int cu = blockIdx.x; cu < A.nu; cu += gridDim.x) {
-    const int u = A.u0 + cu;
-    const int I = b.n_src[u], Nx = b.src_len[u];
-    int lmax = 0;
-    for (int i = 0; i < min(I, b.S); ++i)
-      for (int j = 0; j < b.J; ++j) lmax = max(lmax, b.rir_len[((long long)u * b.S + i) * b.J + j]);
-    const long long T = (I > 0 && Nx > 0 && lmax > 0) ? (long long)Nx + lmax - 1 : 0;
-    const int stride = b.out_stride[u];
-    if (T > N || T > stride) {
-      if (threadIdx.x == 0 && A.j == 0) {
-        flag_status(RSIM_DEV_BADPLAN);
-        b.out_len[u] = 0;
-      }
-      continue;
+  const int cu = blockIdx.y;
+  const int u = A.u0 + cu;
+  const int I = b.n_src[u], Nx = b.src_len[u];
+  int lmax = 0;
+  for (int i = 0; i < min(I, b.S); ++i)
+    for (int j = 0; j < b.J; ++j) lmax = max(lmax, b.rir_len[((long long)u * b.S + i) * b.J + j]);
+  const long long T = (I > 0 && Nx > 0 && lmax > 0) ? (long long)Nx + lmax - 1 : 0;
+  const int stride = b.out_stride[u];
+  const bool first = blockIdx.x == 0 && threadIdx.x == 0 && A.j == 0;
+  if (T > N || T > stride) {
+    if (first) {
+      flag_status(RSIM_DEV_BADPLAN);
+      b.out_len[u] = 0;
     }
-    if (threadIdx.x == 0 && A.j == 0) b.out_len[u] = (int)T;
-    float* yj = A.y + b.out_off[u] + (long long)A.j * stride;
-    const cf* Y = A.Y + (long long)cu * N;
-    for (long long n = threadIdx.x; n < T; n += kFfThreads) yj[n] = Y[n].x * sc;
+    return;
   }
+  if (first) b.out_len[u] = (int)T;
+  float* yj = A.y + b.out_off[u] + (long long)A.j * stride;
+  const cf* Y = A.Y + (long long)cu * N;
+  for (long long n = (long long)blockIdx.x * kFfThreads + threadIdx.x; n < T; n += (long long)gridDim.x * kFfThreads)
+    yj[n] = Y[n].x * sc;
 }
 
 // ================================================= FFT engine test kernels
@@ -2942,6 +3031,13 @@ int ilog2_exact(int n) {
   return l;
 }
 
+// floor(log2 v) for v >= 1
+int ilog2_floor(long long v) {
+  int l = 0;
+  while ((2LL << l) <= v) ++l;
+  return l;
+}
+
 rsim_status image_args_ok(int n_rir, int order, double fs, double c0, int max_len, long long h_len) {
   if (n_rir < 0 || order < 0 || order > kImgMaxOrder || !(fs > 0.0) || !(c0 > 0.0) || max_len < 0 || h_len < 0 ||
       !std::isfinite(fs) || !std::isfinite(c0))
@@ -3317,35 +3413,57 @@ rsim_status rsim_fft_filter(const rsim_batch* b, const float* x, const float* h,
   cf* tmp = A.H + C * S * N;
   A.Y = tmp + C * S * N;
   A.log2n = fft_log2n;
-  const int passes = fft_log2n / 2 + (fft_log2n & 1);
   const DevState& st = dev_state();
   const int cus = st.cus > 0 ? st.cus : 256;
   auto grid_for = [&](long long work) {
     return dim3((unsigned)std::max<long long>(1, std::min<long long>((work + kFfThreads - 1) / kFfThreads,
                                                                       (long long)cus * 16)));
   };
-  // passes over `count` transforms; the data starts in `first` and ends in
-  // `first` after an even number of passes, else in `second`
-  auto fft = [&](cf* first, cf* second, int count, bool inv) {
-    cf* src = first;
-    cf* dst = second;
-    long long Ls = 1;
-    for (int q = 0; q < passes; ++q) {
-      const bool radix2 = (fft_log2n & 1) && q == passes - 1;
-      const long long bf = (N / (radix2 ? 2 : 4)) * count;
-      const void* fn = radix2 ? (inv ? reinterpret_cast<const void*>(&ff_pass_kernel<2, true>)
-                                     : reinterpret_cast<const void*>(&ff_pass_kernel<2, false>))
-                              : (inv ? reinterpret_cast<const void*>(&ff_pass_kernel<4, true>)
-                                     : reinterpret_cast<const void*>(&ff_pass_kernel<4, false>));
-      int ls = (int)Ls, l2 = fft_log2n, cnt = count;
-      void* args[] = {&src, &dst, &l2, &ls, &cnt};
-      if (hipLaunchKernel(fn, grid_for(bf), dim3(kFfThreads), args, 0, stream) != hipSuccess) return false;
-      Ls *= radix2 ? 2 : 4;
-      std::swap(src, dst);
+  // N = N1 N2, N1 = 2^l1 >= N2 = 2^l2, both at most 1024 points
+  const int l1 = (fft_log2n + 1) / 2, l2 = fft_log2n / 2;
+  auto step = [&](const cf* in, cf* out, int count, bool inv, bool first, bool slots) {
+    FfStep S;
+    S.in = in;
+    S.out = out;
+    S.n_src = slots ? b->n_src : nullptr;
+    S.u0 = A.u0;
+    S.S = (int)b->max_src;
+    S.sig_len = N;
+    S.count = count;
+    S.log2n = fft_log2n;
+    if (first) {  // step A: N2 sequences of N1 points (stride N2), twiddled
+      S.log2l = l1;
+      S.cols = 1 << l2;
+      S.in_cs = 1;
+      S.in_ns = 1LL << l2;
+      S.out_cs = 1;
+      S.out_ks = 1LL << l2;
+      S.n_fast = 0;
+      S.twiddle = 1;
+    } else {  // step B: N1 rows of N2 points, outputs at k1 + N1 k2
+      S.log2l = l2;
+      S.cols = 1 << l1;
+      S.in_cs = 1LL << l2;
+      S.in_ns = 1;
+      S.out_cs = 1;
+      S.out_ks = 1LL << l1;
+      S.n_fast = 1;
+      S.twiddle = 0;
     }
-    return true;
+    S.log2c = std::min(ilog2_floor(kFfTile) - S.log2l, ilog2_floor(S.cols));
+    const long long items = (long long)count * (S.cols >> S.log2c);
+    const dim3 grid((unsigned)std::max<long long>(1, std::min<long long>(items, (long long)cus * 2)));
+    void* args[] = {&S};
+    const void* fn = inv ? reinterpret_cast<const void*>(&ff_step_kernel<true>)
+                         : reinterpret_cast<const void*>(&ff_step_kernel<false>);
+    return hipLaunchKernel(fn, grid, dim3(kFfStepThreads), args, 0, stream) == hipSuccess;
   };
-  const bool even = (passes % 2) == 0;
+  // the two steps over `count` transforms: `first` -> `second` -> `first`
+  auto fft = [&](cf* first, cf* second, int count, bool inv) {
+    const bool slots = !inv;  // forward transforms run over source slots
+    return step(first, second, count, inv, true, slots) && step(second, first, count, inv, false, slots);
+  };
+  const bool even = true;  // the data ends where it started
   for (int u0 = 0; u0 < b->n_utt; u0 += chunk) {
     A.u0 = u0;
     A.nu = std::min(chunk, b->n_utt - u0);
@@ -3365,7 +3483,9 @@ rsim_status rsim_fft_filter(const rsim_batch* b, const float* x, const float* h,
       L.Y = even ? A.Y : tmp;
       hipLaunchKernelGGL(ff_mac_kernel, grid_for((long long)A.nu * N), dim3(kFfThreads), 0, stream, L);
       if (!fft(L.Y, even ? tmp : A.Y, A.nu, true)) return clear_error(RSIM_EDEVICE);
-      hipLaunchKernelGGL(ff_store_kernel, dim3((unsigned)A.nu), dim3(kFfThreads), 0, stream, A);
+      const unsigned chunks = (unsigned)std::max<long long>(1, std::min<long long>((N + kFfThreads - 1) / kFfThreads,
+                                                                                 ((long long)cus * 8 + A.nu - 1) / A.nu));
+      hipLaunchKernelGGL(ff_store_kernel, dim3(chunks, (unsigned)A.nu), dim3(kFfThreads), 0, stream, A);
     }
   }
   return hipGetLastError() == hipSuccess ? RSIM_OK : clear_error(RSIM_EDEVICE);
