@@ -952,6 +952,11 @@ __device__ __forceinline__ void bwd_pair_pass(cf* D0, cf* D1, const cf* X0, cons
                                               const cf* __restrict__ G1, cf* __restrict__ Ri, int J, bool first,
                                               bool two, int t_) {
   constexpr int SP = Fft<PL>::SP, M = PL::M;
+  // Slots in batches of QB: all operands of a batch are requested before any
+  // of its accumulators is written back (the compiler cannot tell the
+  // accumulator reads from the writes apart, so reads after a write wait for
+  // it), which makes one memory round trip per batch instead of per slot.
+  constexpr int QB = PL::P < 8 ? PL::P : 8;
   const int t = opaque_v(t_);
   const int vo = 8 * t;
   constexpr int bytes = PL::P * PL::T * 8;
@@ -962,11 +967,20 @@ __device__ __forceinline__ void bwd_pair_pass(cf* D0, cf* D1, const cf* X0, cons
     const rsrc_t rr = make_rsrc(Ri + (long long)j * M, first ? 0 : bytes);
     const rsrc_t rw = make_rsrc(Ri + (long long)j * M, bytes);
 #pragma unroll
-    for (int q = 0; q < PL::P; ++q) {
-      const cf h = ld2(rh, vo, 8 * q * PL::T);
-      const cf g0 = ld2(r0, vo, 8 * q * PL::T);
-      const cf g1 = ld2(r1, vo, 8 * q * PL::T);
-      const cf acc = ld2(rr, vo, 8 * q * PL::T);
+    for (int q0 = 0; q0 < PL::P; q0 += QB) {
+    cf hb[QB], g0b[QB], g1b[QB], ab[QB];
+#pragma unroll
+    for (int e = 0; e < QB; ++e) {
+      const int so = 8 * (q0 + e) * PL::T;
+      hb[e] = ld2(rh, vo, so);
+      g0b[e] = ld2(r0, vo, so);
+      g1b[e] = ld2(r1, vo, so);
+      ab[e] = ld2(rr, vo, so);
+    }
+#pragma unroll
+    for (int e = 0; e < QB; ++e) {
+      const int q = q0 + e;
+      const cf h = hb[e], g0 = g0b[e], g1 = g1b[e], acc = ab[e];
       cf o;
       if (q == SP) {
         const cf c0 = cmacc(D0[q], h, g0), c1 = cmacc(D1[q], h, g1);
@@ -984,6 +998,7 @@ __device__ __forceinline__ void bwd_pair_pass(cf* D0, cf* D1, const cf* X0, cons
         o = cmacc(cmacc(acc, X0[q], g0), X1[q], g1);
       }
       st2(rw, vo, o, 8 * q * PL::T);
+    }
     }
   }
 }
@@ -1038,24 +1053,54 @@ __device__ __forceinline__ void bwd_finish_rir(const BwdArgs& A, long long r, co
   const int L = uni(b.rir_len[r]), L0 = uni(b.rir_len0[r]);
   const long long ro = uni64(b.rir_off[r]);
   const float a = A.alpha[r];
+  // With 1024 threads (128 registers each) the parts and taps are read as
+  // they are needed; otherwise every part is requested at once (then summed
+  // in part order) and the kept taps before the transform.
+  constexpr bool kBatch = PL::T <= 512;
   cf v[P];
   load_spec<PL>(v, R, t);
-  for (int k = 1; k < nparts; ++k) {
-    cf w[P];
-    load_spec<PL>(w, R + k * stride, t);
+  if (kBatch && nparts <= 4) {
+    cf w1[kBatch ? P : 1], w2[kBatch ? P : 1], w3[kBatch ? P : 1];
+    if (nparts > 1) load_spec<PL>(w1, R + stride, t);
+    if (nparts > 2) load_spec<PL>(w2, R + 2 * stride, t);
+    if (nparts > 3) load_spec<PL>(w3, R + 3 * stride, t);
+    if (nparts > 1) {
 #pragma unroll
-    for (int q = 0; q < P; ++q) v[q] = mk(v[q].x + w[q].x, v[q].y + w[q].y);
+      for (int q = 0; q < P; ++q) v[q] = mk(v[q].x + w1[q].x, v[q].y + w1[q].y);
+    }
+    if (nparts > 2) {
+#pragma unroll
+      for (int q = 0; q < P; ++q) v[q] = mk(v[q].x + w2[q].x, v[q].y + w2[q].y);
+    }
+    if (nparts > 3) {
+#pragma unroll
+      for (int q = 0; q < P; ++q) v[q] = mk(v[q].x + w3[q].x, v[q].y + w3[q].y);
+    }
+  } else {
+    for (int k = 1; k < nparts; ++k) {
+      cf w[P];
+      load_spec<PL>(w, R + k * stride, t);
+#pragma unroll
+      for (int q = 0; q < P; ++q) v[q] = mk(v[q].x + w[q].x, v[q].y + w[q].y);
+    }
+  }
+  const rsrc_t hr = make_rsrc(A.h + ro, L * 4);
+  cf hv_all[kBatch ? P : 1];
+  if constexpr (kBatch) {
+#pragma unroll
+    for (int q = 0; q < P; ++q) hv_all[q] = ld2(hr, 8 * (t + q * PL::T));
   }
   Fft<PL>::pre(v, tw, t);
   Fft<PL>::inverse(v, lds, tw, t);
   // v[q] holds r at samples 2(t + qT), 2(t + qT) + 1.
-  const rsrc_t hr = make_rsrc(A.h + ro, L * 4);
   const rsrc_t gw = make_rsrc(A.gh + ro, L * 4);
   double part = 0.0;
 #pragma unroll
   for (int q = 0; q < P; ++q) {
     const int o = 8 * (t + q * PL::T);
-    const cf hv = ld2(hr, o);
+    cf hv;
+    if constexpr (kBatch) hv = hv_all[q];
+    else hv = ld2(hr, o);
     part += (double)hv.x * (double)v[q].x + (double)hv.y * (double)v[q].y;
     st2(gw, o, mk(a * v[q].x, a * v[q].y));
   }
@@ -1113,33 +1158,53 @@ __device__ __forceinline__ void bwd_utterance(const BwdArgs& A, int u, const Sch
     // mics gives both blocks' dx spectra and their share of r.
     for (int bk = b0; bk < b1; bk += 2) {
       const bool two = bk + 1 < b1;
-      for (int hb = 0; hb < (two ? 2 : 1); ++hb) {
+      // the gradient blocks (block hb, mic j) = item k = hb J + j, the next
+      // one requested while the current one is transformed
+      const int ng = (two ? 2 : 1) * J;
+      auto grad_src = [&](int k, const float*& src, int& nv) __attribute__((always_inline)) {
+        const int hb = k / J, j = k - hb * J;
         const int base = (bk + hb) * B;
-        for (int j = 0; j < J; ++j) {
-          cf v[P];
-          load_real<PL>(v, A.gy + yo + (long long)j * ys + base, min(N, tu - base), t);
-          Fft<PL>::forward(v, lds, tw, t);
-          Fft<PL>::post(v, tw, t);
+        src = A.gy + yo + (long long)j * ys + base;
+        nv = min(N, tu - base);
+      };
+      cf vn[P];
+      {
+        const float* src;
+        int nv;
+        grad_src(0, src, nv);
+        load_real<PL>(vn, src, nv, t);
+      }
+      for (int k = 0; k < ng; ++k) {
+        cf v[P];
 #pragma unroll
-          for (int q = 0; q < P; ++q) v[q] = mk(v[q].x * gscale, v[q].y * gscale);
-          store_spec<PL>(Gs + (long long)(hb * J + j) * M, v, t);
+        for (int q = 0; q < P; ++q) v[q] = opaque_c(vn[q]);
+        asm volatile("" ::: "memory");
+        if (k + 1 < ng) {
+          const float* src;
+          int nv;
+          grad_src(k + 1, src, nv);
+          load_real<PL>(vn, src, nv, t);
         }
+        Fft<PL>::forward(v, lds, tw, t);
+        Fft<PL>::post(v, tw, t);
+#pragma unroll
+        for (int q = 0; q < P; ++q) v[q] = mk(v[q].x * gscale, v[q].y * gscale);
+        store_spec<PL>(Gs + (long long)k * M, v, t);
       }
       for (int i = 0; i < I; ++i) {
         const long long so = uni64(b.src_off[(long long)u * NS + i]);
         const int base0 = bk * B, base1 = base0 + B;
         const int nv0 = min(B, Nx - base0), nv1 = two ? min(B, Nx - base1) : 0;
         cf X0[P], X1[P], D0[P], D1[P];
+        // both blocks are requested before the first transform (the second
+        // reads zeros when there is no second block)
         load_real<PL>(X0, A.x + so + base0, nv0, t);
+        load_real<PL>(X1, A.x + so + base1, nv1, t);
         Fft<PL>::forward(X0, lds, tw, t);
         Fft<PL>::post(X0, tw, t);
         if (two) {
-          load_real<PL>(X1, A.x + so + base1, nv1, t);
           Fft<PL>::forward(X1, lds, tw, t);
           Fft<PL>::post(X1, tw, t);
-        } else {
-#pragma unroll
-          for (int q = 0; q < P; ++q) X1[q] = mk(0.f, 0.f);
         }
 #pragma unroll
         for (int q = 0; q < P; ++q) D0[q] = D1[q] = mk(0.f, 0.f);
