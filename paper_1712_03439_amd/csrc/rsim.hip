@@ -1932,6 +1932,21 @@ struct FfStep {
   int log2n, twiddle;        // outputs times W_N^(c k) when twiddle != 0
   const int* n_src;          // signals are source slots (u0 + sig / S, sig mod S): those
   int u0, S;                 // past n_src[u] are skipped (left unwritten); NULL: none
+  // Fused ends (the operands of the filtering), selected per step:
+  //   in_kind  0 the complex array `in`; 1 source slot (u, i) of x as real
+  //            values (zero past N_x); 2 the cut RIR (u, i, j) of h (zero past
+  //            L); 3 sum_i alpha_uij H[cu][i] X[cu][i] over the utterance's
+  //            sources (signal = utterance cu of the chunk)
+  //   out_kind 0 the complex array `out`; 1 mic j's output y_j[n] = Re / N
+  //            for n < T_u (signal = utterance), out_len with mic 0
+  int in_kind, out_kind, j;
+  BatchDev b;
+  const float* x;
+  const float* h;
+  const float* alpha;
+  float* y;
+  const cf* X;  // [chunk][S][N] source spectra
+  const cf* H;  // [chunk][S][N] RIR spectra of mic j
 };
 
 template <int R, bool INV>
@@ -2007,8 +2022,31 @@ __global__ __launch_bounds__(kFfStepThreads) void ff_step_kernel(FfStep S) {
     const long long sig = it / tiles;
     const int c0 = (int)(it - sig * tiles) << S.log2c;
     if (S.n_src && (int)(sig % S.S) >= S.n_src[S.u0 + sig / S.S]) continue;  // uniform
-    const cf* src = S.in + sig * S.sig_len + (long long)c0 * S.in_cs;
-    cf* dst = S.out + sig * S.sig_len + (long long)c0 * S.out_cs;
+    const BatchDev& b = S.b;
+    // the signal's real input (in_kind 1, 2): values below rlen, zero after
+    const float* rin = nullptr;
+    long long rlen = 0;
+    if (S.in_kind == 1 || S.in_kind == 2) {
+      const int cu = (int)(sig / S.S), i = (int)(sig % S.S), u = S.u0 + cu;
+      const bool okI = b.n_src[u] <= b.S;  // a bad count transforms zeros
+      if (S.in_kind == 1) {
+        const long long so = b.src_off[(long long)u * b.S + i];
+        const int nx = b.src_len[u];
+        if (okI && so >= 0 && nx >= 0 && so + nx <= b.x_len) {
+          rin = S.x + so;
+          rlen = nx;
+        }
+      } else {
+        const long long r = ((long long)u * b.S + i) * b.J + S.j;
+        const long long ro = b.rir_off[r];
+        const int len = b.rir_len[r];
+        if (okI && ro >= 0 && len >= 0 && ro + len <= b.h_len) {
+          rin = S.h + ro;
+          rlen = len;
+        }
+      }
+    }
+    const cf* src = S.in_kind == 0 ? S.in + sig * S.sig_len : nullptr;
     __syncthreads();  // the table is written; the previous tile is stored
     for (int e = t; e < C * L; e += kFfStepThreads) {
       int c, n;
@@ -2019,12 +2057,60 @@ __global__ __launch_bounds__(kFfStepThreads) void ff_step_kernel(FfStep S) {
         c = e & (C - 1);
         n = e >> S.log2c;
       }
-      buf[n * CP + c] = src[(long long)c * S.in_cs + (long long)n * S.in_ns];
+      const long long idx = (long long)(c0 + c) * S.in_cs + (long long)n * S.in_ns;
+      cf v;
+      if (S.in_kind == 0) {
+        v = src[idx];
+      } else if (S.in_kind == 3) {
+        const int cu = (int)sig, u = S.u0 + cu;
+        const int I = min(b.n_src[u], b.S);
+        float re = 0.f, im = 0.f;
+        for (int i = 0; i < I; ++i) {
+          const float a = S.alpha[((long long)u * b.S + i) * b.J + S.j];
+          const long long o = ((long long)cu * b.S + i) * S.sig_len + idx;
+          const cf hv = S.H[o], xv = S.X[o];
+          const float pr = hv.x * xv.x - hv.y * xv.y, pi = hv.x * xv.y + hv.y * xv.x;
+          re = __builtin_fmaf(a, pr, re);
+          im = __builtin_fmaf(a, pi, im);
+        }
+        v = mk(re, im);
+      } else {
+        v = mk(idx < rlen ? rin[idx] : 0.f, 0.f);
+      }
+      buf[n * CP + c] = v;
     }
     __syncthreads();
     int Ls = 1, l = S.log2l;
     for (; l >= 2; l -= 2, Ls *= 4) ff_lds_pass<4, INV>(buf, tw, S.log2l, S.log2c, CP, Ls, t);
     if (l == 1) ff_lds_pass<2, INV>(buf, tw, S.log2l, S.log2c, CP, Ls, t);
+    if (S.out_kind == 1) {
+      // y_j[n] = Re(z) / N for n < T_u = Nx + Lmax - 1; an utterance whose
+      // T_u exceeds N or its output stride is skipped with BADPLAN
+      const int u = S.u0 + (int)sig;
+      const int I = b.n_src[u], Nx = b.src_len[u];
+      int lmax = 0;
+      for (int i = 0; i < min(I, b.S); ++i)
+        for (int jj = 0; jj < b.J; ++jj) lmax = max(lmax, b.rir_len[((long long)u * b.S + i) * b.J + jj]);
+      const long long T = (I > 0 && Nx > 0 && lmax > 0) ? (long long)Nx + lmax - 1 : 0;
+      const int stride = b.out_stride[u];
+      const bool lead = c0 == 0 && t == 0 && S.j == 0;
+      if (T > S.sig_len || T > stride) {
+        if (lead) {
+          flag_status(RSIM_DEV_BADPLAN);
+          b.out_len[u] = 0;
+        }
+        continue;
+      }
+      if (lead) b.out_len[u] = (int)T;
+      float* yj = S.y + b.out_off[u] + (long long)S.j * stride;
+      for (int e = t; e < C * L; e += kFfStepThreads) {
+        const int c = e & (C - 1), k = e >> S.log2c;
+        const long long n = (long long)(c0 + c) * S.out_cs + (long long)k * S.out_ks;
+        if (n < T) yj[n] = buf[k * CP + c].x * inv_n;
+      }
+      continue;
+    }
+    cf* dst = S.out + sig * S.sig_len + (long long)c0 * S.out_cs;
     for (int e = t; e < C * L; e += kFfStepThreads) {
       const int c = e & (C - 1), k = e >> S.log2c;
       cf z = buf[k * CP + c];
@@ -2038,102 +2124,6 @@ __global__ __launch_bounds__(kFfStepThreads) void ff_step_kernel(FfStep S) {
       dst[(long long)c * S.out_cs + (long long)k * S.out_ks] = z;
     }
   }
-}
-
-struct FfArgs {
-  BatchDev b;
-  const float* x;
-  const float* h;
-  const float* alpha;
-  float* y;
-  cf* X;    // [C][S][N] source spectra
-  cf* H;    // [C][S][N] RIR spectra of one mic
-  cf* Y;    // [C][N] one mic's spectrum
-  int u0, nu, log2n, j;
-};
-
-// Real signals into complex arrays: kind 0 the sources, 1 the cut RIRs of mic
-// A.j; slots without a signal are zero.  Also checks N >= Nx + Lmax - 1.
-__global__ __launch_bounds__(kFfThreads) void ff_load_kernel(FfArgs A, int kind) {
-  const BatchDev& b = A.b;
-  const long long N = 1LL << A.log2n;
-  const long long total = (long long)A.nu * b.S * N;
-  cf* dst = kind == 0 ? A.X : A.H;
-  for (long long g = (long long)blockIdx.x * kFfThreads + threadIdx.x; g < total;
-       g += (long long)gridDim.x * kFfThreads) {
-    const long long slot = g / N, n = g - slot * N;
-    const int cu = (int)(slot / b.S), i = (int)(slot - (long long)cu * b.S);
-    const int u = A.u0 + cu;
-    const int I = b.n_src[u];
-    if (i >= I) continue;  // an unused slot is neither transformed nor read
-    float v = 0.f;
-    if (I <= b.S) {
-      if (kind == 0) {
-        const long long so = b.src_off[(long long)u * b.S + i];
-        const int Nx = b.src_len[u];
-        if (n < Nx && so >= 0 && so + Nx <= b.x_len) v = A.x[so + n];
-      } else {
-        const long long r = ((long long)u * b.S + i) * b.J + A.j;
-        const long long ro = b.rir_off[r];
-        const int L = b.rir_len[r];
-        if (n < L && ro >= 0 && ro + L <= b.h_len) v = A.h[ro + n];
-      }
-    }
-    dst[g] = mk(v, 0.f);
-  }
-}
-
-// Y[c] = sum_i alpha_ij H[c][i] X[c][i] for mic A.j.
-__global__ __launch_bounds__(kFfThreads) void ff_mac_kernel(FfArgs A) {
-  const BatchDev& b = A.b;
-  const long long N = 1LL << A.log2n;
-  const long long total = (long long)A.nu * N;
-  for (long long g = (long long)blockIdx.x * kFfThreads + threadIdx.x; g < total;
-       g += (long long)gridDim.x * kFfThreads) {
-    const int cu = (int)(g / N);
-    const long long k = g - (long long)cu * N;
-    const int u = A.u0 + cu;
-    const int I = min(b.n_src[u], b.S);
-    float re = 0.f, im = 0.f;
-    for (int i = 0; i < I; ++i) {
-      const float a = A.alpha[((long long)u * b.S + i) * b.J + A.j];
-      const cf hv = A.H[((long long)cu * b.S + i) * N + k], xv = A.X[((long long)cu * b.S + i) * N + k];
-      const float pr = hv.x * xv.x - hv.y * xv.y, pi = hv.x * xv.y + hv.y * xv.x;
-      re = __builtin_fmaf(a, pr, re);
-      im = __builtin_fmaf(a, pi, im);
-    }
-    A.Y[g] = mk(re, im);
-  }
-}
-
-// y_j[n] = Re(Y[n]) / N for n < T_u = Nx + Lmax - 1 (written to out_len with
-// mic 0); an utterance whose T_u exceeds N or its output stride is skipped
-// with RSIM_DEV_BADPLAN.  Grid: (sample chunks, utterances of the chunk).
-__global__ __launch_bounds__(kFfThreads) void ff_store_kernel(FfArgs A) {
-  const BatchDev& b = A.b;
-  const long long N = 1LL << A.log2n;
-  const float sc = 1.0f / (float)N;
-  const int cu = blockIdx.y;
-  const int u = A.u0 + cu;
-  const int I = b.n_src[u], Nx = b.src_len[u];
-  int lmax = 0;
-  for (int i = 0; i < min(I, b.S); ++i)
-    for (int j = 0; j < b.J; ++j) lmax = max(lmax, b.rir_len[((long long)u * b.S + i) * b.J + j]);
-  const long long T = (I > 0 && Nx > 0 && lmax > 0) ? (long long)Nx + lmax - 1 : 0;
-  const int stride = b.out_stride[u];
-  const bool first = blockIdx.x == 0 && threadIdx.x == 0 && A.j == 0;
-  if (T > N || T > stride) {
-    if (first) {
-      flag_status(RSIM_DEV_BADPLAN);
-      b.out_len[u] = 0;
-    }
-    return;
-  }
-  if (first) b.out_len[u] = (int)T;
-  float* yj = A.y + b.out_off[u] + (long long)A.j * stride;
-  const cf* Y = A.Y + (long long)cu * N;
-  for (long long n = (long long)blockIdx.x * kFfThreads + threadIdx.x; n < T; n += (long long)gridDim.x * kFfThreads)
-    yj[n] = Y[n].x * sc;
 }
 
 // ================================================= FFT engine test kernels
@@ -3466,91 +3456,82 @@ rsim_status rsim_fft_filter(const rsim_batch* b, const float* x, const float* h,
   const rsim_status e = ensure_init(stream);
   if (e != RSIM_OK) return e;
   const long long N = 1LL << fft_log2n, C = chunk, S = b->max_src;
-  cf* base = static_cast<cf*>(ws);
-  FfArgs A;
-  A.b = to_dev(b);
-  A.x = x;
-  A.h = h;
-  A.alpha = alpha;
-  A.y = y;
-  A.X = base;
-  A.H = A.X + C * S * N;
-  cf* tmp = A.H + C * S * N;
-  A.Y = tmp + C * S * N;
-  A.log2n = fft_log2n;
+  cf* X = static_cast<cf*>(ws);  // [C][S][N] source spectra
+  cf* H = X + C * S * N;         // [C][S][N] RIR spectra of one mic
+  cf* tmp = H + C * S * N;       // [C][S][N] between the two steps
   const DevState& st = dev_state();
   const int cus = st.cus > 0 ? st.cus : 256;
-  auto grid_for = [&](long long work) {
-    return dim3((unsigned)std::max<long long>(1, std::min<long long>((work + kFfThreads - 1) / kFfThreads,
-                                                                      (long long)cus * 16)));
-  };
   // N = N1 N2, N1 = 2^l1 >= N2 = 2^l2, both at most 1024 points
   const int l1 = (fft_log2n + 1) / 2, l2 = fft_log2n / 2;
-  auto step = [&](const cf* in, cf* out, int count, bool inv, bool first, bool slots) {
-    FfStep S;
-    S.in = in;
-    S.out = out;
-    S.n_src = slots ? b->n_src : nullptr;
-    S.u0 = A.u0;
-    S.S = (int)b->max_src;
-    S.sig_len = N;
-    S.count = count;
-    S.log2n = fft_log2n;
+  FfStep base{};
+  base.sig_len = N;
+  base.log2n = fft_log2n;
+  base.b = to_dev(b);
+  base.x = x;
+  base.h = h;
+  base.alpha = alpha;
+  base.y = y;
+  base.X = X;
+  base.H = H;
+  base.S = (int)S;
+  // step A (first) or B of `count` transforms from `in` to `out`
+  auto step = [&](FfStep S_, const cf* in, cf* out, int count, bool inv, bool first) {
+    S_.in = in;
+    S_.out = out;
+    S_.count = count;
     if (first) {  // step A: N2 sequences of N1 points (stride N2), twiddled
-      S.log2l = l1;
-      S.cols = 1 << l2;
-      S.in_cs = 1;
-      S.in_ns = 1LL << l2;
-      S.out_cs = 1;
-      S.out_ks = 1LL << l2;
-      S.n_fast = 0;
-      S.twiddle = 1;
+      S_.log2l = l1;
+      S_.cols = 1 << l2;
+      S_.in_cs = 1;
+      S_.in_ns = 1LL << l2;
+      S_.out_cs = 1;
+      S_.out_ks = 1LL << l2;
+      S_.n_fast = 0;
+      S_.twiddle = 1;
     } else {  // step B: N1 rows of N2 points, outputs at k1 + N1 k2
-      S.log2l = l2;
-      S.cols = 1 << l1;
-      S.in_cs = 1LL << l2;
-      S.in_ns = 1;
-      S.out_cs = 1;
-      S.out_ks = 1LL << l1;
-      S.n_fast = 1;
-      S.twiddle = 0;
+      S_.log2l = l2;
+      S_.cols = 1 << l1;
+      S_.in_cs = 1LL << l2;
+      S_.in_ns = 1;
+      S_.out_cs = 1;
+      S_.out_ks = 1LL << l1;
+      S_.n_fast = 1;
+      S_.twiddle = 0;
     }
-    S.log2c = std::min(ilog2_floor(kFfTile) - S.log2l, ilog2_floor(S.cols));
-    const long long items = (long long)count * (S.cols >> S.log2c);
+    S_.log2c = std::min(ilog2_floor(kFfTile) - S_.log2l, ilog2_floor(S_.cols));
+    const long long items = (long long)count * (S_.cols >> S_.log2c);
     const dim3 grid((unsigned)std::max<long long>(1, std::min<long long>(items, (long long)cus * 2)));
-    void* args[] = {&S};
+    void* args[] = {&S_};
     const void* fn = inv ? reinterpret_cast<const void*>(&ff_step_kernel<true>)
                          : reinterpret_cast<const void*>(&ff_step_kernel<false>);
     return hipLaunchKernel(fn, grid, dim3(kFfStepThreads), args, 0, stream) == hipSuccess;
   };
-  // the two steps over `count` transforms: `first` -> `second` -> `first`
-  auto fft = [&](cf* first, cf* second, int count, bool inv) {
-    const bool slots = !inv;  // forward transforms run over source slots
-    return step(first, second, count, inv, true, slots) && step(second, first, count, inv, false, slots);
-  };
-  const bool even = true;  // the data ends where it started
   for (int u0 = 0; u0 < b->n_utt; u0 += chunk) {
-    A.u0 = u0;
-    A.nu = std::min(chunk, b->n_utt - u0);
-    const int cs = (int)(A.nu * S);
-    // sources: loaded where the passes end in X
-    FfArgs L = A;
-    L.X = even ? A.X : tmp;
-    hipLaunchKernelGGL(ff_load_kernel, grid_for((long long)cs * N), dim3(kFfThreads), 0, stream, L, 0);
-    if (!fft(L.X, even ? tmp : A.X, cs, false)) return clear_error(RSIM_EDEVICE);
+    const int nu = std::min(chunk, b->n_utt - u0);
+    const int cs = (int)(nu * S);
+    FfStep F = base;
+    F.u0 = u0;
+    F.n_src = b->n_src;  // forward transforms run over source slots
+    // the sources' spectra: real samples -> A -> tmp -> B -> X
+    FfStep A1 = F, B1 = F;
+    A1.in_kind = 1;
+    if (!step(A1, nullptr, tmp, cs, false, true) || !step(B1, tmp, X, cs, false, false))
+      return clear_error(RSIM_EDEVICE);
     for (int j = 0; j < b->n_mic; ++j) {
-      A.j = j;
-      L = A;
-      L.H = even ? A.H : tmp;
-      hipLaunchKernelGGL(ff_load_kernel, grid_for((long long)cs * N), dim3(kFfThreads), 0, stream, L, 1);
-      if (!fft(L.H, even ? tmp : A.H, cs, false)) return clear_error(RSIM_EDEVICE);
-      L = A;
-      L.Y = even ? A.Y : tmp;
-      hipLaunchKernelGGL(ff_mac_kernel, grid_for((long long)A.nu * N), dim3(kFfThreads), 0, stream, L);
-      if (!fft(L.Y, even ? tmp : A.Y, A.nu, true)) return clear_error(RSIM_EDEVICE);
-      const unsigned chunks = (unsigned)std::max<long long>(1, std::min<long long>((N + kFfThreads - 1) / kFfThreads,
-                                                                                 ((long long)cus * 8 + A.nu - 1) / A.nu));
-      hipLaunchKernelGGL(ff_store_kernel, dim3(chunks, (unsigned)A.nu), dim3(kFfThreads), 0, stream, A);
+      // the cut RIRs' spectra of mic j -> H
+      FfStep A2 = F, B2 = F;
+      A2.in_kind = 2;
+      A2.j = j;
+      if (!step(A2, nullptr, tmp, cs, false, true) || !step(B2, tmp, H, cs, false, false))
+        return clear_error(RSIM_EDEVICE);
+      // one inverse per utterance of sum_i alpha H X, stored as y_j
+      FfStep A3 = base, B3 = base;
+      A3.u0 = B3.u0 = u0;
+      A3.in_kind = 3;
+      A3.j = B3.j = j;
+      B3.out_kind = 1;
+      if (!step(A3, nullptr, tmp, nu, true, true) || !step(B3, tmp, nullptr, nu, true, false))
+        return clear_error(RSIM_EDEVICE);
     }
   }
   return hipGetLastError() == hipSuccess ? RSIM_OK : clear_error(RSIM_EDEVICE);
