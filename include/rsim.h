@@ -307,10 +307,13 @@ rsim_status rsim_logmel(const rsim_batch* b, const float* y, float* feat, const 
  * N = 2^fft_log2n >= Nx + Lmax - 1 (the caller's bound for the whole batch;
  * an utterance it does not fit, or whose T_u exceeds its output stride, is
  * skipped with RSIM_DEV_BADPLAN and out_len 0), with the cut lengths in
- * b->rir_len (call after the cut).  The transforms are batched global-memory
- * passes over `chunk` utterances at a time; ws must hold
- * rsim_fft_filter_workspace_bytes(b, fft_log2n, chunk) bytes.  Writes y and
- * out_len like rsim_mix.  1 <= fft_log2n <= 20, chunk >= 1 (RSIM_EINVAL).
+ * b->rir_len (call after the cut).  Each transform takes two passes over
+ * global memory (N = N1 N2, sub-transforms of at most 1024 points in LDS),
+ * batched over `chunk` utterances at a time; ws must hold
+ * rsim_fft_filter_workspace_bytes(b, fft_log2n, chunk) = 3 max_src chunk N
+ * complex floats (source spectra, one mic's RIR spectra, intermediate).
+ * Writes y and out_len like rsim_mix.  1 <= fft_log2n <= 20, chunk >= 1
+ * (RSIM_EINVAL).
  */
 size_t rsim_fft_filter_workspace_bytes(const rsim_batch* b, int32_t fft_log2n, int32_t chunk);
 rsim_status rsim_fft_filter(const rsim_batch* b, const float* x, const float* h, const float* alpha, float* y,

@@ -3443,7 +3443,7 @@ rsim_status rsim_logmel(const rsim_batch* b, const float* y, float* feat, const 
 size_t rsim_fft_filter_workspace_bytes(const rsim_batch* b, int32_t fft_log2n, int32_t chunk) {
   if (!batch_ok(b) || fft_log2n < 1 || fft_log2n > 20 || chunk < 1) return 0;
   const size_t N = (size_t)1 << fft_log2n, C = (size_t)chunk, S = (size_t)b->max_src;
-  return (3 * S + 2) * C * N * sizeof(cf);
+  return 3 * S * C * N * sizeof(cf);
 }
 
 rsim_status rsim_fft_filter(const rsim_batch* b, const float* x, const float* h, const float* alpha, float* y,

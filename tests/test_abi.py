@@ -256,7 +256,7 @@ def test_fft_filter_validation_codes():
     p = ctypes.c_void_p(8)
     b = _host_batch()
     need = lib.rsim_fft_filter_workspace_bytes(ctypes.byref(b), 12, 4)
-    assert need == (3 * 2 + 2) * 4 * 4096 * 8
+    assert need == 3 * 2 * 4 * 4096 * 8  # 3 max_src chunk N complex floats
     for l2, chunk in ((0, 4), (21, 4), (12, 0)):
         assert lib.rsim_fft_filter_workspace_bytes(ctypes.byref(b), l2, chunk) == 0
         assert lib.rsim_fft_filter(ctypes.byref(b), p, p, p, p, l2, chunk, p, need, None) == rsim.RSIM_EINVAL
