@@ -93,3 +93,18 @@ def test_fft_filter_too_small_a_transform_is_flagged():
     rsim.device_status()
     y, rl, ol, alpha = _run(b, math.inf, fft_log2n=12)   # 4096 < 5199
     assert int(ol[0]) == 0 and rsim.device_status() & rsim.DEV_BADPLAN
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("l2,n,L", [(1, 1, 1), (3, 5, 4), (6, 40, 20), (9, 400, 100), (12, 3000, 1000),
+                                    (19, 500000, 300), (20, 1000000, 64)])
+def test_fft_filter_tile_shapes(l2, n, L):
+    # every split N = N1 N2 from 2 to 2^20 points: one-point second steps,
+    # radix-2 passes in either step, eight columns of 1024 points per tile
+    rng = synth.rng_for(67, l2)
+    srcs = [[synth.speech_like(rng, n), synth.white_noise(rng, n)]]
+    rirs = [[[synth.rir(rng, L, 0.5, 0)], [synth.rir(rng, max(1, L // 2), 0.3, 0)]]]
+    b = synth.pack(srcs, rirs, [[0.0, 5.0]], 1)
+    assert n + L - 1 <= (1 << l2)
+    y, rl, ol, alpha = _run(b, math.inf, fft_log2n=l2, chunk=1)
+    _check(b, math.inf, y, rl, ol, alpha, [0])

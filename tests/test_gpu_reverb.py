@@ -119,3 +119,22 @@ def test_kept_rir_longer_than_the_largest_transform_is_flagged():
     assert math.isnan(e[0]) and rsim.device_status() & rsim.DEV_BADPLAN
     ref = oracle.reverb_energy(b.sources(1)[0], b.rirs(1)[0][0])
     assert abs(e[b.max_src] - ref) <= 1e-4 * ref
+
+
+@pytest.mark.gpu
+def test_energies_of_more_slots_than_the_cost_cache_holds():
+    # 9000 utterances x 4 source slots = 36000 slots, more than the LDS cost
+    # cache of a workgroup holds (the balanced ranges are then computed from
+    # the descriptors twice); short sources, few taps, some empty slots
+    rng = synth.rng_for(63, 0)
+    srcs, rirs, snrs = [], [], []
+    for u in range(9000):
+        I = 4 if u == 4321 else 1 + (u % 7 == 0)
+        n = int(rng.integers(50, 300))
+        srcs.append([synth.white_noise(rng, n) for _ in range(I)])
+        rirs.append([[synth.rir(rng, int(rng.integers(1, 40)), 0.2, 0)] for _ in range(I)])
+        snrs.append([0.0] * I)
+    b = synth.pack(srcs, rirs, snrs, 1)
+    assert b.n_utt * b.max_src > 35000
+    _, e, rl = _energies(b, math.inf)
+    _check_energies(b, math.inf, e, rl)
