@@ -43,7 +43,7 @@ __device__ __host__ constexpr int mel_cap(int quarter) {
   return quarter == 0 ? kMelCap0 : quarter == 1 ? kMelCap1 : quarter == 2 ? kMelCap2 : kMelCap3;
 }
 __device__ float g_hann[kMelWin];
-__device__ int g_mel_first[kMelBands], g_mel_count[kMelBands];
+__device__ int g_mel_first[kMelBands];
 __device__ float g_mel_w[kMelBands * kMelCapMax];  // band b's weights at [b * kMelCapMax, + count), zero after
 
 __device__ __forceinline__ void flag_status(int bits) { atomicOr(&g_status, bits); }
@@ -2221,15 +2221,19 @@ struct MelArgs {
 
 __device__ __forceinline__ int mel_frames(int T) { return T >= kMelWin ? 1 + (T - kMelWin) / kMelHop : 0; }
 
-// Band energy sum_i w[i] pw[first + i] over i < count (<= CAP), in bin order.
+// Band energy sum_i w[i] pw[first + i] over i < CAP, in bin order; the
+// weights past the band's bins are zero, so for finite powers those terms
+// add exactly nothing.  (A non-finite power can also make the bands whose
+// padded range covers it NaN; with the full filterbank matrix it makes
+// every band NaN.)
 template <int CAP>
-__device__ __forceinline__ float mel_band(const float* w, const float* pw, int first, int count) {
+__device__ __forceinline__ float mel_band(const float* w, const float* pw, int first) {
   float p[CAP];
 #pragma unroll
   for (int i = 0; i < CAP; ++i) p[i] = pw[first + i];
   float m = 0.f;
 #pragma unroll
-  for (int i = 0; i < CAP; ++i) m = i < count ? __builtin_fmaf(w[i], p[i], m) : m;
+  for (int i = 0; i < CAP; ++i) m = __builtin_fmaf(w[i], p[i], m);
   return m;
 }
 
@@ -2246,12 +2250,9 @@ __global__ __launch_bounds__(kMelGroups * 32) void logmel_kernel(MelArgs A) {
     hw[2 * r + 1] = g_hann[2 * (t + r * PL::T) + 1];
   }
   float w0[kMelCap0], w1[kMelCap1], w2[kMelCap2], w3[kMelCap3];
-  int first[4], count[4];
+  int first[4];
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    first[k] = g_mel_first[t + 32 * k];
-    count[k] = g_mel_count[t + 32 * k];
-  }
+  for (int k = 0; k < 4; ++k) first[k] = g_mel_first[t + 32 * k];
 #pragma unroll
   for (int i = 0; i < kMelCap0; ++i) w0[i] = g_mel_w[(t + 0) * kMelCapMax + i];
 #pragma unroll
@@ -2320,10 +2321,10 @@ __global__ __launch_bounds__(kMelGroups * 32) void logmel_kernel(MelArgs A) {
       __syncthreads();
       if (live) {
         float* out = A.feat + fo + ((long long)j * cap + fr) * kMelBands;
-        const float m0 = mel_band<kMelCap0>(w0, pw, first[0], count[0]);
-        const float m1 = mel_band<kMelCap1>(w1, pw, first[1], count[1]);
-        const float m2 = mel_band<kMelCap2>(w2, pw, first[2], count[2]);
-        const float m3 = mel_band<kMelCap3>(w3, pw, first[3], count[3]);
+        const float m0 = mel_band<kMelCap0>(w0, pw, first[0]);
+        const float m1 = mel_band<kMelCap1>(w1, pw, first[1]);
+        const float m2 = mel_band<kMelCap2>(w2, pw, first[2]);
+        const float m3 = mel_band<kMelCap3>(w3, pw, first[3]);
         out[t] = logf(m0 + 1e-6f);
         out[t + 32] = logf(m1 + 1e-6f);
         out[t + 64] = logf(m2 + 1e-6f);
@@ -2529,7 +2530,6 @@ bool upload_mel_tables() {
   }
   return hipMemcpyToSymbol(HIP_SYMBOL(g_hann), hann.data(), sizeof(float) * kMelWin) == hipSuccess &&
          hipMemcpyToSymbol(HIP_SYMBOL(g_mel_first), first, sizeof(first)) == hipSuccess &&
-         hipMemcpyToSymbol(HIP_SYMBOL(g_mel_count), count, sizeof(count)) == hipSuccess &&
          hipMemcpyToSymbol(HIP_SYMBOL(g_mel_w), w.data(), sizeof(float) * w.size()) == hipSuccess;
 }
 
