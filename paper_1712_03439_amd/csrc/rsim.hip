@@ -462,17 +462,44 @@ __device__ __forceinline__ void load_spec(cf* v, const cf* __restrict__ src, int
   for (int q = 0; q < PL::P; ++q) v[q] = ld2(rs, vo, 8 * q * PL::T);
 }
 
-// Y += H X over the thread's slots; thread 0's slot SP is the packed pair of
+// The mix kernel's RIR spectra in pairs: slots 2p, 2p + 1 of thread t at
+// index p 2T + 2t, so one 128-bit access moves both (half the load
+// instructions of the slot layout for the same bytes).
+template <class PL>
+__device__ __forceinline__ void store_spec_pair(cf* __restrict__ dst, const cf* v, int t) {
+  static_assert(PL::P % 2 == 0, "slots come in pairs");
+  const rsrc_t rs = make_rsrc(dst, PL::P * PL::T * 8);
+  const int vo = 16 * opaque_v(t);
+  typedef unsigned u4 __attribute__((ext_vector_type(4)));
+#pragma unroll
+  for (int p = 0; p < PL::P / 2; ++p) {
+    const f4 w = {v[2 * p].x, v[2 * p].y, v[2 * p + 1].x, v[2 * p + 1].y};
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u4, w), rs, vo, 16 * p * PL::T, 0);
+  }
+}
+template <class PL>
+__device__ __forceinline__ void load_spec_pair(cf* v, const cf* __restrict__ src, int t) {
+  const rsrc_t rs = make_rsrc(src, PL::P * PL::T * 8);
+  const int vo = 16 * opaque_v(t);
+#pragma unroll
+  for (int p = 0; p < PL::P / 2; ++p) {
+    const f4 w = ld4(rs, vo, 16 * p * PL::T);
+    v[2 * p] = mk(w.x, w.y);
+    v[2 * p + 1] = mk(w.z, w.w);
+  }
+}
+
+// Y += H X over the thread's slots (H in the paired layout); thread 0's slot SP is the packed pair of
 // real bins (0, N/2) and multiplies componentwise.
 template <class PL>
 __device__ __forceinline__ void mac(cf* Y, const cf* __restrict__ H, const cf* X, int t_) {
   constexpr int SP = Fft<PL>::SP;
   const int t = opaque_v(t_);
   const rsrc_t rs = make_rsrc(H, PL::P * PL::T * 8);
-  const int vo = 8 * t;
+  const int vo = 16 * t;
 #pragma unroll
   for (int q = 0; q < PL::P; ++q) {
-    const cf hv = ld2(rs, vo, 8 * q * PL::T);
+    const cf hv = ld2(rs, vo + 8 * (q & 1), 16 * (q >> 1) * PL::T);
     if (q == SP) {
       const cf c = cmac(Y[q], hv, X[q]);
       const cf d = mk(__builtin_fmaf(hv.x, X[q].x, Y[q].x), __builtin_fmaf(hv.y, X[q].y, Y[q].y));
@@ -501,7 +528,7 @@ __device__ __forceinline__ void mac_regs(cf* Y, const cf* Hr, const cf* X, int t
   }
 }
 
-// Two mics at once: Y0 += H0 X, Y1 += H1 X, one slot at a time.
+// Two mics at once: Y0 += H0 X, Y1 += H1 X, one slot at a time (H paired).
 template <class PL>
 __device__ __forceinline__ void mac2(cf* Y0, cf* Y1, const cf* __restrict__ H0,
                                      const cf* __restrict__ H1, const cf* X, int t_) {
@@ -509,11 +536,11 @@ __device__ __forceinline__ void mac2(cf* Y0, cf* Y1, const cf* __restrict__ H0,
   const int t = opaque_v(t_);
   const rsrc_t r0 = make_rsrc(H0, PL::P * PL::T * 8);
   const rsrc_t r1 = make_rsrc(H1, PL::P * PL::T * 8);
-  const int vo = 8 * t;
+  const int vo = 16 * t;
 #pragma unroll
   for (int q = 0; q < PL::P; ++q) {
-    const cf h0 = ld2(r0, vo, 8 * q * PL::T);
-    const cf h1 = ld2(r1, vo, 8 * q * PL::T);
+    const cf h0 = ld2(r0, vo + 8 * (q & 1), 16 * (q >> 1) * PL::T);
+    const cf h1 = ld2(r1, vo + 8 * (q & 1), 16 * (q >> 1) * PL::T);
     if (q == SP) {
       const cf c0 = cmac(Y0[q], h0, X[q]), c1 = cmac(Y1[q], h1, X[q]);
       const cf d0 = mk(__builtin_fmaf(h0.x, X[q].x, Y0[q].x), __builtin_fmaf(h0.y, X[q].y, Y0[q].y));
@@ -664,7 +691,7 @@ __device__ __forceinline__ void rir_spectra(const MixArgs& A, const UttDesc& D, 
     const float a = A.alpha[r0 + sl] * cscale;
 #pragma unroll
     for (int q = 0; q < P; ++q) v[q] = mk(v[q].x * a, v[q].y * a);
-    store_spec<PL>(Hs + (long long)sl * M, v, t);
+    store_spec_pair<PL>(Hs + (long long)sl * M, v, t);
   }
 }
 
@@ -756,9 +783,9 @@ __device__ __forceinline__ void mix_utterance(const MixArgs& A, int u, const Sch
 #pragma unroll
           for (int q = 0; q < P; ++q) X[q] = opaque_c(Xn[q]);
           asm volatile("" ::: "memory");
-          load_spec<PL>(Hp0, H0, t);
+          load_spec_pair<PL>(Hp0, H0, t);
           if constexpr (JG == 2) {
-            if (two) load_spec<PL>(Hp1, H0 + M, t);
+            if (two) load_spec_pair<PL>(Hp1, H0 + M, t);
           }
           // With one source, the next group's input is this item's own
           // spectrum, not yet in the cache: it is handed over in registers.
