@@ -497,9 +497,11 @@ __device__ __forceinline__ void mac(cf* Y, const cf* __restrict__ H, const cf* X
   const int t = opaque_v(t_);
   const rsrc_t rs = make_rsrc(H, PL::P * PL::T * 8);
   const int vo = 16 * t;
+  f4 w;
 #pragma unroll
   for (int q = 0; q < PL::P; ++q) {
-    const cf hv = ld2(rs, vo + 8 * (q & 1), 16 * (q >> 1) * PL::T);
+    if ((q & 1) == 0) w = ld4(rs, vo, 16 * (q >> 1) * PL::T);  // slots q, q + 1
+    const cf hv = (q & 1) ? mk(w.z, w.w) : mk(w.x, w.y);
     if (q == SP) {
       const cf c = cmac(Y[q], hv, X[q]);
       const cf d = mk(__builtin_fmaf(hv.x, X[q].x, Y[q].x), __builtin_fmaf(hv.y, X[q].y, Y[q].y));
@@ -537,10 +539,15 @@ __device__ __forceinline__ void mac2(cf* Y0, cf* Y1, const cf* __restrict__ H0,
   const rsrc_t r0 = make_rsrc(H0, PL::P * PL::T * 8);
   const rsrc_t r1 = make_rsrc(H1, PL::P * PL::T * 8);
   const int vo = 16 * t;
+  f4 w0, w1;
 #pragma unroll
   for (int q = 0; q < PL::P; ++q) {
-    const cf h0 = ld2(r0, vo + 8 * (q & 1), 16 * (q >> 1) * PL::T);
-    const cf h1 = ld2(r1, vo + 8 * (q & 1), 16 * (q >> 1) * PL::T);
+    if ((q & 1) == 0) {  // slots q, q + 1
+      w0 = ld4(r0, vo, 16 * (q >> 1) * PL::T);
+      w1 = ld4(r1, vo, 16 * (q >> 1) * PL::T);
+    }
+    const cf h0 = (q & 1) ? mk(w0.z, w0.w) : mk(w0.x, w0.y);
+    const cf h1 = (q & 1) ? mk(w1.z, w1.w) : mk(w1.x, w1.y);
     if (q == SP) {
       const cf c0 = cmac(Y0[q], h0, X[q]), c1 = cmac(Y1[q], h1, X[q]);
       const cf d0 = mk(__builtin_fmaf(h0.x, X[q].x, Y0[q].x), __builtin_fmaf(h0.y, X[q].y, Y0[q].y));
