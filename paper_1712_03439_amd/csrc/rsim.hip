@@ -933,11 +933,11 @@ __device__ __forceinline__ void macc_mem(cf* Y, const cf* __restrict__ Am, const
   const int t = opaque_v(t_);
   const rsrc_t ra = make_rsrc(Am, PL::P * PL::T * 8);
   const rsrc_t rb = make_rsrc(Bm, PL::P * PL::T * 8);
-  const int vo = 8 * t;
+  const int vo = 16 * t;  // paired layout: slot q at (q / 2) 2T + 2t + q % 2
 #pragma unroll
   for (int q = 0; q < PL::P; ++q) {
-    const cf a = ld2(ra, vo, 8 * q * PL::T);
-    const cf bv = ld2(rb, vo, 8 * q * PL::T);
+    const cf a = ld2(ra, vo + 8 * (q & 1), 16 * (q >> 1) * PL::T);
+    const cf bv = ld2(rb, vo + 8 * (q & 1), 16 * (q >> 1) * PL::T);
     if (q == SP) {
       const cf c = cmacc(Y[q], a, bv);
       const cf d = mk(__builtin_fmaf(a.x, bv.x, Y[q].x), __builtin_fmaf(a.y, bv.y, Y[q].y));
@@ -957,11 +957,12 @@ __device__ __forceinline__ void acc_corr(cf* __restrict__ Rm, const cf* X, const
   const rsrc_t rr = make_rsrc(Rm, first ? 0 : PL::P * PL::T * 8);  // a zero range reads zeros
   const rsrc_t rw = make_rsrc(Rm, PL::P * PL::T * 8);
   const rsrc_t rb = make_rsrc(Bm, PL::P * PL::T * 8);
-  const int vo = 8 * t;
+  const int vo = 16 * t;  // paired layout
 #pragma unroll
   for (int q = 0; q < PL::P; ++q) {
-    const cf acc = ld2(rr, vo, 8 * q * PL::T);
-    const cf bv = ld2(rb, vo, 8 * q * PL::T);
+    const int vq = vo + 8 * (q & 1), sq = 16 * (q >> 1) * PL::T;
+    const cf acc = ld2(rr, vq, sq);
+    const cf bv = ld2(rb, vq, sq);
     cf o;
     if (q == SP) {
       const cf c = cmacc(acc, X[q], bv);
@@ -970,7 +971,7 @@ __device__ __forceinline__ void acc_corr(cf* __restrict__ Rm, const cf* X, const
     } else {
       o = cmacc(acc, X[q], bv);
     }
-    st2(rw, vo, o, 8 * q * PL::T);
+    st2(rw, vq, o, sq);
   }
 }
 
@@ -990,10 +991,12 @@ __device__ __forceinline__ void bwd_pair_pass(cf* D0, cf* D1, const cf* X0, cons
   // of its accumulators is written back (the compiler cannot tell the
   // accumulator reads from the writes apart, so reads after a write wait for
   // it), which makes one memory round trip per batch instead of per slot.
+  // The spectra are in the paired layout: one 128-bit access per two slots.
   constexpr int QB = PL::P < 8 ? PL::P : 8;
   const int t = opaque_v(t_);
-  const int vo = 8 * t;
+  const int vo = 16 * t;
   constexpr int bytes = PL::P * PL::T * 8;
+  typedef unsigned u4 __attribute__((ext_vector_type(4)));
   for (int j = 0; j < J; ++j) {
     const rsrc_t rh = make_rsrc(Hi + (long long)j * M, bytes);
     const rsrc_t r0 = make_rsrc(G0 + (long long)j * M, bytes);
@@ -1002,37 +1005,46 @@ __device__ __forceinline__ void bwd_pair_pass(cf* D0, cf* D1, const cf* X0, cons
     const rsrc_t rw = make_rsrc(Ri + (long long)j * M, bytes);
 #pragma unroll
     for (int q0 = 0; q0 < PL::P; q0 += QB) {
-    cf hb[QB], g0b[QB], g1b[QB], ab[QB];
+      f4 hb[QB / 2], g0b[QB / 2], g1b[QB / 2], ab[QB / 2];
 #pragma unroll
-    for (int e = 0; e < QB; ++e) {
-      const int so = 8 * (q0 + e) * PL::T;
-      hb[e] = ld2(rh, vo, so);
-      g0b[e] = ld2(r0, vo, so);
-      g1b[e] = ld2(r1, vo, so);
-      ab[e] = ld2(rr, vo, so);
-    }
-#pragma unroll
-    for (int e = 0; e < QB; ++e) {
-      const int q = q0 + e;
-      const cf h = hb[e], g0 = g0b[e], g1 = g1b[e], acc = ab[e];
-      cf o;
-      if (q == SP) {
-        const cf c0 = cmacc(D0[q], h, g0), c1 = cmacc(D1[q], h, g1);
-        const cf co = cmacc(cmacc(acc, X0[q], g0), X1[q], g1);
-        const cf d0 = mk(__builtin_fmaf(h.x, g0.x, D0[q].x), __builtin_fmaf(h.y, g0.y, D0[q].y));
-        const cf d1 = mk(__builtin_fmaf(h.x, g1.x, D1[q].x), __builtin_fmaf(h.y, g1.y, D1[q].y));
-        const cf dr = mk(__builtin_fmaf(X1[q].x, g1.x, __builtin_fmaf(X0[q].x, g0.x, acc.x)),
-                         __builtin_fmaf(X1[q].y, g1.y, __builtin_fmaf(X0[q].y, g0.y, acc.y)));
-        D0[q] = t == 0 ? d0 : c0;
-        D1[q] = t == 0 ? d1 : c1;
-        o = t == 0 ? dr : co;
-      } else {
-        D0[q] = cmacc(D0[q], h, g0);
-        D1[q] = cmacc(D1[q], h, g1);
-        o = cmacc(cmacc(acc, X0[q], g0), X1[q], g1);
+      for (int e = 0; e < QB / 2; ++e) {
+        const int so = 16 * (q0 / 2 + e) * PL::T;
+        hb[e] = ld4(rh, vo, so);
+        g0b[e] = ld4(r0, vo, so);
+        g1b[e] = ld4(r1, vo, so);
+        ab[e] = ld4(rr, vo, so);
       }
-      st2(rw, vo, o, 8 * q * PL::T);
-    }
+#pragma unroll
+      for (int e = 0; e < QB / 2; ++e) {
+        cf o2[2];
+#pragma unroll
+        for (int hlf = 0; hlf < 2; ++hlf) {
+          const int q = q0 + 2 * e + hlf;
+          const cf h = hlf ? mk(hb[e].z, hb[e].w) : mk(hb[e].x, hb[e].y);
+          const cf g0 = hlf ? mk(g0b[e].z, g0b[e].w) : mk(g0b[e].x, g0b[e].y);
+          const cf g1 = hlf ? mk(g1b[e].z, g1b[e].w) : mk(g1b[e].x, g1b[e].y);
+          const cf acc = hlf ? mk(ab[e].z, ab[e].w) : mk(ab[e].x, ab[e].y);
+          cf o;
+          if (q == SP) {
+            const cf c0 = cmacc(D0[q], h, g0), c1 = cmacc(D1[q], h, g1);
+            const cf co = cmacc(cmacc(acc, X0[q], g0), X1[q], g1);
+            const cf d0 = mk(__builtin_fmaf(h.x, g0.x, D0[q].x), __builtin_fmaf(h.y, g0.y, D0[q].y));
+            const cf d1 = mk(__builtin_fmaf(h.x, g1.x, D1[q].x), __builtin_fmaf(h.y, g1.y, D1[q].y));
+            const cf dr = mk(__builtin_fmaf(X1[q].x, g1.x, __builtin_fmaf(X0[q].x, g0.x, acc.x)),
+                             __builtin_fmaf(X1[q].y, g1.y, __builtin_fmaf(X0[q].y, g0.y, acc.y)));
+            D0[q] = t == 0 ? d0 : c0;
+            D1[q] = t == 0 ? d1 : c1;
+            o = t == 0 ? dr : co;
+          } else {
+            D0[q] = cmacc(D0[q], h, g0);
+            D1[q] = cmacc(D1[q], h, g1);
+            o = cmacc(cmacc(acc, X0[q], g0), X1[q], g1);
+          }
+          o2[hlf] = o;
+        }
+        const f4 w = {o2[0].x, o2[0].y, o2[1].x, o2[1].y};
+        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u4, w), rw, vo, 16 * (q0 / 2 + e) * PL::T, 0);
+      }
     }
   }
 }
@@ -1092,12 +1104,12 @@ __device__ __forceinline__ void bwd_finish_rir(const BwdArgs& A, long long r, co
   // in part order) and the kept taps before the transform.
   constexpr bool kBatch = PL::T <= 512;
   cf v[P];
-  load_spec<PL>(v, R, t);
+  load_spec_pair<PL>(v, R, t);
   if (kBatch && nparts <= 4) {
     cf w1[kBatch ? P : 1], w2[kBatch ? P : 1], w3[kBatch ? P : 1];
-    if (nparts > 1) load_spec<PL>(w1, R + stride, t);
-    if (nparts > 2) load_spec<PL>(w2, R + 2 * stride, t);
-    if (nparts > 3) load_spec<PL>(w3, R + 3 * stride, t);
+    if (nparts > 1) load_spec_pair<PL>(w1, R + stride, t);
+    if (nparts > 2) load_spec_pair<PL>(w2, R + 2 * stride, t);
+    if (nparts > 3) load_spec_pair<PL>(w3, R + 3 * stride, t);
     if (nparts > 1) {
 #pragma unroll
       for (int q = 0; q < P; ++q) v[q] = mk(v[q].x + w1[q].x, v[q].y + w1[q].y);
@@ -1113,7 +1125,7 @@ __device__ __forceinline__ void bwd_finish_rir(const BwdArgs& A, long long r, co
   } else {
     for (int k = 1; k < nparts; ++k) {
       cf w[P];
-      load_spec<PL>(w, R + k * stride, t);
+      load_spec_pair<PL>(w, R + k * stride, t);
 #pragma unroll
       for (int q = 0; q < P; ++q) v[q] = mk(v[q].x + w[q].x, v[q].y + w[q].y);
     }
@@ -1156,7 +1168,7 @@ __device__ __forceinline__ void bwd_rir_spectrum(const BwdArgs& A, long long r, 
   const float a = A.alpha[r];
 #pragma unroll
   for (int q = 0; q < P; ++q) v[q] = mk(v[q].x * a, v[q].y * a);
-  store_spec<PL>(dst, v, t);
+  store_spec_pair<PL>(dst, v, t);
 }
 
 // Work item (u, part) of the adjoint: blocks [b0, b1) of utterance u.  With
@@ -1223,7 +1235,7 @@ __device__ __forceinline__ void bwd_utterance(const BwdArgs& A, int u, const Sch
         Fft<PL>::post(v, tw, t);
 #pragma unroll
         for (int q = 0; q < P; ++q) v[q] = mk(v[q].x * gscale, v[q].y * gscale);
-        store_spec<PL>(Gs + (long long)k * M, v, t);
+        store_spec_pair<PL>(Gs + (long long)k * M, v, t);
       }
       for (int i = 0; i < I; ++i) {
         const long long so = uni64(b.src_off[(long long)u * NS + i]);
@@ -1259,7 +1271,7 @@ __device__ __forceinline__ void bwd_utterance(const BwdArgs& A, int u, const Sch
         Fft<PL>::post(v, tw, t);
 #pragma unroll
         for (int q = 0; q < P; ++q) v[q] = mk(v[q].x * gscale, v[q].y * gscale);
-        store_spec<PL>(Gs + (long long)j * M, v, t);
+        store_spec_pair<PL>(Gs + (long long)j * M, v, t);
       }
       for (int i = 0; i < I; ++i) {
         const long long so = uni64(b.src_off[(long long)u * NS + i]);
@@ -1282,7 +1294,7 @@ __device__ __forceinline__ void bwd_utterance(const BwdArgs& A, int u, const Sch
       cf z[P];
 #pragma unroll
       for (int q = 0; q < P; ++q) z[q] = mk(0.f, 0.f);
-      store_spec<PL>(Rs + (long long)k * M, z, t);
+      store_spec_pair<PL>(Rs + (long long)k * M, z, t);
     }
   }
   if (nparts > 1) return;
