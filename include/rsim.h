@@ -124,6 +124,9 @@ typedef struct rsim_tune {
 rsim_status rsim_init(void);
 
 const char* rsim_strerror(rsim_status s);
+/* 10000 major + 100 minor + patch.  The minor number changes with the layout
+ * of rsim_batch or rsim_tune (1.1: rsim_batch.fft_sizes, rsim_tune.variant);
+ * a caller built against another minor number must not pass them. */
 int32_t rsim_version(void);
 
 /*

@@ -3192,7 +3192,7 @@ const char* rsim_strerror(rsim_status s) {
   return "unknown status";
 }
 
-int32_t rsim_version(void) { return 10000; }
+int32_t rsim_version(void) { return 10100; }
 
 rsim_status rsim_truncate_rir(const float* h, int64_t h_len, const int64_t* off, const int32_t* len0,
                               int32_t n_rir, double eta_db, int32_t* n_c, int32_t* len,

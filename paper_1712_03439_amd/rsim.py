@@ -57,6 +57,7 @@ class RsimTune(ctypes.Structure):
 
 
 _LIB = None
+ABI_VERSION = 10100  # rsim_version() of the layouts of RsimBatch and RsimTune
 
 
 def _lib():
@@ -96,6 +97,10 @@ def _lib():
             fn = getattr(lib, name)
             fn.argtypes = args
             fn.restype = res
+        # the descriptors mirrored above have the layout of version 1.1
+        if lib.rsim_version() // 100 != ABI_VERSION // 100:
+            raise ImportError(f"{LIB_PATH} has ABI version {lib.rsim_version()}, this binding needs "
+                              f"{ABI_VERSION // 10000}.{ABI_VERSION // 100 % 100}; rebuild it")
         _LIB = lib
     return _LIB
 
