@@ -130,7 +130,11 @@ def cpu_baseline(base, eta, n_utt, max_workers=16):
 def differentiation(torch, rsim, synth, dev, reps: int = 10):
     """Forward and adjoint of the mix on the differentiation workload: 64
     utterances of 4 s, 3 sources, 4 mics, 8192-tap RIRs, no cut, N = 16384
-    (hop 8193, 8 blocks), loss sum_j sum_n w_j[n] y_j[n]^2 so g = 2 w y."""
+    (hop 8193, 8 blocks), loss sum_j sum_n w_j[n] y_j[n]^2 so g = 2 w y.  The
+    forward's kernel variant is chosen by the tuner on this batch (with 64
+    utterances, splitting the mics over more work items can fill more CUs)."""
+    from paper_1712_03439_amd import autotune
+
     b = synth.make_config3()
     U, S, J = b.n_utt, b.max_src, b.n_mic
     db = rsim.DeviceBatch(b, device=dev, fft_log2n=np.full(U, 14, np.int32))
@@ -139,19 +143,21 @@ def differentiation(torch, rsim, synth, dev, reps: int = 10):
     stream.wait_stream(torch.cuda.current_stream())
     with torch.cuda.stream(stream):
         rsim.truncate_batch(db, math.inf, stream=stream)
+    tune, entry = autotune.tune(db, alpha, policy=False, stream=stream)
+    with torch.cuda.stream(stream):
         y = torch.zeros(max(db.y_len, 1), dtype=torch.float32, device=dev)
-        ws_f = db.workspace(None)
+        ws_f = db.workspace(tune)
         ws_b = db.workspace(None, backward=True)
-        rsim.mix(db, alpha, y=y, ws=ws_f, stream=stream)
+        rsim.mix(db, alpha, y=y, ws=ws_f, tune=tune, stream=stream)
         w = torch.from_numpy(synth.loss_weights(3, max(db.y_len, 1))).to(dev)
         g = 2.0 * w * y
         for _ in range(2):
-            rsim.mix(db, alpha, y=y, ws=ws_f, stream=stream)
+            rsim.mix(db, alpha, y=y, ws=ws_f, tune=tune, stream=stream)
             rsim.mix_backward(db, alpha, g, ws=ws_b, stream=stream)
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
         ev[0].record(stream)
         for _ in range(reps):
-            rsim.mix(db, alpha, y=y, ws=ws_f, stream=stream)
+            rsim.mix(db, alpha, y=y, ws=ws_f, tune=tune, stream=stream)
         ev[1].record(stream)
         for _ in range(reps):
             rsim.mix_backward(db, alpha, g, ws=ws_b, stream=stream)
@@ -176,6 +182,7 @@ def differentiation(torch, rsim, synth, dev, reps: int = 10):
         byts += 4 * (2 * I * nx + J * int(T[u]) + 2 * int(L[u].sum())) + 8 * I * J
     achieved = flops / (t_b * 1e-3) / 1e12
     return {"workload": "64 utterances of 4 s, 3 sources, 4 mics, 8192-tap RIRs, no cut, N = 16384",
+            "forward_variant": entry["variant"],
             "forward_ms": round(t_f, 4), "backward_ms": round(t_b, 4),
             "audio_s_per_s": round(b.audio_seconds / ((t_f + t_b) * 1e-3), 1),
             "backward_roofline": {"bound": "alu", "achieved": round(achieved, 2), "peak": FP32_PEAK_TFLOPS,
