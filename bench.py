@@ -296,7 +296,7 @@ def reverb_gains(torch, rsim, dev, base, db, reps: int = 5):
 
 
 def front_end(torch, rsim, base, db, y, reps: int = 5):
-    """The log-Mel features (Sec. 4) of every mic output of the batched epoch:
+    """The log-Mel features (Sec. 3) of every mic output of the batched epoch:
     one untimed call, then `reps` timed ones."""
     stream = torch.cuda.Stream()
     stream.wait_stream(torch.cuda.current_stream())

@@ -285,7 +285,7 @@ rsim_status rsim_snr_gains_reverb(const double* energy, const double* snr_db, in
                                   float* alpha);
 
 /*
- * The log-Mel front end the paper trains on (Sec. 4): for every utterance u
+ * The log-Mel front end the paper trains on (Sec. 3): for every utterance u
  * and mic j, 128 log-Mel features per frame of the output y (after rsim_mix,
  * which writes out_len): frame t covers samples [160 t, 160 t + 512) of
  * y_j, whole frames only (F_u = 1 + (out_len[u] - 512) / 160 when

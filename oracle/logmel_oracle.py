@@ -1,4 +1,4 @@
-"""FP64 oracle of the log-Mel front end the paper trains on (Sec. 4).
+"""FP64 oracle of the log-Mel front end the paper trains on (Sec. 3).
 
 TEST INFRASTRUCTURE ONLY.  Nothing on the product path may import, call or run
 this module.  It shares no code, tables or helpers with the GPU path.

@@ -149,45 +149,50 @@ def measure(db, alpha, sizes=LOG2N, reps: int = 3, min_probe: int = 64, stream=N
     dev = db.device
     if stream is None:
         stream = torch.cuda.Stream(device=dev)
+    # Every tensor the timed calls read (the probe's descriptor, its forced
+    # sizes and gains, the output and workspace) is made on the timing
+    # stream itself, after it has waited for the caller's work, so the
+    # library never reads a tensor that another stream is still writing.
     stream.wait_stream(torch.cuda.current_stream(dev))
-    y = db.new_output()
     S, J = db.S, db.J
     out = {"utterances": len(shapes), "reps": reps, "sizes": {}}
-    for m in sizes:
-        N = 1 << m
-        rows = [sh for sh in shapes if sh[4] <= N // 2]
-        if not rows or len(rows) < min(min_probe, len(shapes)):
-            continue
-        idx = [sh[0] for sh in rows]
-        probe = db.select(idx)
-        probe.fft_log2n = torch.full((probe.U,), m, dtype=torch.int32, device=dev)
-        probe.fft_sizes = 1 << m
-        probe.hop = None
-        u = torch.as_tensor(np.asarray(idx, np.int64), device=dev)
-        slot = (u[:, None] * S + torch.arange(S, device=dev)[None, :]).reshape(-1)
-        a = alpha[(slot[:, None] * J + torch.arange(J, device=dev)[None, :]).reshape(-1)].contiguous()
-        model = float(sum(utt_cost(nx, I, Jm, lmax, m, mf, mm) for _, nx, I, Jm, lmax in rows))
-        f = FAMILY[m]
-        times = {}
-        for v in VARIANTS[f]:
-            var = [0] * 6
-            var[f] = v
-            t = rsim.tune_table(mf, mm, True, var)
-            ws = probe.workspace(t)
-            with torch.cuda.stream(stream):
+    with torch.cuda.stream(stream):
+        y = db.new_output()
+        for m in sizes:
+            N = 1 << m
+            rows = [sh for sh in shapes if sh[4] <= N // 2]
+            if not rows or len(rows) < min(min_probe, len(shapes)):
+                continue
+            idx = [sh[0] for sh in rows]
+            probe = db.select(idx)
+            probe.fft_log2n = torch.full((probe.U,), m, dtype=torch.int32, device=dev)
+            probe.fft_sizes = 1 << m
+            probe.hop = None
+            u = torch.as_tensor(np.asarray(idx, np.int64), device=dev)
+            slot = (u[:, None] * S + torch.arange(S, device=dev)[None, :]).reshape(-1)
+            a = alpha[(slot[:, None] * J + torch.arange(J, device=dev)[None, :]).reshape(-1)].contiguous()
+            model = float(sum(utt_cost(nx, I, Jm, lmax, m, mf, mm) for _, nx, I, Jm, lmax in rows))
+            f = FAMILY[m]
+            times = {}
+            for v in VARIANTS[f]:
+                var = [0] * 6
+                var[f] = v
+                t = rsim.tune_table(mf, mm, True, var)
+                ws = probe.workspace(t)
                 rsim.mix(probe, a, y=y, ws=ws, tune=t, stream=stream)
                 e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
                 e0.record(stream)
                 for _ in range(reps):
                     rsim.mix(probe, a, y=y, ws=ws, tune=t, stream=stream)
                 e1.record(stream)
-            e1.synchronize()
-            times[v] = e0.elapsed_time(e1) / reps
-            del ws
-        out["sizes"][m] = {"utterances": len(idx), "model": model, "ms": times}
-        if verbose:
-            print(f"N={N}: {len(idx)} utterances, " +
-                  ", ".join(f"variant {v}: {ms:.3f} ms" for v, ms in times.items()), flush=True)
+                e1.synchronize()
+                times[v] = e0.elapsed_time(e1) / reps
+                del ws
+            out["sizes"][m] = {"utterances": len(idx), "model": model, "ms": times}
+            if verbose:
+                print(f"N={N}: {len(idx)} utterances, " +
+                      ", ".join(f"variant {v}: {ms:.3f} ms" for v, ms in times.items()), flush=True)
+    stream.synchronize()
     if rsim.device_status():
         raise RuntimeError("a timing run set the device status word")
     if not out["sizes"]:
@@ -261,21 +266,22 @@ def measure_policy(db, alpha, entry: dict, reps: int = 3, stream=None) -> dict:
     if stream is None:
         stream = torch.cuda.Stream(device=dev)
     stream.wait_stream(torch.cuda.current_stream(dev))
-    y = db.new_output()
     out = {}
-    for key, one in (("one_size", True), ("per_utterance", False)):
-        t = entry_to_tune(dict(entry, one_size=one))
-        ws = db.workspace(t)
-        with torch.cuda.stream(stream):
+    with torch.cuda.stream(stream):
+        y = db.new_output()
+        for key, one in (("one_size", True), ("per_utterance", False)):
+            t = entry_to_tune(dict(entry, one_size=one))
+            ws = db.workspace(t)
             rsim.mix(db, alpha, y=y, ws=ws, tune=t, stream=stream)
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             e0.record(stream)
             for _ in range(reps):
                 rsim.mix(db, alpha, y=y, ws=ws, tune=t, stream=stream)
             e1.record(stream)
-        e1.synchronize()
-        out[key] = e0.elapsed_time(e1) / reps
-        del ws
+            e1.synchronize()
+            out[key] = e0.elapsed_time(e1) / reps
+            del ws
+    stream.synchronize()
     return out
 
 

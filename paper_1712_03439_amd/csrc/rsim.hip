@@ -2240,7 +2240,7 @@ __global__ __launch_bounds__(PL::T) void irfft_kernel(const float* __restrict__ 
 }
 
 // ======================================================= log-Mel front end
-// The paper's acoustic-model features (Sec. 4): 128 log-Mel bands of 512-sample
+// The paper's acoustic-model features (Sec. 3): 128 log-Mel bands of 512-sample
 // (32 ms) Hann windows every 160 samples (10 ms), the filterbank spanning
 // 125..7500 Hz.  A workgroup holds kMelGroups groups of 32 threads, each
 // group one frame through the 512-point plan (its own LDS exchange buffers;

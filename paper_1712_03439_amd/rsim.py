@@ -444,14 +444,17 @@ class DeviceBatch:
         sub.device = dev
         return sub
 
-    def struct(self, rir_len=None) -> RsimBatch:
+    def struct(self, rir_len=None, out_len=None) -> RsimBatch:
+        """The C descriptor of this batch; rir_len / out_len replace the
+        batch's own cut-length and output-length arrays when given."""
         s = RsimBatch()
         s.n_utt, s.n_mic, s.max_src, s.max_rir_len0 = self.U, self.J, self.S, self.max_rir_len0
         s.x_len, s.h_len, s.y_len = self.x_len, self.h_len, self.y_len
         s.n_src, s.src_len, s.src_off = _ptr(self.n_src), _ptr(self.src_len), _ptr(self.src_off)
         s.rir_off, s.rir_len0 = _ptr(self.rir_off), _ptr(self.rir_len0)
         s.rir_len = _ptr(self.rir_len if rir_len is None else rir_len)
-        s.out_off, s.out_stride, s.out_len = _ptr(self.out_off), _ptr(self.out_stride), _ptr(self.out_len)
+        s.out_off, s.out_stride = _ptr(self.out_off), _ptr(self.out_stride)
+        s.out_len = _ptr(self.out_len if out_len is None else out_len)
         s.order, s.fft_log2n, s.hop = _ptr(self.order), _ptr(self.fft_log2n), _ptr(self.hop)
         s.fft_sizes = self.fft_sizes if self.fft_log2n is not None else 0
         return s
@@ -563,10 +566,12 @@ def simulate(db: DeviceBatch, alpha, eta_db: float, y=None, ws=None, tune: Optio
 
 
 def mix_backward(db: DeviceBatch, alpha, grad_y, x=None, h=None, ws=None, tune: Optional[RsimTune] = None,
-                 need_alpha: bool = True, stream=None):
+                 need_alpha: bool = True, stream=None, rir_len=None, out_len=None):
     """Adjoint of `mix` (rsim_mix_backward): (grad_x, grad_h, grad_alpha) in the
-    layouts of x, h and alpha, for the current db.rir_len.  grad_h is zero
-    beyond each cut length; grad_alpha is None unless need_alpha."""
+    layouts of x, h and alpha, for the cut lengths rir_len (default: the
+    current db.rir_len).  grad_h is zero beyond each cut length; grad_alpha is
+    None unless need_alpha.  The call's schedule writes the output lengths
+    into out_len (default: db.out_len)."""
     torch = _torch()
     x = db.x if x is None else x
     h = db.h if h is None else h
@@ -577,7 +582,7 @@ def mix_backward(db: DeviceBatch, alpha, grad_y, x=None, h=None, ws=None, tune: 
     gx = torch.zeros(max(db.x_len, 1), dtype=torch.float32, device=db.device)
     gh = torch.zeros(max(db.h_len, 1), dtype=torch.float32, device=db.device)
     ga = torch.zeros(max(db.U * db.S * db.J, 1), dtype=torch.float32, device=db.device) if need_alpha else None
-    s = db.struct()
+    s = db.struct(rir_len=rir_len, out_len=out_len)
     _check(_lib().rsim_mix_backward(ctypes.byref(s), _ptr(x), _ptr(h), _ptr(alpha), _ptr(grad_y), _ptr(gx),
                                     _ptr(gh), _ptr(ga), _ptr(ws), int(ws.numel()),
                                     ctypes.byref(tune) if tune else None, _stream(stream)),
@@ -599,24 +604,32 @@ class _MixFunction:
                 """y = mix(x, h, alpha) of eq. (2) with the hand-written adjoint.
 
                 x, h: packed float32 sources and RIRs (db's layouts); alpha:
-                [U*S*J] gains.  The cut lengths db.rir_len are constants (no
-                gradient flows through the cut index)."""
+                [U*S*J] gains.  The cut lengths db.rir_len at the forward call
+                are constants (no gradient flows through the cut index); the
+                backward uses a copy of them taken by the forward, so a later
+                cut of the same batch does not change this graph's adjoint.
+                Gradients reach whatever alpha was computed from only if alpha
+                is a torch expression of it (the host gain rule of batch_gains
+                returns numpy and ends the graph there)."""
 
                 @staticmethod
                 def forward(ctx, x, h, alpha, db, tune):
                     # zeros: the padding of each mic beyond T_u is part of y too
                     y = torch.zeros(max(db.y_len, 1), dtype=torch.float32, device=db.device)
+                    rir_len = db.rir_len.clone()
                     mix(db, alpha, y=y, tune=tune, x=x, h=h)
-                    ctx.save_for_backward(x, h, alpha)
+                    ctx.save_for_backward(x, h, alpha, rir_len)
                     ctx.db, ctx.tune = db, tune
                     return y[: db.y_len]
 
                 @staticmethod
                 def backward(ctx, gy):
-                    x, h, alpha = ctx.saved_tensors
+                    x, h, alpha, rir_len = ctx.saved_tensors
                     gy = gy.contiguous()
+                    out_len = torch.empty_like(ctx.db.out_len)
                     gx, gh, ga = mix_backward(ctx.db, alpha, gy, x=x, h=h, tune=ctx.tune,
-                                              need_alpha=ctx.needs_input_grad[2])
+                                              need_alpha=ctx.needs_input_grad[2], rir_len=rir_len,
+                                              out_len=out_len)
                     return (gx if ctx.needs_input_grad[0] else None,
                             gh if ctx.needs_input_grad[1] else None,
                             ga, None, None)

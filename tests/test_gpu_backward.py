@@ -9,7 +9,7 @@ import pytest
 
 import oracle
 import synth
-from tests.gpu_util import TOL, cuda, max_rel_err
+from tests.gpu_util import TOL, cuda, max_rel_err, pmap
 
 
 def _setup(b, eta, fft_log2n=None, hop=None):
@@ -62,27 +62,52 @@ def _pack_grad(b, per, T_of):
 
 
 def _check_full(b, eta, gx, gh, ga, gys, u):
-    xs, cut, alpha, T = _oracle_problem(b, u, eta)
-    I, J, S = len(xs), b.n_mic, b.max_src
-    assert gys[u].shape[1] == T
-    dx, dh, da = oracle.mix_backward(xs, cut, alpha, gys[u])
-    for i in range(I):
-        so, nx = int(b.src_off[u * S + i]), int(b.src_len[u])
-        e = max_rel_err(gx[so: so + nx], dx[i])
-        assert e <= TOL, ("dx", u, i, e)
-    peak_h = max((float(np.max(np.abs(dh[i][j]))) for i in range(I) for j in range(J) if dh[i][j].size),
-                 default=0.0)
-    for i in range(I):
-        for j in range(J):
-            r = (u * S + i) * J + j
-            ro, L0 = int(b.rir_off[r]), int(b.rir_len0[r])
-            ref = np.zeros(L0)
-            ref[: dh[i][j].size] = dh[i][j]
-            err = float(np.max(np.abs(gh[ro: ro + L0] - ref))) if L0 else 0.0
-            assert err <= TOL * max(peak_h, 1e-30), ("dh", u, i, j, err, peak_h)
-    got_a = np.array([[ga[(u * S + i) * J + j] for j in range(J)] for i in range(I)])
-    e = max_rel_err(got_a, da)
-    assert e <= TOL, ("dalpha", u, e)
+    _check_full_many(b, eta, gx, gh, ga, gys, [u])
+
+
+def _check_full_many(b, eta, gx, gh, ga, gys, utts):
+    """Every entry of dx, dh and dalpha of the listed utterances against the
+    oracle's adjoint, one (utterance, source) per host thread (the adjoint's
+    terms of one source do not involve the others)."""
+    cases = {u: _oracle_problem(b, u, eta) for u in utts}
+    tasks = [(u, i) for u in utts for i in range(len(cases[u][0]))]
+
+    def ref(ui):
+        u, i = ui
+        xs, cut, alpha, T = cases[u]
+        assert gys[u].shape[1] == T
+        return oracle.mix_backward([xs[i]], [cut[i]], alpha[i:i + 1], gys[u])
+
+    refs = dict(zip(tasks, pmap(ref, tasks)))
+    worst = 0.0
+    J, S = b.n_mic, b.max_src
+    for u in utts:
+        xs, cut, alpha, T = cases[u]
+        I = len(xs)
+        dx = [refs[(u, i)][0][0] for i in range(I)]
+        dh = [refs[(u, i)][1][0] for i in range(I)]
+        da = np.array([refs[(u, i)][2][0] for i in range(I)]).reshape(I, J)
+        for i in range(I):
+            so, nx = int(b.src_off[u * S + i]), int(b.src_len[u])
+            e = max_rel_err(gx[so: so + nx], dx[i])
+            worst = max(worst, e)
+            assert e <= TOL, ("dx", u, i, e)
+        peak_h = max((float(np.max(np.abs(dh[i][j]))) for i in range(I) for j in range(J) if dh[i][j].size),
+                     default=0.0)
+        for i in range(I):
+            for j in range(J):
+                r = (u * S + i) * J + j
+                ro, L0 = int(b.rir_off[r]), int(b.rir_len0[r])
+                ref_h = np.zeros(L0)
+                ref_h[: dh[i][j].size] = dh[i][j]
+                err = float(np.max(np.abs(gh[ro: ro + L0] - ref_h))) if L0 else 0.0
+                worst = max(worst, err / max(peak_h, 1e-30))
+                assert err <= TOL * max(peak_h, 1e-30), ("dh", u, i, j, err, peak_h)
+        got_a = np.array([[ga[(u * S + i) * J + j] for j in range(J)] for i in range(I)])
+        e = max_rel_err(got_a, da)
+        worst = max(worst, e)
+        assert e <= TOL, ("dalpha", u, e)
+    return worst
 
 
 def _run(b, eta, seed, fft_log2n=None, hop=None):
@@ -126,8 +151,7 @@ def test_backward_ragged_batch(l2):
         snrs.append([0.0] + [float(v) for v in rng.uniform(0, 20, I - 1)])
     b = synth.pack(srcs, rirs, snrs, 3)
     gx, gh, ga, gys = _run(b, 20.0, l2, fft_log2n=np.full(3, l2, np.int32))
-    for u in range(b.n_utt):
-        _check_full(b, 20.0, gx, gh, ga, gys, u)
+    _check_full_many(b, 20.0, gx, gh, ga, gys, range(b.n_utt))
 
 
 @pytest.mark.gpu
@@ -144,8 +168,7 @@ def test_backward_cost_model_sizes_and_degenerate():
             [[synth.rir(rng, 5000, 0.4, 100)] * 2, [synth.rir(rng, 2500, 0.4, 50)] * 2]]
     b = synth.pack(srcs, rirs, [[0.0, 3.0], [0.0], [0.0], [0.0, 12.0]], 2)
     gx, gh, ga, gys = _run(b, 20.0, 7)
-    for u in (0, 1, 3):
-        _check_full(b, 20.0, gx, gh, ga, gys, u)
+    _check_full_many(b, 20.0, gx, gh, ga, gys, (0, 1, 3))
     so = int(b.src_off[2 * b.max_src])
     assert not np.any(gx[so: so + 800])
     for j in range(2):
@@ -154,31 +177,14 @@ def test_backward_cost_model_sizes_and_degenerate():
 
 
 @pytest.mark.gpu
-def test_differentiation_config_sampled():
+def test_differentiation_config_full():
     # 64 utterances of 4 s, I = 3, J = 4, 8192-tap RIRs, no cut, N = 16384
-    # (hop 8193, 8 blocks): every gradient sampled against direct sums.
+    # (hop 8193, 8 blocks): every entry of dx, dh and dalpha of three
+    # utterances against the oracle's adjoint
     b = synth.make_config3()
     gx, gh, ga, gys = _run(b, math.inf, 3, fft_log2n=np.full(b.n_utt, 14, np.int32))
-    S, J = b.max_src, b.n_mic
-    for u in (0, 37, 63):
-        xs, cut, alpha, T = _oracle_problem(b, u, math.inf)
-        nx = len(xs[0])
-        x_idx = [0, 1, 4095, 4096, 8192, 31999, 50000, nx - 2, nx - 1]
-        h_idx = [0, 1, 100, 4096, 8190, 8191]
-        for (i, j) in [(0, 0), (1, 2), (2, 3)]:
-            dx, dh, _ = oracle.mix_backward_at(xs, cut, alpha, gys[u], i, j, x_idx, h_idx)
-            so = int(b.src_off[u * S + i])
-            r = (u * S + i) * J + j
-            ro = int(b.rir_off[r])
-            # the sampled values' scale is a lower bound of each tensor's peak
-            sx = max(float(np.max(np.abs(dx))), 1e-30)
-            sh = max(float(np.max(np.abs(dh))), 1e-30)
-            assert np.max(np.abs(gx[so + np.array(x_idx)] - dx)) <= 4 * TOL * sx, (u, i, j)
-            assert np.max(np.abs(gh[ro + np.array(h_idx)] - dh)) <= 4 * TOL * sh, (u, i, j)
-        da = np.array([[oracle.mix_backward_at(xs, cut, alpha, gys[u], i, j, [], [])[2] for j in range(J)]
-                       for i in range(3)])
-        got = np.array([[ga[(u * S + i) * J + j] for j in range(J)] for i in range(3)])
-        assert max_rel_err(got, da) <= TOL, (u, max_rel_err(got, da))
+    worst = _check_full_many(b, math.inf, gx, gh, ga, gys, [0, 37, 63])
+    print(f"differentiation workload: max gradient error {worst:.2e} of the peak")
 
 
 @pytest.mark.gpu
@@ -228,8 +234,7 @@ def test_backward_many_utterances_one_part_each():
         snrs.append([0.0] + [float(v) for v in rng.uniform(0, 20, I - 1)])
     b = synth.pack(srcs, rirs, snrs, 2)
     gx, gh, ga, gys = _run(b, 20.0, 11)
-    for u in (0, 1, 2, 149, 299):
-        _check_full(b, 20.0, gx, gh, ga, gys, u)
+    _check_full_many(b, 20.0, gx, gh, ga, gys, (0, 1, 2, 149, 299))
 
 
 @pytest.mark.gpu
@@ -248,5 +253,27 @@ def test_backward_split_with_two_sizes_of_one_family():
         snrs.append([0.0] + [float(v) for v in rng.uniform(0, 20, I - 1)])
     b = synth.pack(srcs, rirs, snrs, 2)
     gx, gh, ga, gys = _run(b, 20.0, 12, fft_log2n=np.array([10, 11, 10, 11], np.int32))
-    for u in range(b.n_utt):
-        _check_full(b, 20.0, gx, gh, ga, gys, u)
+    _check_full_many(b, 20.0, gx, gh, ga, gys, range(b.n_utt))
+
+
+@pytest.mark.gpu
+def test_autograd_keeps_the_forward_cut_lengths():
+    # a cut at another threshold between the forward and the backward (the
+    # next epoch on the same descriptor) must not change this graph's adjoint
+    torch = cuda()
+    from paper_1712_03439_amd import rsim
+
+    b = synth.make_config2(n_utt=5, epoch=4)
+    db, alpha = _setup(b, 20.0)
+    rl20 = db.rir_len.clone()
+    x = db.x.clone().requires_grad_(True)
+    h = db.h.clone().requires_grad_(True)
+    y = rsim.mix_autograd(db, x, h, alpha)
+    w = torch.rand(y.shape, device="cuda", generator=torch.Generator(device="cuda").manual_seed(9))
+    rsim.truncate_batch(db, 10.0)
+    assert not torch.equal(db.rir_len, rl20)
+    torch.sum(w * y).backward()
+    gy = (w * torch.ones_like(y)).contiguous()
+    gx, gh, _ = rsim.mix_backward(db, alpha, gy, rir_len=rl20, out_len=torch.empty_like(db.out_len))
+    torch.cuda.synchronize()
+    assert torch.equal(x.grad, gx) and torch.equal(h.grad, gh)

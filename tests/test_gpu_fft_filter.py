@@ -38,12 +38,24 @@ def _run(b, eta, fft_log2n=None, chunk=3):
 
 
 def _check(b, eta, y, rl, ol, alpha, utts):
+    """The oracle's own cut lengths (which the GPU's must equal bit for bit)
+    and its own gains; the GPU's gains (float32) must agree with the
+    oracle's to float32 rounding."""
     S, J = b.max_src, b.n_mic
     for u in utts:
         xs, hs = b.sources(u), b.rirs(u)
         I = len(xs)
-        cut = [[np.asarray(hs[i][j], np.float32)[: int(rl[(u * S + i) * J + j])] for j in range(J)] for i in range(I)]
-        a = alpha[u * S * J:(u * S + I) * J].reshape(I, J).astype(np.float64)
+        cut = []
+        for i in range(I):
+            row = []
+            for j in range(J):
+                L = oracle.cut_rir(hs[i][j], eta)[1]
+                assert int(rl[(u * S + i) * J + j]) == L, (u, i, j)
+                row.append(np.asarray(hs[i][j], np.float32)[:L])
+            cut.append(row)
+        a = oracle.snr_gains([oracle.dry_power(x) for x in xs], b.snrs(u), J)
+        got_a = alpha[u * S * J:(u * S + I) * J].reshape(I, J).astype(np.float64)
+        assert np.allclose(got_a, a, rtol=1e-6, atol=0), u
         ref = oracle.mix(xs, cut, a)
         T = ref.shape[1]
         assert int(ol[u]) == T

@@ -1,12 +1,13 @@
 """Reverberant-at-mic gains on the GPU (rsim_reverb_energy) against the FP64
 oracle.
 
-Bar, derived from the arithmetic: the energy is sum_l r_hh[l] r_xx[l] with
-r_xx accumulated by float32 transforms over the source's blocks, so its error
-is bounded by a small multiple of float32 rounding times
-sum_l |r_hh[l]| * r_xx[0]; the test allows 1e-5 of that scale (about a
-hundred float32 roundings).  The gains then agree to 1e-4 relative and give
-the requested SNR to 1e-3 dB."""
+Bar: |E_gpu - E_ref| <= 1e-5 E_ref for every (source, mic) slot, the bar of
+the mix's outputs applied to the energy itself.  The energy is
+sum_l r_hh[l] r_xx[l] with r_xx accumulated by float32 transforms, so the
+error scales with float32 rounding times sum_l |r_hh[l]| r_xx[0], a few tens
+of times E for noise-like RIRs; measured on the batched workload it stays
+below 6e-7 E (20 times inside the bar).  The gains then agree to 1e-5
+relative and give the requested SNR to 1e-4 dB."""
 import math
 
 import numpy as np
@@ -43,8 +44,7 @@ def _check_energies(b, eta, e, rl):
                 h = np.asarray(hs[i][j], np.float64)[:L]
                 x = np.asarray(xs[i], np.float64)
                 ref = oracle.reverb_energy(x, h)
-                scale = (np.sum(np.abs(np.correlate(h, h, "full"))) * float(np.dot(x, x))) if L else 0.0
-                assert abs(e[r] - ref) <= 1e-5 * scale + 1e-30, (u, i, j, e[r], ref, scale)
+                assert abs(e[r] - ref) <= TOL * ref + 1e-30, (u, i, j, e[r], ref)
 
 
 @pytest.mark.gpu
@@ -92,11 +92,11 @@ def test_gains_give_the_requested_snr_and_drive_the_mix():
         E = np.array([[oracle.reverb_energy(xs[i], cut[i][j]) for j in range(J)] for i in range(I)])
         ref_a = oracle.snr_gains_reverb(E, b.snrs(u))
         got_a = alpha[u * S * J:(u * S + I) * J].reshape(I, J).astype(np.float64)
-        assert np.allclose(got_a, ref_a, rtol=1e-4, atol=0), u
+        assert np.allclose(got_a, ref_a, rtol=1e-5, atol=0), u
         for i in range(1, I):
             for j in range(J):
                 snr = 10 * math.log10(E[0, j] / (got_a[i, j] ** 2 * E[i, j]))
-                assert abs(snr - b.snrs(u)[i]) <= 1e-3, (u, i, j)
+                assert abs(snr - b.snrs(u)[i]) <= 1e-4, (u, i, j)
         # the mix with these gains (the oracle mixes with the same float32 gains)
         ref = oracle.mix(xs, cut, got_a)
         off, st = int(b.out_off[u]), int(b.out_stride[u])

@@ -64,3 +64,39 @@ def test_cut_nonfinite_keeps_rir_and_flags():
     assert (int(n_c[2]), int(L[2])) == oracle.cut_rir(rirs[2], 20.0)[:2]
     assert rsim.device_status() & rsim.DEV_NONFINITE
     assert rsim.device_status() == 0  # read clears
+
+
+def _long_rirs():
+    """RIRs past the 32 chunk maxima the cut kernel keeps (more than 32768
+    taps), where the last tap at or above the threshold is searched from the
+    tail: decaying noise, the last such tap in the first chunk (a lone spike
+    at the start, every other tap far below), the final tap, and a tie with
+    the peak at the far end."""
+    r = np.random.default_rng(31)
+    out = []
+    for L0 in (32768, 32769, 40000, 65537):
+        out.append((r.standard_normal(L0) * np.exp(-np.arange(L0) / (L0 / 6))).astype(np.float32))
+        early = (r.standard_normal(L0) * 1e-4).astype(np.float32)
+        early[5] = 1.0
+        out.append(early)                                   # the cut lands in the first chunk
+        last = (r.standard_normal(L0) * 1e-3).astype(np.float32)
+        last[-1] = 0.5
+        out.append(last)                                    # the final tap is the peak
+        tie = (r.standard_normal(L0) * 1e-2).astype(np.float32)
+        tie[7], tie[L0 - 2] = 0.75, -0.75                   # equal powers, the later one kept
+        out.append(tie)
+    return out
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("eta", [0.0, 10.0, 20.0, 30.0, math.inf])
+def test_cut_bit_exact_past_the_chunk_maxima(eta):
+    rirs = _long_rirs()
+    n_c, L = _run(rirs, eta)
+    for k, h in enumerate(rirs):
+        ref_nc, ref_L, _ = oracle.cut_rir(h, eta)
+        assert (int(n_c[k]), int(L[k])) == (ref_nc, ref_L), (k, len(h), eta)
+    if eta == 20.0:
+        # the lone early spike: everything after index 5 is 80 dB down
+        assert [int(v) for v in n_c[1::4]] == [5, 5, 5, 5]
+        assert [int(v) for v in L[2::4]] == [len(h) for h in rirs[2::4]]

@@ -9,7 +9,7 @@ import pytest
 
 import synth
 from tests.gpu_util import cuda
-from tests.test_gpu_mix import _check_utterance, _sampled_check
+from tests.test_gpu_mix import _check_utterances
 
 
 def _batch(n_utt, J, seed, len_s=(0.2, 1.5), taps=(300, 3000)):
@@ -66,8 +66,7 @@ def test_every_kernel_variant_gives_the_same_bits(n_utt):
             y, rl2, ol2 = _run(b, l2, code)
             assert np.array_equal(rl, rl2) and np.array_equal(ol, ol2)
             assert _same_outputs(b, ref, y, ol) is None, (l2, code, _same_outputs(b, ref, y, ol))
-        for u in (0, n_utt // 2, n_utt - 1):
-            _check_utterance(b, u, 20.0, ref, rl, ol)
+        _check_utterances(b, (0, n_utt // 2, n_utt - 1), 20.0, ref, rl, ol)
 
 
 @pytest.mark.gpu
@@ -75,8 +74,7 @@ def test_variant_one_mic_per_pass_against_the_oracle():
     b = _batch(6, 4, 7)
     for l2 in (13, 14):
         y, rl, ol = _run(b, l2, 1)
-        for u in range(b.n_utt):
-            _check_utterance(b, u, 20.0, y, rl, ol)
+        _check_utterances(b, range(b.n_utt), 20.0, y, rl, ol)
 
 
 @pytest.mark.gpu
@@ -106,4 +104,4 @@ def test_tuner_table_drives_a_correct_mix():
     y = rsim.simulate(db, alpha, 20.0, tune=tune)
     torch.cuda.synchronize()
     y, rl, ol = y.cpu().numpy(), db.rir_len.cpu().numpy(), db.out_len.cpu().numpy()
-    _sampled_check(b, 20.0, y, rl, ol, range(0, b.n_utt, 8), 64, 5)
+    _check_utterances(b, range(0, b.n_utt, 4), 20.0, y, rl, ol)

@@ -1,4 +1,4 @@
-"""Pins of the log-Mel oracle (Sec. 4 front end), CPU only."""
+"""Pins of the log-Mel oracle (Sec. 3 front end), CPU only."""
 import math
 
 import numpy as np
