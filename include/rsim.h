@@ -184,6 +184,28 @@ rsim_status rsim_simulate(const rsim_batch* b, const float* x, const float* h,
                           int32_t use_graph, hipStream_t stream);
 
 /*
+ * For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): rsim_simulate with
+ * use_graph = 0 and no workspace argument.  The workspace is a scratch array
+ * of RSIM_STATIC_SCRATCH_BYTES that the library holds on each device it runs
+ * on (from the library's load on that device until the process ends); the
+ * call itself allocates nothing (no hipMalloc, no hipFree, no graph).  When
+ * the persistent kernels' per-workgroup slots of a large batch do not all
+ * fit, fewer workgroups run (same results, less parallelism); a batch whose
+ * schedule arrays plus one slot per FFT-size family exceed the array is
+ * rejected with RSIM_EWORKSPACE before anything is launched.  Every call on
+ * a device shares that device's array and leaves its contents behind (the
+ * schedule clears the work counters at the start of each call): calls that
+ * overlap on one device race and give undefined results, so a caller
+ * serialises them (one stream, or events).  Results are bit-identical to
+ * rsim_simulate's for the same batch, eta and tune.
+ */
+#define RSIM_STATIC_SCRATCH_BYTES ((size_t)128 << 20)
+rsim_status rsim_simulate_static(const rsim_batch* b, const float* x, const float* h,
+                                 const float* alpha, double eta_db, int32_t* rir_len_out, float* y,
+                                 const rsim_tune* tune, hipStream_t stream);
+
+/*
  * Adjoint of rsim_mix (eq. (2)).  grad_y has the layout of y (only n < T_u is
  * read).  Writes
  *   grad_x[i][n]  = sum_j alpha_ij sum_{k<L_ij} h_ij[k] g_j[n+k]        (n < Nx)

@@ -2437,6 +2437,13 @@ __global__ void ola_setup_kernel(OlaDesc* d, int nx, int nh, int l2, int hop) {
 
 using namespace rsim;
 
+// Scratch of rsim_simulate_static, for callers that cannot allocate: one copy
+// per device, held from the library's load on that device until the process
+// ends.  Host code never passes this name to a kernel (on the host it is a
+// stand-in, not a device address); init looks up each device's address with
+// hipGetSymbolAddress and the calls use that.
+static __device__ __align__(256) unsigned char scratch[RSIM_STATIC_SCRATCH_BYTES];
+
 namespace {
 
 constexpr int kFamT[kNumFam] = {32, 64, 128, 256, 512, 1024};
@@ -2462,6 +2469,8 @@ struct DevState {
   hipStream_t side[kSide] = {};
   hipEvent_t fork = nullptr;
   hipEvent_t join[kSide] = {};
+  // This device's copy of `scratch` (rsim_simulate_static's workspace).
+  void* static_ws = nullptr;
 };
 
 std::mutex g_mu;
@@ -2613,6 +2622,11 @@ rsim_status init_locked(int dev) {
         return RSIM_EDEVICE;
     }
   }
+  if (!st.static_ws) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return RSIM_EDEVICE;
+    st.static_ws = p;
+  }
   if (hipDeviceSynchronize() != hipSuccess) return RSIM_EDEVICE;
   st.init = true;
   return RSIM_OK;
@@ -2711,7 +2725,12 @@ bool batch_ok(const rsim_batch* b) {
          b->out_off && b->out_stride && b->out_len;
 }
 
-WsLayout layout(const rsim_batch* b, const TuneDev& td, bool backward, const DevState& st) {
+// Workspace layout of a call.  cap > 0 (forward only) bounds the total: when
+// the persistent grids' scratch slots do not fit, every used family's grid is
+// shrunk in proportion (at least one workgroup each; the kernels pop work
+// items until their list is empty, so any grid size is correct).  The result
+// then has total > cap only when even that does not fit.
+WsLayout layout(const rsim_batch* b, const TuneDev& td, bool backward, const DevState& st, size_t cap = 0) {
   WsLayout L;
   const size_t U = (size_t)b->n_utt;
   L.hdr = 0;
@@ -2747,8 +2766,29 @@ WsLayout layout(const rsim_batch* b, const TuneDev& td, bool backward, const Dev
     if (g > (long long)items) g = (long long)items;
     if (g < 1) g = 1;
     L.grid[f] = (int)g;
+  }
+  if (cap > 0 && !backward) {
+    size_t want = 0;
+    for (int f = 0; f < kNumFam; ++f)
+      if (used[f]) want += align256((size_t)L.grid[f] * (size_t)L.slot_cf[f] * sizeof(cf));
+    if (off + want > cap) {
+      const size_t room = cap > off ? cap - off : 0;
+      for (int f = 0; f < kNumFam; ++f) {
+        if (!used[f]) continue;
+        const size_t per = (size_t)L.slot_cf[f] * sizeof(cf);
+        const size_t mine = align256((size_t)L.grid[f] * per);
+        // the family's share of the room, less the alignment padding, so
+        // that the shares' aligned sizes add up to at most the room
+        size_t share = (size_t)((long double)room * (long double)mine / (long double)want);
+        share = share > 256 ? share - 256 : 0;
+        const long long g = per ? (long long)(share / per) : L.grid[f];
+        L.grid[f] = (int)std::max(1LL, std::min<long long>(g, L.grid[f]));
+      }
+    }
+  }
+  for (int f = 0; f < kNumFam; ++f) {
     L.fam_scratch[f] = off;
-    if (used[f]) off += align256((size_t)g * (size_t)L.slot_cf[f] * sizeof(cf));
+    if (used[f]) off += align256((size_t)L.grid[f] * (size_t)L.slot_cf[f] * sizeof(cf));
   }
   for (int f = 0; f < kNumFam; ++f) {
     L.fam_partial[f] = off;
@@ -2984,9 +3024,9 @@ rsim_status issue(CallPlan& P, hipStream_t s, int use_graph) {
 
 // Records the schedule and family kernels of a mix into P.
 void plan_mix(CallPlan& P, const rsim_batch* b, const BatchDev& bd, const TuneDev& td, const float* x,
-              const float* h, const float* alpha, float* y, void* ws, int only_fam = -1) {
+              const float* h, const float* alpha, float* y, void* ws, int only_fam = -1, size_t cap = 0) {
   const DevState& st = dev_state();
-  const WsLayout L = layout(b, td, false, st);
+  const WsLayout L = layout(b, td, false, st, cap);
   char* base = static_cast<char*>(ws);
   SchedArgs SA;
   SA.b = bd;
@@ -3184,7 +3224,8 @@ const char* rsim_strerror(rsim_status s) {
   switch (s) {
     case RSIM_OK: return "ok";
     case RSIM_EINVAL: return "invalid argument";
-    case RSIM_EWORKSPACE: return "workspace missing or too small";
+    case RSIM_EWORKSPACE:
+      return "workspace missing or too small (rsim_simulate_static: the batch does not fit the static scratch)";
     case RSIM_EUNSUPPORTED: return "unsupported FFT size or hop";
     case RSIM_EDEVICE: return "HIP runtime error";
     case RSIM_ENOTINIT: return "library not initialised on this device (call rsim_init outside capture)";
@@ -3255,6 +3296,32 @@ rsim_status rsim_simulate(const rsim_batch* b, const float* x, const float* h, c
   plan_truncate(P.cut, h, bb.h_len, bb.rir_off, bb.rir_len0, (int)n_rir, s, nullptr, rir_len_out);
   plan_mix(P, &bb, bd, td, x, h, alpha, y, ws);
   return issue(P, stream, use_graph);
+}
+
+rsim_status rsim_simulate_static(const rsim_batch* b, const float* x, const float* h, const float* alpha,
+                                 double eta_db, int32_t* rir_len_out, float* y, const rsim_tune* tune,
+                                 hipStream_t stream) {
+  if (!b || !eta_ok(eta_db) || !rir_len_out || !tune_ok(tune)) return RSIM_EINVAL;
+  rsim_batch bb = *b;
+  bb.rir_len = rir_len_out;
+  if (!batch_ok(&bb)) return RSIM_EINVAL;
+  if (bb.n_utt == 0) return RSIM_OK;
+  if (!x || !h || !alpha || !y) return RSIM_EINVAL;
+  const long long n_rir = (long long)bb.n_utt * bb.max_src * bb.n_mic;
+  if (n_rir > 0x7fffffffLL) return RSIM_EINVAL;
+  const rsim_status e = ensure_init(stream);
+  if (e != RSIM_OK) return e;
+  const DevState& st = dev_state();
+  if (!st.static_ws) return RSIM_EDEVICE;
+  const TuneDev td = to_dev(tune);
+  const size_t cap = RSIM_STATIC_SCRATCH_BYTES;
+  if (layout(&bb, td, false, st, cap).total > cap) return RSIM_EWORKSPACE;
+  const BatchDev bd = to_dev(&bb);
+  CallPlan P;
+  P.has_cut = true;
+  plan_truncate(P.cut, h, bb.h_len, bb.rir_off, bb.rir_len0, (int)n_rir, cut_scale(eta_db), nullptr, rir_len_out);
+  plan_mix(P, &bb, bd, td, x, h, alpha, y, st.static_ws, -1, cap);
+  return issue(P, stream, 0);
 }
 
 size_t rsim_ola_workspace_bytes(int32_t fft_n) {

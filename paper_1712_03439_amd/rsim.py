@@ -27,7 +27,7 @@ EXPORTS = (
     "rsim_simulate", "rsim_mix_backward", "rsim_source_power", "rsim_snr_gains",
     "rsim_device_status", "rsim_rfft", "rsim_irfft", "rsim_image_rir", "rsim_simulate_rooms",
     "rsim_reverb_energy", "rsim_snr_gains_reverb", "rsim_logmel", "rsim_fft_filter_workspace_bytes",
-    "rsim_fft_filter",
+    "rsim_fft_filter", "rsim_simulate_static",
 )
 
 
@@ -92,6 +92,7 @@ def _lib():
             "rsim_logmel": ([bp, vp, vp, vp, i64, i32, vp], i32),
             "rsim_fft_filter_workspace_bytes": ([bp, i32, i32], sz),
             "rsim_fft_filter": ([bp, vp, vp, vp, vp, i32, i32, vp, sz, vp], i32),
+            "rsim_simulate_static": ([bp, vp, vp, vp, f64, vp, vp, tp, vp], i32),
         }
         for name, (args, res) in sig.items():
             fn = getattr(lib, name)
@@ -562,6 +563,22 @@ def simulate(db: DeviceBatch, alpha, eta_db: float, y=None, ws=None, tune: Optio
                                 _ptr(db.rir_len), _ptr(y), _ptr(ws), int(ws.numel()),
                                 ctypes.byref(tune) if tune else None, int(bool(use_graph)),
                                 _stream(stream)), "rsim_simulate")
+    return y
+
+
+STATIC_SCRATCH_BYTES = 128 << 20  # RSIM_STATIC_SCRATCH_BYTES
+
+
+def simulate_static(db: DeviceBatch, alpha, eta_db: float, y, tune: Optional[RsimTune] = None, stream=None):
+    """Cut + mix of one epoch without any allocation by the library or here
+    (rsim_simulate_static): y (and db's arrays) are the caller's, the
+    workspace is the library's static scratch on this device.  Calls on one
+    device must not overlap."""
+    _require_cuda(alpha, y)
+    s = db.struct()
+    _check(_lib().rsim_simulate_static(ctypes.byref(s), _ptr(db.x), _ptr(db.h), _ptr(alpha), float(eta_db),
+                                       _ptr(db.rir_len), _ptr(y), ctypes.byref(tune) if tune else None,
+                                       _stream(stream)), "rsim_simulate_static")
     return y
 
 

@@ -1,0 +1,105 @@
+"""rsim_simulate_static (the entry point for callers that cannot allocate: its
+workspace is the library's static scratch) against rsim_simulate on the same
+batches.  Both compute every output sample with the same operations, so the
+outputs, cut lengths and output lengths must be bit-identical; two
+utterances of each batch are also checked against the FP64 oracle (bar:
+1e-5 of the peak per utterance and mic)."""
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from tests.gpu_util import cuda
+from tests.test_gpu_mix import _check_utterances, _large_subset
+
+
+def _reference(b, eta, tune=None, fft_log2n=None):
+    torch = cuda()
+    from paper_1712_03439_amd import rsim
+
+    db = rsim.DeviceBatch(b, fft_log2n=fft_log2n)
+    alpha = torch.from_numpy(rsim.batch_gains(db, b.snr_db)).cuda()
+    y = rsim.simulate(db, alpha, eta, tune=tune)
+    torch.cuda.synchronize()
+    return db, alpha, y.cpu().numpy(), db.rir_len.cpu().numpy(), db.out_len.cpu().numpy()
+
+
+def _static(db, alpha, eta, tune=None):
+    torch = cuda()
+    from paper_1712_03439_amd import rsim
+
+    db.rir_len.fill_(-1)
+    db.out_len.fill_(-1)
+    y = torch.full((max(db.y_len, 1),), float("nan"), device=db.device)
+    rsim.simulate_static(db, alpha, eta, y, tune=tune)
+    return y
+
+
+def _same(b, y_ref, rl_ref, ol_ref, y, rl, ol):
+    assert np.array_equal(rl_ref, rl) and np.array_equal(ol_ref, ol)
+    for u in range(b.n_utt):
+        off, st, T = int(b.out_off[u]), int(b.out_stride[u]), int(ol[u])
+        for j in range(b.n_mic):
+            s = slice(off + j * st, off + j * st + T)
+            assert np.array_equal(y_ref[s], y[s]), (u, j)
+
+
+@pytest.mark.gpu
+def test_static_entry_matches_simulate_on_two_calls_in_a_row():
+    # a 48-utterance batch, then a smaller one: the second call reuses the
+    # scratch the first left behind
+    torch = cuda()
+    big = synth.make_config2(n_utt=48, epoch=21)
+    small = synth.make_config2(n_utt=6, epoch=22)
+    refs = [_reference(b, 20.0) for b in (big, small)]
+    outs = []
+    for (db, alpha, *_r) in refs:
+        y = _static(db, alpha, 20.0)
+        torch.cuda.synchronize()
+        outs.append((y.cpu().numpy(), db.rir_len.cpu().numpy(), db.out_len.cpu().numpy()))
+    for b, (db, alpha, y_ref, rl_ref, ol_ref), (y, rl, ol) in zip((big, small), refs, outs):
+        _same(b, y_ref, rl_ref, ol_ref, y, rl, ol)
+        _check_utterances(b, (0, b.n_utt - 1), 20.0, y, rl, ol)
+
+
+@pytest.mark.gpu
+def test_static_entry_with_fewer_workgroups_than_slots_wanted():
+    # 8 mics, RIRs up to 16000 taps, N = 32768 (family of 1024 threads): the
+    # persistent grid's scratch slots would need several times the static
+    # array, so fewer workgroups run; a smaller 8-mic batch follows
+    torch = cuda()
+    from paper_1712_03439_amd import rsim
+
+    b1 = _large_subset(12, 99)
+    b2 = _large_subset(3, 98)
+    l2a, l2b = np.full(b1.n_utt, 15, np.int32), np.full(b2.n_utt, 15, np.int32)
+    db1, a1, y1_ref, rl1_ref, ol1_ref = _reference(b1, math.inf, fft_log2n=l2a)
+    assert db1.workspace_bytes() > rsim.STATIC_SCRATCH_BYTES
+    db2, a2, y2_ref, rl2_ref, ol2_ref = _reference(b2, 30.0, fft_log2n=l2b)
+    y1 = _static(db1, a1, math.inf)
+    y2 = _static(db2, a2, 30.0)
+    torch.cuda.synchronize()
+    _same(b1, y1_ref, rl1_ref, ol1_ref, y1.cpu().numpy(), db1.rir_len.cpu().numpy(), db1.out_len.cpu().numpy())
+    _same(b2, y2_ref, rl2_ref, ol2_ref, y2.cpu().numpy(), db2.rir_len.cpu().numpy(), db2.out_len.cpu().numpy())
+    _check_utterances(b2, (0,), 30.0, y2.cpu().numpy(), db2.rir_len.cpu().numpy(), db2.out_len.cpu().numpy())
+
+
+@pytest.mark.gpu
+def test_static_entry_rejects_a_batch_that_does_not_fit():
+    # 64 sources x 64 mics forced to N = 32768: one workgroup's slot of RIR
+    # spectra alone is larger than the static array; nothing is launched
+    torch = cuda()
+    from paper_1712_03439_amd import rsim
+
+    rng = synth.rng_for(23, 0)
+    srcs = [[synth.white_noise(rng, 200) for _ in range(64)]]
+    rirs = [[[synth.rir(rng, 8, 0.1, 0) for _ in range(64)] for _ in range(64)]]
+    b = synth.pack(srcs, rirs, [[0.0] * 64], 64)
+    db = rsim.DeviceBatch(b, fft_log2n=np.array([15], np.int32))
+    alpha = torch.ones(64 * 64, device="cuda")
+    with pytest.raises(rsim.RsimError) as e:
+        _static(db, alpha, 20.0)
+    assert e.value.code == rsim.RSIM_EWORKSPACE
+    torch.cuda.synchronize()
+    assert int(db.rir_len.min()) == -1 and int(db.out_len.min()) == -1  # untouched
