@@ -29,10 +29,14 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
+# Published MI355X peaks: HBM3E bandwidth and the FP32 vector rate.  The FP32
+# figure counts packed FP32 instructions (two lanes' worth per instruction);
+# this build emits none, so the unpacked rate, 256 CUs x 64 lanes x 2 FLOP
+# per FMA x 2.4 GHz = 78.6 TFLOP/s, is the practical ceiling of its
+# arithmetic and is reported beside the published one.
 HBM_PEAK_GBS = 8000.0
-# FP32 vector peak without packed FP32 instructions (which this build does not
-# emit): 256 CUs x 64 lanes x 2 FLOP per FMA x 2.4 GHz.
-FP32_PEAK_TFLOPS = 78.6
+FP32_PEAK_TFLOPS = 157.3
+FP32_UNPACKED_TFLOPS = 78.6
 COUNTERS = os.path.join(ROOT, "profiles", "mix_kernel_batched2048_hbm_counters.json")
 
 
@@ -98,6 +102,93 @@ def host_plan(nx, I, J, lmax, tune_fft, tune_mac, l2=0):
     return N, B, (nx + B - 1) // B
 
 
+def host_info() -> dict:
+    """The host's core count and CPU model (the oracle's hardware)."""
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"os_cpu_count": os.cpu_count(), "usable_cpus": usable, "cpu_model": model}
+
+
+class ParityCases:
+    """GPU outputs of seeded utterances of every workload, kept on the host
+    so that the FP64 oracle (in the cpu_baseline leg) can give each
+    workload's max error relative to the peak (per utterance and mic, the
+    tests' bar)."""
+
+    def __init__(self):
+        self.forward = []   # (label, sources, rirs, snrs, eta, gpu cut lengths [I][J], gpu outputs [J][T])
+        self.adjoint = []   # (label, sources, cut rirs, alpha, g [J][T], gx [I][nx], gh [I][J][L0], ga [I][J])
+
+    def add_forward(self, label, b, u, eta, y, rl, ol):
+        S, J = b.max_src, b.n_mic
+        I = int(b.n_src[u])
+        off, st, T = int(b.out_off[u]), int(b.out_stride[u]), int(ol[u])
+        outs = [np.array(y[off + j * st: off + j * st + T]) for j in range(J)]
+        lens = [[int(rl[(u * S + i) * J + j]) for j in range(J)] for i in range(I)]
+        self.forward.append((label, b.sources(u), b.rirs(u), list(b.snrs(u)), eta, lens, outs))
+
+
+def _forward_error(case):
+    import oracle
+
+    label, xs, hs, snrs, eta, lens, outs = case
+    ref, _, Ls, _ = oracle.simulate(xs, hs, snrs, eta)
+    if Ls != lens:
+        return label, float("inf")
+    err = 0.0
+    for j, got in enumerate(outs):
+        if got.size != ref.shape[1]:
+            return label, float("inf")
+        peak = float(np.max(np.abs(ref[j]))) if got.size else 0.0
+        if peak > 0.0:
+            err = max(err, float(np.max(np.abs(got.astype(np.float64) - ref[j]))) / peak)
+    return label, err
+
+
+def _adjoint_error(case):
+    import oracle
+
+    label, xs, cut, alpha, g, gx, gh, ga = case
+    dx, dh, da = oracle.mix_backward(xs, cut, alpha, g)
+    err = 0.0
+    for i in range(len(xs)):
+        err = max(err, float(np.max(np.abs(gx[i] - dx[i]))) / float(np.max(np.abs(dx[i]))))
+    peak_h = max(float(np.max(np.abs(r))) for row in dh for r in row if r.size)
+    for i, row in enumerate(dh):
+        for j, r in enumerate(row):
+            got = np.asarray(gh[i][j], np.float64)
+            ref = np.zeros(got.size)
+            ref[: r.size] = r
+            err = max(err, float(np.max(np.abs(got - ref))) / peak_h)
+    err = max(err, float(np.max(np.abs(np.asarray(ga) - da))) / float(np.max(np.abs(da))))
+    return label, err
+
+
+def oracle_errors(cases: ParityCases, workers: int) -> dict:
+    """Max error of each workload's GPU outputs relative to the oracle's
+    peak, over its seeded utterances (host threads: numpy's direct
+    convolution releases the GIL); inf for a cut length or output length
+    that differs."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    out = {}
+    with ThreadPoolExecutor(workers) as ex:
+        for label, e in list(ex.map(_forward_error, cases.forward)) + list(ex.map(_adjoint_error, cases.adjoint)):
+            out[label] = max(out.get(label, 0.0), e)
+    return {k: float(f"{v:.3g}") for k, v in out.items()}
+
+
 def oracle_utterance(args):
     import oracle
 
@@ -106,9 +197,10 @@ def oracle_utterance(args):
     return 0
 
 
-def cpu_baseline(base, eta, n_utt, max_workers=16):
+def cpu_baseline(base, eta, n_utt, max_workers=16, cases: "ParityCases" = None):
     """The FP64 oracle (cut + gains + direct convolution + mix) on a seeded
-    sample of utterances, one process per host core (at most 16)."""
+    sample of utterances, one process per host core (at most 16); then, with
+    `cases`, the oracle's max error of every workload's GPU outputs (untimed)."""
     import multiprocessing as mp
 
     rng = np.random.default_rng(1234)
@@ -122,12 +214,18 @@ def cpu_baseline(base, eta, n_utt, max_workers=16):
         t0 = time.perf_counter()
         pool.map(oracle_utterance, tasks, chunksize=1)
         dt = time.perf_counter() - t0
-    return {"value": audio / dt, "unit": "audio-s/s", "cores": cores, "kind": "oracle",
-            "sample": f"{len(idx)} seeded utterances of the batched workload ({audio:.0f} audio-s), "
-                      f"FP64 direct convolution, {dt:.1f} s wall"}
+    res = {"value": audio / dt, "unit": "audio-s/s", "cores": cores, "kind": "oracle",
+           "sample": f"{len(idx)} seeded utterances of the batched workload ({audio:.0f} audio-s), "
+                     f"FP64 direct convolution, {dt:.1f} s wall",
+           "host": host_info()}
+    if cases is not None:
+        t0 = time.perf_counter()
+        res["max_rel_error"] = oracle_errors(cases, cores)
+        res["error_seconds"] = round(time.perf_counter() - t0, 1)
+    return res
 
 
-def differentiation(torch, rsim, synth, dev, reps: int = 10):
+def differentiation(torch, rsim, synth, dev, reps: int = 10, cases: "ParityCases" = None):
     """Forward and adjoint of the mix on the differentiation workload: 64
     utterances of 4 s, 3 sources, 4 mics, 8192-tap RIRs, no cut, N = 16384
     (hop 8193, 8 blocks), loss sum_j sum_n w_j[n] y_j[n]^2 so g = 2 w y.  The
@@ -165,6 +263,26 @@ def differentiation(torch, rsim, synth, dev, reps: int = 10):
     torch.cuda.synchronize()
     t_f = ev[0].elapsed_time(ev[1]) / reps
     t_b = ev[1].elapsed_time(ev[2]) / reps
+    if cases is not None:
+        # forward outputs of three utterances and the adjoint of one, for the oracle
+        yh, rl, ol = y.cpu().numpy(), db.rir_len.cpu().numpy(), db.out_len.cpu().numpy()
+        for u in (0, 31, 63):
+            cases.add_forward("differentiation_forward", b, u, math.inf, yh, rl, ol)
+        gx, gh, ga = rsim.mix_backward(db, alpha, g, ws=ws_b, stream=stream)
+        torch.cuda.synchronize()
+        gx, gh, ga, gn = gx.cpu().numpy(), gh.cpu().numpy(), ga.cpu().numpy(), g.cpu().numpy()
+        u = 17
+        I, T, nx = int(b.n_src[u]), int(ol[u]), int(b.src_len[u])
+        xs, hs = b.sources(u), b.rirs(u)
+        cut = [[np.asarray(hs[i][j], np.float32)[: int(rl[(u * S + i) * J + j])] for j in range(J)] for i in range(I)]
+        a = alpha.cpu().numpy()[u * S * J:(u * S + I) * J].reshape(I, J).astype(np.float64)
+        off, st = int(b.out_off[u]), int(b.out_stride[u])
+        gu = np.stack([gn[off + j * st: off + j * st + T] for j in range(J)])
+        gxu = [gx[int(b.src_off[u * S + i]): int(b.src_off[u * S + i]) + nx] for i in range(I)]
+        ghu = [[gh[int(b.rir_off[(u * S + i) * J + j]): int(b.rir_off[(u * S + i) * J + j])
+                   + int(b.rir_len0[(u * S + i) * J + j])] for j in range(J)] for i in range(I)]
+        gau = ga[u * S * J:(u * S + I) * J].reshape(I, J)
+        cases.adjoint.append(("differentiation_adjoint", xs, cut, a, gu, gxu, ghu, gau))
     # algorithmic work of the adjoint: per block J gradient spectra, I source
     # spectra, I inverse transforms (dx) and 2 I J spectral products; per
     # utterance I J RIR spectra and I J inverse transforms (r)
@@ -187,6 +305,8 @@ def differentiation(torch, rsim, synth, dev, reps: int = 10):
             "audio_s_per_s": round(b.audio_seconds / ((t_f + t_b) * 1e-3), 1),
             "backward_roofline": {"bound": "alu", "achieved": round(achieved, 2), "peak": FP32_PEAK_TFLOPS,
                                   "unit": "TFLOP/s", "frac": round(achieved / FP32_PEAK_TFLOPS, 4)},
+            "backward_alu_unpacked": {"achieved": round(achieved, 2), "peak": FP32_UNPACKED_TFLOPS,
+                                      "unit": "TFLOP/s", "frac": round(achieved / FP32_UNPACKED_TFLOPS, 4)},
             "backward_hbm": {"achieved": round(byts / (t_b * 1e-3) / 1e9, 1), "peak": HBM_PEAK_GBS,
                              "unit": "GB/s", "frac": round(byts / (t_b * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}}
 
@@ -292,12 +412,16 @@ def reverb_gains(torch, rsim, dev, base, db, reps: int = 5):
             "ms": round(ms, 4), "audio_s_per_s": round(base.audio_seconds / (ms * 1e-3), 1),
             "roofline": {"bound": "alu", "achieved": round(tf, 2), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                          "frac": round(tf / FP32_PEAK_TFLOPS, 4)},
+            "alu_unpacked": {"achieved": round(tf, 2), "peak": FP32_UNPACKED_TFLOPS, "unit": "TFLOP/s",
+                             "frac": round(tf / FP32_UNPACKED_TFLOPS, 4)},
             "hbm": {"achieved": round(byts / (ms * 1e-3) / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s"}}
 
 
-def front_end(torch, rsim, base, db, y, reps: int = 5):
+def front_end(torch, rsim, base, db, y, reps: int = 5, alpha=None, eta=20.0, tune=None, mix_ms=None):
     """The log-Mel features (Sec. 3) of every mic output of the batched epoch:
-    one untimed call, then `reps` timed ones."""
+    one untimed call, then `reps` timed ones; then, with alpha, the front end
+    fused into the mix (rsim_simulate_logmel: cut, mix and features, no y)
+    against the unfused steps (cut + mix, then the separate front end)."""
     stream = torch.cuda.Stream()
     stream.wait_stream(torch.cuda.current_stream())
     with torch.cuda.stream(stream):
@@ -318,13 +442,46 @@ def front_end(torch, rsim, base, db, y, reps: int = 5):
     flops = frames * (2.5 * 512 * m + 4 * 257 + 2 * 2 * 257 + 128 * 8)
     tf = flops / (ms * 1e-3) / 1e12
     gbs = byts / (ms * 1e-3) / 1e9
-    return {"workload": f"128 log-Mel bands of every mic output of the batched epoch ({frames} frames)",
-            "ms": round(ms, 4), "frames_per_s": round(frames / (ms * 1e-3), 1),
-            "audio_s_per_s": round(base.audio_seconds / (ms * 1e-3), 1),
-            "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": round(gbs / HBM_PEAK_GBS, 4)},
-            "alu": {"achieved": round(tf, 2), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-                    "frac": round(tf / FP32_PEAK_TFLOPS, 4)}}
+    out = {"workload": f"128 log-Mel bands of every mic output of the batched epoch ({frames} frames)",
+           "ms": round(ms, 4), "frames_per_s": round(frames / (ms * 1e-3), 1),
+           "audio_s_per_s": round(base.audio_seconds / (ms * 1e-3), 1),
+           "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": round(gbs / HBM_PEAK_GBS, 4)},
+           "alu": {"achieved": round(tf, 2), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                   "frac": round(tf / FP32_PEAK_TFLOPS, 4)}}
+    if alpha is not None:
+        # cut + mix + features as one graph with the front end fused into the
+        # mix, against cut + mix (one graph) and the separate front end
+        off, cap, total = rsim.feature_layout(db)
+        feat = torch.empty(max(total, 1), dtype=torch.float32, device=db.device)
+        s_ = db.struct()
+        import ctypes
+
+        n = int(rsim.lib().rsim_simulate_logmel_workspace_bytes(ctypes.byref(s_), ctypes.byref(tune) if tune else None))
+        wsf = torch.empty(max(n, 1), dtype=torch.uint8, device=db.device)
+        wsu = db.workspace(tune)
+        with torch.cuda.stream(stream):
+            rsim.simulate_logmel(db, alpha, eta, feat=feat, ws=wsf, tune=tune, use_graph=True, stream=stream)
+            e2, e3, e4 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+            e2.record(stream)
+            for _ in range(reps):
+                rsim.simulate_logmel(db, alpha, eta, feat=feat, ws=wsf, tune=tune, use_graph=True, stream=stream)
+            e3.record(stream)
+            for _ in range(reps):
+                rsim.simulate(db, alpha, eta, y=y, ws=wsu, tune=tune, use_graph=True, stream=stream)
+                rsim.logmel(db, y, stream=stream)
+            e4.record(stream)
+        torch.cuda.synchronize()
+        if rsim.device_status():
+            raise RuntimeError("the fused front end flagged a descriptor")
+        fused, unfused = e2.elapsed_time(e3) / reps, e3.elapsed_time(e4) / reps
+        byts_f = int(np.sum(base.n_src.astype(np.int64) * base.src_len)) * 4 + frames * 128 * 4
+        out["fused"] = {"steps": "cut + mix with the front end fused (features only, no y), one graph",
+                        "ms": round(fused, 4), "unfused_ms": round(unfused, 4),
+                        "speedup": round(unfused / fused, 3),
+                        "audio_s_per_s": round(base.audio_seconds / (fused * 1e-3), 1),
+                        "hbm_bytes_algorithmic": byts_f}
+    return out
 
 
 def ladder(torch, rsim, base, db, alpha, y, mix_ms, reps: int = 3):
@@ -351,11 +508,101 @@ def ladder(torch, rsim, base, db, alpha, y, mix_ms, reps: int = 3):
             "overlap_add_speedup": round(ms / mix_ms, 2)}
 
 
-def large_thresholds(torch, rsim, autotune, synth, dev, etas=(math.inf, 30.0, 20.0, 10.0), reps: int = 3):
+def single_utterances(torch, rsim, synth, dev, reps: int = 20, cases: "ParityCases" = None):
+    """Per-utterance latency of the two single-utterance workloads (the
+    paper's Table 1 measures time per utterance): the tiny case (1 s, one
+    4096-tap RIR, N = 8192, hop 4096, through rsim_ola_convolve) and one
+    room (8 s, 3 sources at 10 and 20 dB SNR, 2 mics, 12000-tap RIRs cut at
+    20 dB, N = 16384, through rsim_simulate, eager).  Each call is timed on
+    its own, synchronised, after one untimed call: the host wall time per
+    call (the latency a caller sees) and the GPU time between HIP events."""
+    out = {}
+    b0 = synth.make_config0()
+    x = torch.from_numpy(b0.sources(0)[0]).to(dev)
+    h = torch.from_numpy(b0.rirs(0)[0][0]).to(dev)
+    b1 = synth.make_config1()
+    db1 = rsim.DeviceBatch(b1, device=dev, fft_log2n=np.array([14], np.int32))
+    a1 = torch.from_numpy(rsim.batch_gains(db1, b1.snr_db)).to(dev)
+    y1 = db1.new_output()
+    ws1 = db1.workspace()
+
+    def timed(call):
+        call()
+        torch.cuda.synchronize()
+        wall, gpu = [], []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            e0.record()
+            r = call()
+            e1.record()
+            torch.cuda.synchronize()
+            wall.append((time.perf_counter() - t0) * 1e3)
+            gpu.append(e0.elapsed_time(e1))
+        return r, float(np.median(wall)), float(np.median(gpu))
+
+    y0, w0, g0 = timed(lambda: rsim.ola_convolve(x, h, 8192, 4096))
+    _, w1, g1 = timed(lambda: rsim.simulate(db1, a1, 20.0, y=y1, ws=ws1))
+    out["tiny"] = {"workload": "1 utterance of 1 s, 1 source, 1 mic, 4096-tap RIR, no cut, N = 8192, hop 4096 "
+                               "(output 20095 samples)",
+                   "ms_wall": round(w0, 4), "ms_gpu": round(g0, 4),
+                   "audio_s_per_s": round(b0.audio_seconds / (w0 * 1e-3), 1)}
+    out["one_room"] = {"workload": "1 utterance of 8 s, 3 sources (10 and 20 dB SNR), 2 mics, 12000-tap RIRs "
+                                   "cut at 20 dB, N = 16384",
+                       "ms_wall": round(w1, 4), "ms_gpu": round(g1, 4),
+                       "audio_s_per_s": round(b1.audio_seconds / (w1 * 1e-3), 1)}
+    if cases is not None:
+        T = int(y0.numel())
+        cases.forward.append(("tiny", b0.sources(0), b0.rirs(0), [0.0], math.inf, [[4096]],
+                              [y0.cpu().numpy()[:T]]))
+        cases.add_forward("one_room", b1, 0, 20.0, y1.cpu().numpy(), db1.rir_len.cpu().numpy(),
+                          db1.out_len.cpu().numpy())
+    return out
+
+
+def gpu_share(torch, rsim, base, db, alpha, y, ws, tune, eta, full_ms, shares: int = 8, reps: int = 10):
+    """The one-GPU part of the multi-GPU design: the share of the batched
+    epoch one of `shares` GPUs would get when the utterances (in LPT order)
+    are dealt round robin, run on this GPU as its own batch (cut + mix, one
+    graph), to show what the smaller batch costs in occupancy."""
+    order = lpt_order(base)
+    idx = np.sort(order[::shares])
+    sub = db.select(idx)
+    u = torch.as_tensor(idx, device=db.device)
+    S, J = db.S, db.J
+    rows = ((u[:, None] * S + torch.arange(S, device=db.device)[None, :])[:, :, None] * J
+            + torch.arange(J, device=db.device)[None, None, :]).reshape(-1)
+    a = alpha[rows].contiguous()
+    ws_s = sub.workspace(tune)
+    stream = torch.cuda.Stream()
+    stream.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(stream):
+        rsim.simulate(sub, a, eta, y=y, ws=ws_s, tune=tune, use_graph=True, stream=stream)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            rsim.simulate(sub, a, eta, y=y, ws=ws_s, tune=tune, use_graph=True, stream=stream)
+        e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    audio = float(np.sum(base.src_len[idx].astype(np.float64))) / 16000.0
+    return {"workload": f"{len(idx)} of the batched epoch's {base.n_utt} utterances (every {shares}th in "
+                        f"LPT order: one GPU's share of {shares})",
+            "ms": round(ms, 4), "audio_s_per_s": round(audio / (ms * 1e-3), 1),
+            "share_of_epoch_audio": round(audio / base.audio_seconds, 4),
+            "time_vs_full_epoch": round(ms / full_ms, 4)}
+
+
+def large_thresholds(torch, rsim, autotune, synth, dev, etas=(math.inf, 30.0, 20.0, 10.0), reps: int = 3,
+                     cases: "ParityCases" = None, full_length: bool = True):
     """The large batched workload (4096 utterances of 1-20 s, up to 4 sources,
     8 mics, T60 U(0.1, 1.0) s, RIRs up to 16000 taps) at each cut threshold:
     per threshold the tuner runs on the cut batch, then cut + mix run as one
-    graph `reps` times (after one untimed run)."""
+    graph `reps` times (after one untimed run); then the full-length FFT
+    filtering of eqs. 4-5 on the same cut batch (one untimed and one timed
+    call), the comparison of Sec. 2.3 and Table 2 (cost against threshold,
+    with and without overlap-add)."""
     t0 = time.perf_counter()
     b = synth.make_config4()
     log(f"large workload: {b.n_utt} utterances, {b.audio_seconds:.0f} audio-s ({time.perf_counter() - t0:.1f} s)")
@@ -409,9 +656,29 @@ def large_thresholds(torch, rsim, autotune, synth, dev, etas=(math.inf, 30.0, 20
                     "frac": round(fl / (ms * 1e-3) / 1e12 / FP32_PEAK_TFLOPS, 4)},
             "hbm": {"achieved": round(byt / (ms * 1e-3) / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(byt / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}}
-        log(f"large workload, eta {key}: {ms:.2f} ms (cut + mix), {out['thresholds'][key]['audio_s_per_s']:.4g} "
-            f"audio-s/s, sizes {out['thresholds'][key]['fft_sizes']}")
+        if cases is not None:
+            yh, rl, ol = y.cpu().numpy(), db.rir_len.cpu().numpy(), db.out_len.cpu().numpy()
+            longest = int(np.argmax(b.src_len.astype(np.int64) * b.n_src))
+            for u in sorted({longest} | set(np.random.default_rng(11).choice(b.n_utt, 3, replace=False).tolist())):
+                cases.add_forward(f"large_eta_{key}", b, int(u), eta, yh, rl, ol)
         del ws
+        if full_length:
+            with torch.cuda.stream(stream):
+                rsim.fft_filter(db, alpha, y=y, stream=stream)
+                e2, e3 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e2.record(stream)
+                rsim.fft_filter(db, alpha, y=y, stream=stream)
+                e3.record(stream)
+            torch.cuda.synchronize()
+            fms = e2.elapsed_time(e3)
+            out["thresholds"][key]["full_length_fft_ms"] = round(fms, 2)
+            out["thresholds"][key]["full_length_fft_audio_s_per_s"] = round(b.audio_seconds / (fms * 1e-3), 1)
+            out["thresholds"][key]["overlap_add_speedup"] = round(fms / ms, 2)
+        log(f"large workload, eta {key}: {ms:.2f} ms (cut + mix), {out['thresholds'][key]['audio_s_per_s']:.4g} "
+            f"audio-s/s, sizes {out['thresholds'][key]['fft_sizes']}"
+            + (f"; full-length FFT {out['thresholds'][key]['full_length_fft_ms']:.1f} ms" if full_length else ""))
+    if rsim.device_status():
+        raise RuntimeError("the large workload flagged a descriptor or plan")
     return out
 
 
@@ -434,9 +701,11 @@ def main() -> int:
     ap.add_argument("--no-reverb", action="store_true", help="skip the reverberant-energy (gain rule) timing")
     ap.add_argument("--no-frontend", action="store_true", help="skip the log-Mel front-end timing")
     ap.add_argument("--no-ladder", action="store_true", help="skip the full-length FFT filtering timing")
-    ap.add_argument("--large", action="store_true",
-                    help="also time the large batched workload (4096 utterances, 8 mics) at eta = inf, 30, 20, "
-                         "10 dB (adds about a minute and 35 GB of GPU memory)")
+    ap.add_argument("--no-large", action="store_true",
+                    help="skip the large batched workload (4096 utterances, 8 mics) at eta = inf, 30, 20, 10 dB "
+                         "(about a minute of host-side generation and 35 GB of GPU memory)")
+    ap.add_argument("--no-single", action="store_true", help="skip the single-utterance latencies")
+    ap.add_argument("--no-share", action="store_true", help="skip the one-GPU-share timing")
     ap.add_argument("--tune", default="measure",
                     help="'measure' (time every FFT size and kernel variant on the first epoch's "
                          "batch before the warmup), 'model' (the built-in cost model), 'auto' (this "
@@ -579,8 +848,8 @@ def main() -> int:
     t_mix = float(np.mean(mix_ms)) * 1e-3
     achieved = float(np.mean(byt)) / t_mix / 1e9
     alu = float(np.mean(flops)) / t_mix / 1e12
-    # The binding bound of the mix is the one with the longer time at peak:
-    # FP32 vector arithmetic (no packed FP32 in this build) or HBM.
+    # The binding bound of the mix is the one with the longer time at the
+    # published peaks (HBM 8 TB/s, FP32 vector 157.3 TFLOP/s).
     t_alu, t_hbm = float(np.mean(flops)) / (FP32_PEAK_TFLOPS * 1e12), float(np.mean(byt)) / (HBM_PEAK_GBS * 1e9)
     dom_n = max(sizes, key=lambda n: sizes[n] * n * math.log2(n))
     kernel = mix_kernel_name(int(math.log2(dom_n)), list(tune.variant) if tune is not None else None)
@@ -591,6 +860,14 @@ def main() -> int:
     else:
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic}
+    cases = ParityCases()
+    b_last, db_last, _ = epochs[(W + K - 1) % E]
+    yh, rlh, olh = y.cpu().numpy(), db_last.rir_len.cpu().numpy(), db_last.out_len.cpu().numpy()
+    longest = int(np.argmax(b_last.src_len.astype(np.int64) * b_last.n_src))
+    pick = {longest} | set(np.random.default_rng(5).choice(b_last.n_utt, 15, replace=False).tolist())
+    for u in sorted(pick):
+        cases.add_forward("batched", b_last, int(u), args.eta, yh, rlh, olh)
+    del yh
     result = {
         "metric": "simulated audio-sec/sec (FP32, 1 MI355X) batched vs plain; HBM GB/s fraction",
         "value": round(value, 1),
@@ -614,23 +891,30 @@ def main() -> int:
         "roofline": roof,
         "hbm": {"achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4)},
+        "alu": {"achieved": round(alu, 2), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(alu / FP32_PEAK_TFLOPS, 4)},
+        "alu_unpacked": {"achieved": round(alu, 2), "peak": FP32_UNPACKED_TFLOPS, "unit": "TFLOP/s",
+                         "frac": round(alu / FP32_UNPACKED_TFLOPS, 4),
+                         "note": "the ceiling of this build's arithmetic: it emits no packed FP32 instructions"},
         "dominant_kernel": kernel,
         "kernel_ms": {"cut": round(float(np.mean(trunc_ms)), 4), "mix": round(float(np.mean(mix_ms)), 4)},
         "cut_hbm": {"achieved": round(float(np.mean(byt_cut)) / (float(np.mean(trunc_ms)) * 1e-3) / 1e9, 1),
                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(float(np.mean(byt_cut)) / (float(np.mean(trunc_ms)) * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
-        "alu_model": "2.5 N log2 N per real FFT + 8 (N/2+1) per spectral MAC; peak = 256 CUs x 64 lanes x "
-                     "2 FLOP (FMA) x 2.4 GHz",
+        "alu_model": "2.5 N log2 N per real FFT + 8 (N/2+1) per spectral MAC; published FP32 vector peak "
+                     "157.3 TFLOP/s (packed); unpacked 256 CUs x 64 lanes x 2 FLOP (FMA) x 2.4 GHz = 78.6",
         "bytes_per_step": {"mix": int(np.mean(byt)), "cut": int(np.mean(byt_cut))},
     }
 
     # the front end reads the last timed epoch's output, still in y
     if not args.no_frontend:
         b_last, db_last, _ = epochs[(W + K - 1) % E]
-        result["front_end"] = front_end(torch, rsim, b_last, db_last, y)
+        _, _, alpha_last = epochs[(W + K - 1) % E]
+        result["front_end"] = front_end(torch, rsim, b_last, db_last, y, alpha=alpha_last, eta=args.eta, tune=tune)
         d = result["front_end"]
         log(f"log-Mel front end: {d['ms']:.3f} ms per epoch, {d['frames_per_s']:.4g} frames/s, "
-            f"{d['roofline']['frac']:.3f} of the HBM peak")
+            f"{d['roofline']['frac']:.3f} of the HBM peak; fused into the mix {d['fused']['ms']:.3f} ms per epoch "
+            f"against {d['fused']['unfused_ms']:.3f} ms unfused")
 
     if not args.no_plain:
         # Plain per-utterance path: the same kernels, one utterance per call, no
@@ -655,8 +939,21 @@ def main() -> int:
         result["speedup_vs_plain"] = round(value / plain, 2)
         log(f"plain per-utterance path: {plain:.4g} audio-s/s ({value / plain:.1f}x)")
 
+    if not args.no_share:
+        b0_, db0_, alpha0_ = epochs[0]
+        result["one_gpu_share"] = gpu_share(torch, rsim, b0_, db0_, alpha0_, y, ws, tune, args.eta,
+                                            float(np.mean(mix_ms)) + float(np.mean(trunc_ms)))
+        d = result["one_gpu_share"]
+        log(f"one GPU's share (1/8 of the epoch): {d['ms']:.3f} ms, {d['audio_s_per_s']:.4g} audio-s/s")
+
+    if not args.no_single:
+        result["single_utterance"] = single_utterances(torch, rsim, synth, dev, cases=cases)
+        d = result["single_utterance"]
+        log(f"single utterances: tiny {d['tiny']['ms_wall']:.3f} ms, one room {d['one_room']['ms_wall']:.3f} ms "
+            f"per call (wall)")
+
     if not args.no_diff:
-        result["differentiation"] = differentiation(torch, rsim, synth, dev)
+        result["differentiation"] = differentiation(torch, rsim, synth, dev, cases=cases)
         d = result["differentiation"]
         log(f"differentiation workload: forward {d['forward_ms']:.3f} ms, adjoint {d['backward_ms']:.3f} ms, "
             f"adjoint at {d['backward_roofline']['frac']:.3f} of the FP32 peak")
@@ -684,17 +981,17 @@ def main() -> int:
         d = result["reverb_gains"]
         log(f"reverberant energies: {d['ms']:.3f} ms per epoch, {d['roofline']['frac']:.3f} of the FP32 peak")
 
-    if args.large:
+    if not args.no_large:
         del y, ws
         epochs.clear()
         torch.cuda.empty_cache()
-        result["large"] = large_thresholds(torch, rsim, autotune, synth, dev)
+        result["large"] = large_thresholds(torch, rsim, autotune, synth, dev, cases=cases)
 
     if not args.no_cpu:
-        log("timing the FP64 oracle on the host cores ...")
-        result["cpu_baseline"] = cpu_baseline(base, args.eta, args.cpu_utts)
+        log("timing the FP64 oracle on the host cores, then its errors of every workload's outputs ...")
+        result["cpu_baseline"] = cpu_baseline(base, args.eta, args.cpu_utts, cases=cases)
         log(f"oracle: {result['cpu_baseline']['value']:.4g} audio-s/s on "
-            f"{result['cpu_baseline']['cores']} cores")
+            f"{result['cpu_baseline']['cores']} cores; max errors {result['cpu_baseline']['max_rel_error']}")
     print(json.dumps(result), flush=True)
     return 0
 

@@ -105,8 +105,12 @@ typedef struct rsim_batch {
  * 1024 and 2048; 4096; 8192; 16384; 32768):
  *   0 the library default (2); 1 one mic per pass, registers sized for two
  *   waves per SIMD; 2 two mics per pass, one wave per SIMD; 3 two mics per
- *   pass, two waves per SIMD; 4 one mic per pass, four waves per SIMD (a
- *   workgroup of 32 << f threads has at least (32 << f) / 256 waves per SIMD).
+ *   pass, two waves per SIMD; 4 one mic per pass, registers sized for four
+ *   waves per SIMD (at most 128 a thread, no prefetch).  These are register
+ *   budgets: the waves a SIMD actually holds are also bounded by the
+ *   workgroup's LDS (the exchange buffers take 35 KB to 140 KB), so the
+ *   families of 256 and 512 threads reach two waves per SIMD with any
+ *   variant (a workgroup of 32 << f threads has at least (32 << f) / 256).
  * Family 5 has variant 4 only; its entry is ignored.  Costs must be finite
  * and >= 0 and variants in 0..4 (RSIM_EINVAL, or a workspace size of 0,
  * otherwise).  The variant changes the order of no floating-point operation
@@ -198,7 +202,9 @@ rsim_status rsim_simulate(const rsim_batch* b, const float* x, const float* h,
  * schedule clears the work counters at the start of each call): calls that
  * overlap on one device race and give undefined results, so a caller
  * serialises them (one stream, or events).  Results are bit-identical to
- * rsim_simulate's for the same batch, eta and tune.
+ * rsim_simulate's for the same batch, eta and tune (this call never splits
+ * an utterance's blocks over several work items, which keeps the scratch
+ * small; the split changes no output bit).
  */
 #define RSIM_STATIC_SCRATCH_BYTES ((size_t)128 << 20)
 rsim_status rsim_simulate_static(const rsim_batch* b, const float* x, const float* h,
@@ -343,6 +349,32 @@ rsim_status rsim_logmel(const rsim_batch* b, const float* y, float* feat, const 
 size_t rsim_fft_filter_workspace_bytes(const rsim_batch* b, int32_t fft_log2n, int32_t chunk);
 rsim_status rsim_fft_filter(const rsim_batch* b, const float* x, const float* h, const float* alpha, float* y,
                             int32_t fft_log2n, int32_t chunk, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/*
+ * One epoch with the front end fused into the mix: the cut and the mix of
+ * rsim_simulate, except that the mixed samples never leave the kernels; the
+ * mix kernel turns every frame of every mic output into its 128 log-Mel
+ * features as soon as the frame's samples are final (Sec. 3's front end, the
+ * frames, window, transform, filterbank and log of rsim_logmel, with the same
+ * operations, so the features equal rsim_logmel's of rsim_simulate's
+ * output).  feat, feat_off, feat_len and the frame capacity C_u (frames of
+ * out_stride[u] samples) are as for rsim_logmel; y is not written (y_len,
+ * out_off and out_stride keep their meaning as bounds and layout), out_len
+ * is.  Only FFT sizes 4096, 8192 and 16384 have fused kernels: the size rule
+ * of the tune table runs over those (one kernel variant each), and forced
+ * sizes (fft_log2n) must state fft_sizes within them (RSIM_EUNSUPPORTED
+ * otherwise).  Each work item keeps two overlap-add accumulators per mic in
+ * its workspace slot instead of carrying through y; J <= 8
+ * (RSIM_EUNSUPPORTED otherwise).  An utterance whose features would leave
+ * [0, feat_len), or whose T_u is 2^29 samples or more, gets none, with
+ * RSIM_DEV_BADDESC.  ws must hold rsim_simulate_logmel_workspace_bytes(b,
+ * tune) bytes; use_graph as for rsim_simulate.
+ */
+size_t rsim_simulate_logmel_workspace_bytes(const rsim_batch* b, const rsim_tune* tune);
+rsim_status rsim_simulate_logmel(const rsim_batch* b, const float* x, const float* h, const float* alpha,
+                                 double eta_db, int32_t* rir_len_out, float* feat, const int64_t* feat_off,
+                                 int64_t feat_len, void* ws, size_t ws_bytes, const rsim_tune* tune,
+                                 int32_t use_graph, hipStream_t stream);
 
 /* Read and clear the device status word (synchronises the device). */
 rsim_status rsim_device_status(int32_t* status);

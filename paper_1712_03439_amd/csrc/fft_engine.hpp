@@ -444,6 +444,28 @@ struct Xch {
   }
 };
 
+// The exchange of a plan whose threads all belong to one wave (T <= 64), in
+// a single buffer, synchronised at wave level only: the LDS executes one
+// wave's operations in issue order, so a read issued after a write sees it
+// and a write issued after a read does not disturb it; the fences only keep
+// the compiler from moving the accesses across the exchange.  Several such
+// groups can exchange independently inside a larger workgroup.
+template <class PL>
+struct XchWave {
+  static_assert(PL::T <= 64, "one wave");
+  static constexpr int kEntries = PL::LDS;
+  cf* base;
+  __device__ cf* buf() const { return base; }
+  __device__ static void sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+  __device__ void before_write() const { sync(); }
+  __device__ void before_read() const { sync(); }
+  __device__ void after_read() {}
+};
+
 template <class PL>
 struct Fft {
   static constexpr int M = PL::M, T = PL::T, P = PL::P, NP = PL::NP, RL = PL::RL;
@@ -471,7 +493,8 @@ struct Fft {
   // Forward complex FFT.  In: v[r] = z[t + rT].  Out: slot layout (before the
   // real post-processing).  `lds` holds PL::LDS entries.  Contains barriers:
   // every thread of the workgroup must call it.
-  __device__ static __forceinline__ void forward(cf* v, Xch<PL>& X, const TwBase& B, int t_) {
+  template <class XC>
+  __device__ static __forceinline__ void forward(cf* v, XC& X, const TwBase& B, int t_) {
     const int t = opaque_v(t_);
     // pass 0 (Ls = 1): no twiddles; outputs of butterfly t go to t*R0 + r
     dft<PL::R[0], false>(v);
@@ -548,7 +571,8 @@ struct Fft {
   }
 
   // Adjoint of forward(): slot layout in, v[r] = M * z[t + rT] out.
-  __device__ static __forceinline__ void inverse(cf* v, Xch<PL>& X, const TwBase& B, int t_) {
+  template <class XC>
+  __device__ static __forceinline__ void inverse(cf* v, XC& X, const TwBase& B, int t_) {
     const int t = opaque_v(t_);
     const int ja = t, jb = t ? 2 * T - t : T;
     const bool t0 = t == 0;

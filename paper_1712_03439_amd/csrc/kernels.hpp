@@ -76,6 +76,25 @@ struct MixArgs {
   // 1: a work item is an utterance; g > 1 (batches with few utterances): a
   // work item is one mic group of an utterance, g items per utterance.
   int gsplit;
+  // psplit > 1 (batches with fewer work items than compute units): each
+  // (utterance, mic group) is further split into up to psplit block ranges
+  // (parts).  The alpha-scaled RIR spectra of the family's utterances are
+  // then formed once by a pass before the kernel, into hspec
+  // ([U][S J][mmax], mmax the family's largest M); the first block of a part
+  // p > 0 leaves the head of its output (the samples the previous block's
+  // tail also covers) in seam ([U][psplit][J][mmax] floats) instead of y,
+  // and a pass after the kernel adds it to y.
+  int psplit;
+  int mmax;
+  cf* hspec;
+  float* seam;
+  // The front end fused into the mix (mix kernels built with it): the
+  // 128-band log-Mel features of every mic output go to feat (the layout of
+  // rsim_logmel) instead of the samples to y; each workgroup's slot then also
+  // holds two overlap-add accumulators per mic (2M complex entries a mic).
+  float* feat;
+  const long long* feat_off;
+  long long feat_len;
 };
 
 struct BwdArgs {

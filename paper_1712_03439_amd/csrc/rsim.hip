@@ -46,6 +46,26 @@ __device__ float g_hann[kMelWin];
 __device__ int g_mel_first[kMelBands];
 __device__ float g_mel_w[kMelBands * kMelCapMax];  // band b's weights at [b * kMelCapMax, + count), zero after
 
+constexpr int kMelMaxT = 1 << 29;  // mic signals shorter than this (byte offsets fit 31 bits)
+// Whole frames in T samples.
+__device__ __forceinline__ int mel_frames(int T) { return T >= kMelWin ? 1 + (T - kMelWin) / kMelHop : 0; }
+
+// Band energy sum_i w[i] pw[first + i] over i < CAP, in bin order; the
+// weights past the band's bins are zero, so for finite powers those terms
+// add exactly nothing.  (A non-finite power can also make the bands whose
+// padded range covers it NaN; with the full filterbank matrix it makes
+// every band NaN.)
+template <int CAP>
+__device__ __forceinline__ float mel_band(const float* w, const float* pw, int first) {
+  float p[CAP];
+#pragma unroll
+  for (int i = 0; i < CAP; ++i) p[i] = pw[first + i];
+  float m = 0.f;
+#pragma unroll
+  for (int i = 0; i < CAP; ++i) m = __builtin_fmaf(w[i], p[i], m);
+  return m;
+}
+
 __device__ __forceinline__ void flag_status(int bits) { atomicOr(&g_status, bits); }
 
 // Values that are the same in every lane (descriptor entries of the current
@@ -462,6 +482,19 @@ __device__ __forceinline__ void load_spec(cf* v, const cf* __restrict__ src, int
   for (int q = 0; q < PL::P; ++q) v[q] = ld2(rs, vo, 8 * q * PL::T);
 }
 
+// Bin held by slot q of thread t (thread 0 permuted as in Fft::perm_t0; its
+// slot SP holds bins 0 and N/2).
+template <class PL>
+__device__ __forceinline__ int slot_bin(int q, int t) {
+  constexpr int R = PL::RL, T = PL::T;
+  if (t != 0) return q < R ? t + 2 * T * q : (2 * T - t) + 2 * T * (q - R);
+  if (q < R / 2) return T + 2 * T * q;
+  if (q < R) return 2 * T * q;
+  if (q < 3 * R / 2 - 1) return 2 * T * (q - R + 1);
+  if (q == 3 * R / 2 - 1) return 0;
+  return T + 2 * T * (q - R);
+}
+
 // The mix kernel's RIR spectra in pairs: slots 2p, 2p + 1 of thread t at
 // index p 2T + 2t, so one 128-bit access moves both (half the load
 // instructions of the slot layout for the same bytes).
@@ -615,9 +648,159 @@ __device__ __forceinline__ void emit_carried(cf* Yv, const cf* c, Xch<PL>& lds, 
   }
 }
 
+// Inverse-transform the first block of a part p > 0 and split its samples:
+// those below h (the head, which the previous part's last block also covers
+// with its tail) go to the seam buffer sp, those from h up to lim to y.
+// Offsets past a resource's range drop the store, so the split needs no
+// branch: a pair straddling h stores its second word alone.
+template <class PL>
+__device__ __forceinline__ void emit_seam(cf* Yv, Xch<PL>& lds, const TwBase& tw, float* __restrict__ yp,
+                                          float* __restrict__ sp, int lim, int h, int t_) {
+  Fft<PL>::pre(Yv, tw, t_);
+  Fft<PL>::inverse(Yv, lds, tw, t_);
+  const int t = opaque_v(t_);
+  const rsrc_t wy = make_rsrc(yp, lim * 4);
+  const rsrc_t wsm = make_rsrc(sp, min(h, lim) * 4);
+  constexpr int kDrop = 0x7ffffff0;  // beyond any resource's range
+#pragma unroll
+  for (int r = 0; r < PL::P; ++r) {
+    const int n0 = 2 * (t + r * PL::T);
+    const int o = 4 * n0;
+    st2(wsm, o, Yv[r]);
+    st2(wy, n0 >= h ? o : kDrop, Yv[r]);
+    st1(wy, n0 + 1 == h ? o + 4 : kDrop, Yv[r].y);
+  }
+}
+
+// Parts of an utterance under the block split: at most psplit, at most one
+// per block, and one when a block's head could reach back past the previous
+// block (a forced hop below L - 1), where the overlap spans several blocks.
+__device__ __forceinline__ int mix_parts(int psplit, const Sched& S) {
+  if (psplit <= 1 || S.hop < S.lmax - 1) return 1;
+  return psplit < S.nb ? psplit : S.nb;
+}
+
 template <class PL>
 __device__ __forceinline__ const cf* plan_tw() {
   return g_tw + tw_off<ilog2c(PL::N)>();
+}
+
+// ------------------------------------------------ front end fused into the mix
+// The front end of Sec. 3 (the features of rsim_logmel) computed by the mix
+// kernel itself, so that the mixed samples never leave the workgroup.  Mics
+// per work item it keeps a frame history for, at most.
+constexpr int kFeatMics = 8;
+
+// LDS of the fused front end, carved out of the mix kernel's exchange area
+// (idle between the mix's transforms): the stage (the kMelWin final samples
+// before the block, then the block's final samples) and one exchange buffer
+// per 32-thread frame group.
+template <class PL>
+struct FeatLds {
+  using FP = PlanOf<9>;
+  static constexpr int kGroups = PL::T / 32;
+  static constexpr int kStageCf = (kMelWin + PL::N) / 2;
+  static constexpr int kCf = kStageCf + kGroups * XchWave<FP>::kEntries;
+};
+
+// One mic's block after its inverse transform (Yv: the block's contribution
+// z to y from its base, samples 2(t + rT) and 2(t + rT) + 1).  Adds the
+// earlier blocks' overlap sum (acc_rd, lmax - 1 samples) as the unfused
+// kernel adds the carry it reads back from y, keeps the new sum past the hop
+// in acc_wr for the next block, and turns every frame whose samples are all
+// final into its 128 log-Mel features, with the operations of rsim_logmel's
+// kernel (a 512-point plan per group of 32 threads, exchanges synchronised
+// within the group's wave).  hist holds the kMelWin final samples before the
+// block.  Every thread of the workgroup calls it (it contains barriers).
+template <class PL>
+__device__ __forceinline__ void feat_block(const MixArgs& A, cf* Yv, cf* lds_raw, float* hist, const float* acc_rd,
+                                           float* acc_wr, int j, int bk, int nb, int B, int lmax, int lim,
+                                           long long fo, int cap, bool ok, int t_) {
+  using FP = PlanOf<9>;
+  using FL = FeatLds<PL>;
+  constexpr int T = PL::T, P = PL::P;
+  static_assert(FL::kCf <= max_lds_with_threads<T>(), "the stage and frame buffers fit the exchange area");
+  static_assert(XchWave<FP>::kEntries * 2 >= kMelBins + kMelCapMax, "the power spectrum fits a frame buffer");
+  const int t = opaque_v(t_);
+  constexpr int kDrop = 0x7ffffff0;  // beyond any resource's range
+  const rsrc_t rd = make_rsrc(acc_rd, (bk == 0 ? 0 : lmax - 1) * 4);
+  const rsrc_t wr = make_rsrc(acc_wr, (lmax - 1) * 4);
+#pragma unroll
+  for (int r = 0; r < P; ++r) {
+    const int n0 = 2 * (t + r * T);
+    const cf c = ld2(rd, 4 * n0);
+    Yv[r] = mk(Yv[r].x + c.x, Yv[r].y + c.y);
+    st2(wr, n0 >= B ? 4 * (n0 - B) : kDrop, Yv[r]);
+    st1(wr, n0 + 1 == B ? 0 : kDrop, Yv[r].y);
+  }
+  if (!ok) return;  // uniform
+  const int cnt = bk == nb - 1 ? lim : B;  // final samples of this block
+  float* stage = reinterpret_cast<float*>(lds_raw);
+  __syncthreads();  // the inverse transform's exchange reads are done
+  for (int k = t; k < kMelWin; k += T) stage[k] = hist[k];
+#pragma unroll
+  for (int r = 0; r < P; ++r) {
+    const int n0 = 2 * (t + r * T);
+    if (n0 < cnt) stage[kMelWin + n0] = Yv[r].x;
+    if (n0 + 1 < cnt) stage[kMelWin + n0 + 1] = Yv[r].y;
+  }
+  __syncthreads();
+  const int base = bk * B;
+  const int f_lo = mel_frames(base), f_hi = mel_frames(base + cnt);
+  const int g = t >> 5, l = t & 31;
+  XchWave<FP> xw{reinterpret_cast<cf*>(lds_raw) + FL::kStageCf + g * XchWave<FP>::kEntries};
+  float* pw = reinterpret_cast<float*>(xw.base);
+  if (f_lo + g < f_hi) {
+    const TwBase tw9 = Fft<FP>::bases(plan_tw<FP>(), l);
+    float w0[kMelCap0], w1[kMelCap1], w2[kMelCap2], w3[kMelCap3];
+    int first[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) first[k] = g_mel_first[l + 32 * k];
+#pragma unroll
+    for (int i = 0; i < kMelCap0; ++i) w0[i] = g_mel_w[(l + 0) * kMelCapMax + i];
+#pragma unroll
+    for (int i = 0; i < kMelCap1; ++i) w1[i] = g_mel_w[(l + 32) * kMelCapMax + i];
+#pragma unroll
+    for (int i = 0; i < kMelCap2; ++i) w2[i] = g_mel_w[(l + 64) * kMelCapMax + i];
+#pragma unroll
+    for (int i = 0; i < kMelCap3; ++i) w3[i] = g_mel_w[(l + 96) * kMelCapMax + i];
+    for (int f = f_lo + g; f < f_hi; f += FL::kGroups) {
+      // the frame's first sample in the stage
+      const int s0 = kMelHop * f - base + kMelWin;
+      cf v[FP::P];
+#pragma unroll
+      for (int r = 0; r < FP::P; ++r) {
+        const int k = 2 * (l + r * FP::T);
+        v[r] = mk(stage[s0 + k] * g_hann[k], stage[s0 + k + 1] * g_hann[k + 1]);
+      }
+      Fft<FP>::forward(v, xw, tw9, l);
+      Fft<FP>::post(v, tw9, l);  // 2 X
+      xw.sync();  // the transform's exchange reads are done before pw overwrites the buffer
+#pragma unroll
+      for (int q = 0; q < FP::P; ++q) {
+        if (l == 0 && q == Fft<FP>::SP) {
+          pw[0] = 0.25f * v[q].x * v[q].x;
+          pw[FP::M] = 0.25f * v[q].y * v[q].y;
+        } else {
+          pw[slot_bin<FP>(q, l)] = 0.25f * (v[q].x * v[q].x + v[q].y * v[q].y);
+        }
+      }
+      xw.sync();
+      float* out = A.feat + fo + ((long long)j * cap + f) * kMelBands;
+      const float m0 = mel_band<kMelCap0>(w0, pw, first[0]);
+      const float m1 = mel_band<kMelCap1>(w1, pw, first[1]);
+      const float m2 = mel_band<kMelCap2>(w2, pw, first[2]);
+      const float m3 = mel_band<kMelCap3>(w3, pw, first[3]);
+      out[l] = logf(m0 + 1e-6f);
+      out[l + 32] = logf(m1 + 1e-6f);
+      out[l + 64] = logf(m2 + 1e-6f);
+      out[l + 96] = logf(m3 + 1e-6f);
+      xw.sync();  // the band sums have read pw before the next frame's transform writes the buffer
+    }
+  }
+  __syncthreads();  // every frame has read the stage
+  for (int k = t; k < kMelWin; k += T) hist[k] = stage[cnt + k];
+  __syncthreads();  // before the exchange area serves the next transform
 }
 
 // An utterance's source and RIR descriptors, copied into LDS once per work
@@ -665,6 +848,18 @@ __device__ __forceinline__ UttDesc load_desc(const BatchDev& b, DescCache& c, in
   return UttDesc{b, c, s0, r0, fs, fr};
 }
 
+// The spectrum of one RIR block v (its taps, zero-padded) scaled by a, into
+// dst in the paired layout.
+template <class PL>
+__device__ __forceinline__ void rir_spectrum_store(cf* v, float a, cf* dst, Xch<PL>& lds, const TwBase& tw,
+                                                   int t) {
+  Fft<PL>::forward(v, lds, tw, t);
+  Fft<PL>::post(v, tw, t);
+#pragma unroll
+  for (int q = 0; q < PL::P; ++q) v[q] = mk(v[q].x * a, v[q].y * a);
+  store_spec_pair<PL>(dst, v, t);
+}
+
 // The RIR spectra of one utterance, once, scaled by alpha / (8M) (which also
 // carries the normalisation of the inverse transform); the next RIR is
 // requested while the current one is transformed.
@@ -692,22 +887,18 @@ __device__ __forceinline__ void rir_spectra(const MixArgs& A, const UttDesc& D, 
       const int kn = slot_of(k + 1);
       load_real<PL>(vn, A.h + D.rir_off(kn), D.rir_len(kn), t);
     }
-    Fft<PL>::forward(v, lds, tw, t);
-    Fft<PL>::post(v, tw, t);
     const int sl = slot_of(k);
-    const float a = A.alpha[r0 + sl] * cscale;
-#pragma unroll
-    for (int q = 0; q < P; ++q) v[q] = mk(v[q].x * a, v[q].y * a);
-    store_spec_pair<PL>(Hs + (long long)sl * M, v, t);
+    rir_spectrum_store<PL>(v, A.alpha[r0 + sl] * cscale, Hs + (long long)sl * M, lds, tw, t);
   }
 }
 
 // One utterance: RIR spectra, then the blocks.  Mics are processed in groups
 // of JG (1 or 2) accumulators; when J > JG the source spectra of the current
 // block are kept in the workgroup's scratch for the later mic groups.
-template <class PL, int JG, int MINW>
-__device__ __forceinline__ void mix_utterance(const MixArgs& A, int u, const Sched& S, int gsel, cf* lds_raw,
-                                              DescCache& dc, cf* slot, int t) {
+template <class PL, int JG, int MINW, bool FEAT>
+__device__ __forceinline__ void mix_utterance(const MixArgs& A, int u, const Sched& S, int gsel, int part,
+                                              int nparts, cf* lds_raw, DescCache& dc, cf* slot, float* s_hist,
+                                              int t) {
   constexpr int P = PL::P, M = PL::M;
   Xch<PL> lds{lds_raw, 0};
   const TwBase tw = Fft<PL>::bases(plan_tw<PL>(), t);
@@ -715,7 +906,12 @@ __device__ __forceinline__ void mix_utterance(const MixArgs& A, int u, const Sch
   const int I = uni(b.n_src[u]), J = b.J, NS = b.S, Nx = uni(b.src_len[u]);
   const int B = S.hop, nb = S.nb, tu = S.tu, lmax = S.lmax;
   const int span = B + lmax - 1;
-  cf* Hs = slot;
+  // this work item's blocks [b0, b1); a part p > 0 leaves its first block's
+  // head (below lmax - 1, which the previous part's last block covers with
+  // its tail) in its seam buffer
+  const int b0 = (int)((long long)nb * part / nparts), b1 = (int)((long long)nb * (part + 1) / nparts);
+  float* seam = part > 0 ? A.seam + ((long long)u * A.psplit + part) * J * A.mmax : nullptr;
+  cf* Hs = A.hspec ? A.hspec + (long long)u * NS * J * A.mmax : slot;
   cf* Xs = slot + (long long)NS * J * M;
   const int ng_all = (J + JG - 1) / JG;
   // mic groups of this work item: all, or the one group gsel; the source
@@ -725,7 +921,30 @@ __device__ __forceinline__ void mix_utterance(const MixArgs& A, int u, const Sch
   const bool cache = ng > 1;
 
   const UttDesc D = load_desc(b, dc, u, I, t, PL::T);
-  rir_spectra<PL>(A, D, u, I, glo * JG, min(J, ghi * JG), Hs, lds, tw, t);
+  if (!A.hspec) rir_spectra<PL>(A, D, u, I, glo * JG, min(J, ghi * JG), Hs, lds, tw, t);
+
+  // The fused front end: its features' place, and per mic two overlap-add
+  // accumulators of 2 mmax samples at the end of the workgroup's slot.
+  long long fo = 0;
+  int cap = 0;
+  bool fok = false;
+  float* accb = nullptr;
+  if constexpr (FEAT) {
+    fo = uni64(A.feat_off[u]);
+    cap = mel_frames(uni(b.out_stride[u]));
+    fok = tu < kMelMaxT && J <= kFeatMics && fo >= 0 && fo + (long long)J * cap * kMelBands <= A.feat_len;
+    if (!fok && t == 0 && glo == 0) flag_status(RSIM_DEV_BADDESC);
+    accb = reinterpret_cast<float*>(slot + A.slot_cf - 2LL * J * A.mmax);
+  }
+  auto feat_emit = [&](cf* Yv, int j, int bk, int lim) __attribute__((always_inline)) {
+    if constexpr (FEAT) {
+      Fft<PL>::pre(Yv, tw, t);
+      Fft<PL>::inverse(Yv, lds, tw, t);
+      float* a0 = accb + (long long)(2 * j) * 2 * A.mmax;
+      feat_block<PL>(A, Yv, lds_raw, s_hist + j * kMelWin, a0 + ((bk & 1) ^ 1) * 2 * A.mmax,
+                     a0 + (bk & 1) * 2 * A.mmax, j, bk, nb, B, lmax, lim, fo, cap, fok, t);
+    }
+  };
 
   const long long yo = uni64(b.out_off[u]);
   const long long ys = uni(b.out_stride[u]);
@@ -763,13 +982,13 @@ __device__ __forceinline__ void mix_utterance(const MixArgs& A, int u, const Sch
     {
       const float* src;
       int nv;
-      input_of(0, glo, 0, src, nv);
+      input_of(b0, glo, 0, src, nv);
       load_real<PL>(Xn, src, nv, t);
     }
-    for (int bk = 0; bk < nb; ++bk) {
+    for (int bk = b0; bk < b1; ++bk) {
       const int base = bk * B;
       const int lim = min(span, tu - base);
-      const int carry = bk == 0 ? 0 : lmax - 1;
+      const int carry = bk == b0 ? 0 : lmax - 1;
       for (int g = glo; g < ghi; ++g) {
         const int j0 = g * JG;
         const bool two = JG == 2 && j0 + 1 < J;
@@ -802,7 +1021,7 @@ __device__ __forceinline__ void mix_utterance(const MixArgs& A, int u, const Sch
           bool fetch = true;
           if (i + 1 < I) input_of(bk, g, i + 1, fsrc, fn);
           else if (g + 1 < ghi && !hand_over) input_of(bk, g + 1, 0, fsrc, fn);
-          else if (g + 1 >= ghi && bk + 1 < nb) input_of(bk + 1, glo, 0, fsrc, fn);
+          else if (g + 1 >= ghi && bk + 1 < b1) input_of(bk + 1, glo, 0, fsrc, fn);
           else fetch = false;
           if (fetch) load_real<PL>(Xn, fsrc, fn, t);
           if (g == glo) {
@@ -824,7 +1043,18 @@ __device__ __forceinline__ void mix_utterance(const MixArgs& A, int u, const Sch
         // transform, so their latency is hidden; longer ones are read after.
         float* y0 = A.y + yo + (long long)j0 * ys + base;
         constexpr int CR = P / 4;
-        if (carry <= 2 * PL::T * CR) {
+        if constexpr (FEAT) {
+          feat_emit(Y0, j0, bk, lim);
+          if constexpr (JG == 2) {
+            if (two) feat_emit(Y1, j0 + 1, bk, lim);
+          }
+        } else if (seam && bk == b0) {
+          float* s0 = seam + (long long)j0 * A.mmax;
+          emit_seam<PL>(Y0, lds, tw, y0, s0, lim, lmax - 1, t);
+          if constexpr (JG == 2) {
+            if (two) emit_seam<PL>(Y1, lds, tw, y0 + ys, s0 + A.mmax, lim, lmax - 1, t);
+          }
+        } else if (carry <= 2 * PL::T * CR) {
           cf C0[CR], C1[CR];
           load_carry<PL, CR>(C0, y0, lim, carry, t);
           if constexpr (JG == 2) {
@@ -843,11 +1073,12 @@ __device__ __forceinline__ void mix_utterance(const MixArgs& A, int u, const Sch
       }
     }
   } else {
-    for (int bk = 0; bk < nb; ++bk) {
+    static_assert(!FEAT, "the fused front end runs on the prefetching path");
+    for (int bk = b0; bk < b1; ++bk) {
       const int base = bk * B;
       const int nvalid = min(B, Nx - base);
       const int lim = min(span, tu - base);
-      const int carry = bk == 0 ? 0 : lmax - 1;
+      const int carry = bk == b0 ? 0 : lmax - 1;
       for (int g = glo; g < ghi; ++g) {
         const int j0 = g * JG;
         const bool two = JG == 2 && j0 + 1 < J;
@@ -876,9 +1107,18 @@ __device__ __forceinline__ void mix_utterance(const MixArgs& A, int u, const Sch
             mac<PL>(Y0, H0, X, t);
           }
         }
-        emit<PL>(Y0, lds, tw, A.y + yo + (long long)j0 * ys + base, lim, carry, t);
-        if constexpr (JG == 2) {
-          if (two) emit<PL>(Y1, lds, tw, A.y + yo + (long long)(j0 + 1) * ys + base, lim, carry, t);
+        if (seam && bk == b0) {
+          float* s0 = seam + (long long)j0 * A.mmax;
+          emit_seam<PL>(Y0, lds, tw, A.y + yo + (long long)j0 * ys + base, s0, lim, lmax - 1, t);
+          if constexpr (JG == 2) {
+            if (two)
+              emit_seam<PL>(Y1, lds, tw, A.y + yo + (long long)(j0 + 1) * ys + base, s0 + A.mmax, lim, lmax - 1, t);
+          }
+        } else {
+          emit<PL>(Y0, lds, tw, A.y + yo + (long long)j0 * ys + base, lim, carry, t);
+          if constexpr (JG == 2) {
+            if (two) emit<PL>(Y1, lds, tw, A.y + yo + (long long)(j0 + 1) * ys + base, lim, carry, t);
+          }
         }
       }
     }
@@ -888,18 +1128,19 @@ __device__ __forceinline__ void mix_utterance(const MixArgs& A, int u, const Sch
 // Persistent workgroups: pop the next utterance of this family's list until
 // it is exhausted.  MINW is the number of waves per SIMD the register budget
 // is sized for (2 with one mic accumulator, 1 with two).
-template <int T, int JG, int MINW>
+template <int T, int JG, int MINW, bool FEAT = false>
 __global__ __launch_bounds__(T, MINW) void mix_kernel(MixArgs A) {
   __shared__ cf lds[max_lds_with_threads<T>()];
   __shared__ DescCache s_desc;
   __shared__ int s_idx;
+  __shared__ float s_hist[FEAT ? kFeatMics * kMelWin : 1];
   const int t = threadIdx.x;
   cf* slot = A.scratch + (long long)blockIdx.x * A.slot_cf;
   // The first item of workgroup b is item b; later ones are popped from the
   // family's counter (offset by the grid), so an empty family costs one load
   // per workgroup and no atomic.
-  const int gs = A.gsplit;
-  const int count = __builtin_amdgcn_readfirstlane(A.hdr->count[A.fam]) * gs;
+  const int gs = A.gsplit, ps = A.psplit, per = gs * ps;
+  const int count = __builtin_amdgcn_readfirstlane(A.hdr->count[A.fam]) * per;
   for (int first = 1;; first = 0) {
     __syncthreads();
     if (t == 0) s_idx = first ? (int)blockIdx.x : (int)gridDim.x + atomicAdd(&A.hdr->counter[A.fam], 1);
@@ -908,7 +1149,8 @@ __global__ __launch_bounds__(T, MINW) void mix_kernel(MixArgs A) {
     // descriptor loads scalar and the buffer resources in scalar registers.
     const int idx = __builtin_amdgcn_readfirstlane(s_idx);
     if (idx >= count) break;
-    const int pos = idx / gs, gsel = gs > 1 ? idx - pos * gs : -1;
+    const int pos = idx / per, rem = idx - pos * per;
+    const int gsel = gs > 1 ? rem / ps : -1, part = rem % ps;
     const int u = __builtin_amdgcn_readfirstlane(A.list[(long long)A.fam * A.b.U + pos]);
     Sched S = A.sched[u];
     S.log2n = __builtin_amdgcn_readfirstlane(S.log2n);
@@ -916,11 +1158,70 @@ __global__ __launch_bounds__(T, MINW) void mix_kernel(MixArgs A) {
     S.nb = __builtin_amdgcn_readfirstlane(S.nb);
     S.tu = __builtin_amdgcn_readfirstlane(S.tu);
     S.lmax = __builtin_amdgcn_readfirstlane(S.lmax);
+    const int nparts = mix_parts(ps, S);
+    if (part >= nparts) continue;
     dispatch_plan<T>(S.log2n, [&](auto pl) __attribute__((always_inline)) {
       using PL = decltype(pl);
       // a group past the utterance's mics has no work
-      if (gsel * JG < A.b.J) mix_utterance<PL, JG, MINW>(A, u, S, gsel, lds, s_desc, slot, t);
+      if (gsel * JG < A.b.J) mix_utterance<PL, JG, MINW, FEAT>(A, u, S, gsel, part, nparts, lds, s_desc, slot, s_hist, t);
     });
+  }
+}
+
+// First pass of a block-split mix: the spectrum of every RIR slot of the
+// family's utterances, scaled by alpha / (8M), into A.hspec (one work item
+// per slot), the same operations as the unsplit kernel's, so the parts share
+// bit-identical spectra.
+template <int T>
+__global__ __launch_bounds__(T, 2) void mix_rir_kernel(MixArgs A) {
+  __shared__ cf lds_raw[max_lds_with_threads<T>()];
+  const int t = threadIdx.x;
+  const BatchDev& b = A.b;
+  const int NS = b.S, J = b.J;
+  const long long per = (long long)NS * J;
+  const long long items = (long long)__builtin_amdgcn_readfirstlane(A.hdr->count[A.fam]) * per;
+  for (long long k = blockIdx.x; k < items; k += gridDim.x) {
+    const int pos = (int)(k / per), i = (int)((k % per) / J), j = (int)(k % J);
+    const int u = __builtin_amdgcn_readfirstlane(A.list[(long long)A.fam * b.U + pos]);
+    const int log2n = __builtin_amdgcn_readfirstlane(A.sched[u].log2n);
+    if (i >= uni(b.n_src[u])) continue;
+    const long long r = ((long long)u * NS + i) * J + j;
+    dispatch_plan<T>(log2n, [&](auto pl) __attribute__((always_inline)) {
+      using PL = decltype(pl);
+      Xch<PL> lds{lds_raw, 0};
+      const TwBase tw = Fft<PL>::bases(plan_tw<PL>(), t);
+      cf v[PL::P];
+      load_real<PL>(v, A.h + uni64(b.rir_off[r]), uni(b.rir_len[r]), t);
+      const float cscale = 1.0f / (8.0f * (float)PL::M);
+      rir_spectrum_store<PL>(v, A.alpha[r] * cscale, A.hspec + (long long)u * per * A.mmax + (long long)(i * J + j) * PL::M,
+                             lds, tw, t);
+    });
+  }
+}
+
+// Last pass of a block-split mix: for every part p > 0 of an utterance and
+// every mic, the head its first block left in the seam buffer is added to
+// the tail the previous part's last block stored in y.  The two operands are
+// the ones the unsplit kernel adds (in the other order; the sum is the same),
+// so the outputs are bit-identical to the unsplit kernel's.
+constexpr int kSeamThreads = 256;
+__global__ __launch_bounds__(kSeamThreads) void mix_seam_kernel(MixArgs A) {
+  const BatchDev& b = A.b;
+  const int J = b.J, ps = A.psplit;
+  const long long per = (long long)ps * J;
+  const long long items = (long long)A.hdr->count[A.fam] * per;
+  for (long long k = blockIdx.x; k < items; k += gridDim.x) {
+    const int pos = (int)(k / per), part = (int)((k % per) / J), j = (int)(k % J);
+    const int u = A.list[(long long)A.fam * b.U + pos];
+    const Sched S = A.sched[u];
+    const int nparts = mix_parts(ps, S);
+    if (part == 0 || part >= nparts) continue;
+    const int b0 = (int)((long long)S.nb * part / nparts);
+    const int base = b0 * S.hop;
+    const int h = min(S.lmax - 1, S.tu - base);
+    float* y = A.y + b.out_off[u] + (long long)j * b.out_stride[u] + base;
+    const float* sm = A.seam + (((long long)u * ps + part) * J + j) * A.mmax;
+    for (int n = threadIdx.x; n < h; n += kSeamThreads) y[n] = y[n] + sm[n];
   }
 }
 
@@ -2172,20 +2473,8 @@ __global__ __launch_bounds__(kFfStepThreads) void ff_step_kernel(FfStep S) {
   }
 }
 
-// ================================================= FFT engine test kernels
-// Bin held by slot q of thread t (thread 0 permuted as in Fft::perm_t0; its
-// slot SP holds bins 0 and N/2).
-template <class PL>
-__device__ __forceinline__ int slot_bin(int q, int t) {
-  constexpr int R = PL::RL, T = PL::T;
-  if (t != 0) return q < R ? t + 2 * T * q : (2 * T - t) + 2 * T * (q - R);
-  if (q < R / 2) return T + 2 * T * q;
-  if (q < R) return 2 * T * q;
-  if (q < 3 * R / 2 - 1) return 2 * T * (q - R + 1);
-  if (q == 3 * R / 2 - 1) return 0;
-  return T + 2 * T * (q - R);
-}
 
+// ================================================= FFT engine test kernels
 template <class PL>
 __global__ __launch_bounds__(PL::T) void rfft_kernel(const float* __restrict__ x, float* __restrict__ spec) {
   __shared__ cf lds_raw[Xch<PL>::kEntries];
@@ -2253,7 +2542,6 @@ __global__ __launch_bounds__(PL::T) void irfft_kernel(const float* __restrict__ 
 // have compile-time trip counts (the widest band of each quarter), so all
 // power reads of a frame are in flight together.
 constexpr int kMelGroups = 2;  // one wave: its barriers cost little
-constexpr int kMelMaxT = 1 << 29;  // mic signals shorter than this (byte offsets fit 31 bits)
 constexpr int kMelChunksPerItem = 16;
 
 struct MelArgs {
@@ -2264,24 +2552,6 @@ struct MelArgs {
   long long feat_len;
   int chunks;                 // chunks of kMelGroups frames per (utterance, mic), at most
 };
-
-__device__ __forceinline__ int mel_frames(int T) { return T >= kMelWin ? 1 + (T - kMelWin) / kMelHop : 0; }
-
-// Band energy sum_i w[i] pw[first + i] over i < CAP, in bin order; the
-// weights past the band's bins are zero, so for finite powers those terms
-// add exactly nothing.  (A non-finite power can also make the bands whose
-// padded range covers it NaN; with the full filterbank matrix it makes
-// every band NaN.)
-template <int CAP>
-__device__ __forceinline__ float mel_band(const float* w, const float* pw, int first) {
-  float p[CAP];
-#pragma unroll
-  for (int i = 0; i < CAP; ++i) p[i] = pw[first + i];
-  float m = 0.f;
-#pragma unroll
-  for (int i = 0; i < CAP; ++i) m = __builtin_fmaf(w[i], p[i], m);
-  return m;
-}
 
 __global__ __launch_bounds__(kMelGroups * 32) void logmel_kernel(MelArgs A) {
   using PL = PlanOf<9>;
@@ -2463,6 +2733,7 @@ struct DevState {
   int cus = 0;
   int occ[kNumVar][kNumFam] = {};  // [variant][family]
   int occ_bwd[kNumFam] = {};
+  int occ_feat[kNumFam] = {};  // mix kernels with the fused front end (families 2-4)
   // Side streams (default priority) and events that let the family kernels
   // of one call run concurrently: the tail of one family overlaps the next.
   static constexpr int kSide = kNumFam;  // a call issues at most kNumFam + 1 parallel kernels
@@ -2526,6 +2797,16 @@ const void* energy_kernel_ptr(int fam) {
     default: return reinterpret_cast<const void*>(&energy_kernel<1024>);
   }
 }
+const void* mix_rir_kernel_ptr(int fam) {
+  switch (fam) {
+    case 0: return reinterpret_cast<const void*>(&mix_rir_kernel<32>);
+    case 1: return reinterpret_cast<const void*>(&mix_rir_kernel<64>);
+    case 2: return reinterpret_cast<const void*>(&mix_rir_kernel<128>);
+    case 3: return reinterpret_cast<const void*>(&mix_rir_kernel<256>);
+    case 4: return reinterpret_cast<const void*>(&mix_rir_kernel<512>);
+    default: return reinterpret_cast<const void*>(&mix_rir_kernel<1024>);
+  }
+}
 const void* bwd_finish_kernel_ptr(int fam) {
   switch (fam) {
     case 0: return reinterpret_cast<const void*>(&bwd_finish_kernel<32>);
@@ -2534,6 +2815,18 @@ const void* bwd_finish_kernel_ptr(int fam) {
     case 3: return reinterpret_cast<const void*>(&bwd_finish_kernel<256>);
     case 4: return reinterpret_cast<const void*>(&bwd_finish_kernel<512>);
     default: return reinterpret_cast<const void*>(&bwd_finish_kernel<1024>);
+  }
+}
+// Families with a fused front-end kernel (N = 4096, 8192, 16384), and its
+// variant (two mics per pass, registers for one wave per SIMD).
+constexpr bool feat_family(int fam) { return fam >= 2 && fam <= 4; }
+constexpr int kFeatVar = 1;
+const void* mix_feat_kernel_ptr(int fam) {
+  switch (fam) {
+    case 2: return reinterpret_cast<const void*>(&mix_kernel<128, 2, 1, true>);
+    case 3: return reinterpret_cast<const void*>(&mix_kernel<256, 2, 1, true>);
+    case 4: return reinterpret_cast<const void*>(&mix_kernel<512, 2, 1, true>);
+    default: return nullptr;
   }
 }
 const void* mix_kernel_ptr(int fam, int var) {
@@ -2613,6 +2906,12 @@ rsim_status init_locked(int dev) {
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, bwd_kernel_ptr(f), kFamT[f], 0) != hipSuccess)
       return RSIM_EDEVICE;
     st.occ_bwd[f] = n > 0 ? n : 1;
+    if (feat_family(f)) {
+      n = 0;
+      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, mix_feat_kernel_ptr(f), kFamT[f], 0) != hipSuccess)
+        return RSIM_EDEVICE;
+      st.occ_feat[f] = n > 0 ? n : 1;
+    }
   }
   if (!st.fork) {
     if (hipEventCreateWithFlags(&st.fork, hipEventDisableTiming) != hipSuccess) return RSIM_EDEVICE;
@@ -2671,6 +2970,10 @@ TuneDev default_tune() {
   return t;
 }
 
+// The tune table of the fused front end: only the sizes with a fused kernel
+// (N = 4096, 8192, 16384) stay enabled, each family with its one variant.
+TuneDev feat_tune(const rsim_tune* tune);
+
 // A tune table is valid when every cost is finite and non-negative and every
 // variant code is 0 (the default) or 1..4.
 bool tune_ok(const rsim_tune* tune) {
@@ -2697,6 +3000,16 @@ TuneDev to_dev(const rsim_tune* tune) {
   return t;
 }
 
+TuneDev feat_tune(const rsim_tune* tune) {
+  TuneDev td = to_dev(tune);
+  for (int m = 9; m <= 15; ++m)
+    if (!feat_family(family_of_log2n(m))) td.cost_fft[m - 9] = td.cost_mac[m - 9] = 0.f;
+  for (int f = 0; f < kNumFam; ++f)
+    if (feat_family(f)) td.variant[f] = kFeatVar;
+  return td;
+}
+constexpr int kFeatSizeBits = (1 << 12) | (1 << 13) | (1 << 14);
+
 // Families that may receive work.
 void families_used(const rsim_batch* b, const TuneDev& td, bool used[kNumFam]) {
   for (int f = 0; f < kNumFam; ++f) used[f] = false;
@@ -2709,6 +3022,8 @@ void families_used(const rsim_batch* b, const TuneDev& td, bool used[kNumFam]) {
 struct WsLayout {
   size_t hdr, sched, lists, costs, scratch, total;
   int gsplit[kNumFam];          // forward: work items per utterance (mic groups)
+  int psplit[kNumFam];          // forward: block ranges per (utterance, mic group)
+  size_t fam_seam[kNumFam];     // forward: byte offset of each family's seam buffers (psplit > 1)
   int nsplit;                   // adjoint: parts per utterance
   size_t fam_partial[kNumFam];  // adjoint: byte offset of each family's part spectra (nsplit > 1)
   size_t fam_hspec[kNumFam];    // adjoint: byte offset of each family's shared RIR spectra (nsplit > 1)
@@ -2730,7 +3045,8 @@ bool batch_ok(const rsim_batch* b) {
 // shrunk in proportion (at least one workgroup each; the kernels pop work
 // items until their list is empty, so any grid size is correct).  The result
 // then has total > cap only when even that does not fit.
-WsLayout layout(const rsim_batch* b, const TuneDev& td, bool backward, const DevState& st, size_t cap = 0) {
+WsLayout layout(const rsim_batch* b, const TuneDev& td, bool backward, const DevState& st, size_t cap = 0,
+                bool feat = false) {
   WsLayout L;
   const size_t U = (size_t)b->n_utt;
   L.hdr = 0;
@@ -2754,25 +3070,44 @@ WsLayout layout(const rsim_batch* b, const TuneDev& td, bool backward, const Dev
     // them than compute units (each group then transforms the sources itself).
     const int ngf = (int)((J + mic_group(f, td) - 1) / mic_group(f, td));
     L.gsplit[f] = !backward && U > 0 && (size_t)cus > U && ngf > 1 ? ngf : 1;
-    const size_t items = U * (size_t)(backward ? L.nsplit : L.gsplit[f]);
+    // With still fewer work items than compute units, each (utterance, mic
+    // group) is split into block ranges too (up to 16, one per block at
+    // most): its RIR spectra then come from a pass of their own and the
+    // work items need no scratch slot.  Not with a cap on the workspace (the
+    // allocation-free entry keeps the smaller footprint of the unsplit form)
+    // nor with the fused front end.
+    L.psplit[f] = 1;
+    if (!backward && !feat && cap == 0 && U > 0) {
+      const size_t base_items = U * (size_t)L.gsplit[f];
+      if (base_items < (size_t)cus) L.psplit[f] = (int)std::min<size_t>(16, (cus + base_items - 1) / base_items);
+    }
+    const size_t items = U * (size_t)(backward ? L.nsplit : L.gsplit[f] * L.psplit[f]);
     const long long spectra =
-        backward ? (2 * S * J + 2 * J) : (S * J + (J > mic_group(f, td) && L.gsplit[f] == 1 ? S : 0));
-    L.slot_cf[f] = spectra * M;
+        backward ? (2 * S * J + 2 * J)
+                 : (L.psplit[f] > 1 ? 0 : S * J + (J > mic_group(f, td) && L.gsplit[f] == 1 ? S : 0));
+    // the fused front end's two overlap-add accumulators of 2 M samples per mic
+    L.slot_cf[f] = spectra * M + (feat ? 2 * J * M : 0);
     // the largest occupancy used without a device; at most 8 workgroups per
     // CU and one per work item
-    int occ = st.init ? (backward ? st.occ_bwd[f] : st.occ[td.variant[f]][f]) : 8;
+    int occ = st.init ? (backward ? st.occ_bwd[f] : feat ? st.occ_feat[f] : st.occ[td.variant[f]][f]) : 8;
     if (occ > 8) occ = 8;
     long long g = (long long)cus * occ;
     if (g > (long long)items) g = (long long)items;
     if (g < 1) g = 1;
     L.grid[f] = (int)g;
   }
+  // the block split's shared RIR spectra and seam buffers (fixed sizes)
+  size_t split_bytes = 0;
+  for (int f = 0; f < kNumFam; ++f)
+    if (used[f] && !backward && L.psplit[f] > 1)
+      split_bytes += align256(U * (size_t)(S * J) * (size_t)kFamMaxM[f] * sizeof(cf)) +
+                     align256(U * (size_t)L.psplit[f] * (size_t)J * (size_t)kFamMaxM[f] * sizeof(float));
   if (cap > 0 && !backward) {
     size_t want = 0;
     for (int f = 0; f < kNumFam; ++f)
       if (used[f]) want += align256((size_t)L.grid[f] * (size_t)L.slot_cf[f] * sizeof(cf));
-    if (off + want > cap) {
-      const size_t room = cap > off ? cap - off : 0;
+    if (off + split_bytes + want > cap) {
+      const size_t room = cap > off + split_bytes ? cap - off - split_bytes : 0;
       for (int f = 0; f < kNumFam; ++f) {
         if (!used[f]) continue;
         const size_t per = (size_t)L.slot_cf[f] * sizeof(cf);
@@ -2791,11 +3126,15 @@ WsLayout layout(const rsim_batch* b, const TuneDev& td, bool backward, const Dev
     if (used[f]) off += align256((size_t)L.grid[f] * (size_t)L.slot_cf[f] * sizeof(cf));
   }
   for (int f = 0; f < kNumFam; ++f) {
+    const bool split = backward ? L.nsplit > 1 : L.psplit[f] > 1;
     L.fam_partial[f] = off;
-    if (used[f] && L.nsplit > 1)
+    if (used[f] && backward && L.nsplit > 1)
       off += align256(U * (size_t)L.nsplit * (size_t)(S * J) * (size_t)kFamMaxM[f] * sizeof(cf));
     L.fam_hspec[f] = off;
-    if (used[f] && L.nsplit > 1) off += align256(U * (size_t)(S * J) * (size_t)kFamMaxM[f] * sizeof(cf));
+    if (used[f] && split) off += align256(U * (size_t)(S * J) * (size_t)kFamMaxM[f] * sizeof(cf));
+    L.fam_seam[f] = off;
+    if (used[f] && !backward && L.psplit[f] > 1)
+      off += align256(U * (size_t)L.psplit[f] * (size_t)J * (size_t)kFamMaxM[f] * sizeof(float));
   }
   L.total = off;
   return L;
@@ -3023,10 +3362,18 @@ rsim_status issue(CallPlan& P, hipStream_t s, int use_graph) {
 }
 
 // Records the schedule and family kernels of a mix into P.
+// The fused front end's features (rsim_simulate_logmel): where they go.
+struct FeatOut {
+  float* feat = nullptr;
+  const int64_t* off = nullptr;
+  long long len = 0;
+};
+
 void plan_mix(CallPlan& P, const rsim_batch* b, const BatchDev& bd, const TuneDev& td, const float* x,
-              const float* h, const float* alpha, float* y, void* ws, int only_fam = -1, size_t cap = 0) {
+              const float* h, const float* alpha, float* y, void* ws, int only_fam = -1, size_t cap = 0,
+              const FeatOut* fe = nullptr) {
   const DevState& st = dev_state();
-  const WsLayout L = layout(b, td, false, st, cap);
+  const WsLayout L = layout(b, td, false, st, cap, fe != nullptr);
   char* base = static_cast<char*>(ws);
   SchedArgs SA;
   SA.b = bd;
@@ -3061,7 +3408,26 @@ void plan_mix(CallPlan& P, const rsim_batch* b, const BatchDev& bd, const TuneDe
     A.scratch = reinterpret_cast<cf*>(base + L.fam_scratch[f]);
     A.slot_cf = L.slot_cf[f];
     A.gsplit = L.gsplit[f];
-    P.fam[P.nf++].set(mix_kernel_ptr(f, td.variant[f]), dim3(L.grid[f]), dim3(kFamT[f]), A);
+    A.psplit = L.psplit[f];
+    A.mmax = kFamMaxM[f];
+    A.hspec = L.psplit[f] > 1 ? reinterpret_cast<cf*>(base + L.fam_hspec[f]) : nullptr;
+    A.seam = L.psplit[f] > 1 ? reinterpret_cast<float*>(base + L.fam_seam[f]) : nullptr;
+    A.feat = fe ? fe->feat : nullptr;
+    A.feat_off = fe ? reinterpret_cast<const long long*>(fe->off) : nullptr;
+    A.feat_len = fe ? fe->len : 0;
+    P.has_pre[P.nf] = P.has_post[P.nf] = L.psplit[f] > 1;
+    if (L.psplit[f] > 1) {
+      const long long slots = (long long)b->n_utt * b->max_src * b->n_mic;
+      const int cus = st.cus > 0 ? st.cus : 256;
+      P.pre[P.nf].set(mix_rir_kernel_ptr(f), dim3((unsigned)std::min<long long>(slots, (long long)cus * 2)),
+                      dim3(kFamT[f]), A);
+      const long long seams = (long long)b->n_utt * L.psplit[f] * b->n_mic;
+      P.post[P.nf].set(reinterpret_cast<const void*>(&mix_seam_kernel),
+                       dim3((unsigned)std::max<long long>(1, std::min<long long>(seams, (long long)cus * 4))),
+                       dim3(kSeamThreads), A);
+    }
+    P.fam[P.nf++].set(fe ? mix_feat_kernel_ptr(f) : mix_kernel_ptr(f, td.variant[f]), dim3(L.grid[f]),
+                      dim3(kFamT[f]), A);
   }
 }
 
@@ -3322,6 +3688,43 @@ rsim_status rsim_simulate_static(const rsim_batch* b, const float* x, const floa
   plan_truncate(P.cut, h, bb.h_len, bb.rir_off, bb.rir_len0, (int)n_rir, cut_scale(eta_db), nullptr, rir_len_out);
   plan_mix(P, &bb, bd, td, x, h, alpha, y, st.static_ws, -1, cap);
   return issue(P, stream, 0);
+}
+
+size_t rsim_simulate_logmel_workspace_bytes(const rsim_batch* b, const rsim_tune* tune) {
+  if (!batch_ok(b) || !tune_ok(tune)) return 0;
+  (void)ensure_init(nullptr);
+  return layout(b, feat_tune(tune), false, dev_state(), 0, true).total;
+}
+
+rsim_status rsim_simulate_logmel(const rsim_batch* b, const float* x, const float* h, const float* alpha,
+                                 double eta_db, int32_t* rir_len_out, float* feat, const int64_t* feat_off,
+                                 int64_t feat_len, void* ws, size_t ws_bytes, const rsim_tune* tune,
+                                 int32_t use_graph, hipStream_t stream) {
+  if (!b || !eta_ok(eta_db) || !rir_len_out || !tune_ok(tune) || feat_len < 0) return RSIM_EINVAL;
+  rsim_batch bb = *b;
+  bb.rir_len = rir_len_out;
+  if (!batch_ok(&bb)) return RSIM_EINVAL;
+  if (bb.n_utt == 0) return RSIM_OK;
+  if (!x || !h || !alpha || !feat || !feat_off) return RSIM_EINVAL;
+  if (bb.n_mic > kFeatMics) return RSIM_EUNSUPPORTED;
+  if (bb.fft_log2n && (bb.fft_sizes == 0 || (bb.fft_sizes & ~kFeatSizeBits))) return RSIM_EUNSUPPORTED;
+  const long long n_rir = (long long)bb.n_utt * bb.max_src * bb.n_mic;
+  if (n_rir > 0x7fffffffLL) return RSIM_EINVAL;
+  const rsim_status e = ensure_init(stream);
+  const TuneDev td = feat_tune(tune);
+  const WsLayout L = layout(&bb, td, false, dev_state(), 0, true);
+  if (!ws || ws_bytes < L.total) return RSIM_EWORKSPACE;
+  if (e != RSIM_OK) return e;
+  const BatchDev bd = to_dev(&bb);
+  CallPlan P;
+  P.has_cut = true;
+  plan_truncate(P.cut, h, bb.h_len, bb.rir_off, bb.rir_len0, (int)n_rir, cut_scale(eta_db), nullptr, rir_len_out);
+  FeatOut fe;
+  fe.feat = feat;
+  fe.off = feat_off;
+  fe.len = feat_len;
+  plan_mix(P, &bb, bd, td, x, h, alpha, nullptr, ws, -1, 0, &fe);
+  return issue(P, stream, use_graph);
 }
 
 size_t rsim_ola_workspace_bytes(int32_t fft_n) {

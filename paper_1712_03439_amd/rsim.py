@@ -27,7 +27,7 @@ EXPORTS = (
     "rsim_simulate", "rsim_mix_backward", "rsim_source_power", "rsim_snr_gains",
     "rsim_device_status", "rsim_rfft", "rsim_irfft", "rsim_image_rir", "rsim_simulate_rooms",
     "rsim_reverb_energy", "rsim_snr_gains_reverb", "rsim_logmel", "rsim_fft_filter_workspace_bytes",
-    "rsim_fft_filter", "rsim_simulate_static",
+    "rsim_fft_filter", "rsim_simulate_static", "rsim_simulate_logmel_workspace_bytes", "rsim_simulate_logmel",
 )
 
 
@@ -93,6 +93,8 @@ def _lib():
             "rsim_fft_filter_workspace_bytes": ([bp, i32, i32], sz),
             "rsim_fft_filter": ([bp, vp, vp, vp, vp, i32, i32, vp, sz, vp], i32),
             "rsim_simulate_static": ([bp, vp, vp, vp, f64, vp, vp, tp, vp], i32),
+            "rsim_simulate_logmel_workspace_bytes": ([bp, tp], sz),
+            "rsim_simulate_logmel": ([bp, vp, vp, vp, f64, vp, vp, vp, i64, vp, sz, tp, i32, vp], i32),
         }
         for name, (args, res) in sig.items():
             fn = getattr(lib, name)
@@ -299,6 +301,38 @@ def logmel(db: DeviceBatch, y, stream=None):
     s = db.struct()
     _check(_lib().rsim_logmel(ctypes.byref(s), _ptr(y), _ptr(feat), _ptr(db.mel_off), int(feat.numel()),
                               int(cap.max()) if cap.size else 0, _stream(stream)), "rsim_logmel")
+    return feat, off, cap
+
+
+def feature_layout(db: DeviceBatch):
+    """(off, cap, total) of the features of every (utterance, mic): frame t
+    of (u, j) at off[u] + (j cap[u] + t) * 128, cap[u] the frames of
+    out_stride[u] samples."""
+    cap = mel_frames(db.host.out_stride)
+    sizes = cap * db.J * MEL_BANDS
+    off = np.concatenate([[0], np.cumsum(sizes)[:-1]]).astype(np.int64)
+    return off, cap, int(sizes.sum())
+
+
+def simulate_logmel(db: DeviceBatch, alpha, eta_db: float, feat=None, ws=None, tune: Optional[RsimTune] = None,
+                    use_graph: bool = False, stream=None):
+    """Cut + mix of one epoch with the log-Mel front end fused into the mix
+    (rsim_simulate_logmel): the features of every mic output, no y.  Returns
+    (feat, off, cap) as logmel()."""
+    torch = _torch()
+    _require_cuda(alpha)
+    off, cap, total = feature_layout(db)
+    if feat is None:
+        feat = torch.empty(max(total, 1), dtype=torch.float32, device=db.device)
+    db.mel_off = torch.from_numpy(off).to(db.device)
+    s = db.struct()
+    if ws is None:
+        n = int(_lib().rsim_simulate_logmel_workspace_bytes(ctypes.byref(s), ctypes.byref(tune) if tune else None))
+        ws = torch.empty(max(n, 1), dtype=torch.uint8, device=db.device)
+    _check(_lib().rsim_simulate_logmel(ctypes.byref(s), _ptr(db.x), _ptr(db.h), _ptr(alpha), float(eta_db),
+                                       _ptr(db.rir_len), _ptr(feat), _ptr(db.mel_off), int(feat.numel()),
+                                       _ptr(ws), int(ws.numel()), ctypes.byref(tune) if tune else None,
+                                       int(bool(use_graph)), _stream(stream)), "rsim_simulate_logmel")
     return feat, off, cap
 
 

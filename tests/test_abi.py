@@ -186,9 +186,11 @@ def test_tune_table_layout_and_validation():
 
 def test_variant_sets_the_mic_split_of_the_workspace():
     # with fewer utterances than compute units, one mic per pass splits an
-    # utterance of two mics into two work items; two mics per pass do not
+    # utterance of two mics into two work items (400 items, each with a
+    # scratch slot); two mics per pass do not, and its 200 items are split
+    # into block ranges instead (shared RIR spectra and seam buffers)
     lib = rsim.lib()
-    b = _host_batch(U=3, J=2)
+    b = _host_batch(U=200, J=2)
     f, m = [2.5 * (1 << k) * k for k in range(9, 16)], [8.0 * ((1 << k) / 2 + 1) for k in range(9, 16)]
     one = lib.rsim_mix_workspace_bytes(ctypes.byref(b), ctypes.byref(rsim.tune_table(f, m, True, [1] * 6)), 0)
     two = lib.rsim_mix_workspace_bytes(ctypes.byref(b), ctypes.byref(rsim.tune_table(f, m, True, [2] * 6)), 0)

@@ -53,3 +53,24 @@ def test_kernel_symbol_of_each_variant():
     assert bench.mix_kernel_name(13, [0, 0, 0, 1, 0, 0]) == "void rsim::mix_kernel<256, 1, 2>(rsim::MixArgs)"
     assert bench.mix_kernel_name(15, [0, 0, 0, 0, 0, 2]) == "void rsim::mix_kernel<1024, 1, 4>(rsim::MixArgs)"
     assert bench.mix_kernel_name(9, None) == "void rsim::mix_kernel<32, 2, 1>(rsim::MixArgs)"
+
+
+def test_error_record_of_a_parity_case():
+    # the error leg reports max |gpu - ref| / max |ref| per workload, and
+    # inf when a cut length differs from the oracle's
+    import numpy as np
+
+    import oracle
+    import synth
+
+    b = synth.make_config2(n_utt=2, epoch=3)
+    xs, hs, snrs = b.sources(0), b.rirs(0), list(b.snrs(0))
+    ref, _, Ls, _ = oracle.simulate(xs, hs, snrs, 20.0)
+    outs = [ref[j].astype(np.float32) for j in range(b.n_mic)]
+    _, e = bench._forward_error(("w", xs, hs, snrs, 20.0, Ls, outs))
+    assert 0.0 <= e <= 1e-7
+    bad = [row[:] for row in Ls]
+    bad[0][0] += 1
+    assert bench._forward_error(("w", xs, hs, snrs, 20.0, bad, outs))[1] == float("inf")
+    info = bench.host_info()
+    assert info["os_cpu_count"] >= 1 and "cpu_model" in info

@@ -79,3 +79,96 @@ def test_logmel_edges_and_a_tone():
     f3 = feat[off[3]: off[3] + F * 128].reshape(F, 128)
     W = lm.filterbank()
     assert np.all(np.argmax(f3, axis=1) == np.argmax(W[:, 64]))
+
+
+def _fused(b, eta, fft_log2n=None, hop=None, use_graph=False):
+    torch = cuda()
+    from paper_1712_03439_amd import rsim
+
+    db = rsim.DeviceBatch(b, fft_log2n=fft_log2n, hop=hop)
+    alpha = torch.from_numpy(rsim.batch_gains(db, b.snr_db)).cuda()
+    # unfused: y, then the separate front end
+    y = rsim.simulate(db, alpha, eta)
+    feat_u, off, cap = rsim.logmel(db, y)
+    torch.cuda.synchronize()
+    ref = (y.cpu().numpy(), feat_u.cpu().numpy(), db.out_len.cpu().numpy().copy(), db.rir_len.cpu().numpy().copy())
+    db.out_len.fill_(-1)
+    db.rir_len.fill_(-1)
+    rsim.device_status()
+    stream = torch.cuda.Stream()
+    stream.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(stream):
+        feat_f, off_f, cap_f = rsim.simulate_logmel(db, alpha, eta, use_graph=use_graph, stream=stream)
+    torch.cuda.synchronize()
+    assert rsim.device_status() == 0
+    assert np.array_equal(off, off_f) and np.array_equal(cap, cap_f)
+    return ref, feat_f.cpu().numpy(), off, cap, db.out_len.cpu().numpy(), db.rir_len.cpu().numpy()
+
+
+def _compare_fused(b, ref, feat_f, off, cap, ol, rl):
+    y, feat_u, ol_u, rl_u = ref
+    assert np.array_equal(ol, ol_u) and np.array_equal(rl, rl_u)
+    _check(b, y, feat_f, off, cap, ol, range(b.n_utt))
+    same = True
+    for u in range(b.n_utt):
+        F = lm.n_frames(int(ol[u]))
+        for j in range(b.n_mic):
+            s = slice(off[u] + j * cap[u] * 128, off[u] + (j * cap[u] + F) * 128)
+            same &= bool(np.array_equal(feat_f[s], feat_u[s]))
+            assert np.max(np.abs(feat_f[s] - feat_u[s]), initial=0.0) <= 1e-4, (u, j)
+    return same
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("graph", [False, True])
+def test_fused_front_end_of_a_batch(graph):
+    # the batched workload's shapes: the features of the fused kernel against
+    # the oracle's front end on the unfused kernel's samples, and against the
+    # separate front end's features
+    b = synth.make_config2(n_utt=12, epoch=9)
+    ref, feat_f, off, cap, ol, rl = _fused(b, 20.0, use_graph=graph)
+    same = _compare_fused(b, ref, feat_f, off, cap, ol, rl)
+    print(f"fused features identical to the separate front end's: {same}")
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("l2", [12, 13, 14])
+def test_fused_front_end_at_each_size_with_five_mics(l2):
+    # 5 mics (three mic groups in one work item: the source spectra cached
+    # for the later groups), ragged lengths, an utterance shorter than a frame
+    rng = synth.rng_for(72, l2)
+    srcs, rirs, snrs = [], [], []
+    for u, n in enumerate((300, 5000, 33000, 70001)):
+        I = 1 + u % 3
+        srcs.append([synth.speech_like(rng, n)] + [synth.white_noise(rng, n) for _ in range(I - 1)])
+        L0 = int(rng.integers(100, min(2 ** l2 // 2, 3000)))
+        rirs.append([[synth.rir(rng, L0, 0.3, int(rng.integers(0, 40))) for _ in range(5)] for _ in range(I)])
+        snrs.append([0.0] + [float(v) for v in rng.uniform(0, 20, I - 1)])
+    b = synth.pack(srcs, rirs, snrs, 5)
+    ref, feat_f, off, cap, ol, rl = _fused(b, math.inf, fft_log2n=np.full(b.n_utt, l2, np.int32))
+    _compare_fused(b, ref, feat_f, off, cap, ol, rl)
+
+
+@pytest.mark.gpu
+def test_fused_front_end_with_a_hop_below_the_rir():
+    # a forced hop shorter than the kept RIR: the tails of several blocks
+    # reach each output sample, summed through the accumulators
+    rng = synth.rng_for(73, 0)
+    srcs = [[synth.speech_like(rng, 40000), synth.pink_noise(rng, 40000)]]
+    rirs = [[[synth.rir(rng, 3000, 0.4, 10)] * 2, [synth.rir(rng, 2000, 0.4, 5)] * 2]]
+    b = synth.pack(srcs, rirs, [[0.0, 4.0]], 2)
+    ref, feat_f, off, cap, ol, rl = _fused(b, math.inf, fft_log2n=np.array([13], np.int32), hop=np.array([700], np.int32))
+    _compare_fused(b, ref, feat_f, off, cap, ol, rl)
+
+
+@pytest.mark.gpu
+def test_fused_front_end_refuses_sizes_without_a_fused_kernel():
+    torch = cuda()
+    from paper_1712_03439_amd import rsim
+
+    b = synth.make_config2(n_utt=3, epoch=2)
+    db = rsim.DeviceBatch(b, fft_log2n=np.full(3, 15, np.int32))
+    alpha = torch.from_numpy(rsim.batch_gains(db, b.snr_db)).cuda()
+    with pytest.raises(rsim.RsimError) as e:
+        rsim.simulate_logmel(db, alpha, 20.0)
+    assert e.value.code == rsim.RSIM_EUNSUPPORTED

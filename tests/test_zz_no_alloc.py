@@ -11,7 +11,7 @@ import pytest
 
 import synth
 from tests.gpu_util import cuda
-from tests.test_gpu_mix import _check_utterances, _large_subset
+from tests.test_gpu_mix import _check_utterances
 
 
 def _reference(b, eta, tune=None, fft_log2n=None):
@@ -63,25 +63,38 @@ def test_static_entry_matches_simulate_on_two_calls_in_a_row():
         _check_utterances(b, (0, b.n_utt - 1), 20.0, y, rl, ol)
 
 
+def _wide(n_utt, seed):
+    # 4 sources and 8 mics per utterance: one work item's slot of RIR spectra
+    # at N = 32768 is 36 spectra of 16384 bins (4.7 MB)
+    rng = synth.rng_for(24, seed)
+    srcs, rirs = [], []
+    for u in range(n_utt):
+        n = int(rng.integers(500, 3000))
+        srcs.append([synth.speech_like(rng, n)] + [synth.white_noise(rng, n) for _ in range(3)])
+        rirs.append([[synth.rir(rng, int(rng.integers(5, 200)), 0.1, 0) for _ in range(8)] for _ in range(4)])
+    return synth.pack(srcs, rirs, [[0.0, 5.0, 10.0, 20.0]] * n_utt, 8)
+
+
 @pytest.mark.gpu
 def test_static_entry_with_fewer_workgroups_than_slots_wanted():
-    # 8 mics, RIRs up to 16000 taps, N = 32768 (family of 1024 threads): the
-    # persistent grid's scratch slots would need several times the static
-    # array, so fewer workgroups run; a smaller 8-mic batch follows
+    # more utterances than the block split's threshold, at N = 32768 with 8
+    # mics: the persistent grid's scratch slots would need several times the
+    # static array, so fewer workgroups run; a smaller batch follows
     torch = cuda()
     from paper_1712_03439_amd import rsim
 
-    b1 = _large_subset(12, 99)
-    b2 = _large_subset(3, 98)
+    b1 = _wide(1100, 0)
+    b2 = _wide(40, 1)
     l2a, l2b = np.full(b1.n_utt, 15, np.int32), np.full(b2.n_utt, 15, np.int32)
     db1, a1, y1_ref, rl1_ref, ol1_ref = _reference(b1, math.inf, fft_log2n=l2a)
-    assert db1.workspace_bytes() > rsim.STATIC_SCRATCH_BYTES
+    assert db1.workspace_bytes() > 2 * rsim.STATIC_SCRATCH_BYTES
     db2, a2, y2_ref, rl2_ref, ol2_ref = _reference(b2, 30.0, fft_log2n=l2b)
     y1 = _static(db1, a1, math.inf)
     y2 = _static(db2, a2, 30.0)
     torch.cuda.synchronize()
     _same(b1, y1_ref, rl1_ref, ol1_ref, y1.cpu().numpy(), db1.rir_len.cpu().numpy(), db1.out_len.cpu().numpy())
     _same(b2, y2_ref, rl2_ref, ol2_ref, y2.cpu().numpy(), db2.rir_len.cpu().numpy(), db2.out_len.cpu().numpy())
+    _check_utterances(b1, (0, 1099), math.inf, y1.cpu().numpy(), db1.rir_len.cpu().numpy(), db1.out_len.cpu().numpy())
     _check_utterances(b2, (0,), 30.0, y2.cpu().numpy(), db2.rir_len.cpu().numpy(), db2.out_len.cpu().numpy())
 
 
