@@ -177,16 +177,30 @@ def _adjoint_error(case):
 
 def oracle_errors(cases: ParityCases, workers: int) -> dict:
     """Max error of each workload's GPU outputs relative to the oracle's
-    peak, over its seeded utterances (host threads: numpy's direct
-    convolution releases the GIL); inf for a cut length or output length
-    that differs."""
-    from concurrent.futures import ThreadPoolExecutor
+    peak, over its seeded utterances (one utterance per worker process);
+    inf for a cut length or output length that differs."""
+    import multiprocessing as mp
 
     out = {}
-    with ThreadPoolExecutor(workers) as ex:
-        for label, e in list(ex.map(_forward_error, cases.forward)) + list(ex.map(_adjoint_error, cases.adjoint)):
-            out[label] = max(out.get(label, 0.0), e)
+    with mp.get_context("spawn").Pool(workers, initializer=_one_thread) as pool:
+        res = pool.map(_forward_error, cases.forward, chunksize=1) + pool.map(_adjoint_error, cases.adjoint,
+                                                                               chunksize=1)
+    for label, e in res:
+        out[label] = max(out.get(label, 0.0), e)
     return {k: float(f"{v:.3g}") for k, v in out.items()}
+
+
+def _one_thread():
+    """Worker set-up: one compute thread per oracle process (the pool fills
+    the cores; numpy's BLAS would otherwise start a thread pool in each)."""
+    os.environ["OMP_NUM_THREADS"] = "1"
+    os.environ["OPENBLAS_NUM_THREADS"] = "1"
+    try:
+        from threadpoolctl import threadpool_limits
+
+        threadpool_limits(1)
+    except ImportError:
+        pass
 
 
 def oracle_utterance(args):
@@ -209,7 +223,7 @@ def cpu_baseline(base, eta, n_utt, max_workers=16, cases: "ParityCases" = None):
     audio = float(np.sum(base.src_len[idx].astype(np.float64))) / 16000.0
     cores = max(1, min(max_workers, os.cpu_count() or 1))
     ctx = mp.get_context("spawn")
-    with ctx.Pool(cores) as pool:
+    with ctx.Pool(cores, initializer=_one_thread) as pool:
         pool.map(oracle_utterance, tasks[:cores])          # warm the workers
         t0 = time.perf_counter()
         pool.map(oracle_utterance, tasks, chunksize=1)

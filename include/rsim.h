@@ -347,6 +347,18 @@ rsim_status rsim_logmel(const rsim_batch* b, const float* y, float* feat, const 
  * (RSIM_EINVAL).
  */
 size_t rsim_fft_filter_workspace_bytes(const rsim_batch* b, int32_t fft_log2n, int32_t chunk);
+/*
+ * The transform size of eqs. 4-5 for each utterance (host arrays, no GPU):
+ * log2n[u] = ceil(log2(src_len[u] + L0max_u - 1)), L0max_u the longest
+ * uncut RIR of the utterance (rir_len0[(u*max_src + i)*n_mic + j] over its
+ * slots), which bounds the linear convolution for any cut; at least 1, and
+ * 0 for an utterance without samples or taps.  A caller runs
+ * rsim_fft_filter once per size that occurs, on the utterances of that size
+ * (the descriptor's arrays are device memory, so the grouping is the
+ * caller's: it needs the sizes on the host to size and launch each group).
+ */
+rsim_status rsim_fft_filter_sizes(const int32_t* src_len, const int32_t* rir_len0, int32_t n_utt, int32_t max_src,
+                                  int32_t n_mic, int32_t* log2n);
 rsim_status rsim_fft_filter(const rsim_batch* b, const float* x, const float* h, const float* alpha, float* y,
                             int32_t fft_log2n, int32_t chunk, void* ws, size_t ws_bytes, hipStream_t stream);
 

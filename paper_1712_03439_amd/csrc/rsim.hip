@@ -3956,6 +3956,27 @@ rsim_status rsim_logmel(const rsim_batch* b, const float* y, float* feat, const 
   return hipGetLastError() == hipSuccess ? RSIM_OK : clear_error(RSIM_EDEVICE);
 }
 
+rsim_status rsim_fft_filter_sizes(const int32_t* src_len, const int32_t* rir_len0, int32_t n_utt, int32_t max_src,
+                                  int32_t n_mic, int32_t* log2n) {
+  if (n_utt < 0 || max_src < 1 || n_mic < 1) return RSIM_EINVAL;
+  if (n_utt == 0) return RSIM_OK;
+  if (!src_len || !rir_len0 || !log2n) return RSIM_EINVAL;
+  const long long per = (long long)max_src * n_mic;
+  for (int u = 0; u < n_utt; ++u) {
+    int l0 = 0;
+    for (long long k = 0; k < per; ++k) l0 = std::max(l0, rir_len0[u * per + k]);
+    const long long need = (long long)src_len[u] + l0 - 1;
+    if (src_len[u] <= 0 || l0 <= 0) {
+      log2n[u] = 0;
+      continue;
+    }
+    int m = 1;
+    while ((1LL << m) < need) ++m;
+    log2n[u] = m;
+  }
+  return RSIM_OK;
+}
+
 size_t rsim_fft_filter_workspace_bytes(const rsim_batch* b, int32_t fft_log2n, int32_t chunk) {
   if (!batch_ok(b) || fft_log2n < 1 || fft_log2n > 20 || chunk < 1) return 0;
   const size_t N = (size_t)1 << fft_log2n, C = (size_t)chunk, S = (size_t)b->max_src;

@@ -28,6 +28,7 @@ EXPORTS = (
     "rsim_device_status", "rsim_rfft", "rsim_irfft", "rsim_image_rir", "rsim_simulate_rooms",
     "rsim_reverb_energy", "rsim_snr_gains_reverb", "rsim_logmel", "rsim_fft_filter_workspace_bytes",
     "rsim_fft_filter", "rsim_simulate_static", "rsim_simulate_logmel_workspace_bytes", "rsim_simulate_logmel",
+    "rsim_fft_filter_sizes",
 )
 
 
@@ -95,6 +96,7 @@ def _lib():
             "rsim_simulate_static": ([bp, vp, vp, vp, f64, vp, vp, tp, vp], i32),
             "rsim_simulate_logmel_workspace_bytes": ([bp, tp], sz),
             "rsim_simulate_logmel": ([bp, vp, vp, vp, f64, vp, vp, vp, i64, vp, sz, tp, i32, vp], i32),
+            "rsim_fft_filter_sizes": ([vp, vp, i32, i32, i32, vp], i32),
         }
         for name, (args, res) in sig.items():
             fn = getattr(lib, name)
@@ -337,14 +339,18 @@ def simulate_logmel(db: DeviceBatch, alpha, eta_db: float, feat=None, ws=None, t
 
 
 def fft_filter_log2n(db: DeviceBatch) -> np.ndarray:
-    """Per utterance, the smallest transform size (log2) that holds its whole
-    convolution with its uncut RIRs (a bound for any cut)."""
+    """Per utterance, the transform size (log2) of eqs. 4-5 that the library
+    assigns (rsim_fft_filter_sizes): it holds the whole convolution with the
+    uncut RIRs, a bound for any cut."""
     b = db.host
     if not db.U:
         return np.zeros(0, np.int64)
-    L0 = np.asarray(b.rir_len0, np.int64).reshape(db.U, db.S * db.J).max(axis=1)
-    need = np.maximum(np.asarray(b.src_len, np.int64) + L0 - 1, 2)
-    return np.ceil(np.log2(need)).astype(np.int64)
+    src = np.ascontiguousarray(b.src_len, np.int32)
+    l0 = np.ascontiguousarray(b.rir_len0, np.int32)
+    out = np.zeros(db.U, np.int32)
+    _check(_lib().rsim_fft_filter_sizes(src.ctypes.data, l0.ctypes.data, db.U, db.S, db.J, out.ctypes.data),
+           "rsim_fft_filter_sizes")
+    return out.astype(np.int64)
 
 
 def fft_filter(db: DeviceBatch, alpha, y=None, chunk: int = 16, stream=None):
@@ -357,7 +363,10 @@ def fft_filter(db: DeviceBatch, alpha, y=None, chunk: int = 16, stream=None):
         y = db.new_output()
     l2s = fft_filter_log2n(db)
     S, J = db.S, db.J
-    for l2 in np.unique(l2s):
+    empty = np.nonzero(l2s == 0)[0]
+    if empty.size:  # no samples or no taps: no output
+        db.out_len[torch.as_tensor(empty, device=db.device)] = 0
+    for l2 in np.unique(l2s[l2s > 0]):
         idx = np.nonzero(l2s == l2)[0]
         sub = db if idx.size == db.U else db.select(idx)
         if sub is db:

@@ -1,7 +1,4 @@
 """Helpers shared by the GPU tests (no arithmetic of the method here)."""
-import os
-from concurrent.futures import ThreadPoolExecutor
-
 import numpy as np
 
 
@@ -21,21 +18,6 @@ def max_rel_err(got, ref):
     if peak == 0.0:
         return err
     return err / peak
-
-
-def host_workers() -> int:
-    """Threads for oracle sums: numpy's direct convolution releases the GIL.
-    At most 16 (a GPU host's share of cores)."""
-    return max(1, min(16, os.cpu_count() or 1))
-
-
-def pmap(fn, items):
-    """[fn(a) for a in items], evaluated on host threads, in order."""
-    items = list(items)
-    if len(items) <= 1:
-        return [fn(a) for a in items]
-    with ThreadPoolExecutor(host_workers()) as ex:
-        return list(ex.map(fn, items))
 
 
 TOL = 1e-5  # max-abs error relative to the output peak, per (utterance, mic)

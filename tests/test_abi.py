@@ -311,3 +311,15 @@ def test_forced_sizes_hint_limits_the_workspace():
     two = lib.rsim_mix_workspace_bytes(ctypes.byref(b), None, 0)
     assert one < two < every
     assert rsim.size_bits(None) == 0 and rsim.size_bits(np.array([14, 12, 14, 16, 8])) == (1 << 14) | (1 << 12)
+
+
+def test_full_length_transform_sizes():
+    # N = 2^ceil(log2(Nx + L0max - 1)) per utterance, L0max over its slots;
+    # 0 without samples or taps
+    lib = rsim.lib()
+    src = np.array([100, 1, 5000, 0, 7], np.int32)
+    l0 = np.array([[29, 3], [1, 0], [0, 4097], [50, 50], [0, 0]], np.int32).reshape(-1)
+    out = np.full(5, -1, np.int32)
+    assert lib.rsim_fft_filter_sizes(src.ctypes.data, l0.ctypes.data, 5, 1, 2, out.ctypes.data) == rsim.RSIM_OK
+    assert list(out) == [7, 1, 14, 0, 0]
+    assert lib.rsim_fft_filter_sizes(src.ctypes.data, l0.ctypes.data, -1, 1, 2, out.ctypes.data) == rsim.RSIM_EINVAL

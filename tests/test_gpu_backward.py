@@ -9,7 +9,8 @@ import pytest
 
 import oracle
 import synth
-from tests.gpu_util import TOL, cuda, max_rel_err, pmap
+from tests import oracle_pool
+from tests.gpu_util import TOL, cuda, max_rel_err
 
 
 def _setup(b, eta, fft_log2n=None, hop=None):
@@ -67,26 +68,22 @@ def _check_full(b, eta, gx, gh, ga, gys, u):
 
 def _check_full_many(b, eta, gx, gh, ga, gys, utts):
     """Every entry of dx, dh and dalpha of the listed utterances against the
-    oracle's adjoint, one (utterance, source) per host thread (the adjoint's
-    terms of one source do not involve the others)."""
+    oracle's adjoint, one (utterance, source) per worker process (the
+    adjoint's terms of one source do not involve the others)."""
     cases = {u: _oracle_problem(b, u, eta) for u in utts}
-    tasks = [(u, i) for u in utts for i in range(len(cases[u][0]))]
-
-    def ref(ui):
-        u, i = ui
-        xs, cut, alpha, T = cases[u]
-        assert gys[u].shape[1] == T
-        return oracle.mix_backward([xs[i]], [cut[i]], alpha[i:i + 1], gys[u])
-
-    refs = dict(zip(tasks, pmap(ref, tasks)))
+    for u in utts:
+        assert gys[u].shape[1] == cases[u][3]
+    keys = [(u, i) for u in utts for i in range(len(cases[u][0]))]
+    tasks = [(cases[u][0][i], cases[u][1][i], cases[u][2][i], gys[u]) for u, i in keys]
+    refs = dict(zip(keys, oracle_pool.pmap(oracle_pool.backward_source, tasks)))
     worst = 0.0
     J, S = b.n_mic, b.max_src
     for u in utts:
         xs, cut, alpha, T = cases[u]
         I = len(xs)
-        dx = [refs[(u, i)][0][0] for i in range(I)]
-        dh = [refs[(u, i)][1][0] for i in range(I)]
-        da = np.array([refs[(u, i)][2][0] for i in range(I)]).reshape(I, J)
+        dx = [refs[(u, i)][0] for i in range(I)]
+        dh = [refs[(u, i)][1] for i in range(I)]
+        da = np.array([refs[(u, i)][2] for i in range(I)]).reshape(I, J)
         for i in range(I):
             so, nx = int(b.src_off[u * S + i]), int(b.src_len[u])
             e = max_rel_err(gx[so: so + nx], dx[i])

@@ -9,7 +9,8 @@ import pytest
 
 import oracle
 import synth
-from tests.gpu_util import TOL, cuda, max_rel_err, pmap
+from tests import oracle_pool
+from tests.gpu_util import TOL, cuda, max_rel_err
 
 
 def _ola(x, h, n, hop=0):
@@ -99,22 +100,16 @@ def _oracle_case(b, u, eta, rir_len):
 
 def _check_utterances(b, utts, eta, y, rir_len, out_len):
     """Every output sample of the listed utterances against the oracle's mix
-    (eq. 2), one (utterance, mic) per host thread: max |y - ref| <= TOL * max |ref|."""
+    (eq. 2), one (utterance, mic) per worker process: max |y - ref| <= TOL * max |ref|."""
     cases = {u: _oracle_case(b, u, eta, rir_len) for u in utts}
     for u, (xs, cut, alpha, T) in cases.items():
         assert int(out_len[u]) == T, (u, int(out_len[u]), T)
 
-    def ref_mic(uj):
-        u, j = uj
-        xs, cut, alpha, T = cases[u]
-        r = oracle.mix(xs, [[cut[i][j]] for i in range(len(xs))], alpha[:, j:j + 1])[0]
-        out = np.zeros(T)
-        out[: r.size] = r
-        return out
-
     pairs = [(u, j) for u in utts for j in range(b.n_mic) if cases[u][3] > 0]
+    tasks = [(cases[u][0], [cases[u][1][i][j] for i in range(len(cases[u][0]))], cases[u][2][:, j], cases[u][3])
+             for u, j in pairs]
     worst = 0.0
-    for (u, j), ref in zip(pairs, pmap(ref_mic, pairs)):
+    for (u, j), ref in zip(pairs, oracle_pool.pmap(oracle_pool.mix_mic, tasks)):
         off, st, T = int(b.out_off[u]), int(b.out_stride[u]), cases[u][3]
         e = max_rel_err(y[off + j * st: off + j * st + T], ref)
         worst = max(worst, e)
