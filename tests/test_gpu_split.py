@@ -18,7 +18,7 @@ from tests.gpu_util import cuda
 from tests.test_gpu_mix import _check_utterances, _large_subset, _simulate
 
 
-def _many(n_utt, seed, l2):
+def _many(n_utt, seed, l2, n_mic=3):
     rng = synth.rng_for(70, seed)
     srcs, rirs, snrs = [], [], []
     for u in range(n_utt):
@@ -26,9 +26,19 @@ def _many(n_utt, seed, l2):
         n = int(rng.integers(3000, 12000))
         srcs.append([synth.speech_like(rng, n)] + [synth.white_noise(rng, n) for _ in range(I - 1)])
         L0 = int(rng.integers(20, 900))
-        rirs.append([[synth.rir(rng, L0, 0.2, int(rng.integers(0, 20))) for _ in range(3)] for _ in range(I)])
+        rirs.append([[synth.rir(rng, L0, 0.2, int(rng.integers(0, 20))) for _ in range(n_mic)] for _ in range(I)])
         snrs.append([0.0] + [float(v) for v in rng.uniform(0, 20, I - 1)])
-    return synth.pack(srcs, rirs, snrs, 3)
+    return synth.pack(srcs, rirs, snrs, n_mic)
+
+
+def _same_bits(big, pick, y_big, ol_big, small, y_small, ol_small):
+    for k, u in enumerate(pick):
+        assert int(ol_small[k]) == int(ol_big[u])
+        T = int(ol_big[u])
+        for j in range(big.n_mic):
+            a = y_big[int(big.out_off[u]) + j * int(big.out_stride[u]):][:T]
+            b = y_small[int(small.out_off[k]) + j * int(small.out_stride[k]):][:T]
+            assert np.array_equal(a, b), (u, j)
 
 
 @pytest.mark.gpu
@@ -41,14 +51,24 @@ def test_split_gives_the_bits_of_the_unsplit_kernel():
     l2 = 11
     _, _, y_big, rl_big, ol_big = _simulate(big, 20.0, fft_log2n=np.full(big.n_utt, l2, np.int32))
     _, _, y_small, rl_small, ol_small = _simulate(small, 20.0, fft_log2n=np.full(small.n_utt, l2, np.int32))
-    for k, u in enumerate(pick):
-        assert int(ol_small[k]) == int(ol_big[u])
-        T = int(ol_big[u])
-        for j in range(big.n_mic):
-            a = y_big[int(big.out_off[u]) + j * int(big.out_stride[u]):][:T]
-            b = y_small[int(small.out_off[k]) + j * int(small.out_stride[k]):][:T]
-            assert np.array_equal(a, b), (u, j)
+    _same_bits(big, pick, y_big, ol_big, small, y_small, ol_small)
     _check_utterances(small, range(small.n_utt), 20.0, y_small, rl_small, ol_small)
+
+
+@pytest.mark.gpu
+def test_split_with_several_mic_groups_per_work_item():
+    # 400 utterances with 5 mics: more utterances than compute units, so a
+    # work item runs all three mic groups (the block's source spectra cached
+    # in its slot for the later groups), and fewer than four items per
+    # compute unit, so the blocks are split as well; against the same
+    # utterances in a 1200-utterance batch (not split)
+    big = _many(1200, 1, 11, n_mic=5)
+    pick = list(range(0, 1200, 3))[:400]
+    small = synth.subset(big, pick)
+    _, _, y_big, rl_big, ol_big = _simulate(big, 20.0, fft_log2n=np.full(big.n_utt, 11, np.int32))
+    _, _, y_small, rl_small, ol_small = _simulate(small, 20.0, fft_log2n=np.full(small.n_utt, 11, np.int32))
+    _same_bits(big, pick, y_big, ol_big, small, y_small, ol_small)
+    _check_utterances(small, (0, 199, 399), 20.0, y_small, rl_small, ol_small)
 
 
 @pytest.mark.gpu
