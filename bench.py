@@ -63,7 +63,7 @@ def mix_kernel_name(log2n: int, variant) -> str:
     f = autotune.FAMILY[log2n]
     code = (variant[f] if variant is not None and variant[f] else autotune.DEFAULT_VARIANT) if f < 5 else 4
     jg, w = VARIANT_TEMPLATE[code]
-    return f"void rsim::mix_kernel<{32 << f}, {jg}, {w}>(rsim::MixArgs)"
+    return f"void rsim::mix_kernel<{32 << f}, {jg}, {w}, false>(rsim::MixArgs)"
 
 
 def counter_traffic(kernel: str):

@@ -48,11 +48,11 @@ def test_missing_or_unreadable_counters_give_no_traffic(tmp_path, monkeypatch):
 def test_kernel_symbol_of_each_variant():
     # variant codes 1..4 = (mic accumulators, waves per SIMD) (1, 2), (2, 1),
     # (2, 2), (1, 4); 0 is the library default (2); the 32768 family runs 4
-    assert bench.mix_kernel_name(14, [0] * 6) == "void rsim::mix_kernel<512, 2, 1>(rsim::MixArgs)"
-    assert bench.mix_kernel_name(14, [0, 0, 0, 0, 3, 0]) == "void rsim::mix_kernel<512, 2, 2>(rsim::MixArgs)"
-    assert bench.mix_kernel_name(13, [0, 0, 0, 1, 0, 0]) == "void rsim::mix_kernel<256, 1, 2>(rsim::MixArgs)"
-    assert bench.mix_kernel_name(15, [0, 0, 0, 0, 0, 2]) == "void rsim::mix_kernel<1024, 1, 4>(rsim::MixArgs)"
-    assert bench.mix_kernel_name(9, None) == "void rsim::mix_kernel<32, 2, 1>(rsim::MixArgs)"
+    assert bench.mix_kernel_name(14, [0] * 6) == "void rsim::mix_kernel<512, 2, 1, false>(rsim::MixArgs)"
+    assert bench.mix_kernel_name(14, [0, 0, 0, 0, 3, 0]) == "void rsim::mix_kernel<512, 2, 2, false>(rsim::MixArgs)"
+    assert bench.mix_kernel_name(13, [0, 0, 0, 1, 0, 0]) == "void rsim::mix_kernel<256, 1, 2, false>(rsim::MixArgs)"
+    assert bench.mix_kernel_name(15, [0, 0, 0, 0, 0, 2]) == "void rsim::mix_kernel<1024, 1, 4, false>(rsim::MixArgs)"
+    assert bench.mix_kernel_name(9, None) == "void rsim::mix_kernel<32, 2, 1, false>(rsim::MixArgs)"
 
 
 def test_error_record_of_a_parity_case():
