@@ -620,8 +620,7 @@ def large_thresholds(torch, rsim, autotune, synth, dev, etas=(math.inf, 30.0, 20
     t0 = time.perf_counter()
     b = synth.make_config4()
     log(f"large workload: {b.n_utt} utterances, {b.audio_seconds:.0f} audio-s ({time.perf_counter() - t0:.1f} s)")
-    order = lpt_order(b)
-    db = rsim.DeviceBatch(b, device=dev, order=order)
+    db = rsim.DeviceBatch(b, device=dev)  # the device schedule orders the work
     alpha = torch.from_numpy(rsim.batch_gains(db, b.snr_db)).to(dev)
     stream = torch.cuda.Stream()
     stream.wait_stream(torch.cuda.current_stream())
@@ -720,6 +719,9 @@ def main() -> int:
                          "(about a minute of host-side generation and 35 GB of GPU memory)")
     ap.add_argument("--no-single", action="store_true", help="skip the single-utterance latencies")
     ap.add_argument("--no-share", action="store_true", help="skip the one-GPU-share timing")
+    ap.add_argument("--order", choices=("device", "host"), default="device",
+                    help="'device': the schedule orders each family's utterances longest work first "
+                         "after the cut; 'host': the order of lpt_order() is passed in")
     ap.add_argument("--tune", default="measure",
                     help="'measure' (time every FFT size and kernel variant on the first epoch's "
                          "batch before the warmup), 'model' (the built-in cost model), 'auto' (this "
@@ -751,7 +753,7 @@ def main() -> int:
     base = synth.make_config2(epoch=0, n_utt=args.n_utt)
     log(f"dataset: {base.n_utt} utterances, {base.audio_seconds:.0f} audio-s, "
         f"{base.x.nbytes / 1e9:.2f} GB of sources ({time.perf_counter() - t0:.1f} s)")
-    order = lpt_order(base)
+    order = lpt_order(base) if args.order == "host" else None
     tune = None if args.tune == "measure" else autotune.load(args.tune)
 
     x_dev = torch.from_numpy(base.x).to(dev)
@@ -900,6 +902,8 @@ def main() -> int:
                                f"{args.eta:g} dB, SNR U(0,30) dB, fresh RIRs every epoch",
                    "global_batch": base.n_utt, "audio_s_per_step": round(audio, 1),
                    "eta_db": args.eta, "hip_graph": use_graph,
+                   "order": "longest work first, device schedule after the cut" if args.order == "device"
+                            else "longest work first by source length x (sources + mics), host",
                    "fft_sizes": {str(k): v // K for k, v in sorted(sizes.items())},
                    "tune": dict(tune_info, policy="one size per batch" if one_size else "size per utterance")},
         "roofline": roof,

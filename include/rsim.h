@@ -76,7 +76,14 @@ typedef struct rsim_batch {
   const int64_t* out_off; /* [U] */
   const int32_t* out_stride; /* [U] */
   int32_t* out_len;       /* [U] written: T_u */
-  const int32_t* order;   /* [U] or NULL: processing order, longest work first */
+  const int32_t* order;   /* [U] or NULL.  Given: the processing order (a
+                           * permutation of 0..U-1; the caller's longest-work-first
+                           * order, say).  NULL: the device schedule orders each
+                           * kernel family's utterances longest work first after
+                           * the cut (transforms nb (I + J) + I J of the plan,
+                           * weighted by N log2 N; ties in index order), for up to
+                           * 8192 utterances per family, index order beyond.
+                           * The order changes no output value. */
   const int32_t* fft_log2n; /* [U] or NULL: forced log2 FFT size per utterance (9..15) */
   const int32_t* hop;     /* [U] or NULL: forced block hop; default N - max L + 1 */
   int32_t fft_sizes;      /* (host) with fft_log2n: bit m set for every forced size

@@ -359,8 +359,56 @@ __global__ __launch_bounds__(kPrepThreads) void prepare_kernel(SchedArgs A) {
 }
 
 // One workgroup of 1024 threads: plans every utterance and appends it to its
-// family's list, keeping the caller's order (a stable compaction per family).
+// family's list in the caller's order (a stable compaction per family).
+// Without a caller's order each list is then sorted longest work first
+// (LPT): by decreasing transform count nb (I + J) + I J of the utterance's
+// plan, weighted by N log2 N (one family can hold two sizes), ties in
+// utterance order.  The key of list position k is (work bits << 32) |
+// (2^32 - 1 - k): positive floats order as their bits, and the complement
+// puts the earlier position first among equal work.  A bitonic network in LDS
+// sorts up to kLptCap entries; a longer list keeps utterance order.
 constexpr int kSchedThreads = 1024;
+constexpr int kLptCap = 8192;
+
+__device__ void lpt_sort_lists(const BatchDev& b, const Sched* __restrict__ sched, int* __restrict__ lists,
+                               const int* count, unsigned long long* s_key, int* s_u, int t) {
+  for (int f = 0; f < kNumFam; ++f) {
+    const int n = count[f];
+    if (n < 2 || n > kLptCap) continue;
+    int p2 = 64;
+    while (p2 < n) p2 <<= 1;
+    int* lf = lists + (long long)f * b.U;
+    for (int k = t; k < p2; k += kSchedThreads) {
+      unsigned long long key = 0ull;  // padding: below every real key
+      if (k < n) {
+        const int u = lf[k];
+        s_u[k] = u;
+        const Sched S = sched[u];
+        const int I = b.n_src[u];
+        const float w = (float)(S.nb * (I + b.J) + I * b.J) * (float)((1 << S.log2n) * S.log2n);
+        key = ((unsigned long long)__float_as_uint(w) << 32) | (unsigned long long)(0xffffffffu - (unsigned)k);
+      }
+      s_key[k] = key;
+    }
+    __syncthreads();
+    for (int size = 2; size <= p2; size <<= 1) {
+      for (int stride = size >> 1; stride > 0; stride >>= 1) {
+        for (int k = t; k < p2 / 2; k += kSchedThreads) {
+          const int lo = 2 * k - (k & (stride - 1)), hi = lo + stride;
+          const bool desc = (lo & size) == 0;  // the final merge (size = p2) is descending throughout
+          const unsigned long long a = s_key[lo], c = s_key[hi];
+          if (desc ? a < c : a > c) {
+            s_key[lo] = c;
+            s_key[hi] = a;
+          }
+        }
+        __syncthreads();
+      }
+    }
+    for (int k = t; k < n; k += kSchedThreads) lf[k] = s_u[0xffffffffu - (unsigned)(s_key[k] & 0xffffffffull)];
+    __syncthreads();
+  }
+}
 
 __global__ __launch_bounds__(kSchedThreads) void schedule_kernel(SchedArgs A) {
   const BatchDev& b = A.b;
@@ -453,6 +501,11 @@ __global__ __launch_bounds__(kSchedThreads) void schedule_kernel(SchedArgs A) {
     __syncthreads();
   }
   if (t < kNumFam) hdr->count[t] = s_base[t];
+  if (!b.order) {
+    __shared__ unsigned long long s_key[kLptCap];
+    __shared__ int s_u[kLptCap];
+    lpt_sort_lists(b, sched, lists, s_base, s_key, s_u, t);
+  }
   if (err) flag_status(err);
 }
 
@@ -1210,7 +1263,10 @@ __global__ __launch_bounds__(T, 2) void mix_rir_kernel(MixArgs A) {
 // the tail the previous part's last block stored in y.  The two operands are
 // the ones the unsplit kernel adds (in the other order; the sum is the same),
 // so the outputs are bit-identical to the unsplit kernel's.
-constexpr int kSeamThreads = 256;
+// Each thread requests kSeamPer elements of both operands before it adds
+// and stores any (the seam buffer and y never overlap), so a seam of up to
+// kSeamThreads * kSeamPer samples costs one memory round trip.
+constexpr int kSeamThreads = 256, kSeamPer = 16;
 __global__ __launch_bounds__(kSeamThreads) void mix_seam_kernel(MixArgs A) {
   const BatchDev& b = A.b;
   const int J = b.J, ps = A.psplit;
@@ -1225,9 +1281,22 @@ __global__ __launch_bounds__(kSeamThreads) void mix_seam_kernel(MixArgs A) {
     const int b0 = (int)((long long)S.nb * part / nparts);
     const int base = b0 * S.hop;
     const int h = min(S.lmax - 1, S.tu - base);
-    float* y = A.y + b.out_off[u] + (long long)j * b.out_stride[u] + base;
-    const float* sm = A.seam + (((long long)u * ps + part) * J + j) * A.mmax;
-    for (int n = threadIdx.x; n < h; n += kSeamThreads) y[n] = y[n] + sm[n];
+    float* __restrict__ y = A.y + b.out_off[u] + (long long)j * b.out_stride[u] + base;
+    const float* __restrict__ sm = A.seam + (((long long)u * ps + part) * J + j) * A.mmax;
+    for (int n0 = 0; n0 < h; n0 += kSeamThreads * kSeamPer) {
+      float yv[kSeamPer], sv[kSeamPer];
+#pragma unroll
+      for (int e = 0; e < kSeamPer; ++e) {
+        const int n = n0 + e * kSeamThreads + (int)threadIdx.x;
+        yv[e] = n < h ? y[n] : 0.0f;
+        sv[e] = n < h ? sm[n] : 0.0f;
+      }
+#pragma unroll
+      for (int e = 0; e < kSeamPer; ++e) {
+        const int n = n0 + e * kSeamThreads + (int)threadIdx.x;
+        if (n < h) y[n] = yv[e] + sv[e];
+      }
+    }
   }
 }
 

@@ -1,0 +1,93 @@
+"""The device schedule's work order (Sec. 2.2's batched execution): without a
+caller's order each kernel family's list is sorted longest work first after
+the cut; with one, the caller's order is kept.  The order changes no output
+value.  The lists are read from the workspace, whose first bytes are the
+schedule's (header: 6 queue heads, 6 list lengths; then one 24-byte plan per
+utterance from byte 256; then one list of U entries per family, 256-byte
+aligned)."""
+import numpy as np
+import pytest
+
+import synth
+from tests.gpu_util import cuda
+
+FAMILY = {9: 0, 10: 1, 11: 1, 12: 2, 13: 3, 14: 4, 15: 5}
+LPT_CAP = 8192
+
+
+def _run(b, order=None, eta=20.0):
+    torch = cuda()
+    from paper_1712_03439_amd import rsim
+
+    db = rsim.DeviceBatch(b, order=order)
+    alpha = torch.from_numpy(rsim.batch_gains(db, b.snr_db)).cuda()
+    ws = db.workspace()
+    y = rsim.simulate(db, alpha, eta, ws=ws)
+    torch.cuda.synchronize()
+    raw = ws.cpu().numpy()
+    U = b.n_utt
+    count = raw[24:48].view(np.int32)
+    sched = raw[256:256 + 24 * U].view(np.int32).reshape(U, 6)
+    lists_at = 256 + ((24 * U + 255) // 256) * 256
+    lists = raw[lists_at:lists_at + 4 * 6 * U].view(np.int32).reshape(6, U)
+    return y.cpu().numpy(), count.copy(), sched.copy(), lists.copy()
+
+
+def _work(b, sched, u):
+    # the schedule's key, in the same FP32 operations
+    l2, nb = int(sched[u, 0]), int(sched[u, 2])
+    I, J = int(b.n_src[u]), int(b.n_mic)
+    return np.float32(nb * (I + J) + I * J) * np.float32((1 << l2) * l2)
+
+
+def _families(sched):
+    fam = {f: [] for f in range(6)}
+    for u in range(sched.shape[0]):
+        if sched[u, 2] > 0:
+            fam[FAMILY[int(sched[u, 0])]].append(u)
+    return fam
+
+
+@pytest.mark.gpu
+def test_device_lpt_order_and_outputs():
+    b = synth.make_config2(n_utt=300, epoch=5)
+    y, count, sched, lists = _run(b)
+    fam = _families(sched)
+    assert sum(len(v) for v in fam.values()) > 0
+    for f in range(6):
+        n = int(count[f])
+        assert n == len(fam[f])
+        got = [int(u) for u in lists[f, :n]]
+        assert sorted(got) == fam[f]  # a permutation of the family's utterances
+        keys = [_work(b, sched, u) for u in got]
+        for k in range(n - 1):
+            assert keys[k] > keys[k + 1] or (keys[k] == keys[k + 1] and got[k] < got[k + 1])
+    # a caller's order is kept, and the order changes no output bit
+    order = np.random.default_rng(1).permutation(b.n_utt).astype(np.int32)
+    y2, count2, sched2, lists2 = _run(b, order=order)
+    assert np.array_equal(count, count2) and np.array_equal(sched, sched2)
+    for f in range(6):
+        want = [int(u) for u in order if sched[u, 2] > 0 and FAMILY[int(sched[u, 0])] == f]
+        assert [int(u) for u in lists2[f, :int(count2[f])]] == want
+    assert np.array_equal(y.view(np.uint32), y2.view(np.uint32))
+
+
+@pytest.mark.gpu
+def test_device_order_beyond_the_sort_capacity_keeps_index_order():
+    # 8200 short utterances, one size: the family's list is longer than the
+    # sort's capacity and stays in utterance order
+    rng = synth.rng_for(31, 0)
+    U = LPT_CAP + 8
+    srcs = [[synth.white_noise(rng, int(rng.integers(20, 200)))] for _ in range(U)]
+    rirs = [[[synth.rir(rng, 40, 0.2, 30)]] for _ in range(U)]
+    b = synth.pack(srcs, rirs, [[0.0]] * U, 1)
+    y, count, sched, lists = _run(b, eta=float("inf"))
+    fam = _families(sched)
+    for f in range(6):
+        n = int(count[f])
+        got = [int(u) for u in lists[f, :n]]
+        if n > LPT_CAP:
+            assert got == fam[f]
+        else:
+            assert sorted(got) == fam[f]
+    assert max(int(c) for c in count) > LPT_CAP
