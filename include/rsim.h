@@ -112,12 +112,12 @@ typedef struct rsim_batch {
  * 1024 and 2048; 4096; 8192; 16384; 32768):
  *   0 the library default (2); 1 one mic per pass, registers sized for two
  *   waves per SIMD; 2 two mics per pass, one wave per SIMD; 3 two mics per
- *   pass, two waves per SIMD; 4 one mic per pass, registers sized for four
- *   waves per SIMD (at most 128 a thread, no prefetch).  These are register
- *   budgets: the waves a SIMD actually holds are also bounded by the
- *   workgroup's LDS (the exchange buffers take 35 KB to 140 KB), so the
- *   families of 256 and 512 threads reach two waves per SIMD with any
- *   variant (a workgroup of 32 << f threads has at least (32 << f) / 256).
+ *   pass, two waves per SIMD; 4 one mic per pass, four waves per SIMD (at
+ *   most 128 registers a thread, no prefetch, and one LDS exchange buffer
+ *   instead of two, so that the LDS admits four waves per SIMD as well).
+ *   Variants 1-3 are register budgets: with two exchange buffers (35 KB to
+ *   140 KB a workgroup) the families of 256 and 512 threads hold two waves
+ *   per SIMD with any of them.
  * Family 5 has variant 4 only; its entry is ignored.  Costs must be finite
  * and >= 0 and variants in 0..4 (RSIM_EINVAL, or a workspace size of 0,
  * otherwise).  The variant changes the order of no floating-point operation

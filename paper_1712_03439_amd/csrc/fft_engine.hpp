@@ -402,6 +402,15 @@ constexpr int max_lds_with_threads() {
     return PlanOf<L2>::T == T && mine > rest ? mine : rest;
   }
 }
+// The same with one exchange buffer per plan.
+template <int T, int L2 = kMinL2>
+constexpr int max_lds_single_with_threads() {
+  if constexpr (L2 > kMaxL2) return 0;
+  else {
+    constexpr int rest = max_lds_single_with_threads<T, L2 + 1>();
+    return PlanOf<L2>::T == T && PlanOf<L2>::LDS > rest ? PlanOf<L2>::LDS : rest;
+  }
+}
 
 template <class PL>
 __device__ __forceinline__ int pad(int i) {
@@ -427,10 +436,11 @@ struct TwBase {
 // because the buffer it writes was last read before the previous exchange's
 // barrier.  With one buffer, a barrier also precedes the writes.  The parity
 // is uniform across the workgroup and starts at 0 for each work item (the
-// persistent loop's barriers separate items).
-template <class PL>
+// persistent loop's barriers separate items).  ONE asks for one buffer where
+// two would fit, so that two workgroups share a CU's LDS.
+template <class PL, bool ONE = false>
 struct Xch {
-  static constexpr bool kDouble = double_exchange(PL::LDS);
+  static constexpr bool kDouble = !ONE && double_exchange(PL::LDS);
   static constexpr int kEntries = (kDouble ? 2 : 1) * PL::LDS;
   cf* base;
   int par;

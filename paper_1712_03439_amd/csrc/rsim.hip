@@ -654,8 +654,8 @@ __device__ __forceinline__ void mac2(cf* Y0, cf* Y1, const cf* __restrict__ H0,
 // m < lim are written; positions m < carry already hold the tails of earlier
 // blocks (written by this workgroup) and are accumulated.  Both limits are
 // buffer range checks, so no element needs a branch.
-template <class PL>
-__device__ __forceinline__ void emit(cf* Yv, Xch<PL>& lds, const TwBase& tw, float* __restrict__ yp, int lim,
+template <class PL, class XC>
+__device__ __forceinline__ void emit(cf* Yv, XC& lds, const TwBase& tw, float* __restrict__ yp, int lim,
                                      int carry, int t_) {
   Fft<PL>::pre(Yv, tw, t_);
   Fft<PL>::inverse(Yv, lds, tw, t_);
@@ -688,8 +688,8 @@ __device__ __forceinline__ void load_carry(cf* c, const float* __restrict__ yp, 
 
 // Inverse-transform one mic spectrum, add the preloaded carry (first CR
 // slots) and store the samples below lim.
-template <class PL, int CR>
-__device__ __forceinline__ void emit_carried(cf* Yv, const cf* c, Xch<PL>& lds, const TwBase& tw, float* __restrict__ yp,
+template <class PL, int CR, class XC>
+__device__ __forceinline__ void emit_carried(cf* Yv, const cf* c, XC& lds, const TwBase& tw, float* __restrict__ yp,
                                              int lim, int t_) {
   Fft<PL>::pre(Yv, tw, t_);
   Fft<PL>::inverse(Yv, lds, tw, t_);
@@ -709,8 +709,8 @@ __device__ __forceinline__ void emit_carried(cf* Yv, const cf* c, Xch<PL>& lds, 
 // with its tail) go to the seam buffer sp, those from h up to lim to y.
 // Offsets past a resource's range drop the store, so the split needs no
 // branch: a pair straddling h stores its second word alone.
-template <class PL>
-__device__ __forceinline__ void emit_seam(cf* Yv, Xch<PL>& lds, const TwBase& tw, float* __restrict__ yp,
+template <class PL, class XC>
+__device__ __forceinline__ void emit_seam(cf* Yv, XC& lds, const TwBase& tw, float* __restrict__ yp,
                                           float* __restrict__ sp, int lim, int h, int t_) {
   Fft<PL>::pre(Yv, tw, t_);
   Fft<PL>::inverse(Yv, lds, tw, t_);
@@ -906,9 +906,8 @@ __device__ __forceinline__ UttDesc load_desc(const BatchDev& b, DescCache& c, in
 
 // The spectrum of one RIR block v (its taps, zero-padded) scaled by a, into
 // dst in the paired layout.
-template <class PL>
-__device__ __forceinline__ void rir_spectrum_store(cf* v, float a, cf* dst, Xch<PL>& lds, const TwBase& tw,
-                                                   int t) {
+template <class PL, class XC>
+__device__ __forceinline__ void rir_spectrum_store(cf* v, float a, cf* dst, XC& lds, const TwBase& tw, int t) {
   Fft<PL>::forward(v, lds, tw, t);
   Fft<PL>::post(v, tw, t);
 #pragma unroll
@@ -919,9 +918,9 @@ __device__ __forceinline__ void rir_spectrum_store(cf* v, float a, cf* dst, Xch<
 // The RIR spectra of one utterance, once, scaled by alpha / (8M) (which also
 // carries the normalisation of the inverse transform); the next RIR is
 // requested while the current one is transformed.
-template <class PL>
+template <class PL, class XC>
 __device__ __forceinline__ void rir_spectra(const MixArgs& A, const UttDesc& D, int u, int I, int jlo, int jhi,
-                                            cf* Hs, Xch<PL>& lds, const TwBase& tw, int t) {
+                                            cf* Hs, XC& lds, const TwBase& tw, int t) {
   constexpr int P = PL::P, M = PL::M;
   const BatchDev& b = A.b;
   const int J = b.J, NS = b.S, JN = jhi - jlo;
@@ -956,7 +955,9 @@ __device__ __forceinline__ void mix_utterance(const MixArgs& A, int u, const Sch
                                               int nparts, cf* lds_raw, DescCache& dc, cf* slot, float* s_hist,
                                               int t) {
   constexpr int P = PL::P, M = PL::M;
-  Xch<PL> lds{lds_raw, 0};
+  // The variant sized for four waves per SIMD keeps one exchange buffer, so
+  // that two workgroups fit a CU's LDS.
+  Xch<PL, (MINW >= 4)> lds{lds_raw, 0};
   const TwBase tw = Fft<PL>::bases(plan_tw<PL>(), t);
   const BatchDev& b = A.b;
   const int I = uni(b.n_src[u]), J = b.J, NS = b.S, Nx = uni(b.src_len[u]);
@@ -1189,7 +1190,7 @@ __device__ __forceinline__ void mix_utterance(const MixArgs& A, int u, const Sch
 // is sized for (2 with one mic accumulator, 1 with two).
 template <int T, int JG, int MINW, bool FEAT = false>
 __global__ __launch_bounds__(T, MINW) void mix_kernel(MixArgs A) {
-  __shared__ cf lds[max_lds_with_threads<T>()];
+  __shared__ cf lds[MINW >= 4 ? max_lds_single_with_threads<T>() : max_lds_with_threads<T>()];
   __shared__ DescCache s_desc;
   __shared__ int s_idx;
   __shared__ float s_hist[FEAT ? kFeatMics * kMelWin : 1];
@@ -2794,7 +2795,8 @@ namespace {
 constexpr int kFamT[kNumFam] = {32, 64, 128, 256, 512, 1024};
 // Kernel variants: (mic accumulators JG, waves per SIMD the registers are
 // sized for).  0: JG 1 / 2 waves, 1: JG 2 / 1 wave, 2: JG 2 / 2 waves,
-// 3: JG 1 / 4 waves.  A tune table names one per family (code = index + 1).
+// 3: JG 1 / 4 waves (with one exchange buffer, so the LDS admits them).  A
+// tune table names one per family (code = index + 1).
 constexpr int kNumVar = 4;
 constexpr int kVarJG[kNumVar] = {1, 2, 2, 1};
 constexpr int kFamMaxM[kNumFam] = {max_m_with_threads<32>(),  max_m_with_threads<64>(),
