@@ -136,8 +136,9 @@ rsim_status rsim_init(void);
 
 const char* rsim_strerror(rsim_status s);
 /* 10000 major + 100 minor + patch.  The minor number changes with the layout
- * of rsim_batch or rsim_tune (1.1: rsim_batch.fft_sizes, rsim_tune.variant);
- * a caller built against another minor number must not pass them. */
+ * of rsim_batch or rsim_tune or with an entry point's signature (1.1:
+ * rsim_batch.fft_sizes, rsim_tune.variant; 1.2: rsim_device_status takes a
+ * stream); a caller built against another minor number must not call it. */
 int32_t rsim_version(void);
 
 /*
@@ -395,8 +396,13 @@ rsim_status rsim_simulate_logmel(const rsim_batch* b, const float* x, const floa
                                  int64_t feat_len, void* ws, size_t ws_bytes, const rsim_tune* tune,
                                  int32_t use_graph, hipStream_t stream);
 
-/* Read and clear the device status word (synchronises the device). */
-rsim_status rsim_device_status(int32_t* status);
+/* Waits for the work queued on `stream` (which includes the library's side
+ * streams of every call made on it), then reads the current device's status
+ * word into *status (host) and clears it.  Flags that kernels still running
+ * on other streams set after the read are kept for the next read; one set
+ * between the read and the clear is lost, so read it when the device's other
+ * streams are idle.  RSIM_EDEVICE if the stream or a copy fails. */
+rsim_status rsim_device_status(hipStream_t stream, int32_t* status);
 
 /*
  * Transform entry points of the FFT engine, for its unit tests: `count` real

@@ -3681,7 +3681,7 @@ const char* rsim_strerror(rsim_status s) {
   return "unknown status";
 }
 
-int32_t rsim_version(void) { return 10100; }
+int32_t rsim_version(void) { return 10200; }
 
 rsim_status rsim_truncate_rir(const float* h, int64_t h_len, const int64_t* off, const int32_t* len0,
                               int32_t n_rir, double eta_db, int32_t* n_c, int32_t* len,
@@ -3914,15 +3914,20 @@ rsim_status rsim_snr_gains(const double* p_dry, const double* snr_db, int32_t I,
   return RSIM_OK;
 }
 
-rsim_status rsim_device_status(int32_t* status) {
+rsim_status rsim_device_status(hipStream_t stream, int32_t* status) {
   if (!status) return RSIM_EINVAL;
-  rsim_status e = ensure_init(nullptr);
+  rsim_status e = ensure_init(stream);
   if (e != RSIM_OK) return e;
-  if (hipDeviceSynchronize() != hipSuccess) return RSIM_EDEVICE;
   int v = 0;
-  if (hipMemcpyFromSymbol(&v, HIP_SYMBOL(g_status), sizeof(int)) != hipSuccess) return RSIM_EDEVICE;
   const int zero = 0;
-  if (hipMemcpyToSymbol(HIP_SYMBOL(g_status), &zero, sizeof(int)) != hipSuccess) return RSIM_EDEVICE;
+  if (hipMemcpyFromSymbolAsync(&v, HIP_SYMBOL(g_status), sizeof(int), 0, hipMemcpyDeviceToHost, stream) !=
+          hipSuccess ||
+      hipStreamSynchronize(stream) != hipSuccess)
+    return clear_error(RSIM_EDEVICE);
+  if (hipMemcpyToSymbolAsync(HIP_SYMBOL(g_status), &zero, sizeof(int), 0, hipMemcpyHostToDevice, stream) !=
+          hipSuccess ||
+      hipStreamSynchronize(stream) != hipSuccess)
+    return clear_error(RSIM_EDEVICE);
   *status = v;
   return RSIM_OK;
 }

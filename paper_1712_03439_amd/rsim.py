@@ -58,7 +58,7 @@ class RsimTune(ctypes.Structure):
 
 
 _LIB = None
-ABI_VERSION = 10100  # rsim_version() of the layouts of RsimBatch and RsimTune
+ABI_VERSION = 10200  # rsim_version() of the layouts of RsimBatch and RsimTune and the signatures
 
 
 def _lib():
@@ -82,7 +82,7 @@ def _lib():
             "rsim_mix_backward": ([bp, vp, vp, vp, vp, vp, vp, vp, vp, sz, tp, vp], i32),
             "rsim_source_power": ([bp, vp, vp, vp], i32),
             "rsim_snr_gains": ([vp, vp, i32, i32, vp], i32),
-            "rsim_device_status": ([vp], i32),
+            "rsim_device_status": ([vp, vp], i32),
             "rsim_rfft": ([vp, i32, i32, vp, vp], i32),
             "rsim_irfft": ([vp, i32, i32, vp, vp], i32),
             "rsim_image_rir": ([vp, vp, i32, i32, f64, f64, vp, i64, vp, vp, i32, vp], i32),
@@ -149,9 +149,11 @@ def init() -> None:
     _check(_lib().rsim_init(), "rsim_init")
 
 
-def device_status() -> int:
+def device_status(stream=None) -> int:
+    """Waits for the work on `stream` (default: the current stream), then
+    reads and clears the device status word (RSIM_DEV_* bits)."""
     st = ctypes.c_int32(0)
-    _check(_lib().rsim_device_status(ctypes.byref(st)), "rsim_device_status")
+    _check(_lib().rsim_device_status(_stream(stream), ctypes.byref(st)), "rsim_device_status")
     return int(st.value)
 
 

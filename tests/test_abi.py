@@ -31,7 +31,7 @@ def test_strerror_and_version():
     lib = rsim.lib()
     for code in range(6):
         assert lib.rsim_strerror(code)
-    assert lib.rsim_version() == rsim.ABI_VERSION == 10100
+    assert lib.rsim_version() == rsim.ABI_VERSION == 10200
 
 
 def test_truncate_rejects_bad_eta_before_touching_the_gpu():

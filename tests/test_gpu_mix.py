@@ -199,6 +199,28 @@ def test_bad_descriptor_is_skipped_and_flagged():
 
 
 @pytest.mark.gpu
+def test_status_read_on_the_calls_stream():
+    # a bad descriptor mixed on a side stream: the status read with that
+    # stream waits for the call and sees the flag, and the read clears it
+    torch = cuda()
+    from paper_1712_03439_amd import rsim
+
+    b = synth.make_config2(n_utt=3, epoch=8)
+    b.src_off = b.src_off.copy()
+    b.src_off[2 * b.max_src] = 10 ** 12          # utterance 2 points outside x
+    rsim.device_status()
+    db = rsim.DeviceBatch(b)
+    alpha = torch.from_numpy(rsim.batch_gains(db, b.snr_db)).cuda()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        rsim.simulate(db, alpha, 20.0, stream=side)
+    assert rsim.device_status(side) & rsim.DEV_BADDESC
+    assert rsim.device_status(side) == 0
+    assert int(db.out_len[2].item()) == 0
+
+
+@pytest.mark.gpu
 def test_graph_and_eager_calls_agree_across_families():
     # One utterance per FFT-size family, so every call runs several family
     # kernels side by side; eager and graph calls on the null stream and on a
