@@ -81,9 +81,9 @@ typedef struct rsim_batch {
                            * order, say).  NULL: the device schedule orders each
                            * kernel family's utterances longest work first after
                            * the cut (transforms nb (I + J) + I J of the plan,
-                           * weighted by N log2 N; ties in index order), for up to
-                           * 8192 utterances per family, index order beyond.
-                           * The order changes no output value. */
+                           * weighted by N log2 N; ties in index order) in
+                           * batches of up to 8192 utterances (index order in
+                           * larger ones).  The order changes no output value. */
   const int32_t* fft_log2n; /* [U] or NULL: forced log2 FFT size per utterance (9..15) */
   const int32_t* hop;     /* [U] or NULL: forced block hop; default N - max L + 1 */
   int32_t fft_sizes;      /* (host) with fft_log2n: bit m set for every forced size

@@ -360,54 +360,96 @@ __global__ __launch_bounds__(kPrepThreads) void prepare_kernel(SchedArgs A) {
 
 // One workgroup of 1024 threads: plans every utterance and appends it to its
 // family's list in the caller's order (a stable compaction per family).
-// Without a caller's order each list is then sorted longest work first
-// (LPT): by decreasing transform count nb (I + J) + I J of the utterance's
-// plan, weighted by N log2 N (one family can hold two sizes), ties in
-// utterance order.  The key of list position k is (work bits << 32) |
-// (2^32 - 1 - k): positive floats order as their bits, and the complement
-// puts the earlier position first among equal work.  A bitonic network in LDS
-// sorts up to kLptCap entries; a longer list keeps utterance order.
+// Without a caller's order, in batches of up to kLptCap utterances, each list
+// is then sorted longest work first (LPT): by decreasing transform count
+// nb (I + J) + I J of the utterance's plan, weighted by N log2 N (one family
+// can hold two sizes), ties in utterance order.  The 32-bit key of list
+// position k is the work's float bits without their 13 lowest (positive
+// floats order as their bits; the rest keeps a relative resolution of 2^-10,
+// ample for an order of work), then kLptCap - 1 - k, so the earlier position
+// comes first among equal work.  Each thread keeps the position, family and
+// work of the (at most kLptChunks) utterances it planned in registers, and a
+// bitonic network sorts each list: its stages with a stride of at most 64
+// exchange within 128 entries, which one wave holds in registers (two per
+// lane) and exchanges by lane shuffles; the longer strides go through LDS.
+// Larger batches keep index order.
 constexpr int kSchedThreads = 1024;
-constexpr int kLptCap = 8192;
+constexpr int kLptBits = 13, kLptCap = 1 << kLptBits, kLptChunks = kLptCap / kSchedThreads;
 
-__device__ void lpt_sort_lists(const BatchDev& b, const Sched* __restrict__ sched, int* __restrict__ lists,
-                               const int* count, unsigned long long* s_key, int* s_u, int t) {
-  for (int f = 0; f < kNumFam; ++f) {
-    const int n = count[f];
-    if (n < 2 || n > kLptCap) continue;
-    int p2 = 64;
-    while (p2 < n) p2 <<= 1;
-    int* lf = lists + (long long)f * b.U;
-    for (int k = t; k < p2; k += kSchedThreads) {
-      unsigned long long key = 0ull;  // padding: below every real key
-      if (k < n) {
-        const int u = lf[k];
-        s_u[k] = u;
-        const Sched S = sched[u];
-        const int I = b.n_src[u];
-        const float w = (float)(S.nb * (I + b.J) + I * b.J) * (float)((1 << S.log2n) * S.log2n);
-        key = ((unsigned long long)__float_as_uint(w) << 32) | (unsigned long long)(0xffffffffu - (unsigned)k);
-      }
-      s_key[k] = key;
+// The stages of sizes `size` (strides smax .. 1, smax <= 64) of the bitonic
+// network (descending where bit `size` of the index is clear) on one wave's
+// block of 128 entries held in registers: lane l holds entries i0 = 2 l and
+// i0 + 1 of the block (whose index bits above 7 are i0's).  Stride 1 pairs a
+// lane's own two entries; stride s >= 2 pairs lane l with lane l ^ (s / 2).
+__device__ __forceinline__ void lpt_wave_stages(unsigned& e0, unsigned& e1, int i0, int lane, int size, int smax) {
+  for (int s = smax; s >= 1; s >>= 1) {
+    const bool desc = (i0 & size) == 0;  // bit `size` lies above s: the same for both entries
+    if (s == 1) {
+      const unsigned a = e0, c = e1;
+      const bool swap = desc ? a < c : a > c;
+      e0 = swap ? c : a;
+      e1 = swap ? a : c;
+    } else {
+      const int m = s >> 1;
+      const unsigned p0 = __shfl_xor(e0, m), p1 = __shfl_xor(e1, m);
+      const bool take_max = ((lane & m) == 0) == desc;  // the lower index keeps the larger key when descending
+      e0 = take_max ? max(e0, p0) : min(e0, p0);
+      e1 = take_max ? max(e1, p1) : min(e1, p1);
     }
-    __syncthreads();
-    for (int size = 2; size <= p2; size <<= 1) {
-      for (int stride = size >> 1; stride > 0; stride >>= 1) {
-        for (int k = t; k < p2 / 2; k += kSchedThreads) {
-          const int lo = 2 * k - (k & (stride - 1)), hi = lo + stride;
-          const bool desc = (lo & size) == 0;  // the final merge (size = p2) is descending throughout
-          const unsigned long long a = s_key[lo], c = s_key[hi];
-          if (desc ? a < c : a > c) {
-            s_key[lo] = c;
-            s_key[hi] = a;
-          }
+  }
+}
+
+// Sorts list f (n entries) given each thread's records: chunk c of thread t
+// is utterance c * kSchedThreads + t, at position pos[c] of list fam[c] with
+// work prefix wk[c].
+__device__ void lpt_sort_list(int* __restrict__ lf, int f, int n, const int* fam, const int* pos,
+                              const unsigned* wk, unsigned* s_key, int* s_u, int t) {
+  int p2 = 128;
+  while (p2 < n) p2 <<= 1;
+  for (int k = n + t; k < p2; k += kSchedThreads) s_key[k] = 0u;  // padding: below every real key
+#pragma unroll
+  for (int c = 0; c < kLptChunks; ++c) {
+    if (fam[c] == f) {
+      s_key[pos[c]] = wk[c] | (unsigned)(kLptCap - 1 - pos[c]);
+      s_u[pos[c]] = c * kSchedThreads + t;
+    }
+  }
+  __syncthreads();
+  // Strides of at most 64 run in registers, one wave per block of 128
+  // entries; the longer ones go through LDS with workgroup barriers.
+  const int lane = t & 63, wv = t >> 6, nblk = p2 >> 7;
+  for (int wb = wv; wb < nblk; wb += kSchedThreads / 64) {
+    const int i0 = 128 * wb + 2 * lane;
+    unsigned e0 = s_key[i0], e1 = s_key[i0 + 1];
+    for (int size = 2; size <= 128; size <<= 1) lpt_wave_stages(e0, e1, i0, lane, size, size >> 1);
+    s_key[i0] = e0;
+    s_key[i0 + 1] = e1;
+  }
+  __syncthreads();
+  for (int size = 256; size <= p2; size <<= 1) {
+    for (int stride = size >> 1; stride >= 128; stride >>= 1) {
+      for (int k = t; k < p2 / 2; k += kSchedThreads) {
+        const int lo = 2 * k - (k & (stride - 1)), hi = lo + stride;
+        const bool desc = (lo & size) == 0;  // the final merge (size = p2) is descending throughout
+        const unsigned a = s_key[lo], c = s_key[hi];
+        if (desc ? a < c : a > c) {
+          s_key[lo] = c;
+          s_key[hi] = a;
         }
-        __syncthreads();
       }
+      __syncthreads();
     }
-    for (int k = t; k < n; k += kSchedThreads) lf[k] = s_u[0xffffffffu - (unsigned)(s_key[k] & 0xffffffffull)];
+    for (int wb = wv; wb < nblk; wb += kSchedThreads / 64) {
+      const int i0 = 128 * wb + 2 * lane;
+      unsigned e0 = s_key[i0], e1 = s_key[i0 + 1];
+      lpt_wave_stages(e0, e1, i0, lane, size, 64);
+      s_key[i0] = e0;
+      s_key[i0 + 1] = e1;
+    }
     __syncthreads();
   }
+  for (int k = t; k < n; k += kSchedThreads) lf[k] = s_u[kLptCap - 1 - (int)(s_key[k] & (kLptCap - 1))];
+  __syncthreads();
 }
 
 __global__ __launch_bounds__(kSchedThreads) void schedule_kernel(SchedArgs A) {
@@ -461,20 +503,29 @@ __global__ __launch_bounds__(kSchedThreads) void schedule_kernel(SchedArgs A) {
     batch_l2 = s_l2;
   }
   __syncthreads();
-  for (int c0 = 0; c0 < b.U; c0 += kSchedThreads) {
+  // Plans the utterances of list positions c0 .. c0 + kSchedThreads - 1 and
+  // appends them to their families' lists; returns this thread's family (-1:
+  // none), its list position and the prefix of its sort key.
+  auto plan_chunk = [&](int c0, int& pos, unsigned& wk) __attribute__((always_inline)) {
     const int idx = c0 + t;
     int fam = -1, u = -1;
+    Sched S = {0, 0, 0, 0, 0, 0};
     if (idx < b.U) {
       u = b.order ? b.order[idx] : idx;
       if (u < 0 || u >= b.U) {
         err |= RSIM_DEV_BADDESC;
         u = -1;
       } else {
-        const Sched S = plan_utterance(b, tune, u, sched[u].lmax, batch_l2, err);
+        S = plan_utterance(b, tune, u, sched[u].lmax, batch_l2, err);
         sched[u] = S;
         b.out_len[u] = S.tu;
         fam = S.nb > 0 ? family_of_log2n(S.log2n) : -1;
       }
+    }
+    if (fam >= 0) {
+      const int I = b.n_src[u];
+      const float work = (float)(S.nb * (I + b.J) + I * b.J) * (float)((1 << S.log2n) * S.log2n);
+      wk = (__float_as_uint(work) >> kLptBits) << kLptBits;
     }
     int pre[kNumFam];
 #pragma unroll
@@ -489,7 +540,8 @@ __global__ __launch_bounds__(kSchedThreads) void schedule_kernel(SchedArgs A) {
       if (fam == f) {
         int o = s_base[f];
         for (int k = 0; k < w; ++k) o += s_wcnt[f][k];
-        lists[(long long)f * b.U + o + pre[f]] = u;
+        pos = o + pre[f];
+        lists[(long long)f * b.U + pos] = u;
       }
     }
     __syncthreads();
@@ -499,12 +551,31 @@ __global__ __launch_bounds__(kSchedThreads) void schedule_kernel(SchedArgs A) {
       s_base[t] += tot;
     }
     __syncthreads();
+    return fam;
+  };
+  const bool lpt = !b.order && b.U <= kLptCap;
+  int r_fam[kLptChunks], r_pos[kLptChunks];
+  unsigned r_wk[kLptChunks];
+#pragma unroll
+  for (int c = 0; c < kLptChunks; ++c) {
+    r_fam[c] = -1;
+    r_pos[c] = 0;
+    r_wk[c] = 0u;
+    if (c * kSchedThreads < b.U) r_fam[c] = plan_chunk(c * kSchedThreads, r_pos[c], r_wk[c]);
+  }
+  for (int c0 = kLptChunks * kSchedThreads; c0 < b.U; c0 += kSchedThreads) {
+    int pos = 0;
+    unsigned wk = 0u;
+    plan_chunk(c0, pos, wk);
   }
   if (t < kNumFam) hdr->count[t] = s_base[t];
-  if (!b.order) {
-    __shared__ unsigned long long s_key[kLptCap];
+  if (lpt) {
+    __shared__ unsigned s_key[kLptCap];
     __shared__ int s_u[kLptCap];
-    lpt_sort_lists(b, sched, lists, s_base, s_key, s_u, t);
+    for (int f = 0; f < kNumFam; ++f) {
+      const int n = s_base[f];
+      if (n >= 2) lpt_sort_list(lists + (long long)f * b.U, f, n, r_fam, r_pos, r_wk, s_key, s_u, t);
+    }
   }
   if (err) flag_status(err);
 }
