@@ -1317,6 +1317,9 @@ __global__ __launch_bounds__(T, 2) void mix_rir_kernel(MixArgs A) {
     const int log2n = __builtin_amdgcn_readfirstlane(A.sched[u].log2n);
     if (i >= uni(b.n_src[u])) continue;
     const long long r = ((long long)u * NS + i) * J + j;
+    // The previous item's transform ended with reads of the exchange buffer
+    // this item's first exchange writes (its parity starts again at 0).
+    __syncthreads();
     dispatch_plan<T>(log2n, [&](auto pl) __attribute__((always_inline)) {
       using PL = decltype(pl);
       Xch<PL> lds{lds_raw, 0};
@@ -1805,6 +1808,9 @@ __global__ __launch_bounds__(T, 2) void bwd_rir_kernel(BwdArgs A) {
     const int u = __builtin_amdgcn_readfirstlane(A.list[(long long)A.fam * b.U + pos]);
     const int log2n = __builtin_amdgcn_readfirstlane(A.sched[u].log2n);
     if (i >= uni(b.n_src[u])) continue;
+    // The previous item's transform ended with reads of the exchange buffer
+    // this item's first exchange writes (its parity starts again at 0).
+    __syncthreads();
     dispatch_plan<T>(log2n, [&](auto pl) __attribute__((always_inline)) {
       using PL = decltype(pl);
       Xch<PL> lds{lds_raw, 0};
