@@ -785,6 +785,7 @@ def main() -> int:
         tune_info = {"source": "measured on the first epoch's batch", "variant": entry["variant"],
                      "ms": {k: v["ms"] for k, v in entry["measured"]["sizes"].items()},
                      "policy_ms": entry.get("policy_ms"),
+                     "sizes_from": entry.get("sizes_from"),
                      "seconds": round(time.perf_counter() - t1, 2)}
         log(f"tuned in {tune_info['seconds']} s: variants {entry['variant']}, "
             + ", ".join(f"N=2^{k}: " + "/".join(f"{t:.3f}" for t in v.values()) + " ms"

@@ -285,6 +285,26 @@ def measure_policy(db, alpha, entry: dict, reps: int = 3, stream=None) -> dict:
     return out
 
 
+def keep_sizes_from_batch_size(entry: dict, shapes) -> int:
+    """With one size per batch: disable (cost 0) every size below the one the
+    schedule picks for `shapes` ((nx, I, J, lmax) of the tuned batch) and
+    return that size's log2 (0, and nothing changed, when no size serves every
+    utterance or the policy is a size per utterance).  A batch that one size
+    serves is served by every larger one, so no batch loses its plan; the
+    kernel families of the disabled sizes are then neither sized nor launched
+    (an empty family still costs a launch in the epoch's graph)."""
+    if not entry.get("one_size", True):
+        return 0
+    l2 = batch_log2n(shapes, entry["cost_fft"], entry["cost_mac"])
+    if l2:
+        for m in LOG2N:
+            if m < l2:
+                entry["cost_fft"][m - 9] = 0.0
+                entry["cost_mac"][m - 9] = 0.0
+        entry["sizes_from"] = l2
+    return l2
+
+
 def entry_to_tune(entry: dict):
     from . import rsim
 
@@ -292,15 +312,18 @@ def entry_to_tune(entry: dict):
                            entry.get("variant"))
 
 
-def tune(db, alpha, save: Optional[str] = None, policy: bool = True, **kw):
-    """measure() then fit(), then (policy) the size policy by measure_policy():
-    the RsimTune for this GPU and the table entry.  With save, the entry is
-    merged into that JSON file under device_name()."""
+def tune(db, alpha, save: Optional[str] = None, policy: bool = True, prune: bool = True, **kw):
+    """measure() then fit(), then (policy) the size policy by measure_policy(),
+    then (prune, with one size per batch) keep_sizes_from_batch_size() on this
+    batch: the RsimTune for this GPU and the table entry.  With save, the
+    entry is merged into that JSON file under device_name()."""
     entry = fit(measure(db, alpha, **kw))
     if policy:
         pm = measure_policy(db, alpha, entry, reps=kw.get("reps", 3), stream=kw.get("stream"))
         entry["one_size"] = choose_policy(pm["one_size"], pm["per_utterance"])
         entry["policy_ms"] = pm
+    if prune:
+        keep_sizes_from_batch_size(entry, [s[1:] for s in batch_shapes(db)])
     if save:
         data = {}
         if os.path.exists(save):

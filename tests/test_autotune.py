@@ -128,3 +128,22 @@ def test_policy_keeps_one_size_within_the_noise():
     assert autotune.choose_policy(10.0, 9.9) is True     # 1 % faster: noise
     assert autotune.choose_policy(10.0, 9.5) is False    # 5 % faster: per utterance
     assert autotune.choose_policy(10.0, 11.0) is True
+
+
+def test_pruning_keeps_the_batch_size_and_every_larger_one():
+    f, c = autotune.model_costs()
+    shapes = [(16000 * 3, 2, 2, 3000), (16000 * 9, 3, 2, 5000), (16000, 1, 2, 700)]
+    entry = {"cost_fft": list(f), "cost_mac": list(c), "one_size": True}
+    m = autotune.batch_log2n(shapes, f, c)
+    assert m > 9
+    assert autotune.keep_sizes_from_batch_size(entry, shapes) == m
+    assert entry["sizes_from"] == m
+    for k in autotune.LOG2N:
+        assert (entry["cost_fft"][k - 9] > 0) == (k >= m) and (entry["cost_mac"][k - 9] > 0) == (k >= m)
+    # the pruned table picks the same size, and every utterance still has one
+    assert autotune.batch_log2n(shapes, entry["cost_fft"], entry["cost_mac"]) == m
+    for nx, I, J, L in shapes + [(50, 1, 2, 20)]:
+        assert autotune.utterance_log2n(nx, I, J, L, entry["cost_fft"], entry["cost_mac"]) >= m
+    # a size per utterance keeps every size
+    e2 = {"cost_fft": list(f), "cost_mac": list(c), "one_size": False}
+    assert autotune.keep_sizes_from_batch_size(e2, shapes) == 0 and e2["cost_fft"] == list(f)

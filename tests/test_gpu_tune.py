@@ -88,7 +88,7 @@ def test_tuner_table_drives_a_correct_mix():
     rsim.truncate_batch(db, 20.0)
     tune, entry = autotune.tune(db, alpha, min_probe=16, reps=2)
     assert all(0 <= v <= 4 for v in entry["variant"]) and entry["variant"][5] in (0, 4)
-    assert all(c > 0 and np.isfinite(c) for c in entry["cost_fft"] + entry["cost_mac"])
+    assert all(c >= 0 and np.isfinite(c) for c in entry["cost_fft"] + entry["cost_mac"])
     sizes = {int(m): r for m, r in entry["measured"]["sizes"].items()}
     shapes = autotune.batch_shapes(db)
     assert 15 in sizes and sizes[15]["utterances"] == len(shapes)
@@ -96,6 +96,11 @@ def test_tuner_table_drives_a_correct_mix():
     # whole batch, no other size timed on the whole batch ran faster
     hs = [(nx, I, J, L) for _, nx, I, J, L in shapes]
     m_star = autotune.batch_log2n(hs, entry["cost_fft"], entry["cost_mac"])
+    # with one size per batch the sizes below it are disabled, the rest kept
+    if entry["one_size"]:
+        assert entry["sizes_from"] == m_star
+        for m in autotune.LOG2N:
+            assert (entry["cost_fft"][m - 9] > 0) == (m >= m_star)
     whole = {m: r["ms"][str(entry["variant"][autotune.FAMILY[m]])] for m, r in sizes.items()
              if r["utterances"] == len(shapes)}
     if m_star in whole:
