@@ -2182,22 +2182,19 @@ __global__ __launch_bounds__(256) void power_kernel(BatchDev b, const float* __r
 // ========================================================= image-method RIRs
 // Eq. (1): the RIR is the sum over the (2K+1)^3 images of the source in the
 // mirrored rooms (a, b, c) of refl^g / d at tap ceil(d fs / c0).  One
-// workgroup per RIR: every image is evaluated in binary64 (no contraction, so
-// each product and sum is rounded on its own, as the definition is written),
-// its amplitude quantised to a multiple of 2^-40 and added with a 64-bit
-// integer atomic to an LDS window of kImgWindow taps, so the sums are exact
-// and do not depend on the order of the images.  The taps are produced one
-// window at a time; a first pass sorts the images into per-window lists by a
-// float32 estimate of their distance (with margins far wider than its
-// rounding), so each window evaluates only its own images, with every lane
-// busy.  RIRs with more list entries than fit (orders above 10) take every
-// image in every window instead.
-constexpr int kImgThreads = 256;
-constexpr int kImgWindow = 2048;
+// workgroup of 1024 threads per RIR: every image is evaluated in binary64 (no
+// contraction, so each product and sum is rounded on its own, as the
+// definition is written), its amplitude quantised to a multiple of 2^-40 and
+// added with a 64-bit integer atomic to an LDS accumulator of kImgWindow taps
+// (128 KB, the whole RIR up to 16384 taps), so the sums are exact and do not
+// depend on the order of the images.  Longer RIRs are produced one window at
+// a time; with more than one window, a float32 estimate of an image's
+// distance (with margins far wider than its rounding) skips the windows its
+// tap cannot fall in before the exact evaluation.
+constexpr int kImgThreads = 1024;
+constexpr int kImgWindow = 16384;
 constexpr int kImgMaxOrder = 16;
-constexpr int kImgMaxWin = 16;     // windows per RIR: up to 32768 taps
-constexpr int kImgListOrder = 10;  // orders with per-window lists (5-bit indices)
-constexpr int kImgListMax = 10240;
+constexpr int kImgMaxLen = 32768;  // taps per RIR, at most (two windows)
 
 struct ImageArgs {
   const double* geom;  // [n_rir][9]: room Lx Ly Lz, source xyz, mic xyz
@@ -2271,23 +2268,15 @@ struct ImageIter {
 
 __global__ __launch_bounds__(kImgThreads) void image_kernel(ImageArgs A) {
 #pragma clang fp contract(off)
-  // acc holds a window's tap sums; before the windows it holds the list
-  // counters cnt[wi * kImgThreads + t] (thread t's images in window wi).
   __shared__ unsigned long long acc[kImgWindow];
-  __shared__ unsigned short list[kImgListMax];  // (ia << 10) | (ib << 5) | ic
   __shared__ double sq[3][2 * kImgMaxOrder + 1];
   __shared__ float sqf[3][2 * kImgMaxOrder + 1];
   __shared__ double pw[3 * kImgMaxOrder + 1];
-  __shared__ int s_base[kImgMaxWin + 1], s_wsum[kImgThreads / 64];
-  static_assert(kImgMaxWin * kImgThreads * sizeof(unsigned short) <= sizeof(acc), "counters fit in acc");
-  unsigned short* cnt = reinterpret_cast<unsigned short*>(acc);
-  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int t = threadIdx.x;
   const int K = A.order, S = 2 * K + 1, S2 = S * S, V = S2 * S;
   const int q2 = kImgThreads / S2, q1 = (kImgThreads % S2) / S, q0 = kImgThreads % S;
   const ImageIter it0{t / S2, (t % S2) / S, t % S};
   const float taps_per_m = (float)(A.fs / A.c0);
-  const bool can_list = K <= kImgListOrder;
-  constexpr int kPer = kImgMaxWin * kImgThreads / kImgThreads;  // counters scanned per thread
   int err = 0;
   for (int r = blockIdx.x; r < A.n_rir; r += gridDim.x) {
     const int len = uni(A.len[r]);
@@ -2302,7 +2291,6 @@ __global__ __launch_bounds__(kImgThreads) void image_kernel(ImageArgs A) {
     const double refl = A.refl[r];
     const bool ok = image_geometry_ok(g, refl);
     if (!ok) err |= RSIM_DEV_BADDESC;
-    const bool listing = ok && can_list;
     __syncthreads();  // the previous RIR's readers of the shared arrays are done
     if (t < 3 * S) {
       const int ax = t / S, a = t - ax * S - K;
@@ -2317,74 +2305,21 @@ __global__ __launch_bounds__(kImgThreads) void image_kernel(ImageArgs A) {
         p = p * refl;
       }
     }
-    if (listing)
-      for (int wi = 0; wi < kImgMaxWin; ++wi) cnt[wi * kImgThreads + t] = 0;
-    __syncthreads();
-    bool listed = false;
-    if (listing) {
-      // Pass 1: each thread counts its images per window in its own counters.
-      ImageIter im = it0;
-      for (int v = t; v < V; v += kImgThreads) {
-        int wlo, whi;
-        image_windows((sqf[0][im.ia] + sqf[1][im.ib]) + sqf[2][im.ic], taps_per_m, nw, wlo, whi);
-        for (int wi = wlo; wi <= whi; ++wi) cnt[wi * kImgThreads + t] += 1;
-        im.step(S, q2, q1, q0);
-      }
-      __syncthreads();
-      // Exclusive scan of the counters in (window, thread) order: thread t
-      // takes kPer consecutive counters, the threads' sums are scanned
-      // within each wave and across the waves.
-      int part = 0;
-      for (int k = 0; k < kPer; ++k) part += cnt[t * kPer + k];
-      int x = part;
-      for (int d = 1; d < 64; d <<= 1) {
-        const int y = __shfl_up(x, d);
-        if (lane >= d) x += y;
-      }
-      if (lane == 63) s_wsum[wave] = x;
-      __syncthreads();
-      int before = x - part;
-      for (int w = 0; w < wave; ++w) before += s_wsum[w];
-      const int total = s_wsum[0] + s_wsum[1] + s_wsum[2] + s_wsum[3];
-      for (int k = 0; k < kPer; ++k) {
-        const int c = cnt[t * kPer + k];
-        cnt[t * kPer + k] = (unsigned short)(total <= kImgListMax ? before : 0);
-        before += c;
-      }
-      __syncthreads();
-      if (t <= nw) s_base[t] = t < nw ? (int)cnt[t * kImgThreads] : total;
-      listed = total <= kImgListMax;
-      __syncthreads();  // window starts read before pass 2 advances the counters
-      // Pass 2: each thread writes its images at its own positions (same
-      // estimate as pass 1, so the same windows).
-      if (listed) {
-        ImageIter jm = it0;
-        for (int v = t; v < V; v += kImgThreads) {
-          int wlo, whi;
-          image_windows((sqf[0][jm.ia] + sqf[1][jm.ib]) + sqf[2][jm.ic], taps_per_m, nw, wlo, whi);
-          for (int wi = wlo; wi <= whi; ++wi) {
-            const int e = cnt[wi * kImgThreads + t];
-            cnt[wi * kImgThreads + t] = (unsigned short)(e + 1);
-            list[e] = (unsigned short)((jm.ia << 10) | (jm.ib << 5) | jm.ic);
-          }
-          jm.step(S, q2, q1, q0);
-        }
-      }
-    }
     for (int wi = 0; wi < nw; ++wi) {
       const int w0 = wi * kImgWindow, wn = min(kImgWindow, len - w0);
-      __syncthreads();  // lists complete; the counters (or the previous window) no longer read
+      __syncthreads();  // the tables are written; the previous window's taps are stored
       for (int k = t; k < wn; k += kImgThreads) acc[k] = 0ull;
       __syncthreads();
-      if (listed) {
-        for (int e = s_base[wi] + t; e < s_base[wi + 1]; e += kImgThreads) {
-          const unsigned c = list[e];
-          image_add(sq, pw, K, (int)(c >> 10), (int)((c >> 5) & 31), (int)(c & 31), A.fs, A.c0, w0, wn, acc);
-        }
-      } else if (ok) {
+      if (ok) {
         ImageIter im = it0;
         for (int v = t; v < V; v += kImgThreads) {
-          image_add(sq, pw, K, im.ia, im.ib, im.ic, A.fs, A.c0, w0, wn, acc);
+          bool in = true;
+          if (nw > 1) {
+            int wlo, whi;
+            image_windows((sqf[0][im.ia] + sqf[1][im.ib]) + sqf[2][im.ic], taps_per_m, nw, wlo, whi);
+            in = wlo <= wi && wi <= whi;
+          }
+          if (in) image_add(sq, pw, K, im.ia, im.ib, im.ic, A.fs, A.c0, w0, wn, acc);
           im.step(S, q2, q1, q0);
         }
       }
@@ -3708,11 +3643,11 @@ rsim_status image_args_ok(int n_rir, int order, double fs, double c0, int max_le
   if (n_rir < 0 || order < 0 || order > kImgMaxOrder || !(fs > 0.0) || !(c0 > 0.0) || max_len < 0 || h_len < 0 ||
       !std::isfinite(fs) || !std::isfinite(c0))
     return RSIM_EINVAL;
-  if (max_len > kImgMaxWin * kImgWindow) return RSIM_EUNSUPPORTED;
+  if (max_len > kImgMaxLen) return RSIM_EUNSUPPORTED;
   return RSIM_OK;
 }
 
-// One workgroup per RIR, at most 8 per compute unit.
+// Persistent workgroups, one per compute unit, taking the RIRs in turn.
 void plan_image(Node& n, const double* geom, const double* refl, int n_rir, int order, double fs, double c0, float* h,
                 long long h_len, const int64_t* off, const int32_t* len, int max_len) {
   ImageArgs A;
@@ -3729,8 +3664,9 @@ void plan_image(Node& n, const double* geom, const double* refl, int n_rir, int 
   A.c0 = c0;
   const DevState& st = dev_state();
   const int cus = st.cus > 0 ? st.cus : 256;
+  // one workgroup per CU (its accumulator takes 128 KB of LDS), each taking RIRs in turn
   n.set(reinterpret_cast<const void*>(&image_kernel),
-        dim3((unsigned)std::max<long long>(1, std::min<long long>(n_rir, (long long)cus * 8))), dim3(kImgThreads), A);
+        dim3((unsigned)std::max<long long>(1, std::min<long long>(n_rir, (long long)cus))), dim3(kImgThreads), A);
 }
 
 }  // namespace

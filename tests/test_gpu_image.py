@@ -64,6 +64,28 @@ def test_orders_bit_exact(order):
 
 
 @pytest.mark.gpu
+def test_rirs_longer_than_one_accumulator_window_bit_exact():
+    # large rooms, so that images reach past 16384 taps (the kernel's LDS
+    # accumulator): lengths around the window edge and up to the 32768 limit;
+    # the taps of the second window are chosen by a float32 distance estimate
+    rng = np.random.default_rng(41)
+    geoms, refls = [], []
+    lens = [16383, 16384, 16385, 20000, 32768]
+    for k in range(len(lens)):
+        room = rng.uniform([40.0, 30.0, 20.0], [70.0, 60.0, 40.0])
+        src = rng.uniform(0.5, room - 0.5)
+        mic = rng.uniform(0.5, room - 0.5)
+        geoms.append(np.concatenate([room, src, mic]))
+        refls.append(float(rng.uniform(0.6, 0.95)))
+    g, r = np.array(geoms), np.array(refls)
+    h, off = _gpu_rirs(g, r, lens, order=8)
+    for k in range(len(lens)):
+        ref = im.image_rir(g[k, :3], g[k, 3:6], g[k, 6:], r[k], lens[k], order=8)
+        assert np.count_nonzero(ref[16384:]) > 0 or lens[k] <= 16384
+        assert np.array_equal(h[off[k]: off[k] + lens[k]], ref), (k, int(np.count_nonzero(h[off[k]: off[k] + lens[k]] != ref)))
+
+
+@pytest.mark.gpu
 def test_bad_geometry_and_ranges():
     torch = cuda()
     from paper_1712_03439_amd import rsim
