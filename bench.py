@@ -31,7 +31,7 @@ if ROOT not in sys.path:
 
 # Published MI355X peaks: HBM3E bandwidth and the FP32 vector rate.  The FP32
 # figure counts packed FP32 instructions (two lanes' worth per instruction);
-# this build emits none, so the unpacked rate, 256 CUs x 64 lanes x 2 FLOP
+# the library emits none, so the unpacked rate, 256 CUs x 64 lanes x 2 FLOP
 # per FMA x 2.4 GHz = 78.6 TFLOP/s, is the practical ceiling of its
 # arithmetic and is reported beside the published one.
 HBM_PEAK_GBS = 8000.0
@@ -733,7 +733,7 @@ def main() -> int:
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(f"bench.py: this build runs the hot path on one GPU; --gpus {args.gpus} is not "
+        print(f"bench.py: the library runs the hot path on one GPU; --gpus {args.gpus} is not "
               f"supported (each GPU would take its own share of the utterances; this path runs on one GPU).",
               file=sys.stderr)
         return 2
@@ -914,7 +914,7 @@ def main() -> int:
                 "frac": round(alu / FP32_PEAK_TFLOPS, 4)},
         "alu_unpacked": {"achieved": round(alu, 2), "peak": FP32_UNPACKED_TFLOPS, "unit": "TFLOP/s",
                          "frac": round(alu / FP32_UNPACKED_TFLOPS, 4),
-                         "note": "the ceiling of this build's arithmetic: it emits no packed FP32 instructions"},
+                         "note": "the ceiling of the library's arithmetic: it emits no packed FP32 instructions"},
         "dominant_kernel": kernel,
         "kernel_ms": {"cut": round(float(np.mean(trunc_ms)), 4), "mix": round(float(np.mean(mix_ms)), 4)},
         "cut_hbm": {"achieved": round(float(np.mean(byt_cut)) / (float(np.mean(trunc_ms)) * 1e-3) / 1e9, 1),
