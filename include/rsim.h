@@ -271,14 +271,15 @@ rsim_status rsim_snr_gains(const double* p_dry, const double* snr_db, int32_t I,
  * is quantised to a multiple of 2^-40 (round half to even) and the taps sum
  * these integers exactly, so the result does not depend on the order of the
  * images; a tap is then converted to binary64, scaled by 2^-40 and rounded
- * once to float32.  max_len >= every len[r] (host) sizes the launch.
+ * once to float32.  max_len (host) bounds every len[r].
  * Validation: n_rir >= 0, 0 <= order <= 16, fs > 0, c0 > 0, max_len >= 0
  * (RSIM_EINVAL); max_len <= 32768 (RSIM_EUNSUPPORTED).  Each RIR needs room
  * sides below 10 km, its source and microphone at least 5 mm inside every wall
  * and at least 1 cm apart (so every image is at least 1 cm from the
  * microphone and no tap's integer sum can overflow) and refl in [0, 1];
- * otherwise its taps are written as zeros and RSIM_DEV_BADDESC is set.  A RIR whose taps fall outside [0, h_len) or whose len exceeds
- * max_len is not written (RSIM_DEV_BADDESC).
+ * otherwise its taps are written as zeros and RSIM_DEV_BADDESC is set.  A
+ * RIR whose taps fall outside [0, h_len) or whose len exceeds max_len is not
+ * written (RSIM_DEV_BADDESC).
  */
 rsim_status rsim_image_rir(const double* geom, const double* refl, int32_t n_rir, int32_t order, double fs,
                            double c0, float* h, int64_t h_len, const int64_t* off, const int32_t* len,

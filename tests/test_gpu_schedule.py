@@ -89,3 +89,25 @@ def test_device_order_beyond_the_sort_capacity_keeps_index_order():
         n = int(count[f])
         assert [int(u) for u in lists[f, :n]] == fam[f]
     assert sum(int(c) for c in count) > LPT_CAP
+
+
+@pytest.mark.gpu
+def test_adjoint_bits_do_not_depend_on_the_order():
+    # the adjoint's work items follow the same lists: the device's
+    # longest-work-first order and a caller's random order give the same bits
+    torch = cuda()
+    from paper_1712_03439_amd import rsim
+
+    b = synth.make_config2(n_utt=40, epoch=6)
+    outs = []
+    for order in (None, np.random.default_rng(2).permutation(b.n_utt).astype(np.int32)):
+        db = rsim.DeviceBatch(b, order=order)
+        alpha = torch.from_numpy(rsim.batch_gains(db, b.snr_db)).cuda()
+        rsim.truncate_batch(db, 20.0)
+        y = rsim.mix(db, alpha, y=torch.zeros(max(db.y_len, 1), dtype=torch.float32, device="cuda"))
+        g = torch.sin(torch.arange(y.numel(), device="cuda", dtype=torch.float32) * 0.01)
+        gx, gh, ga = rsim.mix_backward(db, alpha, g)
+        torch.cuda.synchronize()
+        outs.append([t.cpu().numpy().view(np.uint32) for t in (y, gx, gh, ga)])
+    for a, c in zip(*outs):
+        assert np.array_equal(a, c)
