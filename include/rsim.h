@@ -76,9 +76,12 @@ typedef struct rsim_batch {
   const int64_t* out_off; /* [U] */
   const int32_t* out_stride; /* [U] */
   int32_t* out_len;       /* [U] written: T_u */
-  const int32_t* order;   /* [U] or NULL.  Given: the processing order (a
-                           * permutation of 0..U-1; the caller's longest-work-first
-                           * order, say).  NULL: the device schedule orders each
+  const int32_t* order;   /* [U] or NULL.  Given: the processing order, a
+                           * permutation of 0..U-1 (the caller's longest-work-first
+                           * order, say); with at most 65536 utterances a repeated
+                           * entry is skipped and an utterance left out gets no
+                           * output (T_u = 0), both with RSIM_DEV_BADDESC.  NULL:
+                           * the device schedule orders each
                            * kernel family's utterances longest work first after
                            * the cut (transforms nb (I + J) + I J of the plan,
                            * weighted by N log2 N; ties in index order) in

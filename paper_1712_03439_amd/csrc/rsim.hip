@@ -375,6 +375,7 @@ __global__ __launch_bounds__(kPrepThreads) void prepare_kernel(SchedArgs A) {
 // Larger batches keep index order.
 constexpr int kSchedThreads = 1024;
 constexpr int kLptBits = 13, kLptCap = 1 << kLptBits, kLptChunks = kLptCap / kSchedThreads;
+constexpr int kSeenBits = 65536;  // utterances whose caller's order is checked
 
 // The stages of sizes `size` (strides smax .. 1, smax <= 64) of the bitonic
 // network (descending where bit `size` of the index is clear) on one wave's
@@ -503,6 +504,15 @@ __global__ __launch_bounds__(kSchedThreads) void schedule_kernel(SchedArgs A) {
     batch_l2 = s_l2;
   }
   __syncthreads();
+  // A caller's order must be a permutation: with up to kSeenBits utterances a
+  // bitmap in LDS finds repeated entries (skipped, flagged) and utterances the
+  // order leaves out (no output, flagged).
+  __shared__ unsigned s_seen[kSeenBits / 32];
+  const bool check_order = b.order && b.U <= kSeenBits;
+  if (check_order) {
+    for (int k = t; k < kSeenBits / 32; k += kSchedThreads) s_seen[k] = 0u;
+    __syncthreads();
+  }
   // Plans the utterances of list positions c0 .. c0 + kSchedThreads - 1 and
   // appends them to their families' lists; returns this thread's family (-1:
   // none), its list position and the prefix of its sort key.
@@ -512,7 +522,12 @@ __global__ __launch_bounds__(kSchedThreads) void schedule_kernel(SchedArgs A) {
     Sched S = {0, 0, 0, 0, 0, 0};
     if (idx < b.U) {
       u = b.order ? b.order[idx] : idx;
-      if (u < 0 || u >= b.U) {
+      bool dup = false;
+      if (b.order && u >= 0 && u < b.U && check_order) {
+        const unsigned bit = 1u << (u & 31);
+        dup = (atomicOr(&s_seen[u >> 5], bit) & bit) != 0;
+      }
+      if (u < 0 || u >= b.U || dup) {
         err |= RSIM_DEV_BADDESC;
         u = -1;
       } else {
@@ -524,7 +539,7 @@ __global__ __launch_bounds__(kSchedThreads) void schedule_kernel(SchedArgs A) {
     }
     if (fam >= 0) {
       const int I = b.n_src[u];
-      const float work = (float)(S.nb * (I + b.J) + I * b.J) * (float)((1 << S.log2n) * S.log2n);
+      const float work = ((float)S.nb * (float)(I + b.J) + (float)(I * b.J)) * (float)((1 << S.log2n) * S.log2n);
       wk = (__float_as_uint(work) >> kLptBits) << kLptBits;
     }
     int pre[kNumFam];
@@ -569,6 +584,16 @@ __global__ __launch_bounds__(kSchedThreads) void schedule_kernel(SchedArgs A) {
     plan_chunk(c0, pos, wk);
   }
   if (t < kNumFam) hdr->count[t] = s_base[t];
+  if (check_order) {
+    for (int u = t; u < b.U; u += kSchedThreads) {
+      if (!(s_seen[u >> 5] & (1u << (u & 31)))) {
+        const Sched none = {0, 0, 0, 0, 0, 0};
+        sched[u] = none;
+        b.out_len[u] = 0;
+        err |= RSIM_DEV_BADDESC;
+      }
+    }
+  }
   if (lpt) {
     __shared__ unsigned s_key[kLptCap];
     __shared__ int s_u[kLptCap];

@@ -38,7 +38,7 @@ def _work(b, sched, u):
     # bits without the 13 lowest
     l2, nb = int(sched[u, 0]), int(sched[u, 2])
     I, J = int(b.n_src[u]), int(b.n_mic)
-    w = np.float32(nb * (I + J) + I * J) * np.float32((1 << l2) * l2)
+    w = (np.float32(nb) * np.float32(I + J) + np.float32(I * J)) * np.float32((1 << l2) * l2)
     return int(np.array([w], np.float32).view(np.uint32)[0]) >> 13
 
 
@@ -111,3 +111,30 @@ def test_adjoint_bits_do_not_depend_on_the_order():
         outs.append([t.cpu().numpy().view(np.uint32) for t in (y, gx, gh, ga)])
     for a, c in zip(*outs):
         assert np.array_equal(a, c)
+
+
+@pytest.mark.gpu
+def test_a_caller_order_that_is_not_a_permutation_is_flagged():
+    # utterance 3 twice, utterance 5 left out: 3 is mixed once, 5 gets no
+    # output, every other utterance is as with a valid order, and the status
+    # word says so
+    torch = cuda()
+    from paper_1712_03439_amd import rsim
+
+    b = synth.make_config2(n_utt=12, epoch=9)
+    good = np.arange(b.n_utt, dtype=np.int32)[::-1].copy()
+    bad = good.copy()
+    bad[list(good).index(5)] = 3
+    rsim.device_status()
+    y0, c0, s0, _ = _run(b, order=good)
+    assert rsim.device_status() == 0
+    y1, c1, s1, _ = _run(b, order=bad)
+    assert rsim.device_status() & rsim.DEV_BADDESC
+    assert int(s1[5, 2]) == 0 and int(s0[5, 2]) > 0
+    for u in range(b.n_utt):
+        if u == 5:
+            continue
+        T = int(s0[u, 3])
+        for j in range(b.n_mic):
+            o = int(b.out_off[u]) + j * int(b.out_stride[u])
+            assert np.array_equal(y1[o:o + T].view(np.uint32), y0[o:o + T].view(np.uint32)), (u, j)
