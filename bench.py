@@ -40,15 +40,42 @@ FP32_UNPACKED_TFLOPS = 78.6
 COUNTERS = os.path.join(ROOT, "profiles", "mix_kernel_batched2048_hbm_counters.json")
 
 
+def _code_only(text: str) -> str:
+    """C/C++ source without its comments and blank lines (string and character
+    literals are kept as they are), so that a change of comments alone does
+    not make counters stale."""
+    out, i, n = [], 0, len(text)
+    while i < n:
+        c = text[i]
+        if c in "\"'":
+            j = i + 1
+            while j < n and text[j] != c:
+                j += 2 if text[j] == "\\" else 1
+            out.append(text[i:j + 1])
+            i = j + 1
+        elif text.startswith("//", i):
+            j = text.find("\n", i)
+            i = n if j < 0 else j
+        elif text.startswith("/*", i):
+            j = text.find("*/", i + 2)
+            i = n if j < 0 else j + 2
+        else:
+            out.append(c)
+            i += 1
+    lines = (ln.rstrip() for ln in "".join(out).split("\n"))
+    return "\n".join(ln for ln in lines if ln)
+
+
 def source_digest() -> str:
-    """Digest of the kernel sources; counters taken on other sources are stale."""
+    """Digest of the kernel sources' code (comments left out); counters taken
+    on other code are stale."""
     import hashlib
 
     h = hashlib.sha256()
     for rel in ("paper_1712_03439_amd/csrc/rsim.hip", "paper_1712_03439_amd/csrc/fft_engine.hpp",
                 "paper_1712_03439_amd/csrc/kernels.hpp", "include/rsim.h"):
-        with open(os.path.join(ROOT, rel), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(ROOT, rel), encoding="utf-8") as f:
+            h.update(_code_only(f.read()).encode())
     return h.hexdigest()
 
 

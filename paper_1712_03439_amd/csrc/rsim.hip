@@ -7,15 +7,18 @@
 //   schedule_kernel  FFT size / hop / block count per utterance (one size for
 //                    the batch or each its own, as the text after eq. (6)
 //                    chooses per filtering), lists per workgroup size in the
-//                    caller's order
+//                    caller's order or, without one, longest work first
 //   mix_kernel<T>    persistent workgroups pop work items (an utterance, or
-//                    one mic group of it); each computes the RIR spectra once
-//                    (Sec. 2.2: the RIR FFT is not repeated per block), then
-//                    walks the blocks: FFT of each source block, spectral
-//                    multiply-accumulate over sources per mic, inverse FFT,
-//                    overlap-add (eq. (6)) into y (eq. (2)).
+//                    one mic group of it, or a range of its blocks); each
+//                    computes the RIR spectra once (Sec. 2.2: the RIR FFT is
+//                    not repeated per block), then walks the blocks: FFT of
+//                    each source block, spectral multiply-accumulate over
+//                    sources per mic, inverse FFT, overlap-add (eq. (6)) into
+//                    y (eq. (2)).  With block ranges, mix_rir_kernel<T> forms
+//                    the RIR spectra first and mix_seam_kernel adds the seams.
 // Adjoint (rsim_mix_backward): bwd_kernel<T> per utterance or block range,
-// bwd_finish_kernel<T> for split utterances, bwd_zero_kernel for idle ones.
+// bwd_rir_kernel<T> and bwd_finish_kernel<T> for split utterances,
+// bwd_zero_kernel for idle ones.
 #include <hip/hip_runtime.h>
 
 #include <cmath>

@@ -74,3 +74,10 @@ def test_error_record_of_a_parity_case():
     assert bench._forward_error(("w", xs, hs, snrs, 20.0, bad, outs))[1] == float("inf")
     info = bench.host_info()
     assert info["os_cpu_count"] >= 1 and "cpu_model" in info
+
+
+def test_counter_digest_ignores_comments_only():
+    text = 'int a = 1; // note\n/* block\n note */ const char* s = "a // b"; char q = \'"\';\n\n  int b; /* x */\n'
+    assert bench._code_only(text) == 'int a = 1;\n const char* s = "a // b"; char q = \'"\';\n  int b;'
+    assert bench._code_only(text.replace("note", "other note")) == bench._code_only(text)
+    assert bench._code_only(text.replace("a = 1", "a = 2")) != bench._code_only(text)
