@@ -4,10 +4,18 @@ Argument marshalling only: every step of the hot path runs in the HIP kernels
 behind the C ABI.  PyTorch provides device memory and the current stream.
 The library must have been built (``python -m paper_1712_03439_amd.build``);
 there is no fallback of any kind when it is missing.
+
+Streams: a call given ``stream`` issues all of its work there, the library's
+kernels and this module's own (allocations, fills, small copies), by making
+it torch's current stream for the duration of the call; the tensors it
+allocates therefore belong to that stream.  Inputs written on another stream
+must be ordered before the call by the caller, as for any torch operation.
 """
 from __future__ import annotations
 
 import ctypes
+import functools
+import inspect
 import math
 import os
 from typing import Optional, Sequence
@@ -137,6 +145,22 @@ def _stream(stream=None) -> int:
     return int(s.cuda_stream)
 
 
+def _on_stream(fn):
+    """Runs fn with its `stream` argument, when one is given, as torch's
+    current stream (see the module docstring)."""
+    pos = list(inspect.signature(fn).parameters).index("stream")
+
+    @functools.wraps(fn)
+    def wrapped(*args, **kw):
+        s = kw.get("stream", args[pos] if len(args) > pos else None)
+        if s is None:
+            return fn(*args, **kw)
+        with _torch().cuda.stream(s):
+            return fn(*args, **kw)
+
+    return wrapped
+
+
 def _require_cuda(*ts):
     for t in ts:
         if t is not None and not t.is_cuda:
@@ -157,6 +181,7 @@ def device_status(stream=None) -> int:
     return int(st.value)
 
 
+@_on_stream
 def truncate_rir(h, off, len0, eta_db: float, n_c=None, length=None, stream=None):
     """RIR tail cut-off (eqs. 7-9) on the GPU.  Returns (n_c, len) int32 tensors."""
     torch = _torch()
@@ -171,6 +196,7 @@ def truncate_rir(h, off, len0, eta_db: float, n_c=None, length=None, stream=None
     return n_c, length
 
 
+@_on_stream
 def ola_convolve(x, h, fft_n: int, hop: int = 0, stream=None):
     """Overlap-add FFT convolution of one signal with one RIR (eq. 6)."""
     torch = _torch()
@@ -184,6 +210,7 @@ def ola_convolve(x, h, fft_n: int, hop: int = 0, stream=None):
     return y
 
 
+@_on_stream
 def rfft(x, n: int, stream=None):
     """Forward real FFT of len(x)/n signals of length n (FFT engine test entry)."""
     torch = _torch()
@@ -194,6 +221,7 @@ def rfft(x, n: int, stream=None):
     return spec.view(count, n // 2 + 1, 2)
 
 
+@_on_stream
 def irfft(spec, n: int, stream=None):
     torch = _torch()
     _require_cuda(spec)
@@ -203,6 +231,7 @@ def irfft(spec, n: int, stream=None):
     return x.view(count, n)
 
 
+@_on_stream
 def image_rir(geom, refl, off, length, h, max_len: int, order: int = 8, fs: float = 16000.0,
               c0: float = 343.0, stream=None):
     """Image-method RIRs (eq. 1) written into h at off[r] .. off[r] + length[r].
@@ -223,6 +252,7 @@ def image_rir(geom, refl, off, length, h, max_len: int, order: int = 8, fs: floa
     return h
 
 
+@_on_stream
 def simulate_rooms(db: DeviceBatch, geom, refl, alpha, eta_db: float, order: int = 8, fs: float = 16000.0,
                    c0: float = 343.0, y=None, ws=None, tune: Optional[RsimTune] = None, use_graph: bool = False,
                    stream=None):
@@ -243,6 +273,7 @@ def simulate_rooms(db: DeviceBatch, geom, refl, alpha, eta_db: float, order: int
     return y
 
 
+@_on_stream
 def reverb_energy(db: DeviceBatch, x=None, h=None, stream=None):
     """Energies of the reverberant sources at the mics, float64 [U*S*J] on the
     GPU (rsim_reverb_energy; call after the cut)."""
@@ -288,6 +319,7 @@ def mel_frames(T) -> np.ndarray:
     return np.where(T >= MEL_WIN, 1 + (T - MEL_WIN) // MEL_HOP, 0)
 
 
+@_on_stream
 def logmel(db: DeviceBatch, y, stream=None):
     """128 log-Mel features per frame of every (utterance, mic) output
     (rsim_logmel; call after the mix).  Returns (feat, off, cap): frame t of
@@ -318,6 +350,7 @@ def feature_layout(db: DeviceBatch):
     return off, cap, int(sizes.sum())
 
 
+@_on_stream
 def simulate_logmel(db: DeviceBatch, alpha, eta_db: float, feat=None, ws=None, tune: Optional[RsimTune] = None,
                     use_graph: bool = False, stream=None):
     """Cut + mix of one epoch with the log-Mel front end fused into the mix
@@ -355,6 +388,7 @@ def fft_filter_log2n(db: DeviceBatch) -> np.ndarray:
     return out.astype(np.int64)
 
 
+@_on_stream
 def fft_filter(db: DeviceBatch, alpha, y=None, chunk: int = 16, stream=None):
     """Eqs. 4-5: full-length FFT filtering and mixing of the batch (after the
     cut), for comparison with the overlap-add path.  Utterances are grouped
@@ -560,6 +594,7 @@ def single_workspace_bytes(db: DeviceBatch, tune: Optional[RsimTune] = None) -> 
     return max(1, int(_lib().rsim_mix_workspace_bytes(ctypes.byref(s), ctypes.byref(tune) if tune else None, 0)))
 
 
+@_on_stream
 def simulate_one(db: DeviceBatch, u: int, alpha, eta_db: float, y, ws, tune: Optional[RsimTune] = None,
                  stream=None):
     """Cut + mix of utterance u alone (the plain per-utterance path)."""
@@ -570,6 +605,7 @@ def simulate_one(db: DeviceBatch, u: int, alpha, eta_db: float, y, ws, tune: Opt
                                 0, _stream(stream)), "rsim_simulate")
 
 
+@_on_stream
 def truncate_batch(db: DeviceBatch, eta_db: float, h=None, stream=None):
     """Cut every RIR slot of the batch; writes db.n_c and db.rir_len."""
     _check(_lib().rsim_truncate_rir(_ptr(db.h if h is None else h), db.h_len, _ptr(db.rir_off),
@@ -578,6 +614,7 @@ def truncate_batch(db: DeviceBatch, eta_db: float, h=None, stream=None):
            "rsim_truncate_rir")
 
 
+@_on_stream
 def mix(db: DeviceBatch, alpha, y=None, ws=None, tune: Optional[RsimTune] = None, use_graph: bool = False,
         x=None, h=None, stream=None):
     """Eq. (2) for the whole batch with the current db.rir_len (call truncate_batch first)."""
@@ -594,6 +631,7 @@ def mix(db: DeviceBatch, alpha, y=None, ws=None, tune: Optional[RsimTune] = None
     return y
 
 
+@_on_stream
 def simulate(db: DeviceBatch, alpha, eta_db: float, y=None, ws=None, tune: Optional[RsimTune] = None,
              use_graph: bool = False, x=None, h=None, stream=None):
     """Cut + mix of one epoch (rsim_simulate): writes db.rir_len and y."""
@@ -614,6 +652,7 @@ def simulate(db: DeviceBatch, alpha, eta_db: float, y=None, ws=None, tune: Optio
 STATIC_SCRATCH_BYTES = 128 << 20  # RSIM_STATIC_SCRATCH_BYTES
 
 
+@_on_stream
 def simulate_static(db: DeviceBatch, alpha, eta_db: float, y, tune: Optional[RsimTune] = None, stream=None):
     """Cut + mix of one epoch without any allocation by the library or here
     (rsim_simulate_static): y (and db's arrays) are the caller's, the
@@ -627,6 +666,7 @@ def simulate_static(db: DeviceBatch, alpha, eta_db: float, y, tune: Optional[Rsi
     return y
 
 
+@_on_stream
 def mix_backward(db: DeviceBatch, alpha, grad_y, x=None, h=None, ws=None, tune: Optional[RsimTune] = None,
                  need_alpha: bool = True, stream=None, rir_len=None, out_len=None):
     """Adjoint of `mix` (rsim_mix_backward): (grad_x, grad_h, grad_alpha) in the
@@ -706,6 +746,7 @@ def mix_autograd(db: DeviceBatch, x, h, alpha, tune: Optional[RsimTune] = None):
     return _MixFunction.get().apply(x, h, alpha, db, tune)
 
 
+@_on_stream
 def source_power(db: DeviceBatch, x=None, stream=None):
     torch = _torch()
     p = torch.empty(db.U * db.S, dtype=torch.float64, device=db.device)

@@ -221,6 +221,38 @@ def test_status_read_on_the_calls_stream():
 
 
 @pytest.mark.gpu
+def test_a_given_stream_carries_the_calls_own_work():
+    # calls given a side stream and no stream context: the binding's own
+    # work (the adjoint's zero-filled gradients, the outputs and workspaces it
+    # allocates) goes to that stream with the kernels, so the results equal
+    # those of the same calls on the current stream, bit for bit
+    torch = cuda()
+    from paper_1712_03439_amd import rsim
+
+    b = synth.make_config2(n_utt=24, epoch=3)
+    db = rsim.DeviceBatch(b)
+    alpha = torch.from_numpy(rsim.batch_gains(db, b.snr_db)).cuda()
+    rsim.truncate_batch(db, 20.0)
+    g = torch.sin(torch.arange(max(db.y_len, 1), device="cuda", dtype=torch.float32) * 0.01)
+    x = torch.from_numpy(synth.white_noise(synth.rng_for(16, 0), 20000)).cuda()
+    h = torch.from_numpy(synth.rir(synth.rng_for(16, 1), 3000, 0.4, 25)).cuda()
+    outs = []
+    for side in (None, torch.cuda.Stream()):
+        torch.cuda.synchronize()
+        y = rsim.mix(db, alpha, stream=side)
+        grads = rsim.mix_backward(db, alpha, g, stream=side)
+        c = rsim.ola_convolve(x, h, 8192, stream=side)
+        (side if side is not None else torch.cuda.current_stream()).synchronize()
+        ol = db.out_len.cpu().numpy()
+        yv = y.cpu().numpy()
+        parts = [yv[int(b.out_off[u]) + j * int(b.out_stride[u]):][:int(ol[u])]
+                 for u in range(b.n_utt) for j in range(b.n_mic)]
+        outs.append([np.concatenate(parts)] + [t.cpu().numpy() for t in grads] + [c.cpu().numpy()])
+    for a, c in zip(*outs):
+        assert np.array_equal(a.view(np.uint32), c.view(np.uint32))
+
+
+@pytest.mark.gpu
 def test_graph_and_eager_calls_agree_across_families():
     # One utterance per FFT-size family, so every call runs several family
     # kernels side by side; eager and graph calls on the null stream and on a
