@@ -1,0 +1,80 @@
+"""Seeded random batches through the forward (cut + eq. 2) and the adjoint,
+every output sample and every gradient entry against the FP64 oracle.
+
+Each batch draws its shape from a wide range: 1-27 utterances, 1-8 mics,
+0-4 sources per utterance (0: nothing to write), sources of 1 to 12000
+samples, RIRs of 0 to 3000 taps, a threshold from {inf, 30, 20, 10, 3} dB,
+and one of: the library's own size rule, a forced FFT size per utterance (so
+several kernel families run in one call), a forced size with a forced hop, a
+caller's processing order, or the epoch as one graph.  Bars as in the
+forward and adjoint tests: 1e-5 of the peak per (utterance, mic) and per
+gradient tensor; the cut lengths bit-exact."""
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from tests.gpu_util import cuda
+from tests.test_gpu_backward import _check_full_many, _run
+from tests.test_gpu_mix import _check_utterances, _simulate
+
+ETAS = (math.inf, 30.0, 20.0, 10.0, 3.0)
+MODES = ("rule", "sizes", "sizes+hop", "order", "graph")
+
+
+def _random_batch(k):
+    rng = synth.rng_for(60, k)
+    U = int(rng.integers(1, 28))
+    J = int(rng.choice([1, 2, 3, 4, 5, 8]))
+    srcs, rirs, snrs = [], [], []
+    for _ in range(U):
+        I = int(rng.choice([0, 1, 1, 2, 2, 3, 4]))
+        n = int(rng.choice([1, 7, 64, 513])) if rng.random() < 0.15 else int(rng.integers(100, 12000))
+        kinds = [synth.speech_like, synth.white_noise] + ([synth.pink_noise] if n >= 64 else [])
+        srcs.append([kinds[int(rng.integers(len(kinds)))](rng, n) for _ in range(I)])
+        row = []
+        for _ in range(I):
+            taps = []
+            for _ in range(J):
+                if rng.random() < 0.05:
+                    taps.append(np.zeros(0, np.float32))
+                    continue
+                L0 = int(rng.integers(1, 3000))
+                taps.append(synth.rir(rng, L0, float(rng.uniform(0.1, 0.9)), int(rng.integers(0, min(L0, 200)))))
+            row.append(taps)
+        rirs.append(row)
+        snrs.append([0.0] + [float(rng.uniform(0.0, 30.0)) for _ in range(I - 1)])
+    return synth.pack(srcs, rirs, snrs, J), rng
+
+
+def _forced(b, rng, with_hop):
+    """A random valid FFT size per utterance (and hop): N at least the longest
+    uncut RIR, which bounds every cut length; the hop at most N - L0 + 1."""
+    S, J = b.max_src, b.n_mic
+    l2 = np.zeros(b.n_utt, np.int32)
+    hop = np.zeros(b.n_utt, np.int32)
+    for u in range(b.n_utt):
+        I = int(b.n_src[u])
+        lmax0 = max([int(b.rir_len0[(u * S + i) * J + j]) for i in range(I) for j in range(J)], default=0)
+        lo = max(9, math.ceil(math.log2(max(lmax0, 1))))
+        l2[u] = int(rng.integers(lo, 16))
+        room = (1 << int(l2[u])) - max(lmax0, 1) + 1
+        hop[u] = int(rng.integers(max(1, room // 4), room + 1))
+    return l2, (hop if with_hop else None)
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("k", range(10))
+def test_random_batch_forward_and_adjoint(k):
+    cuda()
+    b, rng = _random_batch(k)
+    eta = ETAS[k % len(ETAS)]
+    mode = MODES[k % len(MODES)]
+    l2, hop = _forced(b, rng, mode == "sizes+hop") if mode.startswith("sizes") else (None, None)
+    order = rng.permutation(b.n_utt).astype(np.int32) if mode == "order" else None
+    print(f"batch {k}: U={b.n_utt} J={b.n_mic} S={b.max_src} eta={eta} mode={mode}", flush=True)
+    db, alpha, y, rl, ol = _simulate(b, eta, fft_log2n=l2, hop=hop, order=order, use_graph=mode == "graph")
+    _check_utterances(b, range(b.n_utt), eta, y, rl, ol)
+    gx, gh, ga, gys = _run(b, eta, 100 + k, fft_log2n=l2, hop=hop)
+    _check_full_many(b, eta, gx, gh, ga, gys, list(range(b.n_utt)))
