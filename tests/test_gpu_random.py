@@ -1,7 +1,7 @@
 """Seeded random batches through the forward (cut + eq. 2) and the adjoint,
 every output sample and every gradient entry against the FP64 oracle.
 
-Each batch draws its shape from a wide range: 1-27 utterances, 1-8 mics,
+Each of 24 batches draws its shape from a wide range: 1-27 utterances, 1-8 mics,
 0-4 sources per utterance (0: nothing to write), sources of 1 to 12000
 samples, RIRs of 0 to 3000 taps, a threshold from {inf, 30, 20, 10, 3} dB,
 and one of: the library's own size rule, a forced FFT size per utterance (so
@@ -65,12 +65,12 @@ def _forced(b, rng, with_hop):
 
 
 @pytest.mark.gpu
-@pytest.mark.parametrize("k", range(10))
+@pytest.mark.parametrize("k", range(24))
 def test_random_batch_forward_and_adjoint(k):
     cuda()
     b, rng = _random_batch(k)
     eta = ETAS[k % len(ETAS)]
-    mode = MODES[k % len(MODES)]
+    mode = MODES[(k + k // len(ETAS)) % len(MODES)]
     l2, hop = _forced(b, rng, mode == "sizes+hop") if mode.startswith("sizes") else (None, None)
     order = rng.permutation(b.n_utt).astype(np.int32) if mode == "order" else None
     print(f"batch {k}: U={b.n_utt} J={b.n_mic} S={b.max_src} eta={eta} mode={mode}", flush=True)
