@@ -187,3 +187,53 @@ def test_rooms_epoch_matches_separate_calls(graph):
         off, st, T = int(b.out_off[u]), int(b.out_stride[u]), int(ol[u])
         for j in range(b.n_mic):
             assert np.array_equal(y1[off + j * st: off + j * st + T], y2[off + j * st: off + j * st + T]), (u, j)
+
+
+def _random_geometry(rng):
+    """A valid geometry from a wide range: room sides log-uniform from 2 cm to
+    2 km, the source and microphone anywhere at least 5 mm inside the walls
+    (often at the 5 mm limit) and at least 1 cm apart."""
+    while True:
+        room = np.exp(rng.uniform(math.log(0.02), math.log(2000.0), 3))
+        lo, hi = np.full(3, 0.005), room - 0.005
+        src = rng.uniform(lo, hi)
+        mic = rng.uniform(lo, hi)
+        for p in (src, mic):
+            edge = rng.random(3) < 0.2
+            p[edge] = np.where(rng.random(int(edge.sum())) < 0.5, lo[edge], hi[edge])
+        if rng.random() < 0.2:   # close together: one axis apart by about 1 cm
+            mic = src.copy()
+            ax = int(rng.integers(3))
+            step = 0.0101 if src[ax] + 0.0101 <= hi[ax] else -0.0101
+            mic[ax] = src[ax] + step
+        if float(np.sum((src - mic) ** 2)) >= 1e-4 and np.all(mic >= lo) and np.all(mic <= hi):
+            return np.concatenate([room, src, mic])
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("fs,c0", [(16000.0, 343.0), (8000.0, 331.3), (48000.0, 346.1)])
+def test_random_geometries_bit_exact(fs, c0):
+    # seeded rooms from centimetres to kilometres, positions at the 5 mm
+    # limit, source and microphone 1 cm apart, reflection 0, 1 or anywhere
+    # between, orders 0-16 and lengths up to the 32768-tap limit
+    torch = cuda()
+    from paper_1712_03439_amd import rsim
+
+    rng = np.random.default_rng(int(fs) + 7)
+    for order in (0, 2, 8, 16):
+        n = 24
+        g = np.array([_random_geometry(rng) for _ in range(n)])
+        r = np.array([[0.0, 1.0][k] if k < 2 else float(rng.uniform(0.0, 1.0)) for k in range(n)])
+        lens = np.array([int(rng.choice([1, 2, 16384, 16385, 32768])) if k % 4 == 0 else int(rng.integers(1, 32769))
+                         for k in range(n)], np.int32)
+        off = np.concatenate([[0], np.cumsum(lens.astype(np.int64))[:-1]]).astype(np.int64)
+        h = torch.full((int(lens.sum()),), -7.0, dtype=torch.float32, device="cuda")
+        rsim.device_status()
+        rsim.image_rir(torch.from_numpy(g).cuda(), torch.from_numpy(r).cuda(), torch.from_numpy(off).cuda(),
+                       torch.from_numpy(lens).cuda(), h, int(lens.max()), order=order, fs=fs, c0=c0)
+        hh = h.cpu().numpy()
+        assert rsim.device_status() == 0
+        for k in range(n):
+            ref = im.image_rir(g[k, :3], g[k, 3:6], g[k, 6:], r[k], int(lens[k]), order=order, fs=fs, c0=c0)
+            got = hh[off[k]: off[k] + lens[k]]
+            assert np.array_equal(got, ref), (order, k, g[k].tolist(), int(np.count_nonzero(got != ref)))
