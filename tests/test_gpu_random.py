@@ -78,3 +78,37 @@ def test_random_batch_forward_and_adjoint(k):
     _check_utterances(b, range(b.n_utt), eta, y, rl, ol)
     gx, gh, ga, gys = _run(b, eta, 100 + k, fft_log2n=l2, hop=hop)
     _check_full_many(b, eta, gx, gh, ga, gys, list(range(b.n_utt)))
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("k", range(8))
+def test_random_batch_energies(k):
+    # the reverberant energies of every (source, mic) slot after the cut, at
+    # the energy bar of the reverberant-gain tests
+    from tests.test_gpu_reverb import _check_energies, _energies
+
+    b, _ = _random_batch(100 + k)
+    eta = ETAS[k % len(ETAS)]
+    print(f"batch {100 + k}: U={b.n_utt} J={b.n_mic} S={b.max_src} eta={eta}", flush=True)
+    _, e, rl = _energies(b, eta)
+    _check_energies(b, eta, e, rl)
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("k", range(8))
+def test_random_batch_features(k):
+    # the front end on the mixed outputs and fused into the mix, at the
+    # feature bars of the front-end tests against the oracle's features of
+    # the unfused kernel's samples.  Sizes are forced per utterance among
+    # those with a fused kernel (4096-16384), so that both paths run the same
+    # transforms: the fused features must then equal the separate ones bit
+    # for bit (with the size rule free, short RIRs can get a smaller N on the
+    # separate path, whose samples then differ by rounding)
+    from tests.test_gpu_logmel import _compare_fused, _fused
+
+    b, rng = _random_batch(200 + k)
+    eta = ETAS[k % len(ETAS)]
+    l2 = rng.integers(12, 15, b.n_utt).astype(np.int32)
+    print(f"batch {200 + k}: U={b.n_utt} J={b.n_mic} S={b.max_src} eta={eta}", flush=True)
+    ref, feat_f, off, cap, ol, rl = _fused(b, eta, fft_log2n=l2, use_graph=bool(k % 2))
+    assert _compare_fused(b, ref, feat_f, off, cap, ol, rl)
