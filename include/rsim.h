@@ -381,7 +381,7 @@ rsim_status rsim_fft_filter(const rsim_batch* b, const float* x, const float* h,
  * features as soon as the frame's samples are final (Sec. 3's front end, the
  * frames, window, transform, filterbank and log of rsim_logmel, with the same
  * operations, so the features equal rsim_logmel's of rsim_simulate's
- * output).  feat, feat_off, feat_len and the frame capacity C_u (frames of
+ * output when that call runs the same transform sizes).  feat, feat_off, feat_len and the frame capacity C_u (frames of
  * out_stride[u] samples) are as for rsim_logmel; y is not written (y_len,
  * out_off and out_stride keep their meaning as bounds and layout), out_len
  * is.  Only FFT sizes 4096, 8192 and 16384 have fused kernels: the size rule
