@@ -1,5 +1,8 @@
 """Seeded random batches through the forward (cut + eq. 2) and the adjoint,
-every output sample and every gradient entry against the FP64 oracle.
+every output sample and every gradient entry against the FP64 oracle; the
+same kind of batches through the reverberant energies, the front end
+(separate and fused), the full-length filtering, and random RIR shapes
+through the cut.
 
 Each of 24 batches draws its shape from a wide range: 1-27 utterances, 1-8 mics,
 0-4 sources per utterance (0: nothing to write), sources of 1 to 12000
@@ -14,6 +17,7 @@ import math
 import numpy as np
 import pytest
 
+import oracle
 import synth
 from tests.gpu_util import cuda
 from tests.test_gpu_backward import _check_full_many, _run
@@ -112,3 +116,57 @@ def test_random_batch_features(k):
     print(f"batch {200 + k}: U={b.n_utt} J={b.n_mic} S={b.max_src} eta={eta}", flush=True)
     ref, feat_f, off, cap, ol, rl = _fused(b, eta, fft_log2n=l2, use_graph=bool(k % 2))
     assert _compare_fused(b, ref, feat_f, off, cap, ol, rl)
+
+
+def _random_rir(rng):
+    """A RIR of a random shape: decaying noise, spikes, silence, plateaus of
+    equal taps, huge or tiny scales (subnormal powers), lengths around the
+    cut kernel's chunking and past its 32768-tap chunk maxima."""
+    L0 = int(rng.choice([0, 1, 2, 63, 64, 65, 1023, 1024, 1025, 32768, 32769])) if rng.random() < 0.2 \
+        else int(rng.integers(1, 40000))
+    kind = int(rng.integers(5))
+    n = np.arange(L0)
+    if kind == 0:
+        h = rng.standard_normal(L0) * np.exp(-n / max(1.0, float(rng.uniform(1, L0 + 1))))
+    elif kind == 1:
+        h = np.zeros(L0)
+        for _ in range(int(rng.integers(1, 6))):
+            if L0:
+                h[int(rng.integers(L0))] = float(rng.choice([-1.0, 1.0])) * float(rng.uniform(0.1, 2.0))
+    elif kind == 2:
+        h = np.full(L0, float(rng.uniform(-1, 1)))                  # every tap equal
+    elif kind == 3:
+        h = rng.standard_normal(L0) * 10.0 ** float(rng.uniform(-25, -19))   # subnormal powers
+    else:
+        h = rng.standard_normal(L0) * 10.0 ** float(rng.uniform(10, 18))     # powers near the float32 top
+    return h.astype(np.float32)
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("k", range(4))
+def test_random_rirs_cut_bit_exact(k):
+    # 300 random RIR shapes per call and thresholds anywhere in 0-60 dB (not
+    # only round values): n_c and L bit-exact against the oracle's rule
+    from tests.test_gpu_truncate import _run as cut
+
+    rng = synth.rng_for(300, k)
+    rirs = [_random_rir(rng) for _ in range(300)]
+    for eta in [float(rng.uniform(0.0, 60.0)) for _ in range(3)] + [0.0, math.inf]:
+        n_c, L = cut(rirs, eta)
+        for r, h in enumerate(rirs):
+            nc_ref, L_ref, _ = oracle.cut_rir(h, eta)
+            assert (int(n_c[r]), int(L[r])) == (nc_ref, L_ref), (k, eta, r, len(h))
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("k", range(6))
+def test_random_batch_full_length_filtering(k):
+    # eqs. 4-5 on random batches, every utterance at its own transform size
+    # (grouped into one call per size), against the oracle's mix
+    from tests.test_gpu_fft_filter import _check, _run as ffilter
+
+    b, _ = _random_batch(400 + k)
+    eta = ETAS[k % len(ETAS)]
+    print(f"batch {400 + k}: U={b.n_utt} J={b.n_mic} S={b.max_src} eta={eta}", flush=True)
+    y, rl, ol, alpha = ffilter(b, eta, chunk=int(1 + k % 4))
+    _check(b, eta, y, rl, ol, alpha, range(b.n_utt))
