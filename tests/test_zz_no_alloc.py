@@ -99,6 +99,25 @@ def test_static_entry_with_fewer_workgroups_than_slots_wanted():
 
 
 @pytest.mark.gpu
+def test_static_entry_on_a_run_of_random_batches():
+    # eight seeded random batches in a row (1-27 utterances, 1-8 mics, 0-4
+    # sources, forced sizes per utterance in half of them): each call's
+    # scratch layout differs from the previous one's, and every call must
+    # give the bits of rsim_simulate
+    torch = cuda()
+    from tests.test_gpu_random import ETAS, _forced, _random_batch
+
+    for k in range(8):
+        b, rng = _random_batch(500 + k)
+        eta = ETAS[k % len(ETAS)]
+        l2 = _forced(b, rng, False)[0] if k % 2 else None
+        db, alpha, y_ref, rl_ref, ol_ref = _reference(b, eta, fft_log2n=l2)
+        y = _static(db, alpha, eta)
+        torch.cuda.synchronize()
+        _same(b, y_ref, rl_ref, ol_ref, y.cpu().numpy(), db.rir_len.cpu().numpy(), db.out_len.cpu().numpy())
+
+
+@pytest.mark.gpu
 def test_static_entry_rejects_a_batch_that_does_not_fit():
     # 64 sources x 64 mics forced to N = 32768: one workgroup's slot of RIR
     # spectra alone is larger than the static array; nothing is launched
