@@ -170,3 +170,36 @@ def test_random_batch_full_length_filtering(k):
     print(f"batch {400 + k}: U={b.n_utt} J={b.n_mic} S={b.max_src} eta={eta}", flush=True)
     y, rl, ol, alpha = ffilter(b, eta, chunk=int(1 + k % 4))
     _check(b, eta, y, rl, ol, alpha, range(b.n_utt))
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("k", range(6))
+def test_random_batch_kernel_variants_same_bits(k):
+    # forced sizes per utterance over every family and a random kernel variant
+    # per family, three times: each choice gives the bits of the default
+    # variants (every variant computes each sample with the same operations)
+    torch = cuda()
+    from paper_1712_03439_amd import autotune, rsim
+
+    b, rng = _random_batch(600 + k)
+    eta = ETAS[k % len(ETAS)]
+    l2 = _forced(b, rng, bool(k % 2))
+    f, m = autotune.model_costs()
+
+    def run(var):
+        db = rsim.DeviceBatch(b, fft_log2n=l2[0], hop=l2[1])
+        alpha = torch.from_numpy(rsim.batch_gains(db, b.snr_db)).cuda()
+        y = rsim.simulate(db, alpha, eta, tune=rsim.tune_table(f, m, False, var), use_graph=bool(var[0] % 2))
+        torch.cuda.synchronize()
+        return y.cpu().numpy(), db.rir_len.cpu().numpy(), db.out_len.cpu().numpy()
+
+    y0, rl0, ol0 = run([0] * 6)
+    for _ in range(3):
+        var = [int(rng.choice(autotune.VARIANTS[fam])) for fam in range(6)]
+        y, rl, ol = run(var)
+        assert np.array_equal(rl, rl0) and np.array_equal(ol, ol0)
+        for u in range(b.n_utt):
+            off, st, T = int(b.out_off[u]), int(b.out_stride[u]), int(ol0[u])
+            for j in range(b.n_mic):
+                s = slice(off + j * st, off + j * st + T)
+                assert np.array_equal(y[s].view(np.uint32), y0[s].view(np.uint32)), (var, u, j)
