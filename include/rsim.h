@@ -57,7 +57,9 @@ typedef enum {
  * for mic j is y[out_off[u] + j*out_stride[u] + n], n < out_len[u], where the
  * library writes out_len[u] = T_u = src_len[u] + max_ij rir_len[r] - 1 (0 if
  * the utterance is empty) and requires out_stride[u] >= T_u.  Samples of y at
- * n >= T_u are not written.
+ * n >= T_u are not written.  A data array (x, h, y and the adjoint's
+ * gradients of the same layouts) may be NULL when its length (x_len, h_len,
+ * y_len) is 0; other NULL arguments give RSIM_EINVAL.
  */
 typedef struct rsim_batch {
   int32_t n_utt;          /* U >= 0 (host) */

@@ -3149,6 +3149,11 @@ struct WsLayout {
   int grid[kNumFam];
 };
 
+// A data array may be NULL when its length is 0: nothing of it is then read
+// or written (every access is bounded by descriptors checked against that
+// length).
+bool arr_ok(const void* p, long long len) { return p != nullptr || len == 0; }
+
 bool batch_ok(const rsim_batch* b) {
   if (!b || b->n_utt < 0 || b->n_mic < 1 || b->max_src < 1 || b->max_rir_len0 < 0) return false;
   if (b->x_len < 0 || b->h_len < 0 || b->y_len < 0) return false;
@@ -3729,7 +3734,7 @@ rsim_status rsim_truncate_rir(const float* h, int64_t h_len, const int64_t* off,
                               hipStream_t stream) {
   if (n_rir < 0 || h_len < 0 || !eta_ok(eta_db)) return RSIM_EINVAL;
   if (n_rir == 0) return RSIM_OK;
-  if (!h || !off || !len0 || !len) return RSIM_EINVAL;
+  if (!arr_ok(h, h_len) || !off || !len0 || !len) return RSIM_EINVAL;
   rsim_status e = ensure_init(stream);
   if (e != RSIM_OK) return e;
   Node n;
@@ -3750,7 +3755,7 @@ rsim_status rsim_mix(const rsim_batch* b, const float* x, const float* h, const 
                      hipStream_t stream) {
   if (!batch_ok(b) || !tune_ok(tune)) return RSIM_EINVAL;
   if (b->n_utt == 0) return RSIM_OK;
-  if (!x || !h || !alpha || !y) return RSIM_EINVAL;
+  if (!arr_ok(x, b->x_len) || !arr_ok(h, b->h_len) || !alpha || !arr_ok(y, b->y_len)) return RSIM_EINVAL;
   const rsim_status e = ensure_init(stream);
   const TuneDev td = to_dev(tune);
   const WsLayout L = layout(b, td, false, dev_state());
@@ -3770,7 +3775,7 @@ rsim_status rsim_simulate(const rsim_batch* b, const float* x, const float* h, c
   bb.rir_len = rir_len_out;
   if (!batch_ok(&bb)) return RSIM_EINVAL;
   if (bb.n_utt == 0) return RSIM_OK;
-  if (!x || !h || !alpha || !y) return RSIM_EINVAL;
+  if (!arr_ok(x, bb.x_len) || !arr_ok(h, bb.h_len) || !alpha || !arr_ok(y, bb.y_len)) return RSIM_EINVAL;
   const rsim_status e = ensure_init(stream);
   const TuneDev td = to_dev(tune);
   const WsLayout L = layout(&bb, td, false, dev_state());
@@ -3795,7 +3800,7 @@ rsim_status rsim_simulate_static(const rsim_batch* b, const float* x, const floa
   bb.rir_len = rir_len_out;
   if (!batch_ok(&bb)) return RSIM_EINVAL;
   if (bb.n_utt == 0) return RSIM_OK;
-  if (!x || !h || !alpha || !y) return RSIM_EINVAL;
+  if (!arr_ok(x, bb.x_len) || !arr_ok(h, bb.h_len) || !alpha || !arr_ok(y, bb.y_len)) return RSIM_EINVAL;
   const long long n_rir = (long long)bb.n_utt * bb.max_src * bb.n_mic;
   if (n_rir > 0x7fffffffLL) return RSIM_EINVAL;
   const rsim_status e = ensure_init(stream);
@@ -3828,7 +3833,7 @@ rsim_status rsim_simulate_logmel(const rsim_batch* b, const float* x, const floa
   bb.rir_len = rir_len_out;
   if (!batch_ok(&bb)) return RSIM_EINVAL;
   if (bb.n_utt == 0) return RSIM_OK;
-  if (!x || !h || !alpha || !feat || !feat_off) return RSIM_EINVAL;
+  if (!arr_ok(x, bb.x_len) || !arr_ok(h, bb.h_len) || !alpha || !feat || !feat_off) return RSIM_EINVAL;
   if (bb.n_mic > kFeatMics) return RSIM_EUNSUPPORTED;
   if (bb.fft_log2n && (bb.fft_sizes == 0 || (bb.fft_sizes & ~kFeatSizeBits))) return RSIM_EUNSUPPORTED;
   const long long n_rir = (long long)bb.n_utt * bb.max_src * bb.n_mic;
@@ -3914,7 +3919,9 @@ rsim_status rsim_mix_backward(const rsim_batch* b, const float* x, const float* 
                               void* ws, size_t ws_bytes, const rsim_tune* tune, hipStream_t stream) {
   if (!batch_ok(b) || !tune_ok(tune)) return RSIM_EINVAL;
   if (b->n_utt == 0) return RSIM_OK;
-  if (!x || !h || !alpha || !grad_y || !grad_x || !grad_h) return RSIM_EINVAL;
+  if (!arr_ok(x, b->x_len) || !arr_ok(h, b->h_len) || !alpha || !arr_ok(grad_y, b->y_len) ||
+      !arr_ok(grad_x, b->x_len) || !arr_ok(grad_h, b->h_len))
+    return RSIM_EINVAL;
   const rsim_status e = ensure_init(stream);
   const TuneDev td = to_dev(tune);
   const WsLayout L = layout(b, td, true, dev_state());
@@ -3929,7 +3936,7 @@ rsim_status rsim_mix_backward(const rsim_batch* b, const float* x, const float* 
 rsim_status rsim_source_power(const rsim_batch* b, const float* x, double* power, hipStream_t stream) {
   if (!batch_ok(b)) return RSIM_EINVAL;
   if (b->n_utt == 0) return RSIM_OK;
-  if (!x || !power) return RSIM_EINVAL;
+  if (!arr_ok(x, b->x_len) || !power) return RSIM_EINVAL;
   rsim_status e = ensure_init(stream);
   if (e != RSIM_OK) return e;
   const long long slots = (long long)b->n_utt * b->max_src;
@@ -4001,7 +4008,8 @@ rsim_status rsim_simulate_rooms(const rsim_batch* b, const float* x, float* h, c
   const rsim_status v = image_args_ok((int)n_rir, order, fs, c0, bb.max_rir_len0, bb.h_len);
   if (v != RSIM_OK) return v;
   if (bb.n_utt == 0) return RSIM_OK;
-  if (!x || !h || !geom || !refl || !alpha || !y) return RSIM_EINVAL;
+  if (!arr_ok(x, bb.x_len) || !arr_ok(h, bb.h_len) || !geom || !refl || !alpha || !arr_ok(y, bb.y_len))
+    return RSIM_EINVAL;
   const rsim_status e = ensure_init(stream);
   const TuneDev td = to_dev(tune);
   const WsLayout L = layout(&bb, td, false, dev_state());
@@ -4023,7 +4031,7 @@ rsim_status rsim_reverb_energy(const rsim_batch* b, const float* x, const float*
                                hipStream_t stream) {
   if (!batch_ok(b)) return RSIM_EINVAL;
   if (b->n_utt == 0) return RSIM_OK;
-  if (!x || !h || !energy) return RSIM_EINVAL;
+  if (!arr_ok(x, b->x_len) || !arr_ok(h, b->h_len) || !energy) return RSIM_EINVAL;
   const rsim_status e = ensure_init(stream);
   if (e != RSIM_OK) return e;
   const BatchDev bd = to_dev(b);
@@ -4066,7 +4074,7 @@ rsim_status rsim_logmel(const rsim_batch* b, const float* y, float* feat, const 
                         int32_t max_frames, hipStream_t stream) {
   if (!batch_ok(b) || max_frames < 0 || feat_len < 0) return RSIM_EINVAL;
   if (b->n_utt == 0 || max_frames == 0) return RSIM_OK;
-  if (!y || !feat || !feat_off) return RSIM_EINVAL;
+  if (!arr_ok(y, b->y_len) || !feat || !feat_off) return RSIM_EINVAL;
   const rsim_status e = ensure_init(stream);
   if (e != RSIM_OK) return e;
   MelArgs A;
@@ -4115,7 +4123,7 @@ rsim_status rsim_fft_filter(const rsim_batch* b, const float* x, const float* h,
                             int32_t fft_log2n, int32_t chunk, void* ws, size_t ws_bytes, hipStream_t stream) {
   if (!batch_ok(b) || fft_log2n < 1 || fft_log2n > 20 || chunk < 1) return RSIM_EINVAL;
   if (b->n_utt == 0) return RSIM_OK;
-  if (!x || !h || !alpha || !y) return RSIM_EINVAL;
+  if (!arr_ok(x, b->x_len) || !arr_ok(h, b->h_len) || !alpha || !arr_ok(y, b->y_len)) return RSIM_EINVAL;
   const size_t need = rsim_fft_filter_workspace_bytes(b, fft_log2n, chunk);
   if (!ws || ws_bytes < need) return RSIM_EWORKSPACE;
   const rsim_status e = ensure_init(stream);

@@ -81,6 +81,11 @@ def test_mix_validation_codes():
     assert lib.rsim_mix(ctypes.byref(b), p, p, p, p, p, need - 1, None, 0, None) == rsim.RSIM_EWORKSPACE
     # missing data pointers
     assert lib.rsim_mix(ctypes.byref(b), None, p, p, p, p, need, None, 0, None) == rsim.RSIM_EINVAL
+    # ... except for an array of length 0: the call gets past the argument
+    # checks (and, without a GPU, stops at the device: RSIM_EDEVICE)
+    nox = _host_batch()
+    nox.x_len = 0
+    assert lib.rsim_mix(ctypes.byref(nox), None, p, p, p, p, need, None, 0, None) != rsim.RSIM_EINVAL
     # bad descriptor scalars
     bad = _host_batch()
     bad.n_mic = 0

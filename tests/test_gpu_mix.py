@@ -183,6 +183,34 @@ def test_ragged_and_degenerate_utterances():
 
 
 @pytest.mark.gpu
+def test_a_batch_without_any_sample_is_accepted_everywhere():
+    # three utterances without sources: x, h and y are empty, so their device
+    # pointers are NULL; every entry point accepts the batch, writes zero
+    # output lengths and flags nothing
+    torch = cuda()
+    from paper_1712_03439_amd import rsim
+
+    b = synth.pack([[], [], []], [[], [], []], [[0.0]] * 3, 2)
+    db = rsim.DeviceBatch(b)
+    assert db.x.numel() == 0 and db.h.numel() == 0 and b.y_len == 0
+    rsim.device_status()
+    alpha = torch.from_numpy(rsim.batch_gains(db, b.snr_db)).cuda()
+    rsim.truncate_batch(db, 20.0)
+    y = rsim.simulate(db, alpha, 20.0)
+    rsim.mix(db, alpha, y=y)
+    gx, gh, ga = rsim.mix_backward(db, alpha, torch.zeros(1, device="cuda"))
+    e = rsim.reverb_energy(db)
+    rsim.logmel(db, y)
+    rsim.simulate_logmel(db, alpha, 20.0)
+    rsim.fft_filter(db, alpha)
+    rsim.simulate_static(db, alpha, 20.0, torch.zeros(1, device="cuda"))
+    torch.cuda.synchronize()
+    assert rsim.device_status() == 0
+    assert not db.out_len.any() and not db.rir_len.any()
+    assert gx.numel() == 0 and gh.numel() == 0 and not ga.any() and not e.any()
+
+
+@pytest.mark.gpu
 def test_bad_descriptor_is_skipped_and_flagged():
     torch = cuda()
     from paper_1712_03439_amd import rsim
