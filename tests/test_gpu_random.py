@@ -2,7 +2,8 @@
 every output sample and every gradient entry against the FP64 oracle; the
 same kind of batches through the reverberant energies, the front end
 (separate and fused), the full-length filtering, and random RIR shapes
-through the cut.
+through the cut; and three wider batches (up to 16 mics, 8 sources, 60000
+samples, 16000 taps) through the forward, the adjoint and the energies.
 
 Each of 24 batches draws its shape from a wide range: 1-27 utterances, 1-8 mics,
 0-4 sources per utterance (0: nothing to write), sources of 1 to 12000
@@ -203,3 +204,38 @@ def test_random_batch_kernel_variants_same_bits(k):
             for j in range(b.n_mic):
                 s = slice(off + j * st, off + j * st + T)
                 assert np.array_equal(y[s].view(np.uint32), y0[s].view(np.uint32)), (var, u, j)
+
+
+def _wide_batch(k):
+    """Wider shapes: up to 40 utterances, 16 mics and 8 sources, sources of
+    up to 60000 samples and RIRs of up to 16000 taps."""
+    rng = synth.rng_for(61, k)
+    U = int(rng.integers(1, 41))
+    J = int(rng.integers(1, 17))
+    srcs, rirs, snrs = [], [], []
+    for _ in range(U):
+        I = int(rng.integers(0, 9))
+        n = int(rng.integers(1, 60000))
+        srcs.append([(synth.white_noise if rng.random() < 0.5 else synth.speech_like)(rng, n) for _ in range(I)])
+        rirs.append([[synth.rir(rng, int(rng.integers(0, 16001)), float(rng.uniform(0.1, 1.0)),
+                                int(rng.integers(0, 300))) for _ in range(J)] for _ in range(I)])
+        snrs.append([0.0] + [float(rng.uniform(0, 30)) for _ in range(I - 1)])
+    return synth.pack(srcs, rirs, snrs, J)
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("k", [0, 12, 18])
+def test_wide_random_batch_forward_adjoint_energies(k):
+    # up to 15 mics and 8 sources: the forward and the adjoint in full and the
+    # reverberant energies, all against the oracle
+    from tests.test_gpu_reverb import _check_energies, _energies
+
+    b = _wide_batch(k)
+    eta = ETAS[k % len(ETAS)]
+    print(f"wide batch {k}: U={b.n_utt} J={b.n_mic} S={b.max_src} eta={eta}", flush=True)
+    db, alpha, y, rl, ol = _simulate(b, eta, use_graph=bool(k % 2))
+    _check_utterances(b, range(b.n_utt), eta, y, rl, ol)
+    gx, gh, ga, gys = _run(b, eta, 900 + k)
+    _check_full_many(b, eta, gx, gh, ga, gys, list(range(b.n_utt)))
+    _, e, rl2 = _energies(b, eta)
+    _check_energies(b, eta, e, rl2)
