@@ -492,3 +492,19 @@ def test_differentiation_workload_forward():
     b = synth.make_config3()
     db, alpha, y, rl, ol = _simulate(b, math.inf, fft_log2n=np.full(b.n_utt, 14, np.int32))
     _check_utterances(b, range(0, 64, 7), math.inf, y, rl, ol)
+
+
+@pytest.mark.gpu
+def test_one_utterance_of_2_to_the_24_samples_in_full():
+    # about 17.5 minutes of audio in one utterance (2^24 + 12345 samples, two
+    # sources, three mics, RIRs of up to 3000 taps): its blocks split over
+    # many workgroups, every output sample against the oracle
+    rng = synth.rng_for(17, 24)
+    n = (1 << 24) + 12345
+    srcs = [[synth.speech_like(rng, n), synth.white_noise(rng, n)]]
+    rirs = [[[synth.rir(rng, int(rng.integers(1000, 3001)), 0.5, int(rng.integers(0, 100))) for _ in range(3)]
+             for _ in range(2)]]
+    b = synth.pack(srcs, rirs, [[0.0, 6.0]], 3)
+    db, alpha, y, rl, ol = _simulate(b, 20.0)
+    assert int(ol[0]) > (1 << 24)
+    _check_utterances(b, [0], 20.0, y, rl, ol)
