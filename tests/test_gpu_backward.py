@@ -339,3 +339,18 @@ def test_autograd_keeps_the_forward_cut_lengths():
     gx, gh, _ = rsim.mix_backward(db, alpha, gy, rir_len=rl20, out_len=torch.empty_like(db.out_len))
     torch.cuda.synchronize()
     assert torch.equal(x.grad, gx) and torch.equal(h.grad, gh)
+
+
+@pytest.mark.gpu
+def test_backward_one_utterance_of_2_to_the_22_samples():
+    # about 4.4 minutes of audio in one utterance (2^22 + 777 samples, two
+    # sources, two mics, RIRs of up to 2000 taps), split into parts: every
+    # entry of dx, dh and dalpha against the oracle
+    rng = synth.rng_for(55, 22)
+    n = (1 << 22) + 777
+    srcs = [[synth.speech_like(rng, n), synth.white_noise(rng, n)]]
+    rirs = [[[synth.rir(rng, int(rng.integers(500, 2001)), 0.4, int(rng.integers(0, 60))) for _ in range(2)]
+             for _ in range(2)]]
+    b = synth.pack(srcs, rirs, [[0.0, 8.0]], 2)
+    gx, gh, ga, gys = _run(b, 20.0, 22)
+    _check_full_many(b, 20.0, gx, gh, ga, gys, [0])
