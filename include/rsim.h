@@ -136,7 +136,13 @@ typedef struct rsim_tune {
 } rsim_tune;
 
 /* Initialise the library on the current device (twiddle tables, launch
- * geometry).  Idempotent.  Must not be called while a stream is capturing. */
+ * geometry).  Idempotent.  Must not be called while a stream is capturing.
+ * Every entry point may be called from several host threads: the library's
+ * host state (per-device tables, side streams and their events, executable
+ * graphs awaiting destruction) is guarded by one lock.  Device work of calls
+ * on different streams is ordered only by what the caller orders, except
+ * that rsim_simulate_static calls on one device share its scratch and must
+ * not overlap. */
 rsim_status rsim_init(void);
 
 const char* rsim_strerror(rsim_status s);
