@@ -508,3 +508,49 @@ def test_one_utterance_of_2_to_the_24_samples_in_full():
     db, alpha, y, rl, ol = _simulate(b, 20.0)
     assert int(ol[0]) > (1 << 24)
     _check_utterances(b, [0], 20.0, y, rl, ol)
+
+
+@pytest.mark.gpu
+def test_calls_from_several_host_threads():
+    # four host threads, each with its own batch and stream, call the library
+    # at once, five times each; every batch mixes two FFT-size families, so
+    # each eager call forks its family kernels onto the library's shared side
+    # streams.  Every call gives the bits of the same call made alone.
+    import threading
+
+    torch = cuda()
+    from paper_1712_03439_amd import rsim
+
+    jobs = []
+    for k in range(4):
+        b = synth.make_config2(n_utt=12 + 5 * k, epoch=40 + k)
+        l2 = np.where(np.arange(b.n_utt) % 2 == 0, 13, 14).astype(np.int32)
+        db = rsim.DeviceBatch(b, fft_log2n=l2)
+        alpha = torch.from_numpy(rsim.batch_gains(db, b.snr_db)).cuda()
+        y = torch.zeros(max(db.y_len, 1), device="cuda")
+        rsim.simulate(db, alpha, 20.0, y=y)
+        torch.cuda.synchronize()
+        jobs.append((db, alpha, y.cpu().numpy()))
+    errors = []
+
+    def work(k):
+        db, alpha, ref = jobs[k]
+        s = torch.cuda.Stream()
+        try:
+            for _ in range(5):
+                with torch.cuda.stream(s):
+                    y = torch.zeros(max(db.y_len, 1), device="cuda")
+                    rsim.simulate(db, alpha, 20.0, y=y, stream=s)
+                s.synchronize()
+                if not np.array_equal(y.cpu().numpy().view(np.uint32), ref.view(np.uint32)):
+                    errors.append(k)
+        except Exception as e:  # reported below
+            errors.append((k, repr(e)))
+
+    threads = [threading.Thread(target=work, args=(k,)) for k in range(4)]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join()
+    assert not errors, errors
+    assert rsim.device_status() == 0
