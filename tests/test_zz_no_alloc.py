@@ -118,6 +118,45 @@ def test_static_entry_on_a_run_of_random_batches():
 
 
 @pytest.mark.gpu
+def test_static_entry_captured_in_a_graph():
+    # the callers the entry is for include code under graph capture: the call
+    # is captured into a torch CUDA graph and replayed three times, the
+    # inputs changed in place by eager work between the replays; every
+    # replay gives the bits of rsim_simulate on the inputs of that moment
+    torch = cuda()
+    from paper_1712_03439_amd import rsim
+
+    b = synth.make_config2(n_utt=10, epoch=50)
+    l2 = np.where(np.arange(b.n_utt) % 2 == 0, 13, 14).astype(np.int32)   # two families
+    db = rsim.DeviceBatch(b, fft_log2n=l2)
+    alpha = torch.from_numpy(rsim.batch_gains(db, b.snr_db)).cuda()
+    y = torch.zeros(max(db.y_len, 1), device="cuda")
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        rsim.simulate_static(db, alpha, 20.0, y, stream=s)   # first use on the device before capture
+    s.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        rsim.simulate_static(db, alpha, 20.0, y, stream=s)
+    torch.cuda.synchronize()
+    for rep in range(3):
+        with torch.no_grad():
+            db.x.mul_(0.5 + rep)
+            db.h.neg_()
+        torch.cuda.synchronize()
+        y.zero_()
+        g.replay()
+        torch.cuda.synchronize()
+        got, rl, ol = y.cpu().numpy(), db.rir_len.cpu().numpy(), db.out_len.cpu().numpy()
+        ref = rsim.simulate(db, alpha, 20.0, y=torch.zeros_like(y))
+        torch.cuda.synchronize()
+        assert np.array_equal(rl, db.rir_len.cpu().numpy()) and np.array_equal(ol, db.out_len.cpu().numpy())
+        assert np.array_equal(got.view(np.uint32), ref.cpu().numpy().view(np.uint32)), rep
+    assert rsim.device_status() == 0
+
+
+@pytest.mark.gpu
 def test_static_entry_rejects_a_batch_that_does_not_fit():
     # 64 sources x 64 mics forced to N = 32768: one workgroup's slot of RIR
     # spectra alone is larger than the static array; nothing is launched
