@@ -223,7 +223,10 @@ rsim_status rsim_simulate(const rsim_batch* b, const float* x, const float* h,
  * serialises them (one stream, or events).  Results are bit-identical to
  * rsim_simulate's for the same batch, eta and tune (this call never splits
  * an utterance's blocks over several work items, which keeps the scratch
- * small; the split changes no output bit).
+ * small; the split changes no output bit).  On a capturing stream the call
+ * records its kernels one after the other (no side streams, no memory set
+ * or copy), so the capture can be replayed; the first call on a device must
+ * come before any capture (it sets the library up).
  */
 #define RSIM_STATIC_SCRATCH_BYTES ((size_t)128 << 20)
 rsim_status rsim_simulate_static(const rsim_batch* b, const float* x, const float* h,
