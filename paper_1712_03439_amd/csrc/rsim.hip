@@ -762,11 +762,17 @@ __device__ __forceinline__ void emit(cf* Yv, XC& lds, const TwBase& tw, float* _
   const rsrc_t wr = make_rsrc(yp, lim * 4);
   const rsrc_t rd = make_rsrc(yp, min(carry, lim) * 4);
   const int vo = 8 * t;
+  // Every carry word is requested before the first store.  Reads and writes
+  // through different resources cannot be told apart by the compiler, so a
+  // read placed after a store waits for it: interleaved, the block would
+  // cost one memory round trip per slot.
+  cf c[PL::P];
+#pragma unroll
+  for (int r = 0; r < PL::P; ++r) c[r] = ld2(rd, vo + 8 * r * PL::T);
 #pragma unroll
   for (int r = 0; r < PL::P; ++r) {
     const int o = vo + 8 * r * PL::T;
-    const cf c = ld2(rd, o);
-    st2(wr, o, mk(Yv[r].x + c.x, Yv[r].y + c.y));
+    st2(wr, o, mk(Yv[r].x + c[r].x, Yv[r].y + c[r].y));
   }
 }
 
@@ -1197,9 +1203,10 @@ __device__ __forceinline__ void mix_utterance(const MixArgs& A, int u, const Sch
             if (two) mac_regs<PL>(Y1, Hp1, X, t);
           }
         }
-        // Carries that fit the first P/4 slots of each thread (all but very
-        // long RIRs) are requested for both mics before either inverse
-        // transform, so their latency is hidden; longer ones are read after.
+        // Carries that fit the first P/4 slots of each thread (most RIRs) are
+        // requested for both mics before either inverse transform, so their
+        // latency is hidden; longer ones are read after the transform, all
+        // words of a block before its first store (one round trip).
         float* y0 = A.y + yo + (long long)j0 * ys + base;
         constexpr int CR = P / 4;
         if constexpr (FEAT) {
