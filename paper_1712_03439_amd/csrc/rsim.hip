@@ -886,11 +886,15 @@ __device__ __forceinline__ void feat_block(const MixArgs& A, cf* Yv, cf* lds_raw
   constexpr int kDrop = 0x7ffffff0;  // beyond any resource's range
   const rsrc_t rd = make_rsrc(acc_rd, (bk == 0 ? 0 : lmax - 1) * 4);
   const rsrc_t wr = make_rsrc(acc_wr, (lmax - 1) * 4);
+  // Every accumulator word is requested before the first store (a read
+  // after a store through another resource would wait for it).
+  cf c[P];
+#pragma unroll
+  for (int r = 0; r < P; ++r) c[r] = ld2(rd, 8 * (t + r * T));
 #pragma unroll
   for (int r = 0; r < P; ++r) {
     const int n0 = 2 * (t + r * T);
-    const cf c = ld2(rd, 4 * n0);
-    Yv[r] = mk(Yv[r].x + c.x, Yv[r].y + c.y);
+    Yv[r] = mk(Yv[r].x + c[r].x, Yv[r].y + c[r].y);
     st2(wr, n0 >= B ? 4 * (n0 - B) : kDrop, Yv[r]);
     st1(wr, n0 + 1 == B ? 0 : kDrop, Yv[r].y);
   }
@@ -1444,20 +1448,34 @@ __device__ __forceinline__ void acc_corr(cf* __restrict__ Rm, const cf* X, const
   const rsrc_t rw = make_rsrc(Rm, PL::P * PL::T * 8);
   const rsrc_t rb = make_rsrc(Bm, PL::P * PL::T * 8);
   const int vo = 16 * t;  // paired layout
+  // Slots in batches of QB, all operands of a batch requested before its
+  // first store (reads and writes through different resources cannot be
+  // told apart by the compiler: a read after a store waits for it).
+  constexpr int QB = PL::P < 8 ? PL::P : 8;
 #pragma unroll
-  for (int q = 0; q < PL::P; ++q) {
-    const int vq = vo + 8 * (q & 1), sq = 16 * (q >> 1) * PL::T;
-    const cf acc = ld2(rr, vq, sq);
-    const cf bv = ld2(rb, vq, sq);
-    cf o;
-    if (q == SP) {
-      const cf c = cmacc(acc, X[q], bv);
-      const cf d = mk(__builtin_fmaf(X[q].x, bv.x, acc.x), __builtin_fmaf(X[q].y, bv.y, acc.y));
-      o = t == 0 ? d : c;
-    } else {
-      o = cmacc(acc, X[q], bv);
+  for (int q0 = 0; q0 < PL::P; q0 += QB) {
+    cf acc[QB], bv[QB];
+#pragma unroll
+    for (int e = 0; e < QB; ++e) {
+      const int q = q0 + e;
+      const int vq = vo + 8 * (q & 1), sq = 16 * (q >> 1) * PL::T;
+      acc[e] = ld2(rr, vq, sq);
+      bv[e] = ld2(rb, vq, sq);
     }
-    st2(rw, vq, o, sq);
+#pragma unroll
+    for (int e = 0; e < QB; ++e) {
+      const int q = q0 + e;
+      const int vq = vo + 8 * (q & 1), sq = 16 * (q >> 1) * PL::T;
+      cf o;
+      if (q == SP) {
+        const cf c = cmacc(acc[e], X[q], bv[e]);
+        const cf d = mk(__builtin_fmaf(X[q].x, bv[e].x, acc[e].x), __builtin_fmaf(X[q].y, bv[e].y, acc[e].y));
+        o = t == 0 ? d : c;
+      } else {
+        o = cmacc(acc[e], X[q], bv[e]);
+      }
+      st2(rw, vq, o, sq);
+    }
   }
 }
 
