@@ -20,7 +20,7 @@ import pytest
 
 import oracle
 import synth
-from tests.gpu_util import cuda
+from tests.gpu_util import TOL, cuda, max_rel_err
 from tests.test_gpu_backward import _check_full_many, _run
 from tests.test_gpu_mix import _check_utterances, _simulate
 
@@ -239,3 +239,25 @@ def test_wide_random_batch_forward_adjoint_energies(k):
     _check_full_many(b, eta, gx, gh, ga, gys, list(range(b.n_utt)))
     _, e, rl2 = _energies(b, eta)
     _check_energies(b, eta, e, rl2)
+
+
+@pytest.mark.gpu
+def test_random_ola_shapes():
+    # rsim_ola_convolve on 40 random (signal, RIR, FFT size, hop) shapes,
+    # the hop anywhere from 1 to its largest value N - L + 1
+    torch = cuda()
+    from paper_1712_03439_amd import rsim
+
+    rng = synth.rng_for(700, 0)
+    for k in range(40):
+        l2 = int(rng.integers(9, 16))
+        N = 1 << l2
+        nh = int(rng.integers(1, N + 1))
+        nx = int(rng.integers(1, 5 * N))
+        hop = int(rng.integers(1, N - nh + 2)) if rng.random() < 0.5 else 0
+        x = rng.standard_normal(nx).astype(np.float32)
+        h = (rng.standard_normal(nh) * np.exp(-np.arange(nh) / (nh / 3 + 1))).astype(np.float32)
+        y = rsim.ola_convolve(torch.from_numpy(x).cuda(), torch.from_numpy(h).cuda(), N, hop).cpu().numpy()
+        ref = oracle.convolve(x, h)
+        assert y.shape == ref.shape, (k, nx, nh, N, hop)
+        assert max_rel_err(y, ref) <= TOL, (k, nx, nh, N, hop, max_rel_err(y, ref))
