@@ -100,6 +100,26 @@ def test_quantised_sum_within_its_bound_of_the_plain_sum():
     assert np.all(np.abs(got - ex) <= cnt * 2.0 ** -41 + np.abs(ex) * 2.0 ** -24 + 1e-15)
 
 
+def test_small_amplitudes_are_rounded_to_nearest():
+    # with r = 0.01 the images after four or more reflections have amplitudes
+    # of about 2^-27 and below, where float32 resolves far finer than the
+    # 2^-40 quantum: at taps holding only such images the quantised sum stays
+    # within count * 2^-41 of the plain binary64 sum, the bound of rounding
+    # each image to nearest (truncating errs by up to twice as much)
+    room, src, mic, r = (7.1, 5.3, 3.1), (2.0, 1.5, 1.2), (5.5, 4.0, 1.6), 0.01
+    length = 6000
+    n, _, g, _ = im.image_taps(room, src, mic, r)
+    keep = n < length
+    cnt = np.bincount(n[keep], minlength=length)
+    gmin = np.full(length, 1 << 30)
+    np.minimum.at(gmin, n[keep], g[keep])
+    small = (cnt > 0) & (gmin >= 4)
+    assert np.count_nonzero(small) > 100
+    ex = im.image_rir_exact(room, src, mic, r, length)[small]
+    got = im.image_rir(room, src, mic, r, length).astype(np.float64)[small]
+    assert np.all(np.abs(got - ex) <= cnt[small] * 2.0 ** -41 + np.abs(ex) * (2.0 ** -24 + 1e-15))
+
+
 def test_taps_beyond_the_length_are_dropped():
     room, src, mic, r = (6.0, 5.0, 3.0), (1.0, 1.0, 1.0), (4.0, 3.0, 2.0), 0.8
     long = im.image_rir(room, src, mic, r, 5000)

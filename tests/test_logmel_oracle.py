@@ -25,6 +25,21 @@ def test_power_spectrum_of_an_on_bin_tone():
     assert np.max(rest) < 1e-16
 
 
+def test_band_energies_and_features_of_an_on_bin_tone():
+    # the tone's power spectrum is fixed in closed form (above), so a band's
+    # energy is its weights at bins 39, 40 and 41 times 64^2, 128^2 and 64^2,
+    # and its feature the natural log of that energy plus 1e-6; at amplitude
+    # 1e-5 the energies are of the order of that floor
+    n = np.arange(512)
+    W = lm.filterbank()
+    for amp in (1.0, 1e-5):
+        y = amp * np.cos(2 * math.pi * 40 * n / 512)
+        E = amp * amp * (W[:, 39] * 64.0 ** 2 + W[:, 40] * 128.0 ** 2 + W[:, 41] * 64.0 ** 2)
+        assert np.count_nonzero(E) >= 2
+        assert np.allclose(lm.mel_energies(y)[0], E, rtol=1e-9, atol=1e-15 * amp * amp)
+        assert np.allclose(lm.logmel(y)[0], np.log(E + 1e-6), rtol=0.0, atol=1e-9)
+
+
 def test_power_spectrum_by_the_dft_sum_and_parseval():
     rng = np.random.default_rng(41)
     y = rng.standard_normal(700)
