@@ -2331,7 +2331,17 @@ __global__ __launch_bounds__(kImgThreads) void image_kernel(ImageArgs A) {
   const ImageIter it0{t / S2, (t % S2) / S, t % S};
   const float taps_per_m = (float)(A.fs / A.c0);
   int err = 0;
-  for (int r = blockIdx.x; r < A.n_rir; r += gridDim.x) {
+  // Round k takes RIRs [k G, k G + m), m = min(G, n_rir - k G) for G
+  // workgroups; workgroup b takes the one at (b + k) mod m.  Across the
+  // rounds a workgroup thus visits every position of a slot pattern that
+  // repeats with a period dividing G (the source and mic slots of
+  // consecutive utterances, of which the higher sources are often empty),
+  // so the busy slots spread evenly over the workgroups.
+  const long long G = gridDim.x;
+  for (long long k0 = 0; k0 < A.n_rir; k0 += G) {
+    const long long m = (long long)A.n_rir - k0 < G ? (long long)A.n_rir - k0 : G;
+    if ((long long)blockIdx.x >= m) break;  // only the last round is partial
+    const int r = (int)(k0 + ((long long)blockIdx.x + k0 / G) % m);
     const int len = uni(A.len[r]);
     const long long off = uni64(A.off[r]);
     if (len < 0 || len > A.max_len || off < 0 || off + len > A.h_len) {
