@@ -2248,6 +2248,7 @@ constexpr int kImgThreads = 1024;
 constexpr int kImgWindow = 16384;
 constexpr int kImgMaxOrder = 16;
 constexpr int kImgMaxLen = 32768;  // taps per RIR, at most (two windows)
+constexpr int kImgChunk = 4 * kImgThreads;  // slots ranked at a time
 
 struct ImageArgs {
   const double* geom;  // [n_rir][9]: room Lx Ly Lz, source xyz, mic xyz
@@ -2325,70 +2326,109 @@ __global__ __launch_bounds__(kImgThreads) void image_kernel(ImageArgs A) {
   __shared__ double sq[3][2 * kImgMaxOrder + 1];
   __shared__ float sqf[3][2 * kImgMaxOrder + 1];
   __shared__ double pw[3 * kImgMaxOrder + 1];
+  __shared__ int s_list[kImgChunk];          // this workgroup's slots of the current chunk
+  __shared__ int s_wcnt[kImgThreads / 64];   // nonzero slots per wave of the chunk
   const int t = threadIdx.x;
   const int K = A.order, S = 2 * K + 1, S2 = S * S, V = S2 * S;
   const int q2 = kImgThreads / S2, q1 = (kImgThreads % S2) / S, q0 = kImgThreads % S;
   const ImageIter it0{t / S2, (t % S2) / S, t % S};
   const float taps_per_m = (float)(A.fs / A.c0);
   int err = 0;
-  // Round k takes RIRs [k G, k G + m), m = min(G, n_rir - k G) for G
-  // workgroups; workgroup b takes the one at (b + k) mod m.  Across the
-  // rounds a workgroup thus visits every position of a slot pattern that
-  // repeats with a period dividing G (the source and mic slots of
-  // consecutive utterances, of which the higher sources are often empty),
-  // so the busy slots spread evenly over the workgroups.
-  const long long G = gridDim.x;
-  for (long long k0 = 0; k0 < A.n_rir; k0 += G) {
-    const long long m = (long long)A.n_rir - k0 < G ? (long long)A.n_rir - k0 : G;
-    if ((long long)blockIdx.x >= m) break;  // only the last round is partial
-    const int r = (int)(k0 + ((long long)blockIdx.x + k0 / G) % m);
-    const int len = uni(A.len[r]);
-    const long long off = uni64(A.off[r]);
-    if (len < 0 || len > A.max_len || off < 0 || off + len > A.h_len) {
-      err |= RSIM_DEV_BADDESC;
-      continue;
+  // The slots with a nonzero length are ranked in slot order and workgroup b
+  // of G takes ranks b, b + G, b + 2G, ...: every workgroup gets the same
+  // number of RIRs to within one, wherever the empty slots lie (in a batch,
+  // the slots of an utterance's missing sources).  Each workgroup ranks the
+  // slots itself, kImgChunk at a time (four consecutive slots per thread, a
+  // ballot per slot and wave, the wave counts in LDS), lists its own slots
+  // of the chunk in LDS, and loads the next chunk's lengths while it makes
+  // this chunk's RIRs.
+  const long long G = gridDim.x, b = blockIdx.x;
+  const int lane = t & 63, wv = t >> 6;
+  const unsigned long long lanes_below = (1ull << lane) - 1ull;
+  int ln[4];
+  for (int j = 0; j < 4; ++j) ln[j] = 4LL * t + j < A.n_rir ? A.len[4LL * t + j] : 0;
+  long long base = 0;  // nonzero slots before the chunk
+  for (long long c0 = 0; c0 < A.n_rir; c0 += kImgChunk) {
+    __syncthreads();  // the previous chunk's list and wave counts are consumed
+    int below = 0, wtot = 0;
+    for (int j = 0; j < 4; ++j) {
+      const unsigned long long bal = __ballot(ln[j] != 0);
+      below += __popcll(bal & lanes_below);
+      wtot += __popcll(bal);
     }
-    if (len == 0) continue;
-    const int nw = (len + kImgWindow - 1) / kImgWindow;
-    const double* g = A.geom + 9LL * r;
-    const double refl = A.refl[r];
-    const bool ok = image_geometry_ok(g, refl);
-    if (!ok) err |= RSIM_DEV_BADDESC;
-    __syncthreads();  // the previous RIR's readers of the shared arrays are done
-    if (t < 3 * S) {
-      const int ax = t / S, a = t - ax * S - K;
-      const double d = image_delta(a, g[ax], g[3 + ax], g[6 + ax]);
-      sq[ax][t - ax * S] = d * d;
-      sqf[ax][t - ax * S] = (float)(d * d);
+    if (lane == 0) s_wcnt[wv] = wtot;
+    __syncthreads();
+    long long pre = 0, tot = 0;
+    for (int i = 0; i < kImgThreads / 64; ++i) {
+      const int v = s_wcnt[i];
+      pre += i < wv ? v : 0;
+      tot += v;
     }
-    if (t == 0) {
-      double p = 1.0;
-      for (int k = 0; k <= 3 * K; ++k) {
-        pw[k] = p;
-        p = p * refl;
+    const long long first = base + ((b - base % G) + G) % G;  // first rank >= base taken by b
+    long long rank = base + pre + below;                        // of this thread's first nonzero slot
+    for (int j = 0; j < 4; ++j) {
+      if (ln[j] == 0) continue;
+      if (rank % G == b) s_list[(rank - first) / G] = (int)(c0 + 4LL * t + j);
+      ++rank;
+    }
+    const long long end = base + tot;
+    const int mine = first < end ? (int)((end - 1 - first) / G + 1) : 0;
+    base = end;
+    __syncthreads();
+    for (int j = 0; j < 4; ++j) {
+      const long long sl = c0 + kImgChunk + 4LL * t + j;
+      ln[j] = sl < A.n_rir ? A.len[sl] : 0;
+    }
+    for (int li = 0; li < mine; ++li) {
+      const int r = uni(s_list[li]);  // the same in every lane: scalar addressing of the slot
+      const int len = uni(A.len[r]);
+      const long long off = uni64(A.off[r]);
+      if (len < 0 || len > A.max_len || off < 0 || off + len > A.h_len) {
+        err |= RSIM_DEV_BADDESC;
+        continue;
       }
-    }
-    for (int wi = 0; wi < nw; ++wi) {
-      const int w0 = wi * kImgWindow, wn = min(kImgWindow, len - w0);
-      __syncthreads();  // the tables are written; the previous window's taps are stored
-      for (int k = t; k < wn; k += kImgThreads) acc[k] = 0ull;
-      __syncthreads();
-      if (ok) {
-        ImageIter im = it0;
-        for (int v = t; v < V; v += kImgThreads) {
-          bool in = true;
-          if (nw > 1) {
-            int wlo, whi;
-            image_windows((sqf[0][im.ia] + sqf[1][im.ib]) + sqf[2][im.ic], taps_per_m, nw, wlo, whi);
-            in = wlo <= wi && wi <= whi;
-          }
-          if (in) image_add(sq, pw, K, im.ia, im.ib, im.ic, A.fs, A.c0, w0, wn, acc);
-          im.step(S, q2, q1, q0);
+      if (len == 0) continue;
+      const int nw = (len + kImgWindow - 1) / kImgWindow;
+      const double* g = A.geom + 9LL * r;
+      const double refl = A.refl[r];
+      const bool ok = image_geometry_ok(g, refl);
+      if (!ok) err |= RSIM_DEV_BADDESC;
+      __syncthreads();  // the previous RIR's readers of the shared arrays are done
+      if (t < 3 * S) {
+        const int ax = t / S, a = t - ax * S - K;
+        const double d = image_delta(a, g[ax], g[3 + ax], g[6 + ax]);
+        sq[ax][t - ax * S] = d * d;
+        sqf[ax][t - ax * S] = (float)(d * d);
+      }
+      if (t == 0) {
+        double p = 1.0;
+        for (int k = 0; k <= 3 * K; ++k) {
+          pw[k] = p;
+          p = p * refl;
         }
       }
-      __syncthreads();
-      for (int k = t; k < wn; k += kImgThreads)
-        A.h[off + w0 + k] = (float)((double)acc[k] * 9.094947017729282e-13);  // 2^-40
+      for (int wi = 0; wi < nw; ++wi) {
+        const int w0 = wi * kImgWindow, wn = min(kImgWindow, len - w0);
+        __syncthreads();  // the tables are written; the previous window's taps are stored
+        for (int k = t; k < wn; k += kImgThreads) acc[k] = 0ull;
+        __syncthreads();
+        if (ok) {
+          ImageIter im = it0;
+          for (int v = t; v < V; v += kImgThreads) {
+            bool in = true;
+            if (nw > 1) {
+              int wlo, whi;
+              image_windows((sqf[0][im.ia] + sqf[1][im.ib]) + sqf[2][im.ic], taps_per_m, nw, wlo, whi);
+              in = wlo <= wi && wi <= whi;
+            }
+            if (in) image_add(sq, pw, K, im.ia, im.ib, im.ic, A.fs, A.c0, w0, wn, acc);
+            im.step(S, q2, q1, q0);
+          }
+        }
+        __syncthreads();
+        for (int k = t; k < wn; k += kImgThreads)
+          A.h[off + w0 + k] = (float)((double)acc[k] * 9.094947017729282e-13);  // 2^-40
+      }
     }
   }
   if (err && t == 0) flag_status(err);
